@@ -1,0 +1,243 @@
+/*
+ * sph.h -- C ABI of libsph, one SPH time step on an AMD MI355X (gfx950).
+ *
+ * The per-timestep particle loop of the SPH mini-app described in
+ * "SPH-EXA: Enhancing the Scalability of SPH codes Via an Exascale-Ready SPH
+ * Mini-App" (Guerrera et al., arXiv:1905.03344): neighbour discovery (here a
+ * Morton cell list in place of the tree walk of Table 1), smoothing-length
+ * update, density sum with standard volume elements (Table 1), equation of
+ * state, momentum equation after Rosswog (2009) with Monaghan (1983)
+ * artificial viscosity, energy equation, Courant time step and the position
+ * and energy update (section "Co-Design of the Mini-App").  The kernel is
+ * the M4 cubic spline with support 0 <= r/h <= 2 (the support convention of
+ * the Sinc and Wendland kernel equations).
+ *
+ * Conventions
+ *   - Every array argument is a DEVICE pointer owned by the caller; the
+ *     library never allocates device memory.  Scratch memory is one
+ *     caller-allocated workspace of sph_workspace_size() bytes, bound with
+ *     sph_bind() together with the HIP stream every call launches on.
+ *   - Calls are asynchronous on the bound stream and return an int status.
+ *     Argument errors are reported at once; conditions found by kernels
+ *     (list overflow, non-convergence, non-finite values) are reported by
+ *     the next sph_sync().  Nothing throws across the ABI.
+ *   - One context per stream; calls on one context must not overlap.
+ *   - Particles are structure-of-arrays.  Carried fields come in ping-pong
+ *     pairs [2]; member `cur` selects the current buffer.  sph_build_cells()
+ *     reorders every carried field from buffer cur into 1-cur and flips cur.
+ */
+#ifndef SPH_H
+#define SPH_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* status codes */
+#define SPH_OK 0
+#define SPH_EINVAL (-1)      /* invalid argument */
+#define SPH_ENOMEM (-2)      /* workspace too small or not bound */
+#define SPH_ECAPACITY (-3)   /* a neighbour list exceeded its capacity (see sph_stats) */
+#define SPH_EHIP (-4)        /* HIP runtime error; text in sph_last_error() */
+#define SPH_ENONFINITE (-5)  /* non-finite field value (only with check_finite) */
+#define SPH_WNOCONV 1        /* warning: some smoothing lengths did not converge */
+
+#define SPH_KERNEL_M4 0
+#define SPH_FP64 0
+#define SPH_MIXED 1
+#define SPH_H_PLAIN 0
+#define SPH_H_LEARNED 1
+
+/* particle flag bits */
+#define SPH_FLAG_NOCONV 1u   /* h iteration ended outside the target band */
+#define SPH_FLAG_LEARNED 2u  /* learned h was accepted (no iteration needed) */
+
+typedef struct sph_ctx sph_ctx;
+
+typedef struct sph_params {
+    int64_t n_max;          /* largest particle count the workspace is sized for */
+    int32_t list_stride;    /* K: capacity of each gather set L_i (default 128) */
+    int32_t pad0;
+    int64_t extra_capacity; /* entries reserved for the one-sided complement E */
+    int32_t periodic[3];    /* 1 = periodic dimension (minimum image, wrap) */
+    int32_t kernel;         /* SPH_KERNEL_M4 */
+    double box_lo[3];       /* box of the periodic dimensions */
+    double box_hi[3];
+    int32_t n_target;       /* target neighbour count (100) */
+    int32_t n_tol;          /* accepted deviation (5) */
+    int32_t h_max_iter;     /* iteration cap of the h solve (32) */
+    int32_t precision;      /* SPH_FP64 or SPH_MIXED */
+    double gamma;           /* adiabatic index (5/3) */
+    double av_alpha;        /* artificial viscosity alpha (1) */
+    double av_beta;         /* artificial viscosity beta (2) */
+    double av_eta2;         /* viscosity softening eta^2 (0.01) */
+    double cfl;             /* Courant factor (0.3) */
+    int32_t h_mode;         /* SPH_H_PLAIN or SPH_H_LEARNED */
+    int32_t check_finite;   /* 1 = count non-finite fields (slower) */
+    int32_t max_level;      /* finest Morton level of the cell table, 1..8 */
+    int32_t search_div;     /* search cells are at least 2h/search_div wide (1 or 2) */
+} sph_params;
+
+typedef struct sph_particles {
+    int64_t n;              /* particle count, <= n_max */
+    int32_t cur;            /* current buffer of each pair, 0 or 1 */
+    int32_t pad0;
+    /* carried fields, ping-pong pairs, each of length n */
+    double *x[2], *y[2], *z[2];      /* position */
+    double *vx[2], *vy[2], *vz[2];   /* velocity (half-step value inside a step) */
+    double *m[2];                    /* mass */
+    double *h[2];                    /* smoothing length */
+    double *u[2];                    /* specific internal energy */
+    double *ax[2], *ay[2], *az[2];   /* acceleration of the last evaluation */
+    double *du[2];                   /* du/dt of the last evaluation */
+    double *rho[2];                  /* density of the last evaluation */
+    double *divv[2];                 /* velocity divergence of the last evaluation */
+    int32_t *nc[2];                  /* |L_i|, gather neighbour count */
+    int32_t *id[2];                  /* persistent particle id */
+    /* single buffers, length n, in the current order */
+    double *pvx, *pvy, *pvz, *pu;    /* velocity and energy used by the force evaluation */
+    double *p, *c;                   /* pressure, sound speed */
+    uint8_t *flags;                  /* SPH_FLAG_* bits */
+    uint32_t *key;                   /* sorted 30-bit cell keys (from sph_build_cells) */
+    int32_t *perm;                   /* perm[k] = position before the sort of sorted particle k */
+} sph_particles;
+
+/* Neighbour lists.  The interaction set of particle i is
+ *   S_i = L_i U E_i,   L_i = { j != i : r_ij^2 < (2 h_i)^2 }  (gather set),
+ *                      E_i = { j : i in L_j, j not in L_i }    (complement),
+ * so that j in S_i <=> i in S_j.  L is stored slot-major ("ELL"):
+ * entry k of L_i is idx[k * stride + i], k < nc[i] (nc in sph_particles);
+ * E is CSR: eidx[eoff[i] .. eoff[i+1]) in ascending index order.
+ * All indices refer to the current (sorted) particle order. */
+typedef struct sph_nlist {
+    int32_t *idx;           /* list_stride * stride entries */
+    int64_t stride;         /* row pitch of idx, >= n (a multiple of 64) */
+    int64_t *eoff;          /* n + 1 */
+    int32_t *eidx;          /* ecap entries */
+    int64_t ecap;
+} sph_nlist;
+
+typedef struct sph_stats {
+    int64_t nonconverged;    /* particles whose h iteration ended outside the band */
+    int64_t list_overflow;   /* particles whose |L_i| exceeded list_stride */
+    int64_t extra_total;     /* |E| summed over particles */
+    int64_t extra_overflow;  /* 1 if |E| exceeded ecap */
+    int64_t nonfinite;       /* non-finite values found (check_finite) */
+    int64_t h_counts;        /* neighbour counts taken by the h iteration (all particles) */
+    int64_t learned_accepted;/* learned mode: particles whose predicted h was accepted */
+    int64_t learned_fallback;/* learned mode: particles that fell back to the iteration */
+    int64_t candidates;      /* candidate pairs tested by the h iteration */
+    double dt;               /* Courant time step of the last evaluation */
+} sph_stats;
+
+/* Fill *p with the defaults above (n_max and capacities set to 0). */
+void sph_default_params(sph_params *p);
+
+/* Validate *p and create a context holding host metadata only.
+ * Returns SPH_EINVAL for an invalid parameter (message via *out == NULL:
+ * use sph_params_error()). */
+int sph_create(const sph_params *p, sph_ctx **out);
+void sph_destroy(sph_ctx *ctx);
+const char *sph_params_error(void);
+
+/* Bytes of device workspace needed for *p (sort buffers, cell table, scan
+ * scratch, reduction partials, status words, MLP buffers). */
+int sph_workspace_size(const sph_params *p, size_t *bytes);
+
+/* Bind a caller-owned device workspace and a HIP stream (hipStream_t cast
+ * to void*; NULL = the null stream).  Uploads the Hernquist-Katz factor
+ * table.  May be called again to rebind. */
+int sph_bind(sph_ctx *ctx, void *workspace, size_t bytes, void *stream);
+
+/* A1-A4: bounding box (exact min/max; periodic dimensions use the box),
+ * 30-bit Morton cell keys (10 bits per dimension of the cell index in the
+ * box), stable LSD radix sort of the keys (ties keep the input order),
+ * permutation of every carried field into buffer 1-cur (cur flips), and the
+ * cell-start table at level max_level.  Writes s->key and s->perm. */
+int sph_build_cells(sph_ctx *ctx, sph_particles *s);
+
+/* A5-A6: smoothing-length iteration per particle from h[cur] (Hernquist &
+ * Katz factor until bracketed, then bisection, until |N_i - n_target| <=
+ * n_tol, at most h_max_iter counts; otherwise the best h is kept and
+ * SPH_FLAG_NOCONV set), with the gather set L_i written in the same pass;
+ * then the complement E.  Updates h[cur], nc[cur], flags. */
+int sph_find_neighbors(sph_ctx *ctx, sph_particles *s, sph_nlist *nl);
+
+/* A7: rho_i = m_i W(0,h_i) + sum_{j in L_i} m_j W(r_ij,h_i) and
+ * divv_i = (1/rho_i) sum_{j in L_i} m_j (v_j - v_i) . grad_i W(r_ij,h_i),
+ * with v the predicted velocity (pvx, pvy, pvz).  Writes rho[cur], divv[cur]. */
+int sph_density(sph_ctx *ctx, sph_particles *s, const sph_nlist *nl);
+
+/* A8: ideal gas, P = (gamma-1) rho u, c = sqrt(gamma (gamma-1) u), u = pu. */
+int sph_eos(sph_ctx *ctx, sph_particles *s);
+
+/* A9: over S_i, with grad W_bar = (grad_i W(r,h_i) + grad_i W(r,h_j))/2,
+ *   a_i  = -sum_j m_j (P_i/rho_i^2 + P_j/rho_j^2 + Pi_ij) grad W_bar
+ *   du_i =  sum_j m_j (P_i/rho_i^2 + Pi_ij/2) v_ij . grad W_bar
+ * Monaghan viscosity Pi_ij for approaching pairs, and the Courant step
+ * dt = cfl min_i h_i / (c_i + 1.2 (alpha c_i + beta max_j |mu_ij|)) written
+ * to the device scalar *d_dt.  Writes ax, ay, az, du of buffer cur. */
+int sph_momentum_energy(sph_ctx *ctx, sph_particles *s, const sph_nlist *nl, double *d_dt);
+
+/* A1-A9 at the stored state (pv = v, pu = u): the force evaluation that
+ * starts a run.  *d_dt receives the Courant step. */
+int sph_evaluate(sph_ctx *ctx, sph_particles *s, sph_nlist *nl, double *d_dt);
+
+/* One kick-drift-kick leapfrog step (A10 around A1-A9):
+ *   v += dt/2 a, u += dt/2 du, x += dt v (periodic wrap); sort;
+ *   pv = v + dt/2 a, pu = u + dt/2 du; A5-A9 at (x, pv, pu);
+ *   v += dt/2 a_new, u += dt/2 du_new.
+ * dt > 0 is used as given; dt <= 0 uses the device scalar *d_dt (the
+ * Courant step of the previous evaluation).  *d_dt receives the new step. */
+int sph_step(sph_ctx *ctx, sph_particles *s, sph_nlist *nl, double dt, double *d_dt);
+
+/* Conservation sums in FP64 with a fixed reduction order:
+ * d_out7 = [P_x, P_y, P_z, L_x, L_y, L_z, E], P = sum m v,
+ * L = sum m x cross v, E = sum m (v.v/2 + u), over buffer cur. */
+int sph_conservation(sph_ctx *ctx, const sph_particles *s, double *d_out7);
+
+/* Wait for the bound stream; fill *st (may be NULL) from the device status
+ * words and reset them.  Returns SPH_ECAPACITY on list overflow,
+ * SPH_ENONFINITE when non-finite values were counted, SPH_WNOCONV when
+ * some h did not converge, SPH_EHIP on a runtime error, else SPH_OK. */
+int sph_sync(sph_ctx *ctx, sph_stats *st);
+
+/* Last error message of this context (static storage inside ctx). */
+const char *sph_last_error(const sph_ctx *ctx);
+
+/* Copy an internal table into caller device memory dst (for tests):
+ * which = 0: cell-start table (int32, 8^max_level + 1 entries),
+ *         1: bounding box (6 doubles: lo[3], hi[3]).
+ * *needed receives the size in bytes; dst may be NULL to query it. */
+int sph_copy_internal(sph_ctx *ctx, int which, void *dst, size_t bytes, size_t *needed);
+
+/* Stage timing with HIP events recorded on the bound stream around each
+ * stage of every subsequent call (overhead: two event records per stage).
+ * Stages: SPH_STAGE_CELLS (A1-A4), _HSOLVE (A5 and the gather sets),
+ * _EXTRA (complement E), _DENSITY (A7), _EOS (A8), _FORCES (A9 + dt),
+ * _INTEGRATE (A10 kicks, drift, prediction). */
+#define SPH_STAGE_CELLS 0
+#define SPH_STAGE_HSOLVE 1
+#define SPH_STAGE_EXTRA 2
+#define SPH_STAGE_DENSITY 3
+#define SPH_STAGE_EOS 4
+#define SPH_STAGE_FORCES 5
+#define SPH_STAGE_INTEGRATE 6
+#define SPH_NSTAGES 7
+
+/* enable = 1 clears the accumulators and starts recording; 0 stops. */
+int sph_timing(sph_ctx *ctx, int enable);
+
+/* Waits for the bound stream, then writes the summed elapsed milliseconds
+ * (ms[k]) and the number of timed intervals (count[k]) of each stage k <
+ * nstages since timing was enabled.  Either pointer may be NULL. */
+int sph_timing_read(sph_ctx *ctx, double *ms, int64_t *count, int nstages);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SPH_H */

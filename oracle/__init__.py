@@ -164,14 +164,15 @@ def hsolve(x, y, z, h_in, periodic, box_lo, box_hi, n_target=100, n_tol=5, max_i
     return h, nc, flag, iters, int(nonconv)
 
 
-def lists(x, y, z, h, periodic, box_lo, box_hi, method=1):
+def lists(x, y, z, h, periodic, box_lo, box_hi, method=1, symmetric=True):
+    """Interaction sets S (symmetric) or gather sets L, CSR with ascending rows."""
     x, y, z, h = _f64(x), _f64(y), _f64(z), _f64(h)
     n = len(x)
     off = np.zeros(n + 1, dtype=np.int64)
     idx_ptr = ctypes.POINTER(ctypes.c_int32)()
     total = lib().or_lists(ctypes.c_int64(n), _p(x), _p(y), _p(z), _p(h), _int3(*periodic),
                            _dbl3(*box_lo), _dbl3(*box_hi), ctypes.c_int(method),
-                           _p(off, _i64), ctypes.byref(idx_ptr))
+                           ctypes.c_int(int(symmetric)), _p(off, _i64), ctypes.byref(idx_ptr))
     idx = np.ctypeslib.as_array(idx_ptr, shape=(max(total, 1),))[:total].copy()
     lib().or_free(idx_ptr)
     return off, idx
@@ -181,16 +182,19 @@ def lists(x, y, z, h, periodic, box_lo, box_hi, method=1):
 # fields
 # ---------------------------------------------------------------------------
 
-def density(x, y, z, vx, vy, vz, m, h, periodic, box_lo, box_hi, off, idx):
+def density(x, y, z, vx, vy, vz, m, h, periodic, box_lo, box_hi, off, idx, with_mag=False):
+    """rho, divv (and, with_mag, (1/rho) sum |m_j (v_j - v_i).grad W|, the scale
+    of the divergence sum used for conditioning-aware comparisons)."""
     arr = [_f64(a) for a in (x, y, z, vx, vy, vz, m, h)]
     n = len(arr[0])
     rho = np.zeros(n)
     divv = np.zeros(n)
+    mag = np.zeros(n)
     off = np.ascontiguousarray(off, dtype=np.int64)
     idx = np.ascontiguousarray(idx, dtype=np.int32)
     lib().or_density(ctypes.c_int64(n), *[_p(a) for a in arr], _int3(*periodic), _dbl3(*box_lo),
-                     _dbl3(*box_hi), _p(off, _i64), _p(idx, _i32), _p(rho), _p(divv))
-    return rho, divv
+                     _dbl3(*box_hi), _p(off, _i64), _p(idx, _i32), _p(rho), _p(divv), _p(mag))
+    return (rho, divv, mag) if with_mag else (rho, divv)
 
 
 def eos(rho, u, gamma=5.0 / 3.0):
@@ -202,17 +206,20 @@ def eos(rho, u, gamma=5.0 / 3.0):
 
 
 def forces(x, y, z, vx, vy, vz, m, h, rho, p, c, periodic, box_lo, box_hi, off, idx,
-           alpha=1.0, beta=2.0, eta2=0.01, cfl=0.3):
+           alpha=1.0, beta=2.0, eta2=0.01, cfl=0.3, with_mag=False):
+    """a, du, per-particle dt, sum_j m_j |f_ij| (and with_mag sum_j m_j |de_ij|)."""
     arr = [_f64(a) for a in (x, y, z, vx, vy, vz, m, h, rho, p, c)]
     n = len(arr[0])
-    out = [np.zeros(n) for _ in range(6)]
+    out = [np.zeros(n) for _ in range(7)]
     off = np.ascontiguousarray(off, dtype=np.int64)
     idx = np.ascontiguousarray(idx, dtype=np.int32)
     lib().or_forces(ctypes.c_int64(n), *[_p(a) for a in arr], _int3(*periodic), _dbl3(*box_lo),
                     _dbl3(*box_hi), _p(off, _i64), _p(idx, _i32), ctypes.c_double(alpha),
                     ctypes.c_double(beta), ctypes.c_double(eta2), ctypes.c_double(cfl),
                     *[_p(a) for a in out])
-    ax, ay, az, du, dt_i, amag = out
+    ax, ay, az, du, dt_i, amag, dumag = out
+    if with_mag:
+        return ax, ay, az, du, dt_i, amag, dumag
     return ax, ay, az, du, dt_i, amag
 
 
@@ -276,6 +283,7 @@ class State:
         self.perm = None
         self.flags = None
         self.nonconv = 0
+        self.keep_gather = False
 
     @property
     def n(self):
@@ -305,6 +313,9 @@ class State:
         f["h"], f["nc"] = h, nc
         self.flags, self.iters, self.nonconv = flag, iters, nonconv
         self.off, self.idx = lists(f["x"], f["y"], f["z"], h, *self.geom(), method)
+        if self.keep_gather:
+            self.loff, self.lidx = lists(f["x"], f["y"], f["z"], h, *self.geom(), method,
+                                         symmetric=False)
 
     def evaluate(self, method=1):
         """Cells, neighbours, density, EOS and forces at the stored state
@@ -344,16 +355,18 @@ class State:
         f = self.f
         self.pv = (vel, u)
         self.find_neighbors(method)
-        rho, divv = density(f["x"], f["y"], f["z"], *vel, f["m"], f["h"], *self.geom(),
-                            self.off, self.idx)
+        rho, divv, dvmag = density(f["x"], f["y"], f["z"], *vel, f["m"], f["h"], *self.geom(),
+                                   self.off, self.idx, with_mag=True)
         f["rho"], f["divv"] = rho, divv
+        self.divv_mag = dvmag
         P, c = eos(rho, u, self.p.gamma)
         self.P, self.c = P, c
-        ax, ay, az, du, dt_i, amag = forces(f["x"], f["y"], f["z"], *vel, f["m"], f["h"], rho, P, c,
-                                            *self.geom(), self.off, self.idx, self.p.alpha,
-                                            self.p.beta, self.p.eta2, self.p.cfl)
+        ax, ay, az, du, dt_i, amag, dumag = forces(f["x"], f["y"], f["z"], *vel, f["m"], f["h"],
+                                                   rho, P, c, *self.geom(), self.off, self.idx,
+                                                   self.p.alpha, self.p.beta, self.p.eta2,
+                                                   self.p.cfl, with_mag=True)
         f["ax"], f["ay"], f["az"], f["du"] = ax, ay, az, du
-        self.amag = amag
+        self.amag, self.dumag, self.dt_i = amag, dumag, dt_i
         self.dt_next = float(dt_i.min()) if len(dt_i) else np.inf
 
     def conservation(self):

@@ -476,11 +476,12 @@ static int cmp_i64(const void *a, const void *b)
     return p < q ? -1 : (p > q);
 }
 
-/* Builds S (ascending per row). off has n+1 entries; *idx_out is malloc'ed
- * (release with or_free). Returns the total number of entries. */
+/* Builds S (symmetric = 1) or the gather sets L (symmetric = 0), ascending
+ * per row. off has n+1 entries; *idx_out is malloc'ed (release with
+ * or_free). Returns the total number of entries. */
 int64_t or_lists(int64_t n, const double *x, const double *y, const double *z, const double *h,
                  const int *periodic, const double *box_lo, const double *box_hi, int method,
-                 int64_t *off, int32_t **idx_out)
+                 int symmetric, int64_t *off, int32_t **idx_out)
 {
     or_geom g;
     geom_init(&g, x, y, z, periodic, box_lo, box_hi);
@@ -506,15 +507,16 @@ int64_t or_lists(int64_t n, const double *x, const double *y, const double *z, c
         Lcnt[i] = c.cnt;
     }
     if (method == 1) grid_free(&G);
-    /* transpose: T_j = { i : j in L_i }, filled with i ascending */
+    /* transpose: T_j = { i : j in L_i }, filled with i ascending (empty when
+     * only the gather sets are asked for) */
     int64_t *Toff = (int64_t *)calloc((size_t)n + 1, sizeof(int64_t));
-    for (int64_t i = 0; i < n; ++i)
+    for (int64_t i = 0; symmetric && i < n; ++i)
         for (int64_t k = 0; k < Lcnt[i]; ++k) Toff[Lrow[i][k] + 1]++;
     for (int64_t j = 0; j < n; ++j) Toff[j + 1] += Toff[j];
     int64_t *Tidx = (int64_t *)malloc(sizeof(int64_t) * (size_t)(Toff[n] > 0 ? Toff[n] : 1));
     int64_t *Tfill = (int64_t *)malloc(sizeof(int64_t) * (size_t)(n > 0 ? n : 1));
     for (int64_t j = 0; j < n; ++j) Tfill[j] = Toff[j];
-    for (int64_t i = 0; i < n; ++i)
+    for (int64_t i = 0; symmetric && i < n; ++i)
         for (int64_t k = 0; k < Lcnt[i]; ++k) Tidx[Tfill[Lrow[i][k]]++] = i;
     free(Tfill);
     /* merge the two ascending rows without duplicates */
@@ -559,7 +561,7 @@ void or_density(int64_t n, const double *x, const double *y, const double *z,
                 const double *vx, const double *vy, const double *vz, const double *m,
                 const double *h, const int *periodic, const double *box_lo,
                 const double *box_hi, const int64_t *off, const int32_t *idx,
-                double *rho, double *divv)
+                double *rho, double *divv, double *divv_mag)
 {
     or_geom g;
     geom_init(&g, x, y, z, periodic, box_lo, box_hi);
@@ -569,7 +571,7 @@ void or_density(int64_t n, const double *x, const double *y, const double *z,
         double twoh = 2.0 * hi;
         double r2max = twoh * twoh;
         double s = m[i] * or_kernel_w(0.0, hi);
-        double dv = 0.0;
+        double dv = 0.0, dvm = 0.0;
         for (int64_t k = off[i]; k < off[i + 1]; ++k) {
             int64_t j = idx[k];
             double dx, dy, dz;
@@ -582,10 +584,12 @@ void or_density(int64_t n, const double *x, const double *y, const double *z,
                 double gw = or_kernel_dwdr(r, hi) / r;
                 double vdot = (vx[j] - vx[i]) * (-dx) + (vy[j] - vy[i]) * (-dy) + (vz[j] - vz[i]) * (-dz);
                 dv += m[j] * vdot * gw;
+                dvm += fabs(m[j] * vdot * gw);
             }
         }
         rho[i] = s;
         divv[i] = dv / s;
+        if (divv_mag) divv_mag[i] = dvm / s;
     }
 }
 
@@ -654,14 +658,14 @@ void or_forces(int64_t n, const double *x, const double *y, const double *z,
                const int *periodic, const double *box_lo, const double *box_hi,
                const int64_t *off, const int32_t *idx, double alpha, double beta, double eta2,
                double cfl, double *ax, double *ay, double *az, double *du, double *dt_i,
-               double *amag)
+               double *amag, double *dumag)
 {
     or_geom g;
     geom_init(&g, x, y, z, periodic, box_lo, box_hi);
     or_phys ph = {0.0, alpha, beta, eta2, cfl};
 #pragma omp parallel for schedule(dynamic, 256)
     for (int64_t i = 0; i < n; ++i) {
-        double sx = 0.0, sy = 0.0, sz = 0.0, se = 0.0, mumax = 0.0, mag = 0.0;
+        double sx = 0.0, sy = 0.0, sz = 0.0, se = 0.0, mumax = 0.0, mag = 0.0, emag = 0.0;
         for (int64_t k = off[i]; k < off[i + 1]; ++k) {
             int64_t j = idx[k];
             double fx, fy, fz, de, mua;
@@ -672,9 +676,11 @@ void or_forces(int64_t n, const double *x, const double *y, const double *z,
             se += m[j] * de;
             if (mua > mumax) mumax = mua;
             mag += m[j] * sqrt(fx * fx + fy * fy + fz * fz);
+            emag += m[j] * fabs(de);
         }
         ax[i] = sx; ay[i] = sy; az[i] = sz; du[i] = se;
         if (amag) amag[i] = mag;
+        if (dumag) dumag[i] = emag;
         if (dt_i) dt_i[i] = cfl * h[i] / (c[i] + 1.2 * (alpha * c[i] + beta * mumax));
     }
 }

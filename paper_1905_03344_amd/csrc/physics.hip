@@ -1,0 +1,405 @@
+// Density and divergence, equation of state, momentum / energy / viscosity
+// with the Courant step, kick-drift-kick integrator and conservation sums.
+#include "sph_internal.h"
+
+// rho_i = m_i W(0,h_i) + sum_{L_i} m_j W(r_ij,h_i);
+// divv_i = (1/rho_i) sum_{L_i} m_j (v_j - v_i) . grad_i W(r_ij,h_i)
+__global__ __launch_bounds__(SPH_BLOCK) void k_density(
+    int64_t n, const double *__restrict__ x, const double *__restrict__ y,
+    const double *__restrict__ z, const double *__restrict__ vx, const double *__restrict__ vy,
+    const double *__restrict__ vz, const double *__restrict__ m, const double *__restrict__ h,
+    const int32_t *__restrict__ nc, const int32_t *__restrict__ idx, int64_t stride, int K,
+    Geo g, double *__restrict__ rho, double *__restrict__ divv)
+{
+    int64_t i = global_index();
+    if (i >= n) return;
+    double xi = x[i], yi = y[i], zi = z[i];
+    double vxi = vx[i], vyi = vy[i], vzi = vz[i];
+    double inv_h = 1.0 / h[i];
+    double s = m[i] * kern_w(0.0, inv_h);
+    double dv = 0.0;
+    int cnt = min(nc[i], K);
+    for (int k = 0; k < cnt; ++k) {
+        int j = idx[(int64_t)k * stride + i];
+        double dx = min_image(xi, x[j], g.per[0], g.L[0], g.halfL[0]);
+        double dy = min_image(yi, y[j], g.per[1], g.L[1], g.halfL[1]);
+        double dz = min_image(zi, z[j], g.per[2], g.L[2], g.halfL[2]);
+        double r2 = dx * dx + dy * dy + dz * dz;
+        double r = sqrt(r2);
+        double mj = m[j];
+        s += mj * kern_w(r, inv_h);
+        if (r > 0.0) {
+            double gw = kern_dwdr(r, inv_h) / r;
+            double vdot = (vx[j] - vxi) * (-dx) + (vy[j] - vyi) * (-dy) + (vz[j] - vzi) * (-dz);
+            dv += mj * vdot * gw;
+        }
+    }
+    rho[i] = s;
+    divv[i] = dv / s;
+}
+
+hipError_t launch_density(sph_ctx *c, sph_particles *s, const sph_nlist *nl)
+{
+    int64_t n = s->n;
+    if (n == 0) return hipSuccess;
+    int cur = s->cur;
+    hipLaunchKernelGGL(k_density, dim3((unsigned)ceil_div(n, SPH_BLOCK)), dim3(SPH_BLOCK), 0,
+                       c->stream, n, s->x[cur], s->y[cur], s->z[cur], s->pvx, s->pvy, s->pvz,
+                       s->m[cur], s->h[cur], s->nc[cur], nl->idx, nl->stride, c->p.list_stride,
+                       make_geo(c->p), s->rho[cur], s->divv[cur]);
+    return hipGetLastError();
+}
+
+// ideal gas
+__global__ __launch_bounds__(SPH_BLOCK) void k_eos(int64_t n, const double *__restrict__ rho,
+                                                   const double *__restrict__ u, double gamma,
+                                                   double *__restrict__ p, double *__restrict__ c,
+                                                   int check, int64_t *__restrict__ status)
+{
+    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    int64_t bad = 0;
+    if (i < n) {
+        double pv = (gamma - 1.0) * rho[i] * u[i];
+        double cv = sqrt(gamma * (gamma - 1.0) * u[i]);
+        p[i] = pv;
+        c[i] = cv;
+        if (check && !(isfinite(pv) && isfinite(cv) && isfinite(rho[i]))) bad = 1;
+    }
+    if (check) block_add_i64(bad, status + ST_NONFINITE);
+}
+
+hipError_t launch_eos(sph_ctx *c, sph_particles *s)
+{
+    int64_t n = s->n;
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_eos, dim3((unsigned)ceil_div(n, SPH_BLOCK)), dim3(SPH_BLOCK), 0,
+                       c->stream, n, s->rho[s->cur], s->pu, c->p.gamma, s->p, s->c,
+                       c->p.check_finite, c->w.status);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// momentum, energy, artificial viscosity, Courant step
+// ---------------------------------------------------------------------------
+struct ForceAcc {
+    double ax, ay, az, du, mumax;
+};
+
+__device__ __forceinline__ void force_pair(int j, double xi, double yi, double zi, double vxi,
+                                           double vyi, double vzi, double hi, double inv_hi,
+                                           double rhoi, double ci, double pi_term,
+                                           const double *__restrict__ x,
+                                           const double *__restrict__ y,
+                                           const double *__restrict__ z,
+                                           const double *__restrict__ vx,
+                                           const double *__restrict__ vy,
+                                           const double *__restrict__ vz,
+                                           const double *__restrict__ m,
+                                           const double *__restrict__ h,
+                                           const double *__restrict__ rho,
+                                           const double *__restrict__ p,
+                                           const double *__restrict__ c, const Geo &g,
+                                           double alpha, double beta, double eta2, ForceAcc &A)
+{
+    double dx = min_image(xi, x[j], g.per[0], g.L[0], g.halfL[0]);
+    double dy = min_image(yi, y[j], g.per[1], g.L[1], g.halfL[1]);
+    double dz = min_image(zi, z[j], g.per[2], g.L[2], g.halfL[2]);
+    double r2 = dx * dx + dy * dy + dz * dz;
+    if (!(r2 > 0.0)) return;
+    double r = sqrt(r2);
+    double inv_r = 1.0 / r;
+    double hj = h[j];
+    double xij = -dx, yij = -dy, zij = -dz;
+    double vxij = vxi - vx[j], vyij = vyi - vy[j], vzij = vzi - vz[j];
+    double w = vxij * xij + vyij * yij + vzij * zij;
+    double gwi = kern_dwdr(r, inv_hi) * inv_r;
+    double gwj = kern_dwdr(r, 1.0 / hj) * inv_r;
+    double gbar = 0.5 * (gwi + gwj);
+    double rhoj = rho[j];
+    double Pi = 0.0;
+    if (w < 0.0) {
+        double hb = 0.5 * (hi + hj);
+        double cb = 0.5 * (ci + c[j]);
+        double rb = 0.5 * (rhoi + rhoj);
+        double mu = hb * w / (r2 + eta2 * hb * hb);
+        Pi = (-alpha * cb * mu + beta * mu * mu) / rb;
+        A.mumax = fmax(A.mumax, fabs(mu));
+    }
+    double pj_term = p[j] / (rhoj * rhoj);
+    double sfac = (pi_term + pj_term) + Pi;
+    double mj = m[j];
+    double f = mj * sfac * gbar;
+    A.ax -= f * xij;
+    A.ay -= f * yij;
+    A.az -= f * zij;
+    A.du += mj * (pi_term + 0.5 * Pi) * gbar * w;
+}
+
+__global__ __launch_bounds__(SPH_BLOCK) void k_forces(
+    int64_t n, const double *__restrict__ x, const double *__restrict__ y,
+    const double *__restrict__ z, const double *__restrict__ vx, const double *__restrict__ vy,
+    const double *__restrict__ vz, const double *__restrict__ m, const double *__restrict__ h,
+    const double *__restrict__ rho, const double *__restrict__ p, const double *__restrict__ c,
+    const int32_t *__restrict__ nc, const int32_t *__restrict__ idx, int64_t stride, int K,
+    const int64_t *__restrict__ eoff, const int32_t *__restrict__ eidx, int64_t ecap, Geo g,
+    double alpha, double beta, double eta2, double cfl, double *__restrict__ ax,
+    double *__restrict__ ay, double *__restrict__ az, double *__restrict__ du,
+    double *__restrict__ dt_part)
+{
+    int64_t i = global_index();
+    double dti = INFINITY;
+    if (i < n) {
+        double xi = x[i], yi = y[i], zi = z[i];
+        double vxi = vx[i], vyi = vy[i], vzi = vz[i];
+        double hi = h[i], inv_hi = 1.0 / hi, rhoi = rho[i], ci = c[i];
+        double pi_term = p[i] / (rhoi * rhoi);
+        ForceAcc A = {0.0, 0.0, 0.0, 0.0, 0.0};
+        int cnt = min(nc[i], K);
+        for (int k = 0; k < cnt; ++k)
+            force_pair(idx[(int64_t)k * stride + i], xi, yi, zi, vxi, vyi, vzi, hi, inv_hi, rhoi,
+                       ci, pi_term, x, y, z, vx, vy, vz, m, h, rho, p, c, g, alpha, beta, eta2, A);
+        int64_t e0 = eoff[i], e1 = eoff[i + 1];
+        if (e1 > ecap) e1 = ecap;
+        for (int64_t k = e0; k < e1; ++k)
+            force_pair(eidx[k], xi, yi, zi, vxi, vyi, vzi, hi, inv_hi, rhoi, ci, pi_term, x, y, z,
+                       vx, vy, vz, m, h, rho, p, c, g, alpha, beta, eta2, A);
+        ax[i] = A.ax;
+        ay[i] = A.ay;
+        az[i] = A.az;
+        du[i] = A.du;
+        dti = cfl * hi / (ci + 1.2 * (alpha * ci + beta * A.mumax));
+    }
+    // block minimum of dt_i (min is exact and order independent)
+    __shared__ double sh[SPH_BLOCK];
+    sh[threadIdx.x] = dti;
+    __syncthreads();
+    for (int s = SPH_BLOCK / 2; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) sh[threadIdx.x] = fmin(sh[threadIdx.x], sh[threadIdx.x + s]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) dt_part[blockIdx.x] = sh[0];
+}
+
+__global__ __launch_bounds__(SPH_BLOCK) void k_min_final(const double *__restrict__ part, int64_t nb,
+                                                         double *__restrict__ out)
+{
+    __shared__ double sh[SPH_BLOCK];
+    double v = INFINITY;
+    for (int64_t k = threadIdx.x; k < nb; k += SPH_BLOCK) v = fmin(v, part[k]);
+    sh[threadIdx.x] = v;
+    __syncthreads();
+    for (int s = SPH_BLOCK / 2; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) sh[threadIdx.x] = fmin(sh[threadIdx.x], sh[threadIdx.x + s]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *out = sh[0];
+}
+
+hipError_t launch_forces(sph_ctx *c, sph_particles *s, const sph_nlist *nl, double *d_dt)
+{
+    int64_t n = s->n;
+    int cur = s->cur;
+    const sph_params &p = c->p;
+    int64_t nb = ceil_div(n > 0 ? n : 1, SPH_BLOCK);
+    // dt partials live in the reduction area sized for n_max / SPH_BLOCK blocks
+    double *part = c->w.red_part;
+    hipLaunchKernelGGL(k_forces, dim3((unsigned)nb), dim3(SPH_BLOCK), 0, c->stream, n, s->x[cur],
+                       s->y[cur], s->z[cur], s->pvx, s->pvy, s->pvz, s->m[cur], s->h[cur],
+                       s->rho[cur], s->p, s->c, s->nc[cur], nl->idx, nl->stride, p.list_stride,
+                       nl->eoff, nl->eidx, nl->ecap, make_geo(p), p.av_alpha, p.av_beta,
+                       p.av_eta2, p.cfl, s->ax[cur], s->ay[cur], s->az[cur], s->du[cur], part);
+    if (d_dt)
+        hipLaunchKernelGGL(k_min_final, dim3(1), dim3(SPH_BLOCK), 0, c->stream, part, nb, d_dt);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// kick-drift-kick pieces; dt read from the device scalar of the step
+// ---------------------------------------------------------------------------
+__global__ void k_set_dt(double dt, const double *__restrict__ src, double *__restrict__ dst)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0) *dst = (dt > 0.0) ? dt : *src;
+}
+
+hipError_t launch_set_dt(sph_ctx *c, double dt, const double *d_dt)
+{
+    hipLaunchKernelGGL(k_set_dt, dim3(1), dim3(64), 0, c->stream, dt, d_dt, c->w.dt_cur);
+    return hipGetLastError();
+}
+
+__global__ __launch_bounds__(SPH_BLOCK) void k_kick_drift(
+    int64_t n, const double *__restrict__ dtp, double *__restrict__ x, double *__restrict__ y,
+    double *__restrict__ z, double *__restrict__ vx, double *__restrict__ vy,
+    double *__restrict__ vz, double *__restrict__ u, const double *__restrict__ ax,
+    const double *__restrict__ ay, const double *__restrict__ az, const double *__restrict__ du,
+    Geo g, double lo0, double lo1, double lo2, double hi0, double hi1, double hi2)
+{
+#pragma clang fp contract(off)
+    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double dt = *dtp;
+    double hdt = 0.5 * dt;
+    double *pos[3] = {x, y, z};
+    double *vel[3] = {vx, vy, vz};
+    const double *acc[3] = {ax, ay, az};
+    const double blo[3] = {lo0, lo1, lo2}, bhi[3] = {hi0, hi1, hi2};
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        double v = vel[d][i] + hdt * acc[d][i];
+        vel[d][i] = v;
+        double q = pos[d][i] + dt * v;
+        if (g.per[d]) {
+            if (q >= bhi[d]) q -= g.L[d];
+            else if (q < blo[d]) q += g.L[d];
+        }
+        pos[d][i] = q;
+    }
+    u[i] = u[i] + hdt * du[i];
+}
+
+hipError_t launch_kick_drift(sph_ctx *c, sph_particles *s)
+{
+    int64_t n = s->n;
+    if (n == 0) return hipSuccess;
+    int k = s->cur;
+    const sph_params &p = c->p;
+    hipLaunchKernelGGL(k_kick_drift, dim3((unsigned)ceil_div(n, SPH_BLOCK)), dim3(SPH_BLOCK), 0,
+                       c->stream, n, c->w.dt_cur, s->x[k], s->y[k], s->z[k], s->vx[k], s->vy[k],
+                       s->vz[k], s->u[k], s->ax[k], s->ay[k], s->az[k], s->du[k], make_geo(p),
+                       p.box_lo[0], p.box_lo[1], p.box_lo[2], p.box_hi[0], p.box_hi[1],
+                       p.box_hi[2]);
+    return hipGetLastError();
+}
+
+// pv = v + dt/2 a, pu = u + dt/2 du   (mode 0)
+// pv = v, pu = u                      (mode 1: evaluation at the stored state)
+__global__ __launch_bounds__(SPH_BLOCK) void k_predict(
+    int64_t n, const double *__restrict__ dtp, int mode, const double *__restrict__ vx,
+    const double *__restrict__ vy, const double *__restrict__ vz, const double *__restrict__ u,
+    const double *__restrict__ ax, const double *__restrict__ ay, const double *__restrict__ az,
+    const double *__restrict__ du, double *__restrict__ pvx, double *__restrict__ pvy,
+    double *__restrict__ pvz, double *__restrict__ pu)
+{
+#pragma clang fp contract(off)
+    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    if (mode == 1) {
+        pvx[i] = vx[i]; pvy[i] = vy[i]; pvz[i] = vz[i]; pu[i] = u[i];
+        return;
+    }
+    double hdt = 0.5 * (*dtp);
+    pvx[i] = vx[i] + hdt * ax[i];
+    pvy[i] = vy[i] + hdt * ay[i];
+    pvz[i] = vz[i] + hdt * az[i];
+    pu[i] = u[i] + hdt * du[i];
+}
+
+static hipError_t predict(sph_ctx *c, sph_particles *s, int mode)
+{
+    int64_t n = s->n;
+    if (n == 0) return hipSuccess;
+    int k = s->cur;
+    hipLaunchKernelGGL(k_predict, dim3((unsigned)ceil_div(n, SPH_BLOCK)), dim3(SPH_BLOCK), 0,
+                       c->stream, n, c->w.dt_cur, mode, s->vx[k], s->vy[k], s->vz[k], s->u[k],
+                       s->ax[k], s->ay[k], s->az[k], s->du[k], s->pvx, s->pvy, s->pvz, s->pu);
+    return hipGetLastError();
+}
+
+hipError_t launch_predict(sph_ctx *c, sph_particles *s) { return predict(c, s, 0); }
+hipError_t launch_copy_pred(sph_ctx *c, sph_particles *s) { return predict(c, s, 1); }
+
+__global__ __launch_bounds__(SPH_BLOCK) void k_kick(int64_t n, const double *__restrict__ dtp,
+                                                    double *__restrict__ vx,
+                                                    double *__restrict__ vy,
+                                                    double *__restrict__ vz,
+                                                    double *__restrict__ u,
+                                                    const double *__restrict__ ax,
+                                                    const double *__restrict__ ay,
+                                                    const double *__restrict__ az,
+                                                    const double *__restrict__ du)
+{
+#pragma clang fp contract(off)
+    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double hdt = 0.5 * (*dtp);
+    vx[i] = vx[i] + hdt * ax[i];
+    vy[i] = vy[i] + hdt * ay[i];
+    vz[i] = vz[i] + hdt * az[i];
+    u[i] = u[i] + hdt * du[i];
+}
+
+hipError_t launch_kick(sph_ctx *c, sph_particles *s)
+{
+    int64_t n = s->n;
+    if (n == 0) return hipSuccess;
+    int k = s->cur;
+    hipLaunchKernelGGL(k_kick, dim3((unsigned)ceil_div(n, SPH_BLOCK)), dim3(SPH_BLOCK), 0,
+                       c->stream, n, c->w.dt_cur, s->vx[k], s->vy[k], s->vz[k], s->u[k], s->ax[k],
+                       s->ay[k], s->az[k], s->du[k]);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// conservation sums: per-block tree sums, then one block over the partials
+// in index order; the same inputs give the same bits every run
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(SPH_BLOCK) void k_cons_partial(
+    int64_t n, const double *__restrict__ x, const double *__restrict__ y,
+    const double *__restrict__ z, const double *__restrict__ vx, const double *__restrict__ vy,
+    const double *__restrict__ vz, const double *__restrict__ m, const double *__restrict__ u,
+    double *__restrict__ part)
+{
+    __shared__ double sh[7][SPH_BLOCK];
+    double a[7] = {0, 0, 0, 0, 0, 0, 0};
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        double mi = m[i];
+        a[0] += mi * vx[i];
+        a[1] += mi * vy[i];
+        a[2] += mi * vz[i];
+        a[3] += mi * (y[i] * vz[i] - z[i] * vy[i]);
+        a[4] += mi * (z[i] * vx[i] - x[i] * vz[i]);
+        a[5] += mi * (x[i] * vy[i] - y[i] * vx[i]);
+        a[6] += mi * (0.5 * (vx[i] * vx[i] + vy[i] * vy[i] + vz[i] * vz[i]) + u[i]);
+    }
+    for (int k = 0; k < 7; ++k) sh[k][threadIdx.x] = a[k];
+    __syncthreads();
+    for (int s = SPH_BLOCK / 2; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s)
+            for (int k = 0; k < 7; ++k) sh[k][threadIdx.x] += sh[k][threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x < 7) part[blockIdx.x * 8 + threadIdx.x] = sh[threadIdx.x][0];
+}
+
+__global__ __launch_bounds__(SPH_BLOCK) void k_cons_final(const double *__restrict__ part,
+                                                          int64_t nb, double *__restrict__ out)
+{
+    __shared__ double sh[7][SPH_BLOCK];
+    double a[7] = {0, 0, 0, 0, 0, 0, 0};
+    for (int64_t b = threadIdx.x; b < nb; b += SPH_BLOCK)
+        for (int k = 0; k < 7; ++k) a[k] += part[b * 8 + k];
+    for (int k = 0; k < 7; ++k) sh[k][threadIdx.x] = a[k];
+    __syncthreads();
+    for (int s = SPH_BLOCK / 2; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s)
+            for (int k = 0; k < 7; ++k) sh[k][threadIdx.x] += sh[k][threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x < 7) out[threadIdx.x] = sh[threadIdx.x][0];
+}
+
+hipError_t launch_conservation(sph_ctx *c, const sph_particles *s, double *out7)
+{
+    int64_t n = s->n;
+    int k = s->cur;
+    int64_t nb = 1024;
+    if (nb > c->w.nb_red) nb = c->w.nb_red;
+    if (n < nb * SPH_BLOCK) nb = ceil_div(n > 0 ? n : 1, SPH_BLOCK);
+    hipLaunchKernelGGL(k_cons_partial, dim3((unsigned)nb), dim3(SPH_BLOCK), 0, c->stream, n,
+                       s->x[k], s->y[k], s->z[k], s->vx[k], s->vy[k], s->vz[k], s->m[k], s->u[k],
+                       c->w.red_part);
+    hipLaunchKernelGGL(k_cons_final, dim3(1), dim3(SPH_BLOCK), 0, c->stream, c->w.red_part, nb,
+                       out7);
+    return hipGetLastError();
+}

@@ -1,0 +1,232 @@
+// Internal declarations of libsph: context, workspace layout, device helpers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/sph.h"
+
+#define SPH_BLOCK 256
+#define SPH_SORT_ITEMS 16                      // keys per thread per sort tile
+#define SPH_SORT_TILE (SPH_BLOCK * SPH_SORT_ITEMS)
+#define SPH_SCAN_ITEMS 8
+#define SPH_SCAN_TILE (SPH_BLOCK * SPH_SCAN_ITEMS)
+
+// device status words (int64) in the workspace
+enum {
+    ST_NONCONV = 0,
+    ST_LIST_OVERFLOW = 1,
+    ST_EXTRA_OVERFLOW = 2,
+    ST_NONFINITE = 3,
+    ST_HCOUNTS = 4,
+    ST_LEARN_ACC = 5,
+    ST_LEARN_FALLBACK = 6,
+    ST_CANDIDATES = 7,
+    ST_COUNT = 16
+};
+
+// Geometry of the periodic box, by value into kernels.
+struct Geo {
+    int per[3];
+    double L[3];      // box_hi - box_lo of periodic dimensions (0 otherwise)
+    double halfL[3];  // 0.5 * L
+};
+
+// Workspace carve-up.
+struct Workspace {
+    double *bbox;          // 6: lo[3], hi[3]
+    double *bbox_part;     // nb_red * 6
+    uint32_t *key_a;       // n_max  (unsorted keys / sort ping)
+    uint32_t *key_b;       // n_max
+    int32_t *val_a;        // n_max
+    int32_t *val_b;        // n_max
+    uint32_t *hist;        // 256 * nb_sort
+    uint64_t *scan_part;   // scan partials
+    int32_t *cell_start;   // 8^max_level + 1
+    double *hk;            // 1024 Hernquist-Katz factors
+    int64_t *status;       // ST_COUNT
+    double *dt_cur;        // 1: dt used by the current step
+    double *red_part;      // nb_red * 8 reduction partials
+    int32_t *ecnt;         // n_max
+    int32_t *efill;        // n_max
+    uint8_t *refill;       // n_max
+    int64_t nb_red;
+    int64_t nb_sort;
+    int64_t scan_part_len;
+};
+
+struct StageTimer;  // per-stage HIP-event intervals (api.cpp)
+
+struct sph_ctx {
+    sph_params p;
+    hipStream_t stream;
+    void *ws_base;
+    size_t ws_bytes;
+    Workspace w;
+    int bound;
+    int timing;
+    StageTimer *timer;
+    char err[512];
+};
+
+size_t sph_layout(const sph_params *p, void *base, Workspace *w);
+
+// ---------------------------------------------------------------------------
+// launchers (each returns hipError_t of the launch)
+// ---------------------------------------------------------------------------
+hipError_t launch_bbox(sph_ctx *c, const double *x, const double *y, const double *z, int64_t n);
+hipError_t launch_keys(sph_ctx *c, const double *x, const double *y, const double *z, int64_t n);
+hipError_t launch_radix_sort(sph_ctx *c, int64_t n, uint32_t *key_out, int32_t *val_out);
+hipError_t launch_permute(sph_ctx *c, sph_particles *s, const int32_t *perm);
+hipError_t launch_cell_table(sph_ctx *c, const uint32_t *sorted_key, int64_t n);
+hipError_t launch_scan_i32_to_i64(sph_ctx *c, const int32_t *in, int64_t *out, int64_t n);
+hipError_t launch_scan_u32(sph_ctx *c, const uint32_t *in, uint32_t *out, int64_t n);
+
+hipError_t launch_hsolve(sph_ctx *c, sph_particles *s, sph_nlist *nl, const double *h_try);
+hipError_t launch_extra(sph_ctx *c, sph_particles *s, sph_nlist *nl);
+hipError_t launch_density(sph_ctx *c, sph_particles *s, const sph_nlist *nl);
+hipError_t launch_eos(sph_ctx *c, sph_particles *s);
+hipError_t launch_forces(sph_ctx *c, sph_particles *s, const sph_nlist *nl, double *d_dt);
+hipError_t launch_kick_drift(sph_ctx *c, sph_particles *s);
+hipError_t launch_predict(sph_ctx *c, sph_particles *s);
+hipError_t launch_kick(sph_ctx *c, sph_particles *s);
+hipError_t launch_set_dt(sph_ctx *c, double dt, const double *d_dt);
+hipError_t launch_copy_pred(sph_ctx *c, sph_particles *s);
+hipError_t launch_conservation(sph_ctx *c, const sph_particles *s, double *out7);
+
+static inline Geo make_geo(const sph_params &p)
+{
+    Geo g;
+    for (int d = 0; d < 3; ++d) {
+        g.per[d] = p.periodic[d] ? 1 : 0;
+        g.L[d] = g.per[d] ? (p.box_hi[d] - p.box_lo[d]) : 0.0;
+        g.halfL[d] = 0.5 * g.L[d];
+    }
+    return g;
+}
+
+__host__ __device__ static inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+// ---------------------------------------------------------------------------
+// device helpers
+// ---------------------------------------------------------------------------
+#ifdef __HIPCC__
+
+// Blocks are dealt to the 8 XCDs round-robin; give each XCD a contiguous
+// range of logical blocks so that spatially adjacent (Morton-adjacent)
+// particles share one L2.
+__device__ __forceinline__ int64_t xcd_block(int64_t b, int64_t nb)
+{
+    const int64_t nx = 8;
+    if (nb < 2 * nx) return b;
+    int64_t per = nb / nx;          // full rounds
+    int64_t full = per * nx;
+    if (b >= full) return b;        // tail blocks keep their index
+    return (b % nx) * per + b / nx;
+}
+
+__device__ __forceinline__ int64_t global_index()
+{
+    return xcd_block(blockIdx.x, gridDim.x) * (int64_t)blockDim.x + threadIdx.x;
+}
+
+// minimum-image difference component: t = b - a, wrapped once
+__device__ __forceinline__ double min_image(double a, double b, int per, double L, double halfL)
+{
+#pragma clang fp contract(off)
+    double t = b - a;
+    if (per) {
+        if (t > halfL) t = t - L;
+        else if (t < -halfL) t = t + L;
+    }
+    return t;
+}
+
+// r^2 = (dx*dx + dy*dy) + dz*dz, each operation rounded on its own
+__device__ __forceinline__ double exact_r2(double dx, double dy, double dz)
+{
+#pragma clang fp contract(off)
+    double a = dx * dx;
+    double b = dy * dy;
+    double c = dz * dz;
+    double ab = a + b;
+    return ab + c;
+}
+
+// integer cell index in [0, 1023] of v within [lo, lo + L]
+__device__ __forceinline__ int cell10(double v, double lo, double L)
+{
+#pragma clang fp contract(off)
+    double w = L / 1024.0;
+    if (!(w > 0.0)) return 0;
+    double t = (v - lo) / w;
+    if (!(t >= 0.0)) return 0;
+    if (!(t < 1024.0)) return 1023;
+    return (int)t;
+}
+
+__device__ __forceinline__ uint32_t spread3(uint32_t v)
+{
+    v &= 0x3FFu;
+    v = (v | (v << 16)) & 0x030000FFu;
+    v = (v | (v << 8)) & 0x0300F00Fu;
+    v = (v | (v << 4)) & 0x030C30C3u;
+    v = (v | (v << 2)) & 0x09249249u;
+    return v;
+}
+
+__device__ __forceinline__ uint32_t morton(uint32_t gx, uint32_t gy, uint32_t gz)
+{
+    return spread3(gx) | (spread3(gy) << 1) | (spread3(gz) << 2);
+}
+
+#define SPH_PI 3.14159265358979323846
+
+// M4 cubic spline W(r, h) and dW/dr (fields; rounding order free)
+__device__ __forceinline__ double kern_w(double r, double inv_h)
+{
+    double q = r * inv_h;
+    double norm = (1.0 / SPH_PI) * inv_h * inv_h * inv_h;
+    double w;
+    if (q < 1.0) w = 1.0 - 1.5 * q * q + 0.75 * q * q * q;
+    else if (q < 2.0) { double t = 2.0 - q; w = 0.25 * t * t * t; }
+    else w = 0.0;
+    return norm * w;
+}
+
+__device__ __forceinline__ double kern_dwdr(double r, double inv_h)
+{
+    double q = r * inv_h;
+    double ih2 = inv_h * inv_h;
+    double norm = (1.0 / SPH_PI) * ih2 * ih2;
+    double w;
+    if (q < 1.0) w = q * (-3.0 + 2.25 * q);
+    else if (q < 2.0) { double t = 2.0 - q; w = -0.75 * t * t; }
+    else w = 0.0;
+    return norm * w;
+}
+
+// wave and block reductions
+__device__ __forceinline__ int64_t wave_sum_i64(int64_t v)
+{
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+// one atomic per block for an int64 counter (deterministic total)
+__device__ __forceinline__ void block_add_i64(int64_t v, int64_t *addr)
+{
+    __shared__ int64_t part[SPH_BLOCK / 64];
+    v = wave_sum_i64(v);
+    int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    if (lane == 0) part[wv] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int64_t t = 0;
+        for (int k = 0; k < (int)(blockDim.x >> 6); ++k) t += part[k];
+        if (t) atomicAdd((unsigned long long *)addr, (unsigned long long)t);
+    }
+    __syncthreads();  // the shared slots are reused by the next call
+}
+
+#endif  // __HIPCC__

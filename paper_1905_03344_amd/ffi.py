@@ -1,0 +1,232 @@
+"""ctypes binding of libsph (include/sph.h): structures and the entry points,
+under the same names.  Argument marshalling only -- every step of the path
+runs in the library's HIP kernels.  Importing this module loads the in-tree
+``libsph.so`` and fails loudly if it is missing."""
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libsph.so")
+
+SPH_OK = 0
+SPH_EINVAL = -1
+SPH_ENOMEM = -2
+SPH_ECAPACITY = -3
+SPH_EHIP = -4
+SPH_ENONFINITE = -5
+SPH_WNOCONV = 1
+
+SPH_KERNEL_M4 = 0
+SPH_FP64 = 0
+SPH_MIXED = 1
+SPH_H_PLAIN = 0
+SPH_H_LEARNED = 1
+SPH_FLAG_NOCONV = 1
+SPH_FLAG_LEARNED = 2
+
+_P = ctypes.c_void_p
+_I32 = ctypes.c_int32
+_I64 = ctypes.c_int64
+_D = ctypes.c_double
+
+
+class sph_params(ctypes.Structure):
+    _fields_ = [("n_max", _I64), ("list_stride", _I32), ("pad0", _I32),
+                ("extra_capacity", _I64), ("periodic", _I32 * 3), ("kernel", _I32),
+                ("box_lo", _D * 3), ("box_hi", _D * 3), ("n_target", _I32), ("n_tol", _I32),
+                ("h_max_iter", _I32), ("precision", _I32), ("gamma", _D), ("av_alpha", _D),
+                ("av_beta", _D), ("av_eta2", _D), ("cfl", _D), ("h_mode", _I32),
+                ("check_finite", _I32), ("max_level", _I32), ("search_div", _I32)]
+
+
+CARRIED_F64 = ("x", "y", "z", "vx", "vy", "vz", "m", "h", "u", "ax", "ay", "az", "du", "rho",
+               "divv")
+CARRIED_I32 = ("nc", "id")
+SINGLE_F64 = ("pvx", "pvy", "pvz", "pu", "p", "c")
+
+
+class sph_particles(ctypes.Structure):
+    _fields_ = ([("n", _I64), ("cur", _I32), ("pad0", _I32)]
+                + [(f, _P * 2) for f in CARRIED_F64]
+                + [(f, _P * 2) for f in CARRIED_I32]
+                + [(f, _P) for f in SINGLE_F64]
+                + [("flags", _P), ("key", _P), ("perm", _P)])
+
+
+class sph_nlist(ctypes.Structure):
+    _fields_ = [("idx", _P), ("stride", _I64), ("eoff", _P), ("eidx", _P), ("ecap", _I64)]
+
+
+class sph_stats(ctypes.Structure):
+    _fields_ = [("nonconverged", _I64), ("list_overflow", _I64), ("extra_total", _I64),
+                ("extra_overflow", _I64), ("nonfinite", _I64), ("h_counts", _I64),
+                ("learned_accepted", _I64), ("learned_fallback", _I64), ("candidates", _I64),
+                ("dt", _D)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class SphError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"libsph error {code}: {msg}")
+        self.code = code
+
+
+_lib = None
+
+# name -> (restype, argtypes)
+_SIGS = {
+    "sph_default_params": (None, [ctypes.POINTER(sph_params)]),
+    "sph_create": (ctypes.c_int, [ctypes.POINTER(sph_params), ctypes.POINTER(_P)]),
+    "sph_destroy": (None, [_P]),
+    "sph_params_error": (ctypes.c_char_p, []),
+    "sph_workspace_size": (ctypes.c_int, [ctypes.POINTER(sph_params), ctypes.POINTER(ctypes.c_size_t)]),
+    "sph_bind": (ctypes.c_int, [_P, _P, ctypes.c_size_t, _P]),
+    "sph_build_cells": (ctypes.c_int, [_P, ctypes.POINTER(sph_particles)]),
+    "sph_find_neighbors": (ctypes.c_int, [_P, ctypes.POINTER(sph_particles), ctypes.POINTER(sph_nlist)]),
+    "sph_density": (ctypes.c_int, [_P, ctypes.POINTER(sph_particles), ctypes.POINTER(sph_nlist)]),
+    "sph_eos": (ctypes.c_int, [_P, ctypes.POINTER(sph_particles)]),
+    "sph_momentum_energy": (ctypes.c_int, [_P, ctypes.POINTER(sph_particles), ctypes.POINTER(sph_nlist), _P]),
+    "sph_evaluate": (ctypes.c_int, [_P, ctypes.POINTER(sph_particles), ctypes.POINTER(sph_nlist), _P]),
+    "sph_step": (ctypes.c_int, [_P, ctypes.POINTER(sph_particles), ctypes.POINTER(sph_nlist), _D, _P]),
+    "sph_conservation": (ctypes.c_int, [_P, ctypes.POINTER(sph_particles), _P]),
+    "sph_sync": (ctypes.c_int, [_P, ctypes.POINTER(sph_stats)]),
+    "sph_last_error": (ctypes.c_char_p, [_P]),
+    "sph_copy_internal": (ctypes.c_int, [_P, ctypes.c_int, _P, ctypes.c_size_t, ctypes.POINTER(ctypes.c_size_t)]),
+    "sph_timing": (ctypes.c_int, [_P, ctypes.c_int]),
+    "sph_timing_read": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(_I64), ctypes.c_int]),
+}
+
+STAGES = ("cells", "hsolve", "extra", "density", "eos", "forces", "integrate")
+
+# entry points of the learned / mixed forms, bound when present
+_OPTIONAL = {}
+
+
+def lib():
+    """Load libsph.so (in-tree).  Raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with "
+                              "`python -m paper_1905_03344_amd.build` (hipcc, gfx950)")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in {**_SIGS, **_OPTIONAL}.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def exported_symbols():
+    return list(_SIGS) + list(_OPTIONAL)
+
+
+def register_optional(name, res, args):
+    _OPTIONAL[name] = (res, args)
+    if _lib is not None:
+        fn = getattr(_lib, name)
+        fn.restype = res
+        fn.argtypes = args
+
+
+def check(code, ctx=None, allow=(SPH_OK,)):
+    if code in allow:
+        return code
+    msg = ""
+    if ctx is not None:
+        raw = lib().sph_last_error(ctx)
+        msg = raw.decode() if raw else ""
+    elif code == SPH_EINVAL:
+        raw = lib().sph_params_error()
+        msg = raw.decode() if raw else ""
+    raise SphError(code, msg)
+
+
+def default_params() -> sph_params:
+    p = sph_params()
+    lib().sph_default_params(ctypes.byref(p))
+    return p
+
+
+# thin wrappers with the C names ------------------------------------------------
+
+def sph_create(p: sph_params):
+    h = _P()
+    check(lib().sph_create(ctypes.byref(p), ctypes.byref(h)))
+    return h
+
+
+def sph_destroy(ctx):
+    lib().sph_destroy(ctx)
+
+
+def sph_workspace_size(p: sph_params) -> int:
+    n = ctypes.c_size_t()
+    check(lib().sph_workspace_size(ctypes.byref(p), ctypes.byref(n)))
+    return n.value
+
+
+def sph_bind(ctx, ws_ptr: int, nbytes: int, stream: int):
+    check(lib().sph_bind(ctx, ws_ptr, nbytes, stream), ctx)
+
+
+def sph_build_cells(ctx, s: sph_particles):
+    check(lib().sph_build_cells(ctx, ctypes.byref(s)), ctx)
+
+
+def sph_find_neighbors(ctx, s, nl):
+    check(lib().sph_find_neighbors(ctx, ctypes.byref(s), ctypes.byref(nl)), ctx)
+
+
+def sph_density(ctx, s, nl):
+    check(lib().sph_density(ctx, ctypes.byref(s), ctypes.byref(nl)), ctx)
+
+
+def sph_eos(ctx, s):
+    check(lib().sph_eos(ctx, ctypes.byref(s)), ctx)
+
+
+def sph_momentum_energy(ctx, s, nl, d_dt: int):
+    check(lib().sph_momentum_energy(ctx, ctypes.byref(s), ctypes.byref(nl), d_dt), ctx)
+
+
+def sph_evaluate(ctx, s, nl, d_dt: int):
+    check(lib().sph_evaluate(ctx, ctypes.byref(s), ctypes.byref(nl), d_dt), ctx)
+
+
+def sph_step(ctx, s, nl, dt: float, d_dt: int):
+    check(lib().sph_step(ctx, ctypes.byref(s), ctypes.byref(nl), float(dt), d_dt), ctx)
+
+
+def sph_conservation(ctx, s, d_out7: int):
+    check(lib().sph_conservation(ctx, ctypes.byref(s), d_out7), ctx)
+
+
+def sph_sync(ctx, allow=(SPH_OK, SPH_WNOCONV)):
+    st = sph_stats()
+    code = lib().sph_sync(ctx, ctypes.byref(st))
+    check(code, ctx, allow)
+    return code, st
+
+
+def sph_copy_internal(ctx, which: int, dst: int, nbytes: int) -> int:
+    need = ctypes.c_size_t()
+    check(lib().sph_copy_internal(ctx, which, dst, nbytes, ctypes.byref(need)), ctx)
+    return need.value
+
+
+def sph_timing(ctx, enable: bool):
+    check(lib().sph_timing(ctx, int(bool(enable))), ctx)
+
+
+def sph_timing_read(ctx):
+    """{stage: (total_ms, intervals)} since timing was enabled."""
+    ms = (ctypes.c_double * len(STAGES))()
+    cnt = (_I64 * len(STAGES))()
+    check(lib().sph_timing_read(ctx, ms, cnt, len(STAGES)), ctx)
+    return {s: (ms[k], cnt[k]) for k, s in enumerate(STAGES)}

@@ -110,10 +110,14 @@ def initial_h(number_density, n_target: float = 100.0) -> np.ndarray:
 
 
 def square_patch(n_side: int, seed: int, jitter: float = 0.01, omega: float = 5.0,
-                 n_target: float = 100.0) -> ParticleSet:
-    """Rotating square patch: n_side^3 particles in [-0.5, 0.5)^3, periodic in z."""
+                 n_target: float = 100.0, spacing: float | None = None) -> ParticleSet:
+    """Rotating square patch: n_side^3 particles in [-0.5, 0.5)^3, periodic in z.
+    With `spacing` the lattice keeps that spacing (and density 1) and the box
+    shrinks to n_side * spacing: a cut-out of a larger patch with the same
+    per-particle work."""
     n = n_side ** 3
-    s = 1.0 / n_side
+    s = 1.0 / n_side if spacing is None else float(spacing)
+    half = 0.5 * n_side * s
     pid = np.arange(n, dtype=np.int64)
     i = pid % n_side
     j = (pid // n_side) % n_side
@@ -122,17 +126,17 @@ def square_patch(n_side: int, seed: int, jitter: float = 0.01, omega: float = 5.
     jx = (2.0 * uniform01(seed, cnt) - 1.0) * (jitter * s)
     jy = (2.0 * uniform01(seed, cnt + np.uint64(1)) - 1.0) * (jitter * s)
     jz = (2.0 * uniform01(seed, cnt + np.uint64(2)) - 1.0) * (jitter * s)
-    x = -0.5 + (i + 0.5) * s + jx
-    y = -0.5 + (j + 0.5) * s + jy
-    z = -0.5 + (k + 0.5) * s + jz
+    x = -half + (i + 0.5) * s + jx
+    y = -half + (j + 0.5) * s + jy
+    z = -half + (k + 0.5) * s + jz
     vx = -omega * y
     vy = omega * x
     vz = np.zeros(n)
-    m = np.full(n, 1.0 / n)
-    h = np.full(n, float(initial_h(float(n), n_target)))
+    m = np.full(n, s ** 3) if spacing is not None else np.full(n, 1.0 / n)
+    h = np.full(n, float(initial_h(1.0 / s ** 3, n_target)))
     u = np.ones(n)
     return ParticleSet(x, y, z, vx, vy, vz, m, h, u, periodic=(0, 0, 1),
-                       box_lo=(-0.5, -0.5, -0.5), box_hi=(0.5, 0.5, 0.5),
+                       box_lo=(-half, -half, -half), box_hi=(half, half, half),
                        name=f"square_patch_{n_side}^3", meta={"seed": seed, "s": s})
 
 

@@ -1,0 +1,212 @@
+"""Device-resident particle state for libsph: torch tensors provide the
+memory and the stream, the library's kernels do all the work.
+
+    sim = Simulation(ic, params)          # ic: inputs.ParticleSet
+    sim.evaluate()                        # forces at t = 0
+    for _ in range(steps): sim.step()     # KDK steps at the Courant dt
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+
+import numpy as np
+import torch
+
+from . import ffi
+
+
+def choose_max_level(n: int, bbox_extent: float, h_min: float, search_div: int = 1) -> int:
+    """Finest cell level the table needs so that search cells can be about
+    2 h_min / search_div wide (between 1 and 8)."""
+    if h_min <= 0 or bbox_extent <= 0:
+        return 1
+    want = bbox_extent * search_div / (2.0 * h_min)
+    lvl = int(math.floor(math.log2(max(want, 1.0))))
+    return max(1, min(8, lvl + 1))
+
+
+class Simulation:
+    def __init__(self, ic, params: ffi.sph_params | None = None, device="cuda", n_max=None,
+                 list_stride=128, extra_per_particle=16, max_level=None, search_div=1,
+                 precision=ffi.SPH_FP64, check_finite=False):
+        self.device = torch.device(device)
+        n = ic.n
+        self.n = n
+        p = params if params is not None else ffi.default_params()
+        p.n_max = int(n_max or n)
+        p.list_stride = int(list_stride)
+        p.extra_capacity = int(max(1024, extra_per_particle * n))
+        for d in range(3):
+            p.periodic[d] = int(ic.periodic[d])
+            p.box_lo[d] = float(ic.box_lo[d])
+            p.box_hi[d] = float(ic.box_hi[d])
+        if max_level is None:
+            ext = max(float(np.ptp(ic.x)), float(np.ptp(ic.y)), float(np.ptp(ic.z)), 1e-300)
+            max_level = choose_max_level(n, ext, float(np.min(ic.h)) * 0.7, search_div)
+        p.max_level = int(max_level)
+        p.search_div = int(search_div)
+        p.precision = int(precision)
+        p.check_finite = int(bool(check_finite))
+        self.params = p
+        self.ctx = ffi.sph_create(p)
+        dev = self.device
+        f64 = dict(dtype=torch.float64, device=dev)
+        i32 = dict(dtype=torch.int32, device=dev)
+        self.t = {}
+        for f in ffi.CARRIED_F64:
+            self.t[f] = [torch.zeros(n, **f64), torch.zeros(n, **f64)]
+        for f in ffi.CARRIED_I32:
+            self.t[f] = [torch.zeros(n, **i32), torch.zeros(n, **i32)]
+        for f in ffi.SINGLE_F64:
+            self.t[f] = torch.zeros(n, **f64)
+        self.t["flags"] = torch.zeros(n, dtype=torch.uint8, device=dev)
+        self.t["key"] = torch.zeros(n, **i32)   # uint32 bits in an int32 tensor
+        self.t["perm"] = torch.zeros(n, **i32)
+        arrays = ic.arrays()
+        for f in ("x", "y", "z", "vx", "vy", "vz", "m", "h", "u"):
+            self.t[f][0].copy_(torch.from_numpy(np.ascontiguousarray(arrays[f], dtype=np.float64)))
+        self.t["id"][0].copy_(torch.arange(n, dtype=torch.int32))
+        # neighbour lists
+        self.stride = max(64, ((n + 63) // 64) * 64)
+        self.nl_idx = torch.zeros(p.list_stride * self.stride, **i32)
+        self.nl_eoff = torch.zeros(n + 1, dtype=torch.int64, device=dev)
+        self.nl_eidx = torch.zeros(p.extra_capacity, **i32)
+        self.d_dt = torch.zeros(1, **f64)
+        self.cons = torch.zeros(8, **f64)
+        # workspace
+        self.ws_bytes = ffi.sph_workspace_size(p)
+        self.ws = torch.empty(self.ws_bytes, dtype=torch.uint8, device=dev)
+        self.stream = torch.cuda.current_stream(dev)
+        ffi.sph_bind(self.ctx, self.ws.data_ptr(), self.ws_bytes, self.stream.cuda_stream)
+        self.s = ffi.sph_particles()
+        self.s.n = n
+        self.s.cur = 0
+        self._fill_ptrs()
+        self.nl = ffi.sph_nlist()
+        self.nl.idx = self.nl_idx.data_ptr()
+        self.nl.stride = self.stride
+        self.nl.eoff = self.nl_eoff.data_ptr()
+        self.nl.eidx = self.nl_eidx.data_ptr()
+        self.nl.ecap = p.extra_capacity
+        self.time = 0.0
+
+    def _fill_ptrs(self):
+        s = self.s
+        for f in ffi.CARRIED_F64 + ffi.CARRIED_I32:
+            arr = getattr(s, f)
+            arr[0] = self.t[f][0].data_ptr()
+            arr[1] = self.t[f][1].data_ptr()
+        for f in ffi.SINGLE_F64 + ("flags", "key", "perm"):
+            setattr(s, f, self.t[f].data_ptr())
+
+    def __del__(self):
+        try:
+            if getattr(self, "ctx", None):
+                ffi.sph_destroy(self.ctx)
+                self.ctx = None
+        except Exception:
+            pass
+
+    # --- field access -------------------------------------------------------
+    @property
+    def cur(self):
+        return self.s.cur
+
+    def field(self, name):
+        """Current buffer of a carried field, or a single buffer."""
+        v = self.t[name]
+        return v[self.s.cur] if isinstance(v, list) else v
+
+    def numpy(self, name):
+        a = self.field(name).cpu().numpy()
+        if name == "key":
+            a = a.view(np.uint32)
+        return a
+
+    def set_field(self, name, values):
+        self.field(name).copy_(torch.as_tensor(np.ascontiguousarray(values)).to(self.device))
+
+    # --- stages -------------------------------------------------------------
+    def build_cells(self):
+        ffi.sph_build_cells(self.ctx, self.s)
+
+    def find_neighbors(self):
+        ffi.sph_find_neighbors(self.ctx, self.s, self.nl)
+
+    def density(self):
+        ffi.sph_density(self.ctx, self.s, self.nl)
+
+    def eos(self):
+        ffi.sph_eos(self.ctx, self.s)
+
+    def momentum_energy(self):
+        ffi.sph_momentum_energy(self.ctx, self.s, self.nl, self.d_dt.data_ptr())
+
+    def evaluate(self):
+        ffi.sph_evaluate(self.ctx, self.s, self.nl, self.d_dt.data_ptr())
+
+    def step(self, dt: float = 0.0):
+        ffi.sph_step(self.ctx, self.s, self.nl, float(dt), self.d_dt.data_ptr())
+
+    def conservation(self):
+        ffi.sph_conservation(self.ctx, self.s, self.cons.data_ptr())
+        return self.cons[:7].cpu().numpy().copy()
+
+    def sync(self, allow=(ffi.SPH_OK, ffi.SPH_WNOCONV)):
+        return ffi.sph_sync(self.ctx, allow)
+
+    def dt(self):
+        return float(self.d_dt.item())
+
+    def copy_pred_from_state(self):
+        """pv = v, pu = u (what sph_evaluate does before the force stages)."""
+        for a, b in (("pvx", "vx"), ("pvy", "vy"), ("pvz", "vz"), ("pu", "u")):
+            self.t[a].copy_(self.field(b))
+
+    # --- tables and lists for tests ------------------------------------------
+    def cell_table(self):
+        need = ffi.sph_copy_internal(self.ctx, 0, 0, 0)
+        out = torch.zeros(need // 4, dtype=torch.int32, device=self.device)
+        ffi.sph_copy_internal(self.ctx, 0, out.data_ptr(), need)
+        return out.cpu().numpy()
+
+    def bbox(self):
+        out = torch.zeros(6, dtype=torch.float64, device=self.device)
+        ffi.sph_copy_internal(self.ctx, 1, out.data_ptr(), 48)
+        return out.cpu().numpy()
+
+    def gather_lists(self):
+        """(nc, L) with L a list of per-particle int32 arrays in stored order."""
+        n = self.n
+        nc = self.numpy("nc")
+        K = self.params.list_stride
+        idx = self.nl_idx.view(K, self.stride)[:, :n].cpu().numpy()
+        return nc, [idx[:min(int(nc[i]), K), i] for i in range(n)]
+
+    def gather_dense(self):
+        """(nc, idx[K, n]) numpy view of the gather sets."""
+        n = self.n
+        K = self.params.list_stride
+        return self.numpy("nc"), self.nl_idx.view(K, self.stride)[:, :n].cpu().numpy()
+
+    def extra_lists(self):
+        eoff = self.nl_eoff.cpu().numpy()
+        tot = int(eoff[-1])
+        eidx = self.nl_eidx[:min(tot, self.params.extra_capacity)].cpu().numpy()
+        return eoff, eidx
+
+    def interaction_csr(self):
+        """S_i = L_i U E_i as CSR with ascending rows (for comparisons)."""
+        nc, idx = self.gather_dense()
+        eoff, eidx = self.extra_lists()
+        n = self.n
+        K = self.params.list_stride
+        rows = []
+        off = np.zeros(n + 1, dtype=np.int64)
+        for i in range(n):
+            r = np.concatenate([idx[:min(int(nc[i]), K), i], eidx[eoff[i]:eoff[i + 1]]])
+            r.sort()
+            rows.append(r)
+            off[i + 1] = off[i] + len(r)
+        return off, (np.concatenate(rows) if rows else np.zeros(0, np.int32))
