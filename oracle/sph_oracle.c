@@ -584,7 +584,10 @@ void or_density(int64_t n, const double *x, const double *y, const double *z,
                 double gw = or_kernel_dwdr(r, hi) / r;
                 double vdot = (vx[j] - vx[i]) * (-dx) + (vy[j] - vy[i]) * (-dy) + (vz[j] - vz[i]) * (-dz);
                 dv += m[j] * vdot * gw;
-                dvm += fabs(m[j] * vdot * gw);
+                /* condition of the dot product: sum of |component products| */
+                double vabs = fabs((vx[j] - vx[i]) * dx) + fabs((vy[j] - vy[i]) * dy) +
+                              fabs((vz[j] - vz[i]) * dz);
+                dvm += fabs(m[j] * gw) * vabs;
             }
         }
         rho[i] = s;
@@ -621,11 +624,13 @@ typedef struct {
 static void pair_force(const or_geom *g, int64_t i, int64_t j, const double *vx,
                        const double *vy, const double *vz, const double *h, const double *rho,
                        const double *p, const double *c, const or_phys *ph,
-                       double *fx, double *fy, double *fz, double *de, double *mu_abs)
+                       double *fx, double *fy, double *fz, double *de, double *mu_abs,
+                       double *de_abs)
 {
     double dx, dy, dz;
     double r2 = pair_r2(g, i, j, &dx, &dy, &dz);
     *fx = *fy = *fz = *de = *mu_abs = 0.0;
+    if (de_abs) *de_abs = 0.0;
     if (!(r2 > 0.0)) return;
     double r = sqrt(r2);
     double xij = -dx, yij = -dy, zij = -dz;
@@ -650,6 +655,10 @@ static void pair_force(const or_geom *g, int64_t i, int64_t j, const double *vx,
     *fy = -sfac * gbar * yij;
     *fz = -sfac * gbar * zij;
     *de = (pi_term + 0.5 * Pi) * gbar * w;
+    /* condition of the energy term: w is a dot product */
+    if (de_abs)
+        *de_abs = fabs((pi_term + 0.5 * Pi) * gbar) *
+                  (fabs(vxij * xij) + fabs(vyij * yij) + fabs(vzij * zij));
 }
 
 void or_forces(int64_t n, const double *x, const double *y, const double *z,
@@ -668,15 +677,15 @@ void or_forces(int64_t n, const double *x, const double *y, const double *z,
         double sx = 0.0, sy = 0.0, sz = 0.0, se = 0.0, mumax = 0.0, mag = 0.0, emag = 0.0;
         for (int64_t k = off[i]; k < off[i + 1]; ++k) {
             int64_t j = idx[k];
-            double fx, fy, fz, de, mua;
-            pair_force(&g, i, j, vx, vy, vz, h, rho, p, c, &ph, &fx, &fy, &fz, &de, &mua);
+            double fx, fy, fz, de, mua, dea;
+            pair_force(&g, i, j, vx, vy, vz, h, rho, p, c, &ph, &fx, &fy, &fz, &de, &mua, &dea);
             sx += m[j] * fx;
             sy += m[j] * fy;
             sz += m[j] * fz;
             se += m[j] * de;
             if (mua > mumax) mumax = mua;
             mag += m[j] * sqrt(fx * fx + fy * fy + fz * fz);
-            emag += m[j] * fabs(de);
+            emag += m[j] * dea;
         }
         ax[i] = sx; ay[i] = sy; az[i] = sz; du[i] = se;
         if (amag) amag[i] = mag;
@@ -698,7 +707,7 @@ void or_pair_term(int64_t n, const double *x, const double *y, const double *z,
     geom_init(&g, x, y, z, periodic, box_lo, box_hi);
     or_phys ph = {0.0, alpha, beta, eta2, 0.0};
     double fx, fy, fz, de, mua;
-    pair_force(&g, i, j, vx, vy, vz, h, rho, p, c, &ph, &fx, &fy, &fz, &de, &mua);
+    pair_force(&g, i, j, vx, vy, vz, h, rho, p, c, &ph, &fx, &fy, &fz, &de, &mua, NULL);
     double mm = m[i] * m[j];
     out4[0] = mm * fx; out4[1] = mm * fy; out4[2] = mm * fz; out4[3] = mua;
 }

@@ -355,6 +355,8 @@ static int find_neighbors_impl(sph_ctx *c, sph_particles *s, sph_nlist *nl, cons
         StageScope scope(c, SPH_STAGE_EXTRA);
         TRY(launch_extra(c, s, nl), "complement lists");
     }
+    c->last_eoff = nl->eoff;
+    c->last_n = s->n;
     return SPH_OK;
 }
 
@@ -473,8 +475,12 @@ extern "C" int sph_sync(sph_ctx *c, sph_stats *st)
     if (!c) return SPH_EINVAL;
     if (!c->bound) return set_err(c, SPH_ENOMEM, "no workspace bound");
     int64_t h[ST_COUNT];
+    int64_t etot = 0;
     TRY(hipStreamSynchronize(c->stream), "sync");
     TRY(hipMemcpy(h, c->w.status, sizeof(h), hipMemcpyDeviceToHost), "read status");
+    if (c->last_eoff)
+        TRY(hipMemcpy(&etot, c->last_eoff + c->last_n, sizeof(etot), hipMemcpyDeviceToHost),
+            "read complement total");
     TRY(hipMemsetAsync(c->w.status, 0, sizeof(h), c->stream), "clear status");
     TRY(hipStreamSynchronize(c->stream), "sync");
     if (st) {
@@ -487,6 +493,7 @@ extern "C" int sph_sync(sph_ctx *c, sph_stats *st)
         st->learned_accepted = h[ST_LEARN_ACC];
         st->learned_fallback = h[ST_LEARN_FALLBACK];
         st->candidates = h[ST_CANDIDATES];
+        st->extra_total = etot;
     }
     if (h[ST_LIST_OVERFLOW] || h[ST_EXTRA_OVERFLOW])
         return set_err(c, SPH_ECAPACITY, "a neighbour list exceeded its capacity");

@@ -65,6 +65,8 @@ struct sph_ctx {
     Workspace w;
     int bound;
     int timing;
+    const int64_t *last_eoff;  // complement offsets of the last neighbour search
+    int64_t last_n;
     StageTimer *timer;
     char err[512];
 };

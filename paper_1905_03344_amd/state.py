@@ -28,7 +28,7 @@ def choose_max_level(n: int, bbox_extent: float, h_min: float, search_div: int =
 
 class Simulation:
     def __init__(self, ic, params: ffi.sph_params | None = None, device="cuda", n_max=None,
-                 list_stride=128, extra_per_particle=16, max_level=None, search_div=1,
+                 list_stride=128, extra_per_particle=48, max_level=None, search_div=1,
                  precision=ffi.SPH_FP64, check_finite=False):
         self.device = torch.device(device)
         n = ic.n
@@ -42,8 +42,11 @@ class Simulation:
             p.box_lo[d] = float(ic.box_lo[d])
             p.box_hi[d] = float(ic.box_hi[d])
         if max_level is None:
-            ext = max(float(np.ptp(ic.x)), float(np.ptp(ic.y)), float(np.ptp(ic.z)), 1e-300)
-            max_level = choose_max_level(n, ext, float(np.min(ic.h)) * 0.7, search_div)
+            if n > 0:
+                ext = max(float(np.ptp(ic.x)), float(np.ptp(ic.y)), float(np.ptp(ic.z)), 1e-300)
+                max_level = choose_max_level(n, ext, float(np.min(ic.h)) * 0.7, search_div)
+            else:
+                max_level = 1
         p.max_level = int(max_level)
         p.search_div = int(search_div)
         p.precision = int(precision)

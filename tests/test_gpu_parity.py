@@ -100,13 +100,14 @@ def test_evaluate_parity(case):
     st = O.State(ic.copy())
     st.keep_gather = True
     st.evaluate(method=1)
-    sim = _sim(ic)
+    sim = _sim(ic, extra_per_particle=64)
     sim.evaluate()
     code, stats = sim.sync()
     compare_cells(sim, st)
     compare_neighbors(sim, st)
     compare_fields(sim, st)
     assert stats.nonconverged == st.nonconv
+    assert stats.extra_total == st.off[-1] - st.loff[-1]
 
 
 def test_stage_calls_parity():
