@@ -72,7 +72,7 @@ def main():
     ap.add_argument("--config", type=int, default=2)
     ap.add_argument("--form", default="plain", choices=["plain", "mixed", "learned"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--search-div", type=int, default=1)
+    ap.add_argument("--search-div", type=int, default=2)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the multi-GPU "
@@ -117,7 +117,7 @@ def main():
     # work of the last step: pairs in S and candidates of the h iteration
     nc = sim.field("nc")
     pairs_l = int(nc.sum().item())
-    pairs_e = int(sim.nl_eoff[-1].item())
+    pairs_e = int(st.extra_total / max(1, args.steps))
     pairs = pairs_l + pairs_e
     cand_per_step = st.candidates / args.steps
     stage_ms = {k: v[0] / max(1, args.steps) for k, v in stages.items()}

@@ -61,7 +61,8 @@ typedef struct sph_params {
     int64_t n_max;          /* largest particle count the workspace is sized for */
     int32_t list_stride;    /* K: capacity of each gather set L_i (default 128) */
     int32_t pad0;
-    int64_t extra_capacity; /* entries reserved for the one-sided complement E */
+    int32_t extra_slots;    /* capacity of each complement row E_i (default 48) */
+    int32_t pad1;
     int32_t periodic[3];    /* 1 = periodic dimension (minimum image, wrap) */
     int32_t kernel;         /* SPH_KERNEL_M4 */
     double box_lo[3];       /* box of the periodic dimensions */
@@ -78,7 +79,7 @@ typedef struct sph_params {
     int32_t h_mode;         /* SPH_H_PLAIN or SPH_H_LEARNED */
     int32_t check_finite;   /* 1 = count non-finite fields (slower) */
     int32_t max_level;      /* finest Morton level of the cell table, 1..8 */
-    int32_t search_div;     /* search cells are at least 2h/search_div wide (1 or 2) */
+    int32_t search_div;     /* search cells are at least 2h/search_div wide (1..4, default 2) */
 } sph_params;
 
 typedef struct sph_particles {
@@ -108,23 +109,24 @@ typedef struct sph_particles {
 /* Neighbour lists.  The interaction set of particle i is
  *   S_i = L_i U E_i,   L_i = { j != i : r_ij^2 < (2 h_i)^2 }  (gather set),
  *                      E_i = { j : i in L_j, j not in L_i }    (complement),
- * so that j in S_i <=> i in S_j.  L is stored slot-major ("ELL"):
- * entry k of L_i is idx[k * stride + i], k < nc[i] (nc in sph_particles);
- * E is CSR: eidx[eoff[i] .. eoff[i+1]) in ascending index order.
- * All indices refer to the current (sorted) particle order. */
+ * so that j in S_i <=> i in S_j.  Both parts are stored slot-major ("ELL")
+ * with row pitch `stride`: entry k of L_i is idx[k * stride + i], k < nc[i]
+ * (nc in sph_particles), in the order the cell walk met them; entry k of
+ * E_i is eidx[k * stride + i], k < ecnt[i], in no particular order (the
+ * force kernel visits each E_i in ascending index order, so results do not
+ * depend on it).  All indices refer to the current (sorted) particle order. */
 typedef struct sph_nlist {
     int32_t *idx;           /* list_stride * stride entries */
-    int64_t stride;         /* row pitch of idx, >= n (a multiple of 64) */
-    int64_t *eoff;          /* n + 1 */
-    int32_t *eidx;          /* ecap entries */
-    int64_t ecap;
+    int64_t stride;         /* row pitch, >= n (a multiple of 64) */
+    int32_t *ecnt;          /* n: |E_i| (entries beyond extra_slots are dropped and counted) */
+    int32_t *eidx;          /* extra_slots * stride entries */
 } sph_nlist;
 
 typedef struct sph_stats {
     int64_t nonconverged;    /* particles whose h iteration ended outside the band */
     int64_t list_overflow;   /* particles whose |L_i| exceeded list_stride */
     int64_t extra_total;     /* |E| summed over particles */
-    int64_t extra_overflow;  /* 1 if |E| exceeded ecap */
+    int64_t extra_overflow;  /* particles whose E row exceeded extra_slots */
     int64_t nonfinite;       /* non-finite values found (check_finite) */
     int64_t h_counts;        /* neighbour counts taken by the h iteration (all particles) */
     int64_t learned_accepted;/* learned mode: particles whose predicted h was accepted */

@@ -97,6 +97,7 @@ extern "C" void sph_default_params(sph_params *p)
 {
     memset(p, 0, sizeof(*p));
     p->list_stride = 128;
+    p->extra_slots = 48;
     p->kernel = SPH_KERNEL_M4;
     p->n_target = 100;
     p->n_tol = 5;
@@ -110,7 +111,7 @@ extern "C" void sph_default_params(sph_params *p)
     p->h_mode = SPH_H_PLAIN;
     p->check_finite = 0;
     p->max_level = 6;
-    p->search_div = 1;
+    p->search_div = 2;
 }
 
 extern "C" const char *sph_params_error(void) { return g_params_error; }
@@ -119,7 +120,7 @@ static const char *validate(const sph_params *p)
 {
     if (p->n_max < 0 || p->n_max > (int64_t)INT32_MAX - 1) return "n_max out of range";
     if (p->list_stride < 1 || p->list_stride > 4096) return "list_stride out of range";
-    if (p->extra_capacity < 0) return "extra_capacity < 0";
+    if (p->extra_slots < 1 || p->extra_slots > 4096) return "extra_slots out of range";
     if (p->kernel != SPH_KERNEL_M4) return "unsupported kernel";
     if (p->n_target < 1 || p->n_target > 1000) return "n_target out of range";
     if (p->n_tol < 0 || p->n_tol >= p->n_target) return "n_tol out of range";
@@ -127,7 +128,7 @@ static const char *validate(const sph_params *p)
     if (p->precision != SPH_FP64 && p->precision != SPH_MIXED) return "unknown precision";
     if (p->h_mode != SPH_H_PLAIN && p->h_mode != SPH_H_LEARNED) return "unknown h_mode";
     if (p->max_level < 1 || p->max_level > 8) return "max_level must be in 1..8";
-    if (p->search_div < 1 || p->search_div > 2) return "search_div must be 1 or 2";
+    if (p->search_div < 1 || p->search_div > 4) return "search_div must be in 1..4";
     if (!(p->gamma > 1.0)) return "gamma must exceed 1";
     if (!(p->cfl > 0.0)) return "cfl must be positive";
     if (!(p->av_eta2 > 0.0)) return "av_eta2 must be positive";
@@ -168,8 +169,6 @@ size_t sph_layout(const sph_params *p, void *base, Workspace *w)
     t.status = (int64_t *)take(ST_COUNT * sizeof(int64_t));
     t.dt_cur = (double *)take(sizeof(double));
     t.red_part = (double *)take(red_len * sizeof(double));
-    t.ecnt = (int32_t *)take(n * sizeof(int32_t));
-    t.efill = (int32_t *)take(n * sizeof(int32_t));
     t.refill = (uint8_t *)take(n);
     t.nb_red = nb_red;
     t.nb_sort = nb_sort;
@@ -316,11 +315,10 @@ static int check_particles(sph_ctx *c, const sph_particles *s)
 static int check_nlist(sph_ctx *c, const sph_particles *s, const sph_nlist *nl)
 {
     if (!nl) return set_err(c, SPH_EINVAL, "nlist is NULL");
-    if (s->n > 0 && (!nl->idx || !nl->eoff || (!nl->eidx && nl->ecap > 0)))
+    if (s->n > 0 && (!nl->idx || !nl->ecnt || !nl->eidx))
         return set_err(c, SPH_EINVAL, "an nlist pointer is NULL");
     if (nl->stride < s->n || (nl->stride % 64) != 0)
         return set_err(c, SPH_EINVAL, "nlist stride must be >= n and a multiple of 64");
-    if (nl->ecap < 0) return set_err(c, SPH_EINVAL, "ecap < 0");
     return SPH_OK;
 }
 
@@ -345,18 +343,18 @@ extern "C" int sph_build_cells(sph_ctx *c, sph_particles *s)
     return SPH_OK;
 }
 
-static int find_neighbors_impl(sph_ctx *c, sph_particles *s, sph_nlist *nl, const double *h_try)
+// A5-A6; with_extra = false leaves the complement to the fused density pass
+static int find_neighbors_impl(sph_ctx *c, sph_particles *s, sph_nlist *nl, const double *h_try,
+                               bool with_extra)
 {
     {
         StageScope scope(c, SPH_STAGE_HSOLVE);
         TRY(launch_hsolve(c, s, nl, h_try), "h iteration");
     }
-    {
+    if (with_extra) {
         StageScope scope(c, SPH_STAGE_EXTRA);
         TRY(launch_extra(c, s, nl), "complement lists");
     }
-    c->last_eoff = nl->eoff;
-    c->last_n = s->n;
     return SPH_OK;
 }
 
@@ -366,7 +364,7 @@ extern "C" int sph_find_neighbors(sph_ctx *c, sph_particles *s, sph_nlist *nl)
     if (r) return r;
     r = check_nlist(c, s, nl);
     if (r) return r;
-    return find_neighbors_impl(c, s, nl, nullptr);
+    return find_neighbors_impl(c, s, nl, nullptr, true);
 }
 
 extern "C" int sph_density(sph_ctx *c, sph_particles *s, const sph_nlist *nl)
@@ -376,7 +374,7 @@ extern "C" int sph_density(sph_ctx *c, sph_particles *s, const sph_nlist *nl)
     r = check_nlist(c, s, nl);
     if (r) return r;
     StageScope scope(c, SPH_STAGE_DENSITY);
-    TRY(launch_density(c, s, nl), "density");
+    TRY(launch_density(c, s, nl, false), "density");
     return SPH_OK;
 }
 
@@ -403,11 +401,12 @@ extern "C" int sph_momentum_energy(sph_ctx *c, sph_particles *s, const sph_nlist
 // A5-A9 on the sorted state with pv/pu already set
 static int evaluate_sorted(sph_ctx *c, sph_particles *s, sph_nlist *nl, double *d_dt)
 {
-    int r = find_neighbors_impl(c, s, nl, nullptr);
+    int r = find_neighbors_impl(c, s, nl, nullptr, false);
     if (r) return r;
     {
+        // density and divergence, with the complement E built in the same pass
         StageScope scope(c, SPH_STAGE_DENSITY);
-        TRY(launch_density(c, s, nl), "density");
+        TRY(launch_density(c, s, nl, true), "density");
     }
     {
         StageScope scope(c, SPH_STAGE_EOS);
@@ -475,12 +474,8 @@ extern "C" int sph_sync(sph_ctx *c, sph_stats *st)
     if (!c) return SPH_EINVAL;
     if (!c->bound) return set_err(c, SPH_ENOMEM, "no workspace bound");
     int64_t h[ST_COUNT];
-    int64_t etot = 0;
     TRY(hipStreamSynchronize(c->stream), "sync");
     TRY(hipMemcpy(h, c->w.status, sizeof(h), hipMemcpyDeviceToHost), "read status");
-    if (c->last_eoff)
-        TRY(hipMemcpy(&etot, c->last_eoff + c->last_n, sizeof(etot), hipMemcpyDeviceToHost),
-            "read complement total");
     TRY(hipMemsetAsync(c->w.status, 0, sizeof(h), c->stream), "clear status");
     TRY(hipStreamSynchronize(c->stream), "sync");
     if (st) {
@@ -493,7 +488,7 @@ extern "C" int sph_sync(sph_ctx *c, sph_stats *st)
         st->learned_accepted = h[ST_LEARN_ACC];
         st->learned_fallback = h[ST_LEARN_FALLBACK];
         st->candidates = h[ST_CANDIDATES];
-        st->extra_total = etot;
+        st->extra_total = h[ST_EXTRA_TOTAL];
     }
     if (h[ST_LIST_OVERFLOW] || h[ST_EXTRA_OVERFLOW])
         return set_err(c, SPH_ECAPACITY, "a neighbour list exceeded its capacity");

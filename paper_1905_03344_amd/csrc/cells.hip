@@ -37,22 +37,38 @@ __global__ __launch_bounds__(SPH_BLOCK) void k_bbox_partial(const double *__rest
     if (threadIdx.x < 6) part[blockIdx.x * 6 + threadIdx.x] = sh[threadIdx.x][0];
 }
 
-__global__ void k_bbox_final(const double *__restrict__ part, int64_t nb, int64_t n, Geo g,
-                             double lo0, double lo1, double lo2, double hi0, double hi1,
-                             double hi2, double *__restrict__ bbox)
+__global__ __launch_bounds__(SPH_BLOCK) void k_bbox_final(const double *__restrict__ part,
+                                                          int64_t nb, int64_t n, Geo g,
+                                                          double lo0, double lo1, double lo2,
+                                                          double hi0, double hi1, double hi2,
+                                                          double *__restrict__ bbox)
 {
-    int d = threadIdx.x;
-    if (d >= 3) return;
-    double a = INFINITY, b = -INFINITY;
-    for (int64_t k = 0; k < nb; ++k) {
-        a = fmin(a, part[k * 6 + d]);
-        b = fmax(b, part[k * 6 + 3 + d]);
+    __shared__ double sh[6][SPH_BLOCK];
+    double v[6] = {INFINITY, INFINITY, INFINITY, -INFINITY, -INFINITY, -INFINITY};
+    for (int64_t k = threadIdx.x; k < nb; k += SPH_BLOCK)
+        for (int d = 0; d < 3; ++d) {
+            v[d] = fmin(v[d], part[k * 6 + d]);
+            v[3 + d] = fmax(v[3 + d], part[k * 6 + 3 + d]);
+        }
+    for (int d = 0; d < 6; ++d) sh[d][threadIdx.x] = v[d];
+    __syncthreads();
+    for (int s = SPH_BLOCK / 2; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s)
+            for (int d = 0; d < 3; ++d) {
+                sh[d][threadIdx.x] = fmin(sh[d][threadIdx.x], sh[d][threadIdx.x + s]);
+                sh[3 + d][threadIdx.x] = fmax(sh[3 + d][threadIdx.x], sh[3 + d][threadIdx.x + s]);
+            }
+        __syncthreads();
     }
-    if (n == 0) { a = 0.0; b = 0.0; }
-    double blo[3] = {lo0, lo1, lo2}, bhi[3] = {hi0, hi1, hi2};
-    if (g.per[d]) { a = blo[d]; b = bhi[d]; }
-    bbox[d] = a;
-    bbox[3 + d] = b;
+    if (threadIdx.x < 3) {
+        int d = threadIdx.x;
+        double a = sh[d][0], b = sh[3 + d][0];
+        if (n == 0) { a = 0.0; b = 0.0; }
+        double blo[3] = {lo0, lo1, lo2}, bhi[3] = {hi0, hi1, hi2};
+        if (g.per[d]) { a = blo[d]; b = bhi[d]; }
+        bbox[d] = a;
+        bbox[3 + d] = b;
+    }
 }
 
 hipError_t launch_bbox(sph_ctx *c, const double *x, const double *y, const double *z, int64_t n)
@@ -62,7 +78,7 @@ hipError_t launch_bbox(sph_ctx *c, const double *x, const double *y, const doubl
     hipLaunchKernelGGL(k_bbox_partial, dim3((unsigned)nb), dim3(SPH_BLOCK), 0, c->stream, x, y, z,
                        n, c->w.bbox_part);
     const sph_params &p = c->p;
-    hipLaunchKernelGGL(k_bbox_final, dim3(1), dim3(64), 0, c->stream, c->w.bbox_part, nb, n,
+    hipLaunchKernelGGL(k_bbox_final, dim3(1), dim3(SPH_BLOCK), 0, c->stream, c->w.bbox_part, nb, n,
                        make_geo(p), p.box_lo[0], p.box_lo[1], p.box_lo[2], p.box_hi[0],
                        p.box_hi[1], p.box_hi[2], c->w.bbox);
     return hipGetLastError();

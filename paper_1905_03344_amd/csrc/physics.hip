@@ -3,50 +3,82 @@
 #include "sph_internal.h"
 
 // rho_i = m_i W(0,h_i) + sum_{L_i} m_j W(r_ij,h_i);
-// divv_i = (1/rho_i) sum_{L_i} m_j (v_j - v_i) . grad_i W(r_ij,h_i)
+// divv_i = (1/rho_i) sum_{L_i} m_j (v_j - v_i) . grad_i W(r_ij,h_i).
+// With EXTRA the same pass appends i to E_j for every one-sided pair.
+template <int PM, bool EXTRA>
 __global__ __launch_bounds__(SPH_BLOCK) void k_density(
     int64_t n, const double *__restrict__ x, const double *__restrict__ y,
     const double *__restrict__ z, const double *__restrict__ vx, const double *__restrict__ vy,
     const double *__restrict__ vz, const double *__restrict__ m, const double *__restrict__ h,
     const int32_t *__restrict__ nc, const int32_t *__restrict__ idx, int64_t stride, int K,
-    Geo g, double *__restrict__ rho, double *__restrict__ divv)
+    Geo g, double *__restrict__ rho, double *__restrict__ divv, int32_t *__restrict__ ecnt,
+    int32_t *__restrict__ eidx, int slots, int64_t *__restrict__ status)
 {
     int64_t i = global_index();
-    if (i >= n) return;
-    double xi = x[i], yi = y[i], zi = z[i];
-    double vxi = vx[i], vyi = vy[i], vzi = vz[i];
-    double inv_h = 1.0 / h[i];
-    double s = m[i] * kern_w(0.0, inv_h);
-    double dv = 0.0;
-    int cnt = min(nc[i], K);
-    for (int k = 0; k < cnt; ++k) {
-        int j = idx[(int64_t)k * stride + i];
-        double dx = min_image(xi, x[j], g.per[0], g.L[0], g.halfL[0]);
-        double dy = min_image(yi, y[j], g.per[1], g.L[1], g.halfL[1]);
-        double dz = min_image(zi, z[j], g.per[2], g.L[2], g.halfL[2]);
-        double r2 = dx * dx + dy * dy + dz * dz;
-        double r = sqrt(r2);
-        double mj = m[j];
-        s += mj * kern_w(r, inv_h);
-        if (r > 0.0) {
-            double gw = kern_dwdr(r, inv_h) / r;
-            double vdot = (vx[j] - vxi) * (-dx) + (vy[j] - vyi) * (-dy) + (vz[j] - vzi) * (-dz);
-            dv += mj * vdot * gw;
+    int64_t appended = 0, dropped = 0;
+    if (i < n) {
+        double xi = x[i], yi = y[i], zi = z[i];
+        double vxi = vx[i], vyi = vy[i], vzi = vz[i];
+        double inv_h = 1.0 / h[i];
+        double s = m[i] * kern_w(0.0, inv_h);
+        double dv = 0.0;
+        int cnt = min(nc[i], K);
+        for (int k = 0; k < cnt; ++k) {
+            int j = idx[(int64_t)k * stride + i];
+            double dx = mimg<PM, 0>(xi, x[j], g);
+            double dy = mimg<PM, 1>(yi, y[j], g);
+            double dz = mimg<PM, 2>(zi, z[j], g);
+            double r2 = exact_r2(dx, dy, dz);
+            if (EXTRA) {
+#pragma clang fp contract(off)
+                double twoh = 2.0 * h[j];
+                if (!(r2 < twoh * twoh))
+                    extra_append(j, (int)i, ecnt, eidx, stride, slots, appended, dropped);
+            }
+            double r = sqrt(r2);
+            double mj = m[j];
+            s += mj * kern_w(r, inv_h);
+            if (r > 0.0) {
+                double gw = kern_dwdr(r, inv_h) / r;
+                double vdot = (vx[j] - vxi) * (-dx) + (vy[j] - vyi) * (-dy) + (vz[j] - vzi) * (-dz);
+                dv += mj * vdot * gw;
+            }
         }
+        rho[i] = s;
+        divv[i] = dv / s;
     }
-    rho[i] = s;
-    divv[i] = dv / s;
+    if (EXTRA) {
+        block_add_i64(appended, status + ST_EXTRA_TOTAL);
+        block_add_i64(dropped, status + ST_EXTRA_OVERFLOW);
+    }
 }
 
-hipError_t launch_density(sph_ctx *c, sph_particles *s, const sph_nlist *nl)
+hipError_t launch_density(sph_ctx *c, sph_particles *s, const sph_nlist *nl, bool build_extra)
 {
     int64_t n = s->n;
+    if (build_extra) {
+        hipError_t e = launch_zero_i32(c, nl->ecnt, n);
+        if (e != hipSuccess) return e;
+    }
     if (n == 0) return hipSuccess;
     int cur = s->cur;
-    hipLaunchKernelGGL(k_density, dim3((unsigned)ceil_div(n, SPH_BLOCK)), dim3(SPH_BLOCK), 0,
-                       c->stream, n, s->x[cur], s->y[cur], s->z[cur], s->pvx, s->pvy, s->pvz,
-                       s->m[cur], s->h[cur], s->nc[cur], nl->idx, nl->stride, c->p.list_stride,
-                       make_geo(c->p), s->rho[cur], s->divv[cur]);
+    Geo g = make_geo(c->p);
+    unsigned nb = (unsigned)ceil_div(n, SPH_BLOCK);
+    if (build_extra) {
+        SPH_DISPATCH_PM(periodic_mask(g),
+            hipLaunchKernelGGL((k_density<PM, true>), dim3(nb), dim3(SPH_BLOCK), 0, c->stream, n,
+                               s->x[cur], s->y[cur], s->z[cur], s->pvx, s->pvy, s->pvz, s->m[cur],
+                               s->h[cur], s->nc[cur], nl->idx, nl->stride, c->p.list_stride, g,
+                               s->rho[cur], s->divv[cur], nl->ecnt, nl->eidx, c->p.extra_slots,
+                               c->w.status))
+    } else {
+        SPH_DISPATCH_PM(periodic_mask(g),
+            hipLaunchKernelGGL((k_density<PM, false>), dim3(nb), dim3(SPH_BLOCK), 0, c->stream, n,
+                               s->x[cur], s->y[cur], s->z[cur], s->pvx, s->pvy, s->pvz, s->m[cur],
+                               s->h[cur], s->nc[cur], nl->idx, nl->stride, c->p.list_stride, g,
+                               s->rho[cur], s->divv[cur], nl->ecnt, nl->eidx, c->p.extra_slots,
+                               c->w.status))
+    }
     return hipGetLastError();
 }
 
@@ -85,6 +117,7 @@ struct ForceAcc {
     double ax, ay, az, du, mumax;
 };
 
+template <int PM>
 __device__ __forceinline__ void force_pair(int j, double xi, double yi, double zi, double vxi,
                                            double vyi, double vzi, double hi, double inv_hi,
                                            double rhoi, double ci, double pi_term,
@@ -101,9 +134,9 @@ __device__ __forceinline__ void force_pair(int j, double xi, double yi, double z
                                            const double *__restrict__ c, const Geo &g,
                                            double alpha, double beta, double eta2, ForceAcc &A)
 {
-    double dx = min_image(xi, x[j], g.per[0], g.L[0], g.halfL[0]);
-    double dy = min_image(yi, y[j], g.per[1], g.L[1], g.halfL[1]);
-    double dz = min_image(zi, z[j], g.per[2], g.L[2], g.halfL[2]);
+    double dx = mimg<PM, 0>(xi, x[j], g);
+    double dy = mimg<PM, 1>(yi, y[j], g);
+    double dz = mimg<PM, 2>(zi, z[j], g);
     double r2 = dx * dx + dy * dy + dz * dz;
     if (!(r2 > 0.0)) return;
     double r = sqrt(r2);
@@ -135,13 +168,14 @@ __device__ __forceinline__ void force_pair(int j, double xi, double yi, double z
     A.du += mj * (pi_term + 0.5 * Pi) * gbar * w;
 }
 
+template <int PM>
 __global__ __launch_bounds__(SPH_BLOCK) void k_forces(
     int64_t n, const double *__restrict__ x, const double *__restrict__ y,
     const double *__restrict__ z, const double *__restrict__ vx, const double *__restrict__ vy,
     const double *__restrict__ vz, const double *__restrict__ m, const double *__restrict__ h,
     const double *__restrict__ rho, const double *__restrict__ p, const double *__restrict__ c,
     const int32_t *__restrict__ nc, const int32_t *__restrict__ idx, int64_t stride, int K,
-    const int64_t *__restrict__ eoff, const int32_t *__restrict__ eidx, int64_t ecap, Geo g,
+    const int32_t *__restrict__ ecnt, const int32_t *__restrict__ eidx, int slots, Geo g,
     double alpha, double beta, double eta2, double cfl, double *__restrict__ ax,
     double *__restrict__ ay, double *__restrict__ az, double *__restrict__ du,
     double *__restrict__ dt_part)
@@ -156,13 +190,21 @@ __global__ __launch_bounds__(SPH_BLOCK) void k_forces(
         ForceAcc A = {0.0, 0.0, 0.0, 0.0, 0.0};
         int cnt = min(nc[i], K);
         for (int k = 0; k < cnt; ++k)
-            force_pair(idx[(int64_t)k * stride + i], xi, yi, zi, vxi, vyi, vzi, hi, inv_hi, rhoi,
+            force_pair<PM>(idx[(int64_t)k * stride + i], xi, yi, zi, vxi, vyi, vzi, hi, inv_hi, rhoi,
                        ci, pi_term, x, y, z, vx, vy, vz, m, h, rho, p, c, g, alpha, beta, eta2, A);
-        int64_t e0 = eoff[i], e1 = eoff[i + 1];
-        if (e1 > ecap) e1 = ecap;
-        for (int64_t k = e0; k < e1; ++k)
-            force_pair(eidx[k], xi, yi, zi, vxi, vyi, vzi, hi, inv_hi, rhoi, ci, pi_term, x, y, z,
+        // E_i in ascending index order (its slots were filled by atomics)
+        const int ne = min(ecnt[i], slots);
+        int last = -1;
+        for (int q = 0; q < ne; ++q) {
+            int nxt = 0x7fffffff;
+            for (int k = 0; k < ne; ++k) {
+                int v = eidx[(int64_t)k * stride + i];
+                nxt = (v > last && v < nxt) ? v : nxt;
+            }
+            last = nxt;
+            force_pair<PM>(nxt, xi, yi, zi, vxi, vyi, vzi, hi, inv_hi, rhoi, ci, pi_term, x, y, z,
                        vx, vy, vz, m, h, rho, p, c, g, alpha, beta, eta2, A);
+        }
         ax[i] = A.ax;
         ay[i] = A.ay;
         az[i] = A.az;
@@ -203,11 +245,13 @@ hipError_t launch_forces(sph_ctx *c, sph_particles *s, const sph_nlist *nl, doub
     int64_t nb = ceil_div(n > 0 ? n : 1, SPH_BLOCK);
     // dt partials live in the reduction area sized for n_max / SPH_BLOCK blocks
     double *part = c->w.red_part;
-    hipLaunchKernelGGL(k_forces, dim3((unsigned)nb), dim3(SPH_BLOCK), 0, c->stream, n, s->x[cur],
-                       s->y[cur], s->z[cur], s->pvx, s->pvy, s->pvz, s->m[cur], s->h[cur],
-                       s->rho[cur], s->p, s->c, s->nc[cur], nl->idx, nl->stride, p.list_stride,
-                       nl->eoff, nl->eidx, nl->ecap, make_geo(p), p.av_alpha, p.av_beta,
-                       p.av_eta2, p.cfl, s->ax[cur], s->ay[cur], s->az[cur], s->du[cur], part);
+    Geo g = make_geo(p);
+    SPH_DISPATCH_PM(periodic_mask(g),
+        hipLaunchKernelGGL(k_forces<PM>, dim3((unsigned)nb), dim3(SPH_BLOCK), 0, c->stream, n,
+                           s->x[cur], s->y[cur], s->z[cur], s->pvx, s->pvy, s->pvz, s->m[cur],
+                           s->h[cur], s->rho[cur], s->p, s->c, s->nc[cur], nl->idx, nl->stride,
+                           p.list_stride, nl->ecnt, nl->eidx, p.extra_slots, g, p.av_alpha, p.av_beta,
+                           p.av_eta2, p.cfl, s->ax[cur], s->ay[cur], s->az[cur], s->du[cur], part))
     if (d_dt)
         hipLaunchKernelGGL(k_min_final, dim3(1), dim3(SPH_BLOCK), 0, c->stream, part, nb, d_dt);
     return hipGetLastError();

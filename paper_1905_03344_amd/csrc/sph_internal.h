@@ -22,6 +22,7 @@ enum {
     ST_LEARN_ACC = 5,
     ST_LEARN_FALLBACK = 6,
     ST_CANDIDATES = 7,
+    ST_EXTRA_TOTAL = 8,
     ST_COUNT = 16
 };
 
@@ -47,8 +48,6 @@ struct Workspace {
     int64_t *status;       // ST_COUNT
     double *dt_cur;        // 1: dt used by the current step
     double *red_part;      // nb_red * 8 reduction partials
-    int32_t *ecnt;         // n_max
-    int32_t *efill;        // n_max
     uint8_t *refill;       // n_max
     int64_t nb_red;
     int64_t nb_sort;
@@ -65,8 +64,6 @@ struct sph_ctx {
     Workspace w;
     int bound;
     int timing;
-    const int64_t *last_eoff;  // complement offsets of the last neighbour search
-    int64_t last_n;
     StageTimer *timer;
     char err[512];
 };
@@ -86,7 +83,8 @@ hipError_t launch_scan_u32(sph_ctx *c, const uint32_t *in, uint32_t *out, int64_
 
 hipError_t launch_hsolve(sph_ctx *c, sph_particles *s, sph_nlist *nl, const double *h_try);
 hipError_t launch_extra(sph_ctx *c, sph_particles *s, sph_nlist *nl);
-hipError_t launch_density(sph_ctx *c, sph_particles *s, const sph_nlist *nl);
+hipError_t launch_density(sph_ctx *c, sph_particles *s, const sph_nlist *nl, bool build_extra);
+hipError_t launch_zero_i32(sph_ctx *c, int32_t *a, int64_t n);
 hipError_t launch_eos(sph_ctx *c, sph_particles *s);
 hipError_t launch_forces(sph_ctx *c, sph_particles *s, const sph_nlist *nl, double *d_dt);
 hipError_t launch_kick_drift(sph_ctx *c, sph_particles *s);
@@ -138,10 +136,52 @@ __device__ __forceinline__ double min_image(double a, double b, int per, double 
 #pragma clang fp contract(off)
     double t = b - a;
     if (per) {
-        if (t > halfL) t = t - L;
-        else if (t < -halfL) t = t + L;
+        double up = t - L, dn = t + L;
+        t = (t > halfL) ? up : ((t < -halfL) ? dn : t);
     }
     return t;
+}
+
+// minimum image with the periodic dimensions known at compile time (bit d
+// of PM set = dimension d periodic); same arithmetic as min_image
+template <int PM, int D>
+__device__ __forceinline__ double mimg(double a, double b, const Geo &g)
+{
+#pragma clang fp contract(off)
+    double t = b - a;
+    if constexpr (((PM >> D) & 1) != 0) {
+        double up = t - g.L[D], dn = t + g.L[D];
+        t = (t > g.halfL[D]) ? up : ((t < -g.halfL[D]) ? dn : t);
+    }
+    return t;
+}
+
+static inline int periodic_mask(const Geo &g) { return g.per[0] | (g.per[1] << 1) | (g.per[2] << 2); }
+
+// launches KERNEL<PM, ...> for the runtime periodic mask pm
+#define SPH_DISPATCH_PM(pm, LAUNCH)                  \
+    switch (pm) {                                    \
+    case 0: { constexpr int PM = 0; LAUNCH; } break; \
+    case 1: { constexpr int PM = 1; LAUNCH; } break; \
+    case 2: { constexpr int PM = 2; LAUNCH; } break; \
+    case 3: { constexpr int PM = 3; LAUNCH; } break; \
+    case 4: { constexpr int PM = 4; LAUNCH; } break; \
+    case 5: { constexpr int PM = 5; LAUNCH; } break; \
+    case 6: { constexpr int PM = 6; LAUNCH; } break; \
+    default: { constexpr int PM = 7; LAUNCH; } break; \
+    }
+
+// Complement rows: i goes into E_j when j is in L_i but i is not in L_j,
+// i.e. r_ij^2 >= (2 h_j)^2 (the same exact test j's own gather used).
+// Slots come from an integer atomic; rows past `slots` are counted.
+__device__ __forceinline__ void extra_append(int j, int i, int32_t *__restrict__ ecnt,
+                                             int32_t *__restrict__ eidx, int64_t stride, int slots,
+                                             int64_t &appended, int64_t &dropped)
+{
+    int k = atomicAdd(&ecnt[j], 1);
+    if (k < slots) eidx[(int64_t)k * stride + j] = i;
+    else if (k == slots) ++dropped;   // count each overflowing row once
+    ++appended;
 }
 
 // r^2 = (dx*dx + dy*dy) + dz*dz, each operation rounded on its own

@@ -34,7 +34,7 @@ _D = ctypes.c_double
 
 class sph_params(ctypes.Structure):
     _fields_ = [("n_max", _I64), ("list_stride", _I32), ("pad0", _I32),
-                ("extra_capacity", _I64), ("periodic", _I32 * 3), ("kernel", _I32),
+                ("extra_slots", _I32), ("pad1", _I32), ("periodic", _I32 * 3), ("kernel", _I32),
                 ("box_lo", _D * 3), ("box_hi", _D * 3), ("n_target", _I32), ("n_tol", _I32),
                 ("h_max_iter", _I32), ("precision", _I32), ("gamma", _D), ("av_alpha", _D),
                 ("av_beta", _D), ("av_eta2", _D), ("cfl", _D), ("h_mode", _I32),
@@ -56,7 +56,7 @@ class sph_particles(ctypes.Structure):
 
 
 class sph_nlist(ctypes.Structure):
-    _fields_ = [("idx", _P), ("stride", _I64), ("eoff", _P), ("eidx", _P), ("ecap", _I64)]
+    _fields_ = [("idx", _P), ("stride", _I64), ("ecnt", _P), ("eidx", _P)]
 
 
 class sph_stats(ctypes.Structure):

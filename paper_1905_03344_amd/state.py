@@ -28,7 +28,7 @@ def choose_max_level(n: int, bbox_extent: float, h_min: float, search_div: int =
 
 class Simulation:
     def __init__(self, ic, params: ffi.sph_params | None = None, device="cuda", n_max=None,
-                 list_stride=128, extra_per_particle=48, max_level=None, search_div=1,
+                 list_stride=128, extra_per_particle=48, max_level=None, search_div=2,
                  precision=ffi.SPH_FP64, check_finite=False):
         self.device = torch.device(device)
         n = ic.n
@@ -36,7 +36,7 @@ class Simulation:
         p = params if params is not None else ffi.default_params()
         p.n_max = int(n_max or n)
         p.list_stride = int(list_stride)
-        p.extra_capacity = int(max(1024, extra_per_particle * n))
+        p.extra_slots = int(extra_per_particle)
         for d in range(3):
             p.periodic[d] = int(ic.periodic[d])
             p.box_lo[d] = float(ic.box_lo[d])
@@ -73,8 +73,8 @@ class Simulation:
         # neighbour lists
         self.stride = max(64, ((n + 63) // 64) * 64)
         self.nl_idx = torch.zeros(p.list_stride * self.stride, **i32)
-        self.nl_eoff = torch.zeros(n + 1, dtype=torch.int64, device=dev)
-        self.nl_eidx = torch.zeros(p.extra_capacity, **i32)
+        self.nl_ecnt = torch.zeros(self.stride, **i32)
+        self.nl_eidx = torch.zeros(p.extra_slots * self.stride, **i32)
         self.d_dt = torch.zeros(1, **f64)
         self.cons = torch.zeros(8, **f64)
         # workspace
@@ -89,9 +89,8 @@ class Simulation:
         self.nl = ffi.sph_nlist()
         self.nl.idx = self.nl_idx.data_ptr()
         self.nl.stride = self.stride
-        self.nl.eoff = self.nl_eoff.data_ptr()
+        self.nl.ecnt = self.nl_ecnt.data_ptr()
         self.nl.eidx = self.nl_eidx.data_ptr()
-        self.nl.ecap = p.extra_capacity
         self.time = 0.0
 
     def _fill_ptrs(self):
@@ -194,10 +193,16 @@ class Simulation:
         return self.numpy("nc"), self.nl_idx.view(K, self.stride)[:, :n].cpu().numpy()
 
     def extra_lists(self):
-        eoff = self.nl_eoff.cpu().numpy()
-        tot = int(eoff[-1])
-        eidx = self.nl_eidx[:min(tot, self.params.extra_capacity)].cpu().numpy()
-        return eoff, eidx
+        """(eoff, eidx): the complement rows as CSR with ascending rows."""
+        n = self.n
+        ke = self.params.extra_slots
+        ecnt = np.minimum(self.nl_ecnt[:n].cpu().numpy(), ke)
+        e = self.nl_eidx.view(ke, self.stride)[:, :n].cpu().numpy()
+        mask = np.arange(ke)[:, None] < ecnt[None, :]
+        kk, ii = np.nonzero(mask)
+        code = np.sort(ii.astype(np.int64) * max(n, 1) + e[kk, ii].astype(np.int64))
+        eoff = np.concatenate([[0], np.cumsum(np.bincount(ii, minlength=n))]).astype(np.int64)
+        return eoff, (code % max(n, 1)).astype(np.int32)
 
     def interaction_csr(self):
         """S_i = L_i U E_i as CSR with ascending rows (for comparisons)."""

@@ -100,7 +100,7 @@ def test_evaluate_parity(case):
     st = O.State(ic.copy())
     st.keep_gather = True
     st.evaluate(method=1)
-    sim = _sim(ic, extra_per_particle=64)
+    sim = _sim(ic, extra_per_particle=96)
     sim.evaluate()
     code, stats = sim.sync()
     compare_cells(sim, st)
@@ -171,7 +171,7 @@ def test_deterministic_runs():
     ic = inputs.clumpy(n_clumps=3, per_clump=2000, n_background=1500, seed=21)
     outs = []
     for _ in range(2):
-        sim = _sim(ic)
+        sim = _sim(ic, extra_per_particle=96)
         sim.evaluate()
         for _ in range(2):
             sim.step(0.0)
