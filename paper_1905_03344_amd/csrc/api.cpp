@@ -170,6 +170,20 @@ size_t sph_layout(const sph_params *p, void *base, Workspace *w)
     t.dt_cur = (double *)take(sizeof(double));
     t.red_part = (double *)take(red_len * sizeof(double));
     t.refill = (uint8_t *)take(n);
+    t.work = (int32_t *)take(n * sizeof(int32_t));
+    t.woff = (int64_t *)take((n + 1) * sizeof(int64_t));
+    t.wl = (int32_t *)take(n * sizeof(int32_t));
+    t.hs_next = (double *)take(n * sizeof(double));
+    t.hs_lo = (double *)take(n * sizeof(double));
+    t.hs_hi = (double *)take(n * sizeof(double));
+    t.hs_best_h = (double *)take(n * sizeof(double));
+    t.hs_last_h = (double *)take(n * sizeof(double));
+    t.hs_best_n = (int32_t *)take(n * sizeof(int32_t));
+    t.hs_itk = (int32_t *)take(n * sizeof(int32_t));
+    t.hs_bits = (int32_t *)take(n * sizeof(int32_t));
+    t.shell_stride = ceil_div(n, 64) * 64;
+    t.shell_j = (int32_t *)take(48 * t.shell_stride * sizeof(int32_t));
+    t.shell_r2 = (double *)take(48 * t.shell_stride * sizeof(double));
     t.nb_red = nb_red;
     t.nb_sort = nb_sort;
     t.scan_part_len = scan_part;

@@ -122,21 +122,27 @@ __device__ __forceinline__ int count_fill(const Search &S, const double *__restr
 }
 
 // ---------------------------------------------------------------------------
-// Smoothing-length iteration, wave-cooperative.
-// A wave owns 64 consecutive (Morton-sorted) particles.  Per count it builds
-// the union of its members' search boxes, walks the cells of that box in
-// batches of 64 (one cell per lane, prefix sums of the cell sizes), streams
-// the candidates in tiles of 64 through LDS and lets every lane test every
-// candidate of the tile against its own particle (broadcast LDS reads), so
-// control flow is uniform across the wave and candidate loads are coalesced.
+// Smoothing-length iteration.
 // Per particle the arithmetic is the iteration of the paper's reading:
 //   N = count at h; keep the best (h, N) by |N - target| (ties: smaller h);
 //   stop when |N - target| <= tol; below the band raise the lower bracket,
 //   above it lower the upper bracket; bisect once both are set, else
 //   h *= T[min(N, 1023)]; at most maxit counts.
-// The gather set of the last counted h is written (slot-major).
 // With h_try (learned mode) the first count is taken at h_try[i]; in band it
 // is accepted, otherwise the plain iteration starts from h[i].
+// The gather set of the last counted h is written (slot-major); particles
+// whose kept h is not the last counted one are rewritten by k_refill.
+//
+// Counting is wave-cooperative: a wave owns 64 particles (consecutive in
+// Morton order, or consecutive entries of a worklist), builds the union of
+// their search boxes, walks its cells in batches of 64 (one cell per lane,
+// prefix sums of the cell sizes), streams the candidates in tiles of 64
+// through LDS and lets every lane test every candidate of the tile against
+// its own particle (broadcast LDS reads).  Control flow is uniform and
+// candidate loads are coalesced.  Round 0 counts every particle once; each
+// further round counts the particles still outside the band (a compacted
+// worklist, Morton order kept) with their iteration state carried over; a
+// per-particle kernel finishes the few that remain.
 // ---------------------------------------------------------------------------
 struct Cand {
     double x, y, z;
@@ -184,43 +190,87 @@ __device__ __forceinline__ void wave_lds_sync()
 
 #define WAVES_PER_BLOCK (SPH_BLOCK / 64)
 
-template <int PM>
-__global__ __launch_bounds__(SPH_BLOCK) void k_hsolve(
-    int64_t n, const double *__restrict__ x, const double *__restrict__ y,
-    const double *__restrict__ z, const uint32_t *__restrict__ key, double *__restrict__ h,
-    int32_t *__restrict__ nc, uint8_t *__restrict__ flags, uint8_t *__restrict__ refill,
-    int32_t *__restrict__ idx, int64_t stride, int K, const int32_t *__restrict__ cs,
-    const double *__restrict__ bbox, Geo g, int lmax, int div, const double *__restrict__ hk,
-    int target, int tol, int maxit, const double *__restrict__ h_try,
-    int64_t *__restrict__ status)
+struct WaveLds {
+    Cand c[64];
+    int start[64];
+    int pre[64];
+};
+
+// hits of one LDS tile for this lane: bit t of *in set when candidate t has
+// r^2 < A (inside the shell), bit t of *sh when A <= r^2 < B (in the shell).
+// FULL tiles skip the bound test; PMW is the periodic mask the tile needs
+// (0 when the sub-group's box cannot wrap).
+template <int PMW, bool FULL>
+__device__ __forceinline__ void tile_hits(const WaveLds &L, int m, double xi, double yi, double zi,
+                                          double A2, double B2, const Geo &g, uint64_t *in,
+                                          uint64_t *sh)
 {
 #pragma clang fp contract(off)
-    __shared__ Cand s_c[WAVES_PER_BLOCK][64];
-    __shared__ int s_start[WAVES_PER_BLOCK][64];
-    __shared__ int s_pre[WAVES_PER_BLOCK][64];
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    const int64_t grp = xcd_block(blockIdx.x, gridDim.x) * WAVES_PER_BLOCK + w;
-    const int64_t i = grp * 64 + lane;
-    const bool valid = i < n;
-    const Search S = make_search(cs, lmax, div, bbox, g);
-
-    double xi = 0.0, yi = 0.0, zi = 0.0, hcur = 0.0, hnext = 0.0;
-    uint32_t ki = 0;
-    if (valid) {
-        xi = x[i]; yi = y[i]; zi = z[i];
-        hcur = h[i];
-        ki = key[i];
+    uint64_t hin = 0, hsh = 0;
+    const int nb8 = FULL ? 8 : ((m + 7) >> 3);
+    for (int b = 0; b < nb8; ++b) {
+        uint32_t i8 = 0, s8 = 0;
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int t = 8 * b + u;
+            const Cand cd = L.c[t];
+            double dx = mimg<PMW, 0>(xi, cd.x, g);
+            double dy = mimg<PMW, 1>(yi, cd.y, g);
+            double dz = mimg<PMW, 2>(zi, cd.z, g);
+            double r2 = exact_r2(dx, dy, dz);
+            bool a = r2 < A2, b2 = r2 < B2;
+            if (!FULL) { a = a && (t < m); b2 = b2 && (t < m); }
+            i8 |= a ? (1u << u) : 0u;
+            s8 |= b2 ? (1u << u) : 0u;
+        }
+        hin |= (uint64_t)i8 << (8 * b);
+        hsh |= (uint64_t)s8 << (8 * b);
     }
-    bool tried = (h_try == nullptr);
-    hnext = (!tried && valid) ? h_try[i] : hcur;   // h of the next count
-    bool stop = !valid, conv = false;
-    double lo_b = 0.0, hi_b = 0.0, best_h = hcur, last_h = hcur;
-    bool have_lo = false, have_hi = false;
-    int best_n = -1, itk = 0;
-    uint8_t fl = 0;
-    int64_t counts = 0, tested = 0, acc = 0, fallback = 0;
+    *in = hin;
+    *sh = hsh & ~hin;
+}
 
-    uint64_t pending = __ballot(valid);
+// exact r^2 of lane position and tile candidate t (same arithmetic as above)
+template <int PMW>
+__device__ __forceinline__ double tile_r2(const WaveLds &L, int t, double xi, double yi, double zi,
+                                          const Geo &g)
+{
+#pragma clang fp contract(off)
+    const Cand cd = L.c[t];
+    return exact_r2(mimg<PMW, 0>(xi, cd.x, g), mimg<PMW, 1>(yi, cd.y, g),
+                    mimg<PMW, 2>(zi, cd.z, g));
+}
+
+// Shell around a counted h: members with A <= r^2 < B, A = (2h(1-d))^2,
+// B = (2h(1+d))^2, d = 1/32.  For any h' with A <= (2h')^2 <= B the count
+// is exactly N_inner + #{shell: r^2 < (2h')^2}: both sides use the same
+// rounded r^2 and the same rounded (2h')^2.
+#define SPH_SHELL_SLOTS 48
+struct Shell {
+    int32_t *j;     // SPH_SHELL_SLOTS * sstride
+    double *r2;     // SPH_SHELL_SLOTS * sstride
+    int64_t sstride;
+};
+
+// One wave-cooperative count for every lane with act set at its own hc:
+// members with r^2 < A are written to idx (slot-major, at most K), shell
+// members (A <= r^2 < B) to the shell arrays (at most SPH_SHELL_SLOTS;
+// *nsh = -1 when more).  Returns the number of inner members (self
+// excluded); self is never a shell member.
+template <int PM>
+__device__ int wave_count(WaveLds &L, bool act, int64_t i, double xi, double yi, double zi,
+                          uint32_t ki, double hc, double A2, double B2,
+                          const double *__restrict__ x, const double *__restrict__ y,
+                          const double *__restrict__ z, int32_t *__restrict__ idx, int64_t stride,
+                          int K, const Shell &SH, int *nsh_out, const Search &S, const Geo &g,
+                          int64_t &tested)
+{
+#pragma clang fp contract(off)
+    const int lane = threadIdx.x & 63;
+    const double twoh = 2.0 * hc;
+    int N = 0, nsh = 0;
+    int32_t *wp = idx + i;   // slot N of this particle's gather set
+    uint64_t pending = __ballot(act);
     while (pending) {
         // sub-group: the pending lanes, split by Morton prefix while their
         // positions spread over more than 1.5 search diameters (a group that
@@ -228,7 +278,7 @@ __global__ __launch_bounds__(SPH_BLOCK) void k_hsolve(
         uint64_t members = pending;
         for (int sp = 0; sp < 32; ++sp) {
             bool mem = (members >> lane) & 1ull;
-            double Rm = wave_max_d(mem ? 2.0 * hnext : 0.0);
+            double Rm = wave_max_d(mem ? twoh : 0.0);
             double ext = 0.0;
             const double p3[3] = {xi, yi, zi};
             for (int d = 0; d < 3; ++d) {
@@ -246,172 +296,396 @@ __global__ __launch_bounds__(SPH_BLOCK) void k_hsolve(
             members &= __ballot(((ki ^ lk) >> hb) == 0u);
         }
         pending &= ~members;
-        const bool mem = (members >> lane) & 1ull;
+        const bool me = (members >> lane) & 1ull;
 
-        while (true) {
-            const bool act = mem && !stop;
-            if (!__ballot(act)) break;
-            const double hc = hnext;
-            const double twoh = 2.0 * hc;
-            const double r2max = twoh * twoh;
-            // union box of the active lanes
-            double Rmax = wave_max_d(act ? twoh : 0.0);
-            double blo[3], bhi[3];
-            {
-                const double p3[3] = {xi, yi, zi};
-                for (int d = 0; d < 3; ++d) {
-                    blo[d] = wave_min_d(act ? p3[d] - twoh : INFINITY) - S.margin;
-                    bhi[d] = wave_max_d(act ? p3[d] + twoh : -INFINITY) + S.margin;
-                }
-            }
-            double span = fmax(fmax(bhi[0] - blo[0], bhi[1] - blo[1]), bhi[2] - blo[2]);
-            int l = S.lmax;
-            while (l > 0) {
-                bool ok = true;
-                for (int d = 0; d < 3; ++d) {
-                    double cw = ldexp(S.L[d], -l);
-                    if (S.L[d] > 0.0 && (cw * S.div < Rmax + S.margin || cw * 16.0 < span)) ok = false;
-                }
-                if (ok) break;
-                --l;
-            }
-            const int nl = 1 << l;
-            const int msk = nl - 1;
-            int a[3], cnt[3];
+        // union box of the sub-group, wide enough for the shell's outer radius
+        const double Rout = sqrt(B2) * (1.0 + 1e-12);
+        double Rmax = wave_max_d(me ? Rout : 0.0);
+        double blo[3], bhi[3];
+        {
+            const double p3[3] = {xi, yi, zi};
             for (int d = 0; d < 3; ++d) {
-                if (!(S.L[d] > 0.0)) { a[d] = 0; cnt[d] = 1; continue; }
-                double wd = ldexp(S.L[d], -l);
-                double ta = floor((blo[d] - S.lo[d]) / wd);
-                double tb = floor((bhi[d] - S.lo[d]) / wd);
-                ta = fmin(fmax(ta, -2.0 * nl), 3.0 * nl);
-                tb = fmin(fmax(tb, -2.0 * nl), 3.0 * nl);
-                int ia = (int)ta, ib = (int)tb;
-                if (S.g.per[d]) {
-                    if (ib - ia + 1 >= nl) { ia = 0; ib = nl - 1; }
-                } else {
-                    ia = max(ia, 0);
-                    ib = min(ib, nl - 1);
-                }
-                a[d] = ia;
-                cnt[d] = max(ib - ia + 1, 0);
+                blo[d] = wave_min_d(me ? p3[d] - Rout : INFINITY) - S.margin;
+                bhi[d] = wave_max_d(me ? p3[d] + Rout : -INFINITY) + S.margin;
             }
-            const int sh = 3 * (S.lmax - l);
-            const int ncell = cnt[0] * cnt[1] * cnt[2];
-            int N = 0;
-            int32_t *wp = idx + i;   // slot N of this particle's gather set
-            for (int cb = 0; cb < ncell; cb += 64) {
-                int c = cb + lane;
-                int s0 = 0, len = 0;
-                if (c < ncell) {
-                    int kx = c % cnt[0];
-                    int ky = (c / cnt[0]) % cnt[1];
-                    int kz = c / (cnt[0] * cnt[1]);
-                    uint32_t code = morton((uint32_t)((a[0] + kx) & msk),
-                                           (uint32_t)((a[1] + ky) & msk),
-                                           (uint32_t)((a[2] + kz) & msk));
-                    s0 = S.cs[(int64_t)code << sh];
-                    len = S.cs[((int64_t)code + 1) << sh] - s0;
+        }
+        double span = fmax(fmax(bhi[0] - blo[0], bhi[1] - blo[1]), bhi[2] - blo[2]);
+        int l = S.lmax;
+        while (l > 0) {
+            bool ok = true;
+            for (int d = 0; d < 3; ++d) {
+                double cw = ldexp(S.L[d], -l);
+                if (S.L[d] > 0.0 && (cw * S.div < Rmax + S.margin || cw * 16.0 < span)) ok = false;
+            }
+            if (ok) break;
+            --l;
+        }
+        const int nl = 1 << l;
+        const int msk = nl - 1;
+        int a[3], cnt[3];
+        bool wraps = false;
+        for (int d = 0; d < 3; ++d) {
+            if (!(S.L[d] > 0.0)) { a[d] = 0; cnt[d] = 1; continue; }
+            double wd = ldexp(S.L[d], -l);
+            double ta = floor((blo[d] - S.lo[d]) / wd);
+            double tb = floor((bhi[d] - S.lo[d]) / wd);
+            ta = fmin(fmax(ta, -2.0 * nl), 3.0 * nl);
+            tb = fmin(fmax(tb, -2.0 * nl), 3.0 * nl);
+            int ia = (int)ta, ib = (int)tb;
+            if (S.g.per[d]) {
+                if (ib - ia + 1 >= nl) { ia = 0; ib = nl - 1; }
+                // without a wrapped cell and with the box (plus one cell of
+                // slack) under half the period, every |x_j - x_i| < L/2: the
+                // minimum image is the plain difference
+                if (ia < 0 || ib >= nl || (double)(ib - ia + 2) * wd > g.halfL[d]) wraps = true;
+            } else {
+                ia = max(ia, 0);
+                ib = min(ib, nl - 1);
+            }
+            a[d] = ia;
+            cnt[d] = max(ib - ia + 1, 0);
+        }
+        const int sh = 3 * (S.lmax - l);
+        const int ncell = cnt[0] * cnt[1] * cnt[2];
+        for (int cb = 0; cb < ncell; cb += 64) {
+            int c = cb + lane;
+            int s0 = 0, len = 0;
+            if (c < ncell) {
+                int kx = c % cnt[0];
+                int ky = (c / cnt[0]) % cnt[1];
+                int kz = c / (cnt[0] * cnt[1]);
+                uint32_t code = morton((uint32_t)((a[0] + kx) & msk), (uint32_t)((a[1] + ky) & msk),
+                                       (uint32_t)((a[2] + kz) & msk));
+                s0 = S.cs[(int64_t)code << sh];
+                len = S.cs[((int64_t)code + 1) << sh] - s0;
+            }
+            int incl = wave_incl_scan_i(len);
+            int total = __shfl(incl, 63, 64);
+            wave_lds_sync();
+            L.start[lane] = s0;
+            L.pre[lane] = incl - len;
+            wave_lds_sync();
+            if (me) tested += total;
+            for (int base = 0; base < total; base += 64) {
+                int v = base + lane;
+                if (v < total) {
+                    int r = 0;
+                    for (int st = 32; st > 0; st >>= 1)
+                        if (L.pre[r + st] <= v) r += st;
+                    int j = L.start[r] + (v - L.pre[r]);
+                    Cand cd;
+                    cd.x = x[j];
+                    cd.y = y[j];
+                    cd.z = z[j];
+                    cd.j = j;
+                    cd.pad = 0;
+                    L.c[lane] = cd;
                 }
-                int incl = wave_incl_scan_i(len);
-                int total = __shfl(incl, 63, 64);
                 wave_lds_sync();
-                s_start[w][lane] = s0;
-                s_pre[w][lane] = incl - len;
-                wave_lds_sync();
-                if (act) tested += total;
-                for (int base = 0; base < total; base += 64) {
-                    int v = base + lane;
-                    if (v < total) {
-                        int r = 0;
-                        for (int st = 32; st > 0; st >>= 1)
-                            if (s_pre[w][r + st] <= v) r += st;
-                        int j = s_start[w][r] + (v - s_pre[w][r]);
-                        Cand cd;
-                        cd.x = x[j];
-                        cd.y = y[j];
-                        cd.z = z[j];
-                        cd.j = j;
-                        cd.pad = 0;
-                        s_c[w][lane] = cd;
+                const int m = min(64, total - base);
+                if (me) {
+                    uint64_t hin, hsh;
+                    if (m == 64) {
+                        if (wraps) tile_hits<PM, true>(L, m, xi, yi, zi, A2, B2, g, &hin, &hsh);
+                        else tile_hits<0, true>(L, m, xi, yi, zi, A2, B2, g, &hin, &hsh);
+                    } else {
+                        if (wraps) tile_hits<PM, false>(L, m, xi, yi, zi, A2, B2, g, &hin, &hsh);
+                        else tile_hits<0, false>(L, m, xi, yi, zi, A2, B2, g, &hin, &hsh);
                     }
-                    wave_lds_sync();
-                    const int m = min(64, total - base);
-                    if (act) {
-#pragma unroll 4
-                        for (int t = 0; t < m; ++t) {
-                            const Cand cd = s_c[w][t];
-                            double dx = mimg<PM, 0>(xi, cd.x, g);
-                            double dy = mimg<PM, 1>(yi, cd.y, g);
-                            double dz = mimg<PM, 2>(zi, cd.z, g);
-                            double r2 = exact_r2(dx, dy, dz);
-                            if (r2 < r2max && cd.j != (int)i) {
-                                if (N < K) *wp = cd.j;
-                                wp += stride;
-                                ++N;
-                            }
+                    // inner members in candidate order, skipping self
+                    while (hin) {
+                        int t = __ffsll((unsigned long long)hin) - 1;
+                        hin &= hin - 1;
+                        int j = L.c[t].j;
+                        if (j != (int)i) {
+                            if (N < K) *wp = j;
+                            wp += stride;
+                            ++N;
                         }
                     }
-                    wave_lds_sync();
-                }
-            }
-            if (act) {
-                ++counts;
-                last_h = hc;
-                int dev = N > target ? N - target : target - N;
-                if (!tried) {
-                    tried = true;
-                    if (dev <= tol) {
-                        stop = conv = true;
-                        best_h = hc;
-                        best_n = N;
-                        fl = SPH_FLAG_LEARNED;
-                        ++acc;
-                    } else {
-                        ++fallback;
-                        hnext = hcur;
-                    }
-                } else {
-                    int bdev = best_n > target ? best_n - target : target - best_n;
-                    if (best_n < 0 || dev < bdev || (dev == bdev && hc < best_h)) {
-                        best_h = hc;
-                        best_n = N;
-                    }
-                    if (dev <= tol) {
-                        stop = conv = true;
-                    } else {
-                        if (N < target - tol) {
-                            if (!have_lo || hc > lo_b) lo_b = hc;
-                            have_lo = true;
+                    // shell members with their exact r^2
+                    while (hsh) {
+                        int t = __ffsll((unsigned long long)hsh) - 1;
+                        hsh &= hsh - 1;
+                        if (nsh >= 0 && nsh < SPH_SHELL_SLOTS) {
+                            double r2 = wraps ? tile_r2<PM>(L, t, xi, yi, zi, g)
+                                              : tile_r2<0>(L, t, xi, yi, zi, g);
+                            SH.j[(int64_t)nsh * SH.sstride + i] = L.c[t].j;
+                            SH.r2[(int64_t)nsh * SH.sstride + i] = r2;
+                            ++nsh;
                         } else {
-                            if (!have_hi || hc < hi_b) hi_b = hc;
-                            have_hi = true;
+                            nsh = -1;
                         }
-                        ++itk;
-                        if (itk >= maxit) stop = true;
-                        else if (have_lo && have_hi) hnext = 0.5 * (lo_b + hi_b);
-                        else hnext = hc * hk[N < 1023 ? N : 1023];
                     }
                 }
+                wave_lds_sync();
             }
         }
     }
-    int64_t nonconv = 0, overflow = 0;
-    if (valid) {
-        if (!conv) { fl |= SPH_FLAG_NOCONV; ++nonconv; }
-        h[i] = best_h;
-        nc[i] = best_n;
-        flags[i] = fl;
-        bool again = best_h != last_h;
-        refill[i] = again ? 1 : 0;
-        if (!again && best_n > K) ++overflow;
+    *nsh_out = nsh;
+    return N;
+}
+
+// iteration state carried between rounds (structure of arrays)
+struct HIter {
+    double *next, *lo, *hi, *best_h, *last_h;
+    int32_t *best_n, *itk, *bits;   // bits: 1 lower bracket, 2 upper bracket, 4 try pending
+};
+
+struct HState {
+    double next, lo, hi, best_h, last_h;
+    int best_n, itk, bits;
+};
+
+__device__ __forceinline__ HState hs_load(const HIter &H, int64_t i)
+{
+    HState s;
+    s.next = H.next[i]; s.lo = H.lo[i]; s.hi = H.hi[i];
+    s.best_h = H.best_h[i]; s.last_h = H.last_h[i];
+    s.best_n = H.best_n[i]; s.itk = H.itk[i]; s.bits = H.bits[i];
+    return s;
+}
+
+__device__ __forceinline__ void hs_store(const HIter &H, int64_t i, const HState &s)
+{
+    H.next[i] = s.next; H.lo[i] = s.lo; H.hi[i] = s.hi;
+    H.best_h[i] = s.best_h; H.last_h[i] = s.last_h;
+    H.best_n[i] = s.best_n; H.itk[i] = s.itk; H.bits[i] = s.bits;
+}
+
+// one step of the iteration after a count N at hc.
+// returns 0 = count again at s.next, 1 = converged, 2 = stopped unconverged
+__device__ __forceinline__ int h_update(HState &s, double hc, int N, double h_prev, int target,
+                                        int tol, int maxit, const double *__restrict__ hk,
+                                        uint8_t &fl, int64_t &acc, int64_t &fallback)
+{
+#pragma clang fp contract(off)
+    s.last_h = hc;
+    int dev = N > target ? N - target : target - N;
+    if (s.bits & 4) {   // the learned try
+        s.bits &= ~4;
+        if (dev <= tol) {
+            s.best_h = hc;
+            s.best_n = N;
+            fl = SPH_FLAG_LEARNED;
+            ++acc;
+            return 1;
+        }
+        ++fallback;
+        s.next = h_prev;
+        return 0;
     }
-    block_add_i64(counts, status + ST_HCOUNTS);
-    block_add_i64(tested, status + ST_CANDIDATES);
-    block_add_i64(nonconv, status + ST_NONCONV);
-    block_add_i64(overflow, status + ST_LIST_OVERFLOW);
-    if (h_try) {
-        block_add_i64(acc, status + ST_LEARN_ACC);
-        block_add_i64(fallback, status + ST_LEARN_FALLBACK);
+    int bdev = s.best_n > target ? s.best_n - target : target - s.best_n;
+    if (s.best_n < 0 || dev < bdev || (dev == bdev && hc < s.best_h)) {
+        s.best_h = hc;
+        s.best_n = N;
+    }
+    if (dev <= tol) return 1;
+    if (N < target - tol) {
+        if (!(s.bits & 1) || hc > s.lo) s.lo = hc;
+        s.bits |= 1;
+    } else {
+        if (!(s.bits & 2) || hc < s.hi) s.hi = hc;
+        s.bits |= 2;
+    }
+    ++s.itk;
+    if (s.itk >= maxit) return 2;
+    if ((s.bits & 3) == 3) s.next = 0.5 * (s.lo + s.hi);
+    else s.next = hc * hk[N < 1023 ? N : 1023];
+    return 0;
+}
+
+// final values of a finished particle
+__device__ __forceinline__ void h_finish(const HState &s, int res, uint8_t fl, int64_t i,
+                                         double *__restrict__ h, int32_t *__restrict__ nc,
+                                         uint8_t *__restrict__ flags, uint8_t *__restrict__ refill,
+                                         int K, int64_t &nonconv, int64_t &overflow)
+{
+    if (res != 1) { fl |= SPH_FLAG_NOCONV; ++nonconv; }
+    h[i] = s.best_h;
+    nc[i] = s.best_n;
+    flags[i] = fl;
+    bool again = s.best_h != s.last_h;
+    refill[i] = again ? 1 : 0;
+    if (!again && s.best_n > K) ++overflow;
+}
+
+struct HArgs {
+    const double *x, *y, *z;
+    const uint32_t *key;
+    double *h;
+    const double *h_try;
+    int32_t *nc;
+    uint8_t *flags;
+    uint8_t *refill;
+    int32_t *work;
+    int32_t *idx;
+    int64_t stride;
+    int K;
+    const int32_t *cs;
+    const double *bbox;
+    const double *hk;
+    Geo g;
+    int lmax, div, target, tol, maxit;
+    HIter H;
+    Shell SH;
+    int64_t *status;
+};
+
+// Round 0 (wl == nullptr: every particle, grouped by index) and later rounds
+// (the worklist wl of wcount particles).  After its count a particle keeps
+// iterating on its shell while the next h stays inside it; particles that
+// need another full count save their state and raise work[i].
+template <int PM>
+__global__ __launch_bounds__(SPH_BLOCK) void k_hsolve_round(HArgs A, int64_t n,
+                                                            const int32_t *__restrict__ wl,
+                                                            const int64_t *__restrict__ wcount)
+{
+#pragma clang fp contract(off)
+    __shared__ WaveLds lds[WAVES_PER_BLOCK];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    // a compacted worklist occupies the first blocks only: deal those to the
+    // XCDs round-robin (plain block order) instead of in contiguous ranges
+    const int64_t blk = wl ? (int64_t)blockIdx.x : xcd_block(blockIdx.x, gridDim.x);
+    const int64_t grp = blk * WAVES_PER_BLOCK + w;
+    const int64_t slot = grp * 64 + lane;
+    const int64_t total = wl ? *wcount : n;
+    const bool valid = slot < total;
+    const int64_t i = valid ? (wl ? (int64_t)wl[slot] : slot) : 0;
+    const Search S = make_search(A.cs, A.lmax, A.div, A.bbox, A.g);
+
+    double xi = 0.0, yi = 0.0, zi = 0.0, hprev = 0.0;
+    uint32_t ki = 0;
+    HState st = {};
+    if (valid) {
+        xi = A.x[i]; yi = A.y[i]; zi = A.z[i];
+        ki = A.key[i];
+        hprev = A.h[i];
+        if (wl) {
+            st = hs_load(A.H, i);
+        } else {
+            st.next = A.h_try ? A.h_try[i] : hprev;
+            st.lo = st.hi = 0.0;
+            st.best_h = st.last_h = hprev;
+            st.best_n = -1;
+            st.itk = 0;
+            st.bits = A.h_try ? 4 : 0;
+        }
+    }
+    int64_t tested = 0, counts = 0, acc = 0, fallback = 0, nonconv = 0, overflow = 0;
+    const double hc = st.next;
+    const double ta = 2.0 * hc * (1.0 - 1.0 / 32.0), tb = 2.0 * hc * (1.0 + 1.0 / 32.0);
+    const double A2 = ta * ta, B2 = tb * tb;
+    int nin = 0, nsh = 0;
+    // a wave whose slots are all past the end has nothing to do
+    if (__ballot(valid))
+        nin = wave_count<PM>(lds[w], valid, i, xi, yi, zi, ki, hc, A2, B2, A.x, A.y, A.z, A.idx,
+                             A.stride, A.K, A.SH, &nsh, S, A.g, tested);
+    if (valid) {
+        uint8_t fl = 0;
+        const int ns = nsh > 0 ? nsh : 0;
+        auto shell_count = [&](double r2m) {
+            int c = nin;
+            for (int k = 0; k < ns; ++k) c += A.SH.r2[(int64_t)k * A.SH.sstride + i] < r2m ? 1 : 0;
+            return c;
+        };
+        auto in_shell = [&](double r2m) { return nsh >= 0 && r2m >= A2 && r2m <= B2; };
+        const double t0 = 2.0 * hc;
+        int N = nsh >= 0 ? shell_count(t0 * t0) : -1;
+        int res;
+        if (N < 0) {
+            // shell overflow: the exact count needs a full pass (next round)
+            res = 0;
+        } else {
+            ++counts;
+            res = h_update(st, hc, N, hprev, A.target, A.tol, A.maxit, A.hk, fl, acc, fallback);
+            while (res == 0) {
+                const double tn = 2.0 * st.next;
+                const double r2n = tn * tn;
+                if (!in_shell(r2n)) break;
+                const double hn = st.next;
+                int Nn = shell_count(r2n);
+                ++counts;
+                res = h_update(st, hn, Nn, hprev, A.target, A.tol, A.maxit, A.hk, fl, acc, fallback);
+            }
+        }
+        if (res == 0) {
+            if (N < 0) st.next = hc;   // count again in full
+            hs_store(A.H, i, st);
+            A.work[i] = 1;
+        } else {
+            // the gather set of the kept h: inner members are in place when
+            // the kept h lies in this shell; append its shell members
+            const double tk = 2.0 * st.best_h;
+            const double r2k = tk * tk;
+            if (in_shell(r2k) && st.best_n == shell_count(r2k)) {
+                int pos = nin;
+                for (int k = 0; k < ns; ++k) {
+                    if (A.SH.r2[(int64_t)k * A.SH.sstride + i] < r2k) {
+                        if (pos < A.K) A.idx[(int64_t)pos * A.stride + i] = A.SH.j[(int64_t)k * A.SH.sstride + i];
+                        ++pos;
+                    }
+                }
+                st.last_h = st.best_h;
+            } else {
+                st.last_h = -1.0;   // the kept h lies outside this shell: rewrite its set
+            }
+            h_finish(st, res, fl, i, A.h, A.nc, A.flags, A.refill, A.K, nonconv, overflow);
+            A.work[i] = 0;
+        }
+    }
+    block_add_i64(counts, A.status + ST_HCOUNTS);
+    block_add_i64(tested, A.status + ST_CANDIDATES);
+    block_add_i64(nonconv, A.status + ST_NONCONV);
+    block_add_i64(overflow, A.status + ST_LIST_OVERFLOW);
+    if (A.h_try) {
+        block_add_i64(acc, A.status + ST_LEARN_ACC);
+        block_add_i64(fallback, A.status + ST_LEARN_FALLBACK);
+    }
+}
+
+// worklist: wl[woff[i]] = i for flagged particles (index order kept)
+__global__ __launch_bounds__(SPH_BLOCK) void k_compact(int64_t n, const int32_t *__restrict__ work,
+                                                       const int64_t *__restrict__ woff,
+                                                       int32_t *__restrict__ wl)
+{
+    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i < n && work[i]) wl[woff[i]] = (int32_t)i;
+}
+
+// The particles still iterating after the wave rounds: one thread each.
+template <int PM>
+__global__ __launch_bounds__(SPH_BLOCK) void k_hsolve_tail(HArgs A, const int32_t *__restrict__ wl,
+                                                           const int64_t *__restrict__ wcount)
+{
+#pragma clang fp contract(off)
+    const int64_t total = *wcount;
+    int64_t counts = 0, tested = 0, nonconv = 0, overflow = 0, acc = 0, fallback = 0;
+    for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < total;
+         t += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t i = wl[t];
+        const Search S = make_search(A.cs, A.lmax, 1, A.bbox, A.g);
+        const double xi = A.x[i], yi = A.y[i], zi = A.z[i];
+        const double hprev = A.h[i];
+        HState st = hs_load(A.H, i);
+        uint8_t fl = 0;
+        int res = 0;
+        while (res == 0) {
+            const double hc = st.next;
+            int N = count_fill<PM>(S, A.x, A.y, A.z, i, xi, yi, zi, hc, A.idx, A.stride, A.K,
+                                   true, tested);
+            ++counts;
+            res = h_update(st, hc, N, hprev, A.target, A.tol, A.maxit, A.hk, fl, acc, fallback);
+        }
+        h_finish(st, res, fl, i, A.h, A.nc, A.flags, A.refill, A.K, nonconv, overflow);
+    }
+    block_add_i64(counts, A.status + ST_HCOUNTS);
+    block_add_i64(tested, A.status + ST_CANDIDATES);
+    block_add_i64(nonconv, A.status + ST_NONCONV);
+    block_add_i64(overflow, A.status + ST_LIST_OVERFLOW);
+    if (A.h_try) {
+        block_add_i64(acc, A.status + ST_LEARN_ACC);
+        block_add_i64(fallback, A.status + ST_LEARN_FALLBACK);
     }
 }
 
@@ -435,6 +709,8 @@ __global__ __launch_bounds__(SPH_BLOCK) void k_refill(
     block_add_i64(overflow, status + ST_LIST_OVERFLOW);
 }
 
+#define SPH_WAVE_ROUNDS 3
+
 hipError_t launch_hsolve(sph_ctx *c, sph_particles *s, sph_nlist *nl, const double *h_try)
 {
     int64_t n = s->n;
@@ -443,16 +719,56 @@ hipError_t launch_hsolve(sph_ctx *c, sph_particles *s, sph_nlist *nl, const doub
     int cur = s->cur;
     unsigned nb = (unsigned)ceil_div(n, SPH_BLOCK);
     Geo g = make_geo(p);
-    SPH_DISPATCH_PM(periodic_mask(g),
-        hipLaunchKernelGGL(k_hsolve<PM>, dim3(nb), dim3(SPH_BLOCK), 0, c->stream, n, s->x[cur],
-                           s->y[cur], s->z[cur], s->key, s->h[cur], s->nc[cur], s->flags,
-                           c->w.refill, nl->idx, nl->stride, p.list_stride, c->w.cell_start,
-                           c->w.bbox, g, p.max_level, p.search_div, c->w.hk, p.n_target, p.n_tol,
-                           p.h_max_iter, h_try, c->w.status);
-        hipLaunchKernelGGL(k_refill<PM>, dim3(nb), dim3(SPH_BLOCK), 0, c->stream, n, s->x[cur],
-                           s->y[cur], s->z[cur], s->h[cur], s->nc[cur], c->w.refill, nl->idx,
-                           nl->stride, p.list_stride, c->w.cell_start, c->w.bbox, g, p.max_level,
-                           1, c->w.status))
+    HArgs A;
+    A.x = s->x[cur]; A.y = s->y[cur]; A.z = s->z[cur];
+    A.key = s->key;
+    A.h = s->h[cur];
+    A.h_try = h_try;
+    A.nc = s->nc[cur];
+    A.flags = s->flags;
+    A.refill = c->w.refill;
+    A.work = c->w.work;
+    A.idx = nl->idx;
+    A.stride = nl->stride;
+    A.K = p.list_stride;
+    A.cs = c->w.cell_start;
+    A.bbox = c->w.bbox;
+    A.hk = c->w.hk;
+    A.g = g;
+    A.lmax = p.max_level;
+    A.div = p.search_div;
+    A.target = p.n_target;
+    A.tol = p.n_tol;
+    A.maxit = p.h_max_iter;
+    A.H = {c->w.hs_next, c->w.hs_lo, c->w.hs_hi, c->w.hs_best_h, c->w.hs_last_h,
+           c->w.hs_best_n, c->w.hs_itk, c->w.hs_bits};
+    A.SH = {c->w.shell_j, c->w.shell_r2, c->w.shell_stride};
+    A.status = c->w.status;
+    const int pm = periodic_mask(g);
+    SPH_DISPATCH_PM(pm,
+        hipLaunchKernelGGL(k_hsolve_round<PM>, dim3(nb), dim3(SPH_BLOCK), 0, c->stream, A, n,
+                           (const int32_t *)nullptr, (const int64_t *)nullptr))
+    for (int r = 0; r <= SPH_WAVE_ROUNDS; ++r) {
+        hipError_t e = launch_scan_i32_to_i64(c, c->w.work, c->w.woff, n);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(k_compact, dim3(nb), dim3(SPH_BLOCK), 0, c->stream, n, c->w.work,
+                           c->w.woff, c->w.wl);
+        if (r < SPH_WAVE_ROUNDS) {
+            // the worklist size is only known on the device: launch for all
+            // and let waves past its end return at once
+            SPH_DISPATCH_PM(pm,
+                hipLaunchKernelGGL(k_hsolve_round<PM>, dim3(nb), dim3(SPH_BLOCK), 0, c->stream,
+                                   A, n, c->w.wl, c->w.woff + n))
+        } else {
+            SPH_DISPATCH_PM(pm,
+                hipLaunchKernelGGL(k_hsolve_tail<PM>, dim3(nb), dim3(SPH_BLOCK), 0, c->stream, A,
+                                   c->w.wl, c->w.woff + n))
+        }
+    }
+    SPH_DISPATCH_PM(pm,
+        hipLaunchKernelGGL(k_refill<PM>, dim3(nb), dim3(SPH_BLOCK), 0, c->stream, n, A.x, A.y,
+                           A.z, A.h, A.nc, A.refill, A.idx, A.stride, A.K, A.cs, A.bbox, g,
+                           A.lmax, 1, A.status))
     return hipGetLastError();
 }
 

@@ -49,6 +49,14 @@ struct Workspace {
     double *dt_cur;        // 1: dt used by the current step
     double *red_part;      // nb_red * 8 reduction partials
     uint8_t *refill;       // n_max
+    int32_t *work;         // n_max: particles needing the per-particle iteration
+    int64_t *woff;         // n_max + 1: their worklist positions
+    int32_t *wl;           // n_max: the worklist
+    double *hs_next, *hs_lo, *hs_hi, *hs_best_h, *hs_last_h;  // h iteration state, n_max each
+    int32_t *hs_best_n, *hs_itk, *hs_bits;
+    int32_t *shell_j;      // 48 slots per particle, slot-major with shell_stride
+    double *shell_r2;
+    int64_t shell_stride;
     int64_t nb_red;
     int64_t nb_sort;
     int64_t scan_part_len;
