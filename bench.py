@@ -32,6 +32,13 @@ FORCE_FLOPS_PER_PAIR = 67
 HSOLVE_FLOPS_PER_CANDIDATE = 9
 FP64_PEAK_TFLOPS = 78.6
 HBM_PEAK_GBS = 8000.0
+# algorithmic HBM bytes of the force kernel per particle, besides 4 B per list
+# entry: own fields x y z v(3) m h rho P c (88 B), nc and E count (8 B), and
+# the writes a(3) du (32 B); neighbour data are re-reads of those fields
+FORCE_BYTES_PER_PARTICLE = 128
+FORCE_BYTES_PER_ENTRY = 4
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_forces_traffic.json")
+FORCE_SOURCE = os.path.join(ROOT, "paper_1905_03344_amd", "csrc", "physics.hip")
 
 CONFIG_NAMES = {
     1: "square_patch_20^3_8k_fp64",
@@ -64,6 +71,36 @@ def cpu_baseline(config: int):
                       f"after an untimed t=0 evaluation, {dt:.2f} s"}
 
 
+def source_digest(path):
+    import hashlib
+    with open(path, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def measured_traffic():
+    """HBM bytes per k_forces launch from the committed PMC summary, or None
+    when the kernel source changed since the counters were taken."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            t = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if t.get("source_sha256_16") != source_digest(FORCE_SOURCE):
+        return None
+    return t.get("bytes_per_launch")
+
+
+def copy_calibration(nbytes=1 << 30, reps=3):
+    """A plain device copy of known size, for scaling FETCH_SIZE/WRITE_SIZE."""
+    import torch
+    a = torch.empty(nbytes // 8, dtype=torch.float64, device="cuda").fill_(1.0)
+    b = torch.empty_like(a)
+    for _ in range(reps):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes": nbytes, "reps": reps}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -73,7 +110,12 @@ def main():
     ap.add_argument("--form", default="plain", choices=["plain", "mixed", "learned"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--search-div", type=int, default=2)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a 1 GiB device copy (PMC byte-counter calibration)")
     args = ap.parse_args()
+    if args.copy_calibration:
+        copy_calibration()
+        return
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the multi-GPU "
               "decomposition is a design, not part of this build", file=sys.stderr)
@@ -123,13 +165,20 @@ def main():
     stage_ms = {k: v[0] / max(1, args.steps) for k, v in stages.items()}
     force_flops = FORCE_FLOPS_PER_PAIR * pairs
     hs_flops = HSOLVE_FLOPS_PER_CANDIDATE * cand_per_step
-    force_tf = force_flops / (stage_ms["forces"] * 1e-3) / 1e12 if stage_ms["forces"] else 0
+    t_force = stage_ms["forces"] * 1e-3
+    force_tf = force_flops / t_force / 1e12 if t_force else 0
     hs_tf = hs_flops / (stage_ms["hsolve"] * 1e-3) / 1e12 if stage_ms["hsolve"] else 0
-    dominant = max(("hsolve", "forces"), key=lambda k: stage_ms[k])
-    achieved = force_tf if dominant == "forces" else hs_tf
-    roofline = {"bound": "alu", "kernel": "k_forces" if dominant == "forces" else "k_hsolve",
-                "achieved": round(achieved, 3), "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
-                "frac": round(achieved / FP64_PEAK_TFLOPS, 4), "traffic": None}
+    force_bytes = FORCE_BYTES_PER_PARTICLE * n + FORCE_BYTES_PER_ENTRY * pairs
+    force_gbs = force_bytes / t_force / 1e9 if t_force else 0
+    traffic = measured_traffic()
+    # the dominant kernel: k_forces has the longest single launch of the step
+    roofline = {"bound": "alu", "kernel": "k_forces", "achieved": round(force_tf, 3),
+                "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+                "frac": round(force_tf / FP64_PEAK_TFLOPS, 4), "traffic": traffic,
+                "flops_per_launch": force_flops, "launch_ms": round(stage_ms["forces"], 4),
+                "hbm": {"algorithmic_bytes": force_bytes, "achieved": round(force_gbs, 1),
+                        "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                        "frac": round(force_gbs / HBM_PEAK_GBS, 4)}}
     out = {
         "metric": "particle-updates/s per full SPH step",
         "value": value,

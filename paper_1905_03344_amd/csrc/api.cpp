@@ -407,8 +407,11 @@ extern "C" int sph_momentum_energy(sph_ctx *c, sph_particles *s, const sph_nlist
     if (r) return r;
     r = check_nlist(c, s, nl);
     if (r) return r;
-    StageScope scope(c, SPH_STAGE_FORCES);
-    TRY(launch_forces(c, s, nl, d_dt), "forces");
+    {
+        StageScope scope(c, SPH_STAGE_FORCES);
+        TRY(launch_forces(c, s, nl, d_dt), "forces");
+    }
+    TRY(launch_dt_min(c, s->n, d_dt), "dt minimum");
     return SPH_OK;
 }
 
@@ -430,6 +433,7 @@ static int evaluate_sorted(sph_ctx *c, sph_particles *s, sph_nlist *nl, double *
         StageScope scope(c, SPH_STAGE_FORCES);
         TRY(launch_forces(c, s, nl, d_dt), "forces");
     }
+    TRY(launch_dt_min(c, s->n, d_dt), "dt minimum");
     return SPH_OK;
 }
 

@@ -252,8 +252,15 @@ hipError_t launch_forces(sph_ctx *c, sph_particles *s, const sph_nlist *nl, doub
                            s->h[cur], s->rho[cur], s->p, s->c, s->nc[cur], nl->idx, nl->stride,
                            p.list_stride, nl->ecnt, nl->eidx, p.extra_slots, g, p.av_alpha, p.av_beta,
                            p.av_eta2, p.cfl, s->ax[cur], s->ay[cur], s->az[cur], s->du[cur], part))
+    return hipGetLastError();
+}
+
+hipError_t launch_dt_min(sph_ctx *c, int64_t n, double *d_dt)
+{
+    int64_t nb = ceil_div(n > 0 ? n : 1, SPH_BLOCK);
     if (d_dt)
-        hipLaunchKernelGGL(k_min_final, dim3(1), dim3(SPH_BLOCK), 0, c->stream, part, nb, d_dt);
+        hipLaunchKernelGGL(k_min_final, dim3(1), dim3(SPH_BLOCK), 0, c->stream, c->w.red_part, nb,
+                           d_dt);
     return hipGetLastError();
 }
 

@@ -95,6 +95,7 @@ hipError_t launch_density(sph_ctx *c, sph_particles *s, const sph_nlist *nl, boo
 hipError_t launch_zero_i32(sph_ctx *c, int32_t *a, int64_t n);
 hipError_t launch_eos(sph_ctx *c, sph_particles *s);
 hipError_t launch_forces(sph_ctx *c, sph_particles *s, const sph_nlist *nl, double *d_dt);
+hipError_t launch_dt_min(sph_ctx *c, int64_t n, double *d_dt);
 hipError_t launch_kick_drift(sph_ctx *c, sph_particles *s);
 hipError_t launch_predict(sph_ctx *c, sph_particles *s);
 hipError_t launch_kick(sph_ctx *c, sph_particles *s);
