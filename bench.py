@@ -131,7 +131,8 @@ def main():
     log(f"bench: config {args.config}, form {args.form}, building inputs")
     ic = inputs.config_ic(args.config)
     n = ic.n
-    sim = Simulation(ic, search_div=args.search_div)
+    precision = ffi.SPH_FP64 if args.form == "plain" else ffi.SPH_MIXED
+    sim = Simulation(ic, search_div=args.search_div, precision=precision)
     log(f"bench: n={n} max_level={sim.params.max_level} workspace={sim.ws_bytes/2**20:.1f} MiB")
     sim.evaluate()
     sim.sync()

@@ -184,6 +184,7 @@ size_t sph_layout(const sph_params *p, void *base, Workspace *w)
     t.shell_stride = ceil_div(n, 64) * 64;
     t.shell_j = (int32_t *)take(48 * t.shell_stride * sizeof(int32_t));
     t.shell_r2 = (double *)take(48 * t.shell_stride * sizeof(double));
+    t.mixrec = p->precision == SPH_MIXED ? take(n * 64) : nullptr;
     t.nb_red = nb_red;
     t.nb_sort = nb_sort;
     t.scan_part_len = scan_part;
@@ -388,7 +389,8 @@ extern "C" int sph_density(sph_ctx *c, sph_particles *s, const sph_nlist *nl)
     r = check_nlist(c, s, nl);
     if (r) return r;
     StageScope scope(c, SPH_STAGE_DENSITY);
-    TRY(launch_density(c, s, nl, false), "density");
+    if (c->p.precision == SPH_MIXED) TRY(launch_density_mixed(c, s, nl, false), "density (mixed)");
+    else TRY(launch_density(c, s, nl, false), "density");
     return SPH_OK;
 }
 
@@ -397,7 +399,8 @@ extern "C" int sph_eos(sph_ctx *c, sph_particles *s)
     int r = check_particles(c, s);
     if (r) return r;
     StageScope scope(c, SPH_STAGE_EOS);
-    TRY(launch_eos(c, s), "eos");
+    if (c->p.precision == SPH_MIXED) TRY(launch_eos_mixed(c, s), "eos (mixed)");
+    else TRY(launch_eos(c, s), "eos");
     return SPH_OK;
 }
 
@@ -409,7 +412,8 @@ extern "C" int sph_momentum_energy(sph_ctx *c, sph_particles *s, const sph_nlist
     if (r) return r;
     {
         StageScope scope(c, SPH_STAGE_FORCES);
-        TRY(launch_forces(c, s, nl, d_dt), "forces");
+        if (c->p.precision == SPH_MIXED) TRY(launch_forces_mixed(c, s, nl), "forces (mixed)");
+        else TRY(launch_forces(c, s, nl, d_dt), "forces");
     }
     TRY(launch_dt_min(c, s->n, d_dt), "dt minimum");
     return SPH_OK;
@@ -420,18 +424,22 @@ static int evaluate_sorted(sph_ctx *c, sph_particles *s, sph_nlist *nl, double *
 {
     int r = find_neighbors_impl(c, s, nl, nullptr, false);
     if (r) return r;
+    const bool mixed = c->p.precision == SPH_MIXED;
     {
         // density and divergence, with the complement E built in the same pass
         StageScope scope(c, SPH_STAGE_DENSITY);
-        TRY(launch_density(c, s, nl, true), "density");
+        if (mixed) TRY(launch_density_mixed(c, s, nl, true), "density (mixed)");
+        else TRY(launch_density(c, s, nl, true), "density");
     }
     {
         StageScope scope(c, SPH_STAGE_EOS);
-        TRY(launch_eos(c, s), "eos");
+        if (mixed) TRY(launch_eos_mixed(c, s), "eos (mixed)");
+        else TRY(launch_eos(c, s), "eos");
     }
     {
         StageScope scope(c, SPH_STAGE_FORCES);
-        TRY(launch_forces(c, s, nl, d_dt), "forces");
+        if (mixed) TRY(launch_forces_mixed(c, s, nl), "forces (mixed)");
+        else TRY(launch_forces(c, s, nl, d_dt), "forces");
     }
     TRY(launch_dt_min(c, s->n, d_dt), "dt minimum");
     return SPH_OK;

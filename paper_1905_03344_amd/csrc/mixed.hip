@@ -1,0 +1,376 @@
+// Mixed-precision form of the density and force kernels: pair arithmetic in
+// FP32 on cell-relative split coordinates, Neumaier-compensated FP32 sums,
+// results stored in FP64.  Neighbour sets, counts and h come from the exact
+// FP64 search; the one-sided complement test keeps its exact answer through
+// an FP32 prefilter with an FP64 test for the ambiguous band.
+#include "sph_internal.h"
+
+// Per-particle FP32 record, 64 bytes:
+//   a = {delta_x, delta_y, delta_z, cell}   cell = gx | gy << 10 | gz << 20
+//   b = {vx, vy, vz, m}
+//   c = {h, 1/h, rho, P/rho^2}
+//   d = {c_sound, 0, 0, 0}
+// with x = lo + g * w + delta, w = L/1024 the key-cell width.
+struct __align__(16) MixRec {
+    float4 a, b, c, d;
+};
+
+struct MixGeo {
+    float w[3];    // key-cell width per dimension
+    int per[3];
+};
+
+// Neumaier (1974) compensated summation in FP32
+struct NeuF {
+    float s, c;
+};
+__device__ __forceinline__ void neu_add(NeuF &a, float v)
+{
+#pragma clang fp contract(off)
+    float t = a.s + v;
+    a.c += (fabsf(a.s) >= fabsf(v)) ? ((a.s - t) + v) : ((v - t) + a.s);
+    a.s = t;
+}
+__device__ __forceinline__ double neu_val(const NeuF &a) { return (double)a.s + (double)a.c; }
+
+__device__ __forceinline__ uint32_t cell_of(float4 a) { return __float_as_uint(a.w); }
+
+// offset x_j - x_i in dimension D from split coordinates (wrap on the
+// integer cell difference in periodic dimensions)
+template <int PM, int D>
+__device__ __forceinline__ float split_diff(uint32_t gi, uint32_t gj, float di, float dj,
+                                            const MixGeo &G)
+{
+    int ci = (int)((gi >> (10 * D)) & 1023u), cj = (int)((gj >> (10 * D)) & 1023u);
+    int dg = cj - ci;
+    if constexpr (((PM >> D) & 1) != 0) {
+        dg = dg > 512 ? dg - 1024 : (dg < -512 ? dg + 1024 : dg);
+    }
+    return (float)dg * G.w[D] + (dj - di);
+}
+
+// M4 kernel and derivative in FP32
+__device__ __forceinline__ float kern_w_f(float r, float inv_h)
+{
+    float q = r * inv_h;
+    float norm = (float)(1.0 / SPH_PI) * inv_h * inv_h * inv_h;
+    float w;
+    if (q < 1.0f) w = 1.0f - 1.5f * q * q + 0.75f * q * q * q;
+    else if (q < 2.0f) { float t = 2.0f - q; w = 0.25f * t * t * t; }
+    else w = 0.0f;
+    return norm * w;
+}
+__device__ __forceinline__ float kern_dwdr_f(float r, float inv_h)
+{
+    float q = r * inv_h;
+    float ih2 = inv_h * inv_h;
+    float norm = (float)(1.0 / SPH_PI) * ih2 * ih2;
+    float w;
+    if (q < 1.0f) w = q * (-3.0f + 2.25f * q);
+    else if (q < 2.0f) { float t = 2.0f - q; w = -0.75f * t * t; }
+    else w = 0.0f;
+    return norm * w;
+}
+
+// ---------------------------------------------------------------------------
+// pack: split coordinates, FP32 velocity (the predicted one), m, h, 1/h
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(SPH_BLOCK) void k_pack_mixed(
+    int64_t n, const double *__restrict__ x, const double *__restrict__ y,
+    const double *__restrict__ z, const double *__restrict__ vx, const double *__restrict__ vy,
+    const double *__restrict__ vz, const double *__restrict__ m, const double *__restrict__ h,
+    const double *__restrict__ bbox, MixRec *__restrict__ rec)
+{
+    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const double p[3] = {x[i], y[i], z[i]};
+    uint32_t cell = 0;
+    float dl[3];
+    for (int d = 0; d < 3; ++d) {
+        double lo = bbox[d], L = bbox[3 + d] - lo;
+        int g = cell10(p[d], lo, L);
+        double w = L / 1024.0;
+        dl[d] = (float)((p[d] - lo) - (double)g * w);
+        cell |= (uint32_t)g << (10 * d);
+    }
+    MixRec r;
+    r.a = make_float4(dl[0], dl[1], dl[2], __uint_as_float(cell));
+    r.b = make_float4((float)vx[i], (float)vy[i], (float)vz[i], (float)m[i]);
+    double hi = h[i];
+    r.c = make_float4((float)hi, (float)(1.0 / hi), 0.0f, 0.0f);
+    r.d = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    rec[i] = r;
+}
+
+// ---------------------------------------------------------------------------
+// density and divergence in FP32; complement E via prefilter + exact test
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ MixGeo mix_geo(const double *__restrict__ bbox, const Geo &g)
+{
+    MixGeo G;
+    for (int d = 0; d < 3; ++d) {
+        G.w[d] = (float)((bbox[3 + d] - bbox[d]) / 1024.0);
+        G.per[d] = g.per[d];
+    }
+    return G;
+}
+
+template <int PM, bool EXTRA>
+__global__ __launch_bounds__(SPH_BLOCK) void k_density_mixed(
+    int64_t n, const MixRec *__restrict__ rec, const int32_t *__restrict__ nc,
+    const int32_t *__restrict__ idx, int64_t stride, int K, const double *__restrict__ bbox, Geo g,
+    const double *__restrict__ x, const double *__restrict__ y, const double *__restrict__ z,
+    const double *__restrict__ h, double *__restrict__ rho, double *__restrict__ divv,
+    int32_t *__restrict__ ecnt, int32_t *__restrict__ eidx, int slots,
+    int64_t *__restrict__ status)
+{
+    int64_t i = global_index();
+    int64_t appended = 0, dropped = 0;
+    const MixGeo G = mix_geo(bbox, g);
+    if (i < n) {
+        const MixRec ri = rec[i];
+        const uint32_t gi = cell_of(ri.a);
+        const float inv_h = ri.c.y;
+        NeuF s = {ri.b.w * kern_w_f(0.0f, inv_h), 0.0f};
+        NeuF dv = {0.0f, 0.0f};
+        int cnt = min(nc[i], K);
+        for (int k = 0; k < cnt; ++k) {
+            const int j = idx[(int64_t)k * stride + i];
+            const float4 aj = rec[j].a;
+            const float4 bj = rec[j].b;
+            const uint32_t gj = cell_of(aj);
+            float dx = split_diff<PM, 0>(gi, gj, ri.a.x, aj.x, G);
+            float dy = split_diff<PM, 1>(gi, gj, ri.a.y, aj.y, G);
+            float dz = split_diff<PM, 2>(gi, gj, ri.a.z, aj.z, G);
+            float r2 = dx * dx + dy * dy + dz * dz;
+            if (EXTRA) {
+                // is i outside j's gather sphere?  FP32 decides clear cases
+                // (|error| of r2 is below 1e-6 relative), FP64 the band
+                const float hj = rec[j].c.x;
+                const float lim = 4.0f * hj * hj;
+                bool outside;
+                if (r2 > lim * (1.0f + 1e-5f)) {
+                    outside = true;
+                } else if (r2 < lim * (1.0f - 1e-5f)) {
+                    outside = false;
+                } else {
+#pragma clang fp contract(off)
+                    double ex = mimg<PM, 0>(x[i], x[j], g), ey = mimg<PM, 1>(y[i], y[j], g),
+                           ez = mimg<PM, 2>(z[i], z[j], g);
+                    double e2 = exact_r2(ex, ey, ez);
+                    double twoh = 2.0 * h[j];
+                    outside = !(e2 < twoh * twoh);
+                }
+                if (outside) extra_append(j, (int)i, ecnt, eidx, stride, slots, appended, dropped);
+            }
+            float r = sqrtf(r2);
+            const float mj = bj.w;
+            neu_add(s, mj * kern_w_f(r, inv_h));
+            if (r > 0.0f) {
+                float gw = kern_dwdr_f(r, inv_h) / r;
+                float vdot = (bj.x - ri.b.x) * (-dx) + (bj.y - ri.b.y) * (-dy) + (bj.z - ri.b.z) * (-dz);
+                neu_add(dv, mj * vdot * gw);
+            }
+        }
+        double sd = neu_val(s);
+        rho[i] = sd;
+        divv[i] = neu_val(dv) / sd;
+    }
+    if (EXTRA) {
+        block_add_i64(appended, status + ST_EXTRA_TOTAL);
+        block_add_i64(dropped, status + ST_EXTRA_OVERFLOW);
+    }
+}
+
+// EOS in FP64 (as the plain form) and the FP32 force fields of the record
+__global__ __launch_bounds__(SPH_BLOCK) void k_eos_mixed(int64_t n, const double *__restrict__ rho,
+                                                         const double *__restrict__ u, double gamma,
+                                                         double *__restrict__ p,
+                                                         double *__restrict__ c,
+                                                         MixRec *__restrict__ rec, int check,
+                                                         int64_t *__restrict__ status)
+{
+    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    int64_t bad = 0;
+    if (i < n) {
+        double rh = rho[i];
+        double pv = (gamma - 1.0) * rh * u[i];
+        double cv = sqrt(gamma * (gamma - 1.0) * u[i]);
+        p[i] = pv;
+        c[i] = cv;
+        rec[i].c.z = (float)rh;
+        rec[i].c.w = (float)(pv / (rh * rh));
+        rec[i].d.x = (float)cv;
+        if (check && !(isfinite(pv) && isfinite(cv) && isfinite(rh))) bad = 1;
+    }
+    if (check) block_add_i64(bad, status + ST_NONFINITE);
+}
+
+// ---------------------------------------------------------------------------
+// momentum, energy, viscosity and Courant step in FP32
+// ---------------------------------------------------------------------------
+struct ForceAccF {
+    NeuF ax, ay, az, du;
+    float mumax;
+};
+
+template <int PM>
+__device__ __forceinline__ void force_pair_f(const MixRec &ri, uint32_t gi, int j,
+                                             const MixRec *__restrict__ rec, const MixGeo &G,
+                                             float alpha, float beta, float eta2, ForceAccF &A)
+{
+    const MixRec rj = rec[j];
+    const uint32_t gj = cell_of(rj.a);
+    float dx = split_diff<PM, 0>(gi, gj, ri.a.x, rj.a.x, G);
+    float dy = split_diff<PM, 1>(gi, gj, ri.a.y, rj.a.y, G);
+    float dz = split_diff<PM, 2>(gi, gj, ri.a.z, rj.a.z, G);
+    float r2 = dx * dx + dy * dy + dz * dz;
+    if (!(r2 > 0.0f)) return;
+    float inv_r = rsqrtf(r2);
+    float r = r2 * inv_r;
+    float xij = -dx, yij = -dy, zij = -dz;
+    float vxij = ri.b.x - rj.b.x, vyij = ri.b.y - rj.b.y, vzij = ri.b.z - rj.b.z;
+    float w = vxij * xij + vyij * yij + vzij * zij;
+    float gwi = kern_dwdr_f(r, ri.c.y) * inv_r;
+    float gwj = kern_dwdr_f(r, rj.c.y) * inv_r;
+    float gbar = 0.5f * (gwi + gwj);
+    float Pi = 0.0f;
+    if (w < 0.0f) {
+        float hb = 0.5f * (ri.c.x + rj.c.x);
+        float cb = 0.5f * (ri.d.x + rj.d.x);
+        float rb = 0.5f * (ri.c.z + rj.c.z);
+        float mu = hb * w / (r2 + eta2 * hb * hb);
+        Pi = (-alpha * cb * mu + beta * mu * mu) / rb;
+        A.mumax = fmaxf(A.mumax, fabsf(mu));
+    }
+    float sfac = (ri.c.w + rj.c.w) + Pi;
+    float mj = rj.b.w;
+    float f = mj * sfac * gbar;
+    neu_add(A.ax, -f * xij);
+    neu_add(A.ay, -f * yij);
+    neu_add(A.az, -f * zij);
+    neu_add(A.du, mj * (ri.c.w + 0.5f * Pi) * gbar * w);
+}
+
+template <int PM>
+__global__ __launch_bounds__(SPH_BLOCK) void k_forces_mixed(
+    int64_t n, const MixRec *__restrict__ rec, const int32_t *__restrict__ nc,
+    const int32_t *__restrict__ idx, int64_t stride, int K, const int32_t *__restrict__ ecnt,
+    const int32_t *__restrict__ eidx, int slots, const double *__restrict__ bbox, Geo g,
+    float alpha, float beta, float eta2, double alpha_d, double beta_d, double cfl,
+    const double *__restrict__ h,
+    const double *__restrict__ c, double *__restrict__ ax, double *__restrict__ ay,
+    double *__restrict__ az, double *__restrict__ du, double *__restrict__ dt_part)
+{
+    int64_t i = global_index();
+    double dti = INFINITY;
+    const MixGeo G = mix_geo(bbox, g);
+    if (i < n) {
+        const MixRec ri = rec[i];
+        const uint32_t gi = cell_of(ri.a);
+        ForceAccF A = {{0.f, 0.f}, {0.f, 0.f}, {0.f, 0.f}, {0.f, 0.f}, 0.f};
+        int cnt = min(nc[i], K);
+        for (int k = 0; k < cnt; ++k)
+            force_pair_f<PM>(ri, gi, idx[(int64_t)k * stride + i], rec, G, alpha, beta, eta2, A);
+        const int ne = min(ecnt[i], slots);
+        int last = -1;
+        for (int q = 0; q < ne; ++q) {
+            int nxt = 0x7fffffff;
+            for (int k = 0; k < ne; ++k) {
+                int v = eidx[(int64_t)k * stride + i];
+                nxt = (v > last && v < nxt) ? v : nxt;
+            }
+            last = nxt;
+            force_pair_f<PM>(ri, gi, nxt, rec, G, alpha, beta, eta2, A);
+        }
+        ax[i] = neu_val(A.ax);
+        ay[i] = neu_val(A.ay);
+        az[i] = neu_val(A.az);
+        du[i] = neu_val(A.du);
+        double ci = c[i];
+        dti = cfl * h[i] / (ci + 1.2 * (alpha_d * ci + beta_d * (double)A.mumax));
+    }
+    __shared__ double sh[SPH_BLOCK];
+    sh[threadIdx.x] = dti;
+    __syncthreads();
+    for (int s = SPH_BLOCK / 2; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) sh[threadIdx.x] = fmin(sh[threadIdx.x], sh[threadIdx.x + s]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) dt_part[blockIdx.x] = sh[0];
+}
+
+// ---------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------
+hipError_t launch_pack_mixed(sph_ctx *c, sph_particles *s)
+{
+    int64_t n = s->n;
+    if (n == 0) return hipSuccess;
+    int k = s->cur;
+    hipLaunchKernelGGL(k_pack_mixed, dim3((unsigned)ceil_div(n, SPH_BLOCK)), dim3(SPH_BLOCK), 0,
+                       c->stream, n, s->x[k], s->y[k], s->z[k], s->pvx, s->pvy, s->pvz, s->m[k],
+                       s->h[k], c->w.bbox, (MixRec *)c->w.mixrec);
+    return hipGetLastError();
+}
+
+hipError_t launch_density_mixed(sph_ctx *c, sph_particles *s, const sph_nlist *nl,
+                                bool build_extra)
+{
+    int64_t n = s->n;
+    if (build_extra) {
+        hipError_t e = launch_zero_i32(c, nl->ecnt, n);
+        if (e != hipSuccess) return e;
+    }
+    if (n == 0) return hipSuccess;
+    hipError_t e = launch_pack_mixed(c, s);
+    if (e != hipSuccess) return e;
+    int cur = s->cur;
+    Geo g = make_geo(c->p);
+    unsigned nb = (unsigned)ceil_div(n, SPH_BLOCK);
+    const MixRec *rec = (const MixRec *)c->w.mixrec;
+    if (build_extra) {
+        SPH_DISPATCH_PM(periodic_mask(g),
+            hipLaunchKernelGGL((k_density_mixed<PM, true>), dim3(nb), dim3(SPH_BLOCK), 0,
+                               c->stream, n, rec, s->nc[cur], nl->idx, nl->stride,
+                               c->p.list_stride, c->w.bbox, g, s->x[cur], s->y[cur], s->z[cur], s->h[cur],
+                               s->rho[cur], s->divv[cur], nl->ecnt, nl->eidx, c->p.extra_slots,
+                               c->w.status))
+    } else {
+        SPH_DISPATCH_PM(periodic_mask(g),
+            hipLaunchKernelGGL((k_density_mixed<PM, false>), dim3(nb), dim3(SPH_BLOCK), 0,
+                               c->stream, n, rec, s->nc[cur], nl->idx, nl->stride,
+                               c->p.list_stride, c->w.bbox, g, s->x[cur], s->y[cur], s->z[cur], s->h[cur],
+                               s->rho[cur], s->divv[cur], nl->ecnt, nl->eidx, c->p.extra_slots,
+                               c->w.status))
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_eos_mixed(sph_ctx *c, sph_particles *s)
+{
+    int64_t n = s->n;
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_eos_mixed, dim3((unsigned)ceil_div(n, SPH_BLOCK)), dim3(SPH_BLOCK), 0,
+                       c->stream, n, s->rho[s->cur], s->pu, c->p.gamma, s->p, s->c,
+                       (MixRec *)c->w.mixrec, c->p.check_finite, c->w.status);
+    return hipGetLastError();
+}
+
+hipError_t launch_forces_mixed(sph_ctx *c, sph_particles *s, const sph_nlist *nl)
+{
+    int64_t n = s->n;
+    int cur = s->cur;
+    const sph_params &p = c->p;
+    int64_t nb = ceil_div(n > 0 ? n : 1, SPH_BLOCK);
+    Geo g = make_geo(p);
+    SPH_DISPATCH_PM(periodic_mask(g),
+        hipLaunchKernelGGL(k_forces_mixed<PM>, dim3((unsigned)nb), dim3(SPH_BLOCK), 0, c->stream,
+                           n, (const MixRec *)c->w.mixrec, s->nc[cur], nl->idx, nl->stride,
+                           p.list_stride, nl->ecnt, nl->eidx, p.extra_slots, c->w.bbox, g,
+                           (float)p.av_alpha,
+                           (float)p.av_beta, (float)p.av_eta2, p.av_alpha, p.av_beta, p.cfl,
+                           s->h[cur], s->c, s->ax[cur], s->ay[cur], s->az[cur], s->du[cur],
+                           c->w.red_part))
+    return hipGetLastError();
+}

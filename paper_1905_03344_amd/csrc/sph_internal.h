@@ -57,6 +57,7 @@ struct Workspace {
     int32_t *shell_j;      // 48 slots per particle, slot-major with shell_stride
     double *shell_r2;
     int64_t shell_stride;
+    void *mixrec;          // n_max records of 64 bytes (mixed form)
     int64_t nb_red;
     int64_t nb_sort;
     int64_t scan_part_len;
@@ -96,6 +97,11 @@ hipError_t launch_zero_i32(sph_ctx *c, int32_t *a, int64_t n);
 hipError_t launch_eos(sph_ctx *c, sph_particles *s);
 hipError_t launch_forces(sph_ctx *c, sph_particles *s, const sph_nlist *nl, double *d_dt);
 hipError_t launch_dt_min(sph_ctx *c, int64_t n, double *d_dt);
+hipError_t launch_pack_mixed(sph_ctx *c, sph_particles *s);
+hipError_t launch_density_mixed(sph_ctx *c, sph_particles *s, const sph_nlist *nl,
+                                bool build_extra);
+hipError_t launch_eos_mixed(sph_ctx *c, sph_particles *s);
+hipError_t launch_forces_mixed(sph_ctx *c, sph_particles *s, const sph_nlist *nl);
 hipError_t launch_kick_drift(sph_ctx *c, sph_particles *s);
 hipError_t launch_predict(sph_ctx *c, sph_particles *s);
 hipError_t launch_kick(sph_ctx *c, sph_particles *s);
