@@ -220,7 +220,7 @@ int sph_copy_internal(sph_ctx *ctx, int which, void *dst, size_t bytes, size_t *
  * stage of every subsequent call (overhead: two event records per stage).
  * Stages: SPH_STAGE_CELLS (A1-A4), _HSOLVE (A5 and the gather sets),
  * _EXTRA (complement E), _DENSITY (A7), _EOS (A8), _FORCES (A9 + dt),
- * _INTEGRATE (A10 kicks, drift, prediction). */
+ * _INTEGRATE (A10 kicks, drift, prediction), _MLP (learned h prediction). */
 #define SPH_STAGE_CELLS 0
 #define SPH_STAGE_HSOLVE 1
 #define SPH_STAGE_EXTRA 2
@@ -228,7 +228,8 @@ int sph_copy_internal(sph_ctx *ctx, int which, void *dst, size_t bytes, size_t *
 #define SPH_STAGE_EOS 4
 #define SPH_STAGE_FORCES 5
 #define SPH_STAGE_INTEGRATE 6
-#define SPH_NSTAGES 7
+#define SPH_STAGE_MLP 7          /* learned mode: feature build + MLP inference */
+#define SPH_NSTAGES 8
 
 /* enable = 1 clears the accumulators and starts recording; 0 stops. */
 int sph_timing(sph_ctx *ctx, int enable);
@@ -237,6 +238,99 @@ int sph_timing(sph_ctx *ctx, int enable);
  * (ms[k]) and the number of timed intervals (count[k]) of each stage k <
  * nstages since timing was enabled.  Either pointer may be NULL. */
 int sph_timing_read(sph_ctx *ctx, double *ms, int64_t *count, int nstages);
+
+/* ------------------------------------------------------------------------
+ * Learned smoothing length (production form: h_mode = SPH_H_LEARNED).
+ *
+ * The paper's h update is an iteration towards a target neighbour count
+ * (section "Co-Design of the Mini-App", the smoothing-length step of the
+ * per-timestep loop); this form predicts its outcome.  A 6-64-64-1 MLP with
+ * tanh hidden layers maps the standardised features of particle i,
+ *   f1 = log h_i, f2 = N_i/100 - 1, f3 = log(rho_i h_i^3 / m_i),
+ *   f4 = dt (div v)_i, f5 = dt |v_i| / h_i, f6 = dt c_i / h_i,
+ * taken from the previous evaluation (h, N, rho, div v) and the predicted
+ * state of this step (v = pv, c = sqrt(gamma (gamma-1) pu), dt of the step),
+ * to y ~ log(h_c / h_i), h_c the centre of the band of solutions (targets
+ * below).  In sph_step (and sph_find_neighbors) the first
+ * count of particle i is taken at h_i exp(clamp(y, -1/2, 1/2)); within
+ * n_tol of n_target it is accepted (SPH_FLAG_LEARNED), otherwise the plain
+ * iteration runs from h_i exactly as in SPH_H_PLAIN.  sph_evaluate always
+ * uses the plain iteration (no previous evaluation to take features from).
+ *
+ * Numerics: features in FP64, rounded to FP32, standardised in FP64
+ * z = (f - mean)/std and rounded to bfloat16 (round to nearest even).
+ * Weights bfloat16, biases FP32, products summed in FP32 (MFMA), tanh in
+ * FP32, hidden activations rounded to bfloat16 before the next layer.
+ *
+ * Parameters: SPH_MLP_NPARAM floats, [out][in] row-major,
+ *   W1[64][6] at 0, b1[64] at 384, W2[64][64] at 448, b2[64] at 4544,
+ *   W3[64] at 4608, b3 at 4672.
+ * They live in the bound workspace (FP32 master, bf16 copy, Adam moments,
+ * the 12 standardisation constants); binding again clears them.
+ * Feature rows are SPH_MLP_NFEAT floats: f1..f6 and two zeros.
+ * ------------------------------------------------------------------------ */
+#define SPH_MLP_NPARAM 4673
+#define SPH_MLP_NFEAT 8
+
+/* Upload FP32 parameters (host array of SPH_MLP_NPARAM) and the
+ * standardisation constants (host array mean[6], std[6], std > 0; NULL keeps
+ * the current ones, zeros and ones after a bind).  Clears the Adam moments
+ * and step counter.  Synchronous.  SPH_EINVAL for NULL params or std <= 0. */
+int sph_mlp_set_weights(sph_ctx *ctx, const float *params, const double *norm12);
+
+/* Download the FP32 parameters and the standardisation constants to host
+ * arrays (either may be NULL).  Synchronous.  SPH_EINVAL before any
+ * sph_mlp_set_weights since the bind. */
+int sph_mlp_get_weights(sph_ctx *ctx, float *params, double *norm12);
+
+/* Set the standardisation constants from n >= 1 device feature rows: FP64
+ * mean and population standard deviation of each feature (1 where it is 0),
+ * summed in a fixed order. */
+int sph_mlp_fit_norm(sph_ctx *ctx, const float *d_feat, int64_t n);
+
+/* Feature rows [n][SPH_MLP_NFEAT] of the current buffer of *s into d_feat,
+ * with dt read from the device scalar *d_dt and v, u from pv, pu. */
+int sph_get_features(sph_ctx *ctx, const sph_particles *s, const double *d_dt, float *d_feat);
+
+/* Training sink: while set (both non-NULL), every sph_step writes, in the
+ * particle order of that step, the feature rows of its start into
+ * d_feat[n][SPH_MLP_NFEAT] and the targets into d_target[n] (n = particles
+ * of the step; device arrays of at least n_max rows).  The target is
+ * log(h_c) - f1 with h_c = h_new (n_target / N_new)^(1/3): the solved h moved
+ * to the centre of the band by the h^3 scaling of the count (N_new > 0).
+ * NULL, NULL turns it off. */
+int sph_set_harvest(sph_ctx *ctx, float *d_feat, float *d_target);
+
+/* Inference on n device feature rows: y[n] (device), and, when non-NULL,
+ * the bfloat16 bit patterns of the two hidden layers' rounded activations
+ * d_h1[n][64], d_h2[n][64] (for checking). */
+int sph_mlp_forward(sph_ctx *ctx, const float *d_feat, int64_t n, float *d_y, uint16_t *d_h1,
+                    uint16_t *d_h2);
+
+/* Mean squared error L = (1/n) sum_p (y_p - t_p)^2 over batch rows
+ * p = d_rows[row0 + k], k < n (d_rows NULL: p = row0 + k), and its gradient
+ * with respect to every parameter (chain rule; the bfloat16 roundings taken
+ * as identity).  d_grad (device, SPH_MLP_NPARAM + 1 floats) receives the
+ * gradient in parameter order and L last.  Per-wave partials are reduced in
+ * a fixed order, so the result is reproducible. */
+int sph_mlp_backward(sph_ctx *ctx, const float *d_feat, const float *d_target,
+                     const int32_t *d_rows, int64_t row0, int64_t n, float *d_grad);
+
+/* One Adam step (Kingma & Ba 2015), step number t >= 1, on the FP32 master
+ * parameters with gradient d_grad (device); the bfloat16 copy is refreshed
+ * with round to nearest even. */
+int sph_mlp_adam_step(sph_ctx *ctx, const float *d_grad, double lr, double beta1, double beta2,
+                      double eps, int32_t t);
+
+/* Epoch loop on the device: for each of `epochs` passes over the n rows in
+ * the order d_order (device, n indices; NULL = 0..n-1), batches of `batch`
+ * consecutive entries (the last may be short): sph_mlp_backward, then Adam
+ * (beta 0.9, 0.999, eps 1e-8) with the context's step counter.  d_loss
+ * (device, epochs * ceil(n/batch) floats, or NULL) receives each batch's
+ * loss. */
+int sph_mlp_train(sph_ctx *ctx, const float *d_feat, const float *d_target,
+                  const int32_t *d_order, int64_t n, int32_t batch, int32_t epochs, double lr,
+                  float *d_loss);
 
 #ifdef __cplusplus
 }

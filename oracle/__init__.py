@@ -284,6 +284,10 @@ class State:
         self.flags = None
         self.nonconv = 0
         self.keep_gather = False
+        # smoothing lengths to evaluate at instead of solving for them (in
+        # the order after the next sort); used to check a form that chose
+        # its own in-band h against these same stages at that h
+        self.h_given = None
 
     @property
     def n(self):
@@ -307,9 +311,16 @@ class State:
 
     def find_neighbors(self, method=1):
         f = self.f
-        h, nc, flag, iters, nonconv = hsolve(f["x"], f["y"], f["z"], f["h"], *self.geom(),
-                                             self.p.n_target, self.p.n_tol, self.p.max_iter,
-                                             method)
+        if self.h_given is not None:
+            h = _f64(self.h_given).copy()
+            nc = count(f["x"], f["y"], f["z"], h, *self.geom(), method)
+            flag = np.zeros(self.n, dtype=np.uint8)
+            iters, nonconv = np.zeros(self.n, dtype=np.int32), 0
+            self.h_given = None
+        else:
+            h, nc, flag, iters, nonconv = hsolve(f["x"], f["y"], f["z"], f["h"], *self.geom(),
+                                                 self.p.n_target, self.p.n_tol, self.p.max_iter,
+                                                 method)
         f["h"], f["nc"] = h, nc
         self.flags, self.iters, self.nonconv = flag, iters, nonconv
         self.off, self.idx = lists(f["x"], f["y"], f["z"], h, *self.geom(), method)

@@ -185,6 +185,14 @@ size_t sph_layout(const sph_params *p, void *base, Workspace *w)
     t.shell_j = (int32_t *)take(48 * t.shell_stride * sizeof(int32_t));
     t.shell_r2 = (double *)take(48 * t.shell_stride * sizeof(double));
     t.mixrec = p->precision == SPH_MIXED ? take(n * 64) : nullptr;
+    t.mlp_master = (float *)take(SPH_MLP_ROW * sizeof(float));
+    t.mlp_m = (float *)take(SPH_MLP_ROW * sizeof(float));
+    t.mlp_v = (float *)take(SPH_MLP_ROW * sizeof(float));
+    t.mlp_grad = (float *)take(SPH_MLP_ROW * sizeof(float));
+    t.mlp_wb = (uint16_t *)take(SPH_MLP_ROW * sizeof(uint16_t));
+    t.mlp_norm = (double *)take(12 * sizeof(double));
+    t.mlp_part = (float *)take((size_t)SPH_MLP_TRAIN_WAVES * SPH_MLP_ROW * sizeof(float));
+    t.h_try = p->h_mode == SPH_H_LEARNED ? (double *)take(n * sizeof(double)) : nullptr;
     t.nb_red = nb_red;
     t.nb_sort = nb_sort;
     t.scan_part_len = scan_part;
@@ -298,6 +306,24 @@ extern "C" int sph_bind(sph_ctx *c, void *workspace, size_t bytes, void *stream)
     r = hip_check(c, hipMemsetAsync(c->w.status, 0, ST_COUNT * sizeof(int64_t), c->stream),
                   "clear status");
     if (r) return r;
+    r = hip_check(c, hipMemsetAsync(c->w.dt_cur, 0, sizeof(double), c->stream), "clear dt");
+    if (r) return r;
+    // MLP state: zero parameters and moments, standardisation (0, 1)
+    const double norm0[12] = {0, 0, 0, 0, 0, 0, 1, 1, 1, 1, 1, 1};
+    r = hip_check(c, hipMemcpyAsync(c->w.mlp_norm, norm0, sizeof(norm0), hipMemcpyHostToDevice,
+                                    c->stream), "upload standardisation");
+    if (r) return r;
+    for (float *q : {c->w.mlp_master, c->w.mlp_m, c->w.mlp_v, c->w.mlp_grad}) {
+        r = hip_check(c, hipMemsetAsync(q, 0, SPH_MLP_ROW * sizeof(float), c->stream), "clear MLP");
+        if (r) return r;
+    }
+    r = hip_check(c, hipMemsetAsync(c->w.mlp_wb, 0, SPH_MLP_ROW * sizeof(uint16_t), c->stream),
+                  "clear MLP");
+    if (r) return r;
+    c->mlp_ready = 0;
+    c->mlp_t = 0;
+    c->harvest_feat = nullptr;
+    c->harvest_target = nullptr;
     // the factor table lives in a host array: wait for the copy
     r = hip_check(c, hipStreamSynchronize(c->stream), "bind");
     if (r) return r;
@@ -373,13 +399,28 @@ static int find_neighbors_impl(sph_ctx *c, sph_particles *s, sph_nlist *nl, cons
     return SPH_OK;
 }
 
+// learned mode: predicted smoothing lengths of this step into w.h_try
+static int mlp_predict(sph_ctx *c, sph_particles *s, const double **h_try)
+{
+    *h_try = nullptr;
+    if (c->p.h_mode != SPH_H_LEARNED) return SPH_OK;
+    if (!c->mlp_ready) return set_err(c, SPH_EINVAL, "learned h mode: no MLP weights set");
+    StageScope scope(c, SPH_STAGE_MLP);
+    TRY(launch_mlp_predict(c, s, c->w.h_try), "MLP prediction");
+    *h_try = c->w.h_try;
+    return SPH_OK;
+}
+
 extern "C" int sph_find_neighbors(sph_ctx *c, sph_particles *s, sph_nlist *nl)
 {
     int r = check_particles(c, s);
     if (r) return r;
     r = check_nlist(c, s, nl);
     if (r) return r;
-    return find_neighbors_impl(c, s, nl, nullptr, true);
+    const double *h_try = nullptr;
+    r = mlp_predict(c, s, &h_try);
+    if (r) return r;
+    return find_neighbors_impl(c, s, nl, h_try, true);
 }
 
 extern "C" int sph_density(sph_ctx *c, sph_particles *s, const sph_nlist *nl)
@@ -420,9 +461,10 @@ extern "C" int sph_momentum_energy(sph_ctx *c, sph_particles *s, const sph_nlist
 }
 
 // A5-A9 on the sorted state with pv/pu already set
-static int evaluate_sorted(sph_ctx *c, sph_particles *s, sph_nlist *nl, double *d_dt)
+static int evaluate_sorted(sph_ctx *c, sph_particles *s, sph_nlist *nl, double *d_dt,
+                           const double *h_try)
 {
-    int r = find_neighbors_impl(c, s, nl, nullptr, false);
+    int r = find_neighbors_impl(c, s, nl, h_try, false);
     if (r) return r;
     const bool mixed = c->p.precision == SPH_MIXED;
     {
@@ -455,7 +497,7 @@ extern "C" int sph_evaluate(sph_ctx *c, sph_particles *s, sph_nlist *nl, double 
     r = sph_build_cells(c, s);
     if (r) return r;
     TRY(launch_copy_pred(c, s), "copy prediction");
-    return evaluate_sorted(c, s, nl, d_dt);
+    return evaluate_sorted(c, s, nl, d_dt, nullptr);
 }
 
 extern "C" int sph_step(sph_ctx *c, sph_particles *s, sph_nlist *nl, double dt, double *d_dt)
@@ -477,8 +519,19 @@ extern "C" int sph_step(sph_ctx *c, sph_particles *s, sph_nlist *nl, double dt, 
         StageScope scope(c, SPH_STAGE_INTEGRATE);
         TRY(launch_predict(c, s), "predict");
     }
-    r = evaluate_sorted(c, s, nl, d_dt);
+    if (c->harvest_feat) {
+        StageScope scope(c, SPH_STAGE_MLP);
+        TRY(launch_mlp_features(c, s, c->w.dt_cur, c->harvest_feat), "harvest features");
+    }
+    const double *h_try = nullptr;
+    r = mlp_predict(c, s, &h_try);
     if (r) return r;
+    r = evaluate_sorted(c, s, nl, d_dt, h_try);
+    if (r) return r;
+    if (c->harvest_feat) {
+        StageScope scope(c, SPH_STAGE_MLP);
+        TRY(launch_mlp_targets(c, s, c->harvest_feat, c->harvest_target), "harvest targets");
+    }
     {
         StageScope scope(c, SPH_STAGE_INTEGRATE);
         TRY(launch_kick(c, s), "kick");
@@ -544,5 +597,142 @@ extern "C" int sph_copy_internal(sph_ctx *c, int which, void *dst, size_t bytes,
     if (!dst) return SPH_OK;
     if (bytes < sz) return set_err(c, SPH_EINVAL, "destination too small");
     TRY(hipMemcpyAsync(dst, src, sz, hipMemcpyDeviceToDevice, c->stream), "copy internal");
+    return SPH_OK;
+}
+
+// ---------------------------------------------------------------------------
+// learned smoothing length
+// ---------------------------------------------------------------------------
+static int check_bound(sph_ctx *c)
+{
+    if (!c) return SPH_EINVAL;
+    if (!c->bound) return set_err(c, SPH_ENOMEM, "no workspace bound");
+    return SPH_OK;
+}
+
+extern "C" int sph_mlp_set_weights(sph_ctx *c, const float *params, const double *norm12)
+{
+    int r = check_bound(c);
+    if (r) return r;
+    if (!params) return set_err(c, SPH_EINVAL, "params is NULL");
+    if (norm12)
+        for (int k = 0; k < 6; ++k)
+            if (!(norm12[6 + k] > 0.0) || !(norm12[k] == norm12[k]))
+                return set_err(c, SPH_EINVAL, "standardisation std must be positive");
+    TRY(hipMemcpyAsync(c->w.mlp_master, params, SPH_MLP_NPARAM * sizeof(float),
+                       hipMemcpyHostToDevice, c->stream), "upload MLP parameters");
+    if (norm12)
+        TRY(hipMemcpyAsync(c->w.mlp_norm, norm12, 12 * sizeof(double), hipMemcpyHostToDevice,
+                           c->stream), "upload standardisation");
+    TRY(hipMemsetAsync(c->w.mlp_m, 0, SPH_MLP_ROW * sizeof(float), c->stream), "clear Adam");
+    TRY(hipMemsetAsync(c->w.mlp_v, 0, SPH_MLP_ROW * sizeof(float), c->stream), "clear Adam");
+    TRY(launch_mlp_refresh(c), "bf16 copy");
+    TRY(hipStreamSynchronize(c->stream), "sync");   // host sources
+    c->mlp_ready = 1;
+    c->mlp_t = 0;
+    return SPH_OK;
+}
+
+extern "C" int sph_mlp_get_weights(sph_ctx *c, float *params, double *norm12)
+{
+    int r = check_bound(c);
+    if (r) return r;
+    if (!c->mlp_ready) return set_err(c, SPH_EINVAL, "no MLP weights set");
+    TRY(hipStreamSynchronize(c->stream), "sync");
+    if (params)
+        TRY(hipMemcpy(params, c->w.mlp_master, SPH_MLP_NPARAM * sizeof(float),
+                      hipMemcpyDeviceToHost), "download MLP parameters");
+    if (norm12)
+        TRY(hipMemcpy(norm12, c->w.mlp_norm, 12 * sizeof(double), hipMemcpyDeviceToHost),
+            "download standardisation");
+    return SPH_OK;
+}
+
+extern "C" int sph_mlp_fit_norm(sph_ctx *c, const float *d_feat, int64_t n)
+{
+    int r = check_bound(c);
+    if (r) return r;
+    if (!d_feat || n < 1) return set_err(c, SPH_EINVAL, "need n >= 1 feature rows");
+    TRY(launch_mlp_fit_norm(c, d_feat, n), "standardisation");
+    return SPH_OK;
+}
+
+extern "C" int sph_get_features(sph_ctx *c, const sph_particles *s, const double *d_dt,
+                                float *d_feat)
+{
+    int r = check_particles(c, s);
+    if (r) return r;
+    if (!d_dt || (s->n > 0 && !d_feat)) return set_err(c, SPH_EINVAL, "NULL pointer");
+    TRY(launch_mlp_features(c, s, d_dt, d_feat), "features");
+    return SPH_OK;
+}
+
+extern "C" int sph_set_harvest(sph_ctx *c, float *d_feat, float *d_target)
+{
+    int r = check_bound(c);
+    if (r) return r;
+    if ((d_feat == nullptr) != (d_target == nullptr))
+        return set_err(c, SPH_EINVAL, "harvest needs both arrays or neither");
+    c->harvest_feat = d_feat;
+    c->harvest_target = d_target;
+    return SPH_OK;
+}
+
+extern "C" int sph_mlp_forward(sph_ctx *c, const float *d_feat, int64_t n, float *d_y,
+                               uint16_t *d_h1, uint16_t *d_h2)
+{
+    int r = check_bound(c);
+    if (r) return r;
+    if (!c->mlp_ready) return set_err(c, SPH_EINVAL, "no MLP weights set");
+    if (n < 0) return set_err(c, SPH_EINVAL, "n < 0");
+    if (n > 0 && (!d_feat || !d_y)) return set_err(c, SPH_EINVAL, "NULL pointer");
+    TRY(launch_mlp_forward(c, d_feat, n, d_y, d_h1, d_h2), "MLP forward");
+    return SPH_OK;
+}
+
+extern "C" int sph_mlp_backward(sph_ctx *c, const float *d_feat, const float *d_target,
+                                const int32_t *d_rows, int64_t row0, int64_t n, float *d_grad)
+{
+    int r = check_bound(c);
+    if (r) return r;
+    if (!c->mlp_ready) return set_err(c, SPH_EINVAL, "no MLP weights set");
+    if (n < 1 || row0 < 0) return set_err(c, SPH_EINVAL, "need n >= 1 and row0 >= 0");
+    if (!d_feat || !d_target || !d_grad) return set_err(c, SPH_EINVAL, "NULL pointer");
+    TRY(launch_mlp_grad(c, d_feat, d_target, d_rows, row0, n, d_grad, nullptr), "MLP backward");
+    return SPH_OK;
+}
+
+extern "C" int sph_mlp_adam_step(sph_ctx *c, const float *d_grad, double lr, double beta1,
+                                 double beta2, double eps, int32_t t)
+{
+    int r = check_bound(c);
+    if (r) return r;
+    if (!c->mlp_ready) return set_err(c, SPH_EINVAL, "no MLP weights set");
+    if (!d_grad || t < 1) return set_err(c, SPH_EINVAL, "need a gradient and t >= 1");
+    if (!(beta1 >= 0.0 && beta1 < 1.0) || !(beta2 >= 0.0 && beta2 < 1.0) || !(eps > 0.0))
+        return set_err(c, SPH_EINVAL, "Adam constants out of range");
+    TRY(launch_mlp_adam(c, d_grad, lr, beta1, beta2, eps, t), "Adam");
+    return SPH_OK;
+}
+
+extern "C" int sph_mlp_train(sph_ctx *c, const float *d_feat, const float *d_target,
+                             const int32_t *d_order, int64_t n, int32_t batch, int32_t epochs,
+                             double lr, float *d_loss)
+{
+    int r = check_bound(c);
+    if (r) return r;
+    if (!c->mlp_ready) return set_err(c, SPH_EINVAL, "no MLP weights set");
+    if (n < 1 || batch < 1 || epochs < 0) return set_err(c, SPH_EINVAL, "bad sizes");
+    if (!d_feat || !d_target) return set_err(c, SPH_EINVAL, "NULL pointer");
+    const int64_t nb = ceil_div(n, batch);
+    for (int e = 0; e < epochs; ++e)
+        for (int64_t b = 0; b < nb; ++b) {
+            const int64_t row0 = b * batch;
+            const int64_t cnt = n - row0 < batch ? n - row0 : batch;
+            float *lo = d_loss ? d_loss + (int64_t)e * nb + b : nullptr;
+            TRY(launch_mlp_grad(c, d_feat, d_target, d_order, row0, cnt, c->w.mlp_grad, lo),
+                "MLP backward");
+            TRY(launch_mlp_adam(c, c->w.mlp_grad, lr, 0.9, 0.999, 1e-8, ++c->mlp_t), "Adam");
+        }
     return SPH_OK;
 }

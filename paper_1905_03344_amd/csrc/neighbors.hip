@@ -128,8 +128,15 @@ __device__ __forceinline__ int count_fill(const Search &S, const double *__restr
 //   stop when |N - target| <= tol; below the band raise the lower bracket,
 //   above it lower the upper bracket; bisect once both are set, else
 //   h *= T[min(N, 1023)]; at most maxit counts.
-// With h_try (learned mode) the first count is taken at h_try[i]; in band it
-// is accepted, otherwise the plain iteration starts from h[i].
+// With h_try (learned mode) round 0 counts at h_try[i] and accepts it when
+// in the band.  A miss whose plain start h[i] lies inside the try's shell
+// goes on with the plain iteration from h[i] on that shell, as the plain
+// solve's round 0 would; any other miss (also one whose count is unknown
+// because the try's shell overflowed) starts the plain iteration from h[i]
+// in the worklist rounds, which get one round more.  Every particle has the
+// same budget of full walks in the rounds before the per-particle tail, so a
+// miss follows the plain solve's path: cells are walked in Morton order, so
+// its gather set does not depend on which wave counts it.
 // The gather set of the last counted h is written (slot-major); particles
 // whose kept h is not the last counted one are rewritten by k_refill.
 //
@@ -194,7 +201,23 @@ struct WaveLds {
     Cand c[64];
     int start[64];
     int pre[64];
+    int qs[128];   // queue of non-empty cells in Morton order: first particle
+    int ql[128];   // and particle count
 };
+
+// ascending bitonic sort of one value per lane across the wave
+__device__ __forceinline__ uint32_t wave_sort_u32(uint32_t v)
+{
+    const int lane = threadIdx.x & 63;
+    for (int k = 2; k <= 64; k <<= 1)
+        for (int j = k >> 1; j > 0; j >>= 1) {
+            uint32_t o = (uint32_t)__shfl_xor((int)v, j, 64);
+            bool up = (lane & k) == 0;
+            bool lower = (lane & j) == 0;
+            v = (lower == up) ? min(v, o) : max(v, o);
+        }
+    return v;
+}
 
 // hits of one LDS tile for this lane: bit t of *in set when candidate t has
 // r^2 < A (inside the shell), bit t of *sh when A <= r^2 < B (in the shell).
@@ -315,7 +338,7 @@ __device__ int wave_count(WaveLds &L, bool act, int64_t i, double xi, double yi,
             bool ok = true;
             for (int d = 0; d < 3; ++d) {
                 double cw = ldexp(S.L[d], -l);
-                if (S.L[d] > 0.0 && (cw * S.div < Rmax + S.margin || cw * 16.0 < span)) ok = false;
+                if (S.L[d] > 0.0 && (cw * S.div < Rmax + S.margin || cw * 11.0 < span)) ok = false;
             }
             if (ok) break;
             --l;
@@ -346,19 +369,34 @@ __device__ int wave_count(WaveLds &L, bool act, int64_t i, double xi, double yi,
             cnt[d] = max(ib - ia + 1, 0);
         }
         const int sh = 3 * (S.lmax - l);
-        const int ncell = cnt[0] * cnt[1] * cnt[2];
-        for (int cb = 0; cb < ncell; cb += 64) {
-            int c = cb + lane;
-            int s0 = 0, len = 0;
-            if (c < ncell) {
-                int kx = c % cnt[0];
-                int ky = (c / cnt[0]) % cnt[1];
-                int kz = c / (cnt[0] * cnt[1]);
-                uint32_t code = morton((uint32_t)((a[0] + kx) & msk), (uint32_t)((a[1] + ky) & msk),
-                                       (uint32_t)((a[2] + kz) & msk));
-                s0 = S.cs[(int64_t)code << sh];
-                len = S.cs[((int64_t)code + 1) << sh] - s0;
+        // Cells are visited in ascending Morton code, so every lane meets its
+        // candidates in ascending particle index whatever the sub-group:
+        // the gather set of a particle at a given h comes out in one order.
+        // The box is covered by aligned blocks of 4^3 cells (fewer at levels
+        // 0 and 1) whose codes are sorted across the wave (at most 64: at
+        // most 13 cells, so 4 blocks, per dimension by the level choice);
+        // inside a block lane t takes the cell of local code t.
+        const int kb = l < 2 ? l : 2;
+        const int NB = nl >> kb;   // blocks per dimension
+        int sa[3], sb[3], nbd[3];
+        for (int d = 0; d < 3; ++d) {
+            sa[d] = a[d] & msk;
+            if (cnt[d] + (1 << kb) - 1 >= nl) {
+                sb[d] = 0;
+                nbd[d] = NB;
+            } else {
+                const int e = (sa[d] + cnt[d] - 1) & msk;
+                sb[d] = sa[d] >> kb;
+                nbd[d] = (((e >> kb) - sb[d]) & (NB - 1)) + 1;
             }
+        }
+        const int nblk = (cnt[0] > 0 && cnt[1] > 0 && cnt[2] > 0) ? nbd[0] * nbd[1] * nbd[2] : 0;
+        const int nloc = 1 << (3 * kb);
+        const uint32_t lx = compact3((uint32_t)lane), ly = compact3((uint32_t)lane >> 1),
+                       lz = compact3((uint32_t)lane >> 2);
+
+        // one batch of up to 64 non-empty cells (this lane: s0, len)
+        auto batch = [&](int s0, int len) {
             int incl = wave_incl_scan_i(len);
             int total = __shfl(incl, 63, 64);
             wave_lds_sync();
@@ -420,6 +458,67 @@ __device__ int wave_count(WaveLds &L, bool act, int64_t i, double xi, double yi,
                 }
                 wave_lds_sync();
             }
+        };
+
+        int qn = 0;   // cells waiting in the queue
+        // (more than 64 blocks cannot occur; they would still be covered,
+        // 64 at a time)
+        for (int cb = 0; cb < nblk; cb += 64) {
+        const int nb = min(64, nblk - cb);
+        uint32_t bcode = 0xFFFFFFFFu;
+        if (lane < nb) {
+            const int k = cb + lane;
+            const int kx = k % nbd[0];
+            const int ky = (k / nbd[0]) % nbd[1];
+            const int kz = k / (nbd[0] * nbd[1]);
+            bcode = morton((uint32_t)((sb[0] + kx) & (NB - 1)), (uint32_t)((sb[1] + ky) & (NB - 1)),
+                           (uint32_t)((sb[2] + kz) & (NB - 1)));
+        }
+        bcode = wave_sort_u32(bcode);
+        for (int b = 0; b < nb; ++b) {
+            const uint32_t bc = (uint32_t)__shfl((int)bcode, b, 64);
+            int s0 = 0, len = 0;
+            if (lane < nloc) {
+                const uint32_t f[3] = {(compact3(bc) << kb) | lx, (compact3(bc >> 1) << kb) | ly,
+                                       (compact3(bc >> 2) << kb) | lz};
+                bool in = true;
+                for (int d = 0; d < 3; ++d)
+                    in = in && (int)(((int)f[d] - sa[d]) & msk) < cnt[d];
+                if (in) {
+                    const uint32_t code = (bc << (3 * kb)) | (uint32_t)lane;
+                    s0 = S.cs[(int64_t)code << sh];
+                    len = S.cs[((int64_t)code + 1) << sh] - s0;
+                }
+            }
+            const uint64_t ne = __ballot(len > 0);
+            const int pos = qn + __popcll(ne & ((1ull << lane) - 1ull));
+            wave_lds_sync();
+            if (len > 0) {
+                L.qs[pos] = s0;
+                L.ql[pos] = len;
+            }
+            qn += __popcll(ne);
+            wave_lds_sync();
+            if (qn >= 64) {
+                const int q0 = L.qs[lane], q1 = L.ql[lane];
+                const int rest = qn - 64;
+                const int r0 = lane < rest ? L.qs[64 + lane] : 0;
+                const int r1 = lane < rest ? L.ql[64 + lane] : 0;
+                wave_lds_sync();
+                if (lane < rest) {
+                    L.qs[lane] = r0;
+                    L.ql[lane] = r1;
+                }
+                qn = rest;
+                batch(q0, q1);
+            }
+        }
+        }
+        if (qn > 0) {
+            wave_lds_sync();
+            const int q0 = lane < qn ? L.qs[lane] : 0;
+            const int q1 = lane < qn ? L.ql[lane] : 0;
+            batch(q0, q1);
         }
     }
     *nsh_out = nsh;
@@ -429,7 +528,8 @@ __device__ int wave_count(WaveLds &L, bool act, int64_t i, double xi, double yi,
 // iteration state carried between rounds (structure of arrays)
 struct HIter {
     double *next, *lo, *hi, *best_h, *last_h;
-    int32_t *best_n, *itk, *bits;   // bits: 1 lower bracket, 2 upper bracket, 4 try pending
+    int32_t *best_n, *itk, *bits;   // bits: 1 lower bracket, 2 upper bracket, 4 try pending,
+                                    // bits 8..15: full walks taken (HS_WALK units)
 };
 
 struct HState {
@@ -452,6 +552,9 @@ __device__ __forceinline__ void hs_store(const HIter &H, int64_t i, const HState
     H.best_h[i] = s.best_h; H.last_h[i] = s.last_h;
     H.best_n[i] = s.best_n; H.itk[i] = s.itk; H.bits[i] = s.bits;
 }
+
+#define HS_WALK 256        // one full walk in the bits field
+#define SPH_WAVE_ROUNDS 3  // worklist rounds after round 0 (one more after a try pass)
 
 // one step of the iteration after a count N at hc.
 // returns 0 = count again at s.next, 1 = converged, 2 = stopped unconverged
@@ -550,8 +653,12 @@ __global__ __launch_bounds__(SPH_BLOCK) void k_hsolve_round(HArgs A, int64_t n,
     const int64_t grp = blk * WAVES_PER_BLOCK + w;
     const int64_t slot = grp * 64 + lane;
     const int64_t total = wl ? *wcount : n;
-    const bool valid = slot < total;
-    const int64_t i = valid ? (wl ? (int64_t)wl[slot] : slot) : 0;
+    const bool listed = slot < total;
+    const int64_t i = listed ? (wl ? (int64_t)wl[slot] : slot) : 0;
+    // each particle takes at most SPH_WAVE_ROUNDS + 1 full walks in these
+    // rounds (a learned try that is left behind does not count); one that
+    // has used them waits, still listed, for the per-particle tail
+    const bool valid = listed && (!wl || (A.H.bits[i] >> 8) < SPH_WAVE_ROUNDS + 1);
     const Search S = make_search(A.cs, A.lmax, A.div, A.bbox, A.g);
 
     double xi = 0.0, yi = 0.0, zi = 0.0, hprev = 0.0;
@@ -593,7 +700,32 @@ __global__ __launch_bounds__(SPH_BLOCK) void k_hsolve_round(HArgs A, int64_t n,
         const double t0 = 2.0 * hc;
         int N = nsh >= 0 ? shell_count(t0 * t0) : -1;
         int res;
-        if (N < 0) {
+        st.bits += HS_WALK;
+        const double tp = 2.0 * hprev;
+        if (A.h_try && !wl && (N < 0 || !in_shell(tp * tp))) {
+            // the try pass, for a particle whose plain start h_prev lies
+            // outside the try's shell (or whose count is unknown because the
+            // shell overflowed): accept the predicted h when in band,
+            // otherwise the plain iteration starts from h_prev in the
+            // worklist rounds, with the plain start's state and walk budget
+            ++counts;
+            if (N >= 0) {
+                res = h_update(st, hc, N, hprev, A.target, A.tol, A.maxit, A.hk, fl, acc,
+                               fallback);
+            } else {
+                ++fallback;
+                res = 0;
+            }
+            if (res == 0) {
+                st.next = hprev;
+                st.lo = st.hi = 0.0;
+                st.best_h = st.last_h = hprev;
+                st.best_n = -1;
+                st.itk = 0;
+                st.bits = 0;
+            }
+            N = 0;   // state already set for the next round
+        } else if (N < 0) {
             // shell overflow: the exact count needs a full pass (next round)
             res = 0;
         } else {
@@ -709,8 +841,6 @@ __global__ __launch_bounds__(SPH_BLOCK) void k_refill(
     block_add_i64(overflow, status + ST_LIST_OVERFLOW);
 }
 
-#define SPH_WAVE_ROUNDS 3
-
 hipError_t launch_hsolve(sph_ctx *c, sph_particles *s, sph_nlist *nl, const double *h_try)
 {
     int64_t n = s->n;
@@ -748,12 +878,14 @@ hipError_t launch_hsolve(sph_ctx *c, sph_particles *s, sph_nlist *nl, const doub
     SPH_DISPATCH_PM(pm,
         hipLaunchKernelGGL(k_hsolve_round<PM>, dim3(nb), dim3(SPH_BLOCK), 0, c->stream, A, n,
                            (const int32_t *)nullptr, (const int64_t *)nullptr))
-    for (int r = 0; r <= SPH_WAVE_ROUNDS; ++r) {
+    // after a try pass the misses get the plain solve's full set of rounds
+    const int rounds = SPH_WAVE_ROUNDS + (h_try ? 1 : 0);
+    for (int r = 0; r <= rounds; ++r) {
         hipError_t e = launch_scan_i32_to_i64(c, c->w.work, c->w.woff, n);
         if (e != hipSuccess) return e;
         hipLaunchKernelGGL(k_compact, dim3(nb), dim3(SPH_BLOCK), 0, c->stream, n, c->w.work,
                            c->w.woff, c->w.wl);
-        if (r < SPH_WAVE_ROUNDS) {
+        if (r < rounds) {
             // the worklist size is only known on the device: launch for all
             // and let waves past its end return at once
             SPH_DISPATCH_PM(pm,

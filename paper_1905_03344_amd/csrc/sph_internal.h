@@ -12,6 +12,10 @@
 #define SPH_SCAN_ITEMS 8
 #define SPH_SCAN_TILE (SPH_BLOCK * SPH_SCAN_ITEMS)
 
+// learned smoothing length: gradient partial rows (one per training wave)
+#define SPH_MLP_TRAIN_WAVES 256
+#define SPH_MLP_ROW 4680   // SPH_MLP_NPARAM gradients, the loss, padding
+
 // device status words (int64) in the workspace
 enum {
     ST_NONCONV = 0,
@@ -58,6 +62,14 @@ struct Workspace {
     double *shell_r2;
     int64_t shell_stride;
     void *mixrec;          // n_max records of 64 bytes (mixed form)
+    // learned smoothing length
+    float *mlp_master;     // SPH_MLP_NPARAM FP32 parameters
+    float *mlp_m, *mlp_v;  // Adam moments
+    float *mlp_grad;       // gradient + loss (SPH_MLP_NPARAM + 1)
+    uint16_t *mlp_wb;      // bf16 copies of the parameters
+    double *mlp_norm;      // feature mean[6], std[6]
+    float *mlp_part;       // per-wave gradient partial rows
+    double *h_try;         // n_max predicted smoothing lengths (learned mode)
     int64_t nb_red;
     int64_t nb_sort;
     int64_t scan_part_len;
@@ -74,6 +86,10 @@ struct sph_ctx {
     int bound;
     int timing;
     StageTimer *timer;
+    int mlp_ready;         // weights set since the last bind
+    int mlp_t;             // Adam step counter of sph_mlp_train
+    float *harvest_feat;   // step sink of (features, target) rows, or NULL
+    float *harvest_target;
     char err[512];
 };
 
@@ -102,6 +118,20 @@ hipError_t launch_density_mixed(sph_ctx *c, sph_particles *s, const sph_nlist *n
                                 bool build_extra);
 hipError_t launch_eos_mixed(sph_ctx *c, sph_particles *s);
 hipError_t launch_forces_mixed(sph_ctx *c, sph_particles *s, const sph_nlist *nl);
+hipError_t launch_mlp_predict(sph_ctx *c, sph_particles *s, double *h_try);
+hipError_t launch_mlp_features(sph_ctx *c, const sph_particles *s, const double *d_dt,
+                               float *feat);
+hipError_t launch_mlp_targets(sph_ctx *c, const sph_particles *s, const float *feat,
+                              float *target);
+hipError_t launch_mlp_forward(sph_ctx *c, const float *feat, int64_t n, float *y, uint16_t *h1,
+                              uint16_t *h2);
+hipError_t launch_mlp_grad(sph_ctx *c, const float *feat, const float *target,
+                           const int32_t *rows, int64_t row0, int64_t n, float *grad,
+                           float *loss_out);
+hipError_t launch_mlp_adam(sph_ctx *c, const float *grad, double lr, double b1, double b2,
+                           double eps, int t);
+hipError_t launch_mlp_refresh(sph_ctx *c);
+hipError_t launch_mlp_fit_norm(sph_ctx *c, const float *feat, int64_t n);
 hipError_t launch_kick_drift(sph_ctx *c, sph_particles *s);
 hipError_t launch_predict(sph_ctx *c, sph_particles *s);
 hipError_t launch_kick(sph_ctx *c, sph_particles *s);
@@ -235,6 +265,17 @@ __device__ __forceinline__ uint32_t spread3(uint32_t v)
 __device__ __forceinline__ uint32_t morton(uint32_t gx, uint32_t gy, uint32_t gz)
 {
     return spread3(gx) | (spread3(gy) << 1) | (spread3(gz) << 2);
+}
+
+// inverse of spread3: bits 0, 3, 6, ... of v packed into bits 0, 1, 2, ...
+__device__ __forceinline__ uint32_t compact3(uint32_t v)
+{
+    v &= 0x09249249u;
+    v = (v ^ (v >> 2)) & 0x030C30C3u;
+    v = (v ^ (v >> 4)) & 0x0300F00Fu;
+    v = (v ^ (v >> 8)) & 0x030000FFu;
+    v = (v ^ (v >> 16)) & 0x000003FFu;
+    return v;
 }
 
 #define SPH_PI 3.14159265358979323846

@@ -98,9 +98,24 @@ _SIGS = {
     "sph_copy_internal": (ctypes.c_int, [_P, ctypes.c_int, _P, ctypes.c_size_t, ctypes.POINTER(ctypes.c_size_t)]),
     "sph_timing": (ctypes.c_int, [_P, ctypes.c_int]),
     "sph_timing_read": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(_I64), ctypes.c_int]),
+    "sph_mlp_set_weights": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_float), ctypes.POINTER(_D)]),
+    "sph_mlp_get_weights": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_float), ctypes.POINTER(_D)]),
+    "sph_mlp_fit_norm": (ctypes.c_int, [_P, _P, _I64]),
+    "sph_get_features": (ctypes.c_int, [_P, ctypes.POINTER(sph_particles), _P, _P]),
+    "sph_set_harvest": (ctypes.c_int, [_P, _P, _P]),
+    "sph_mlp_forward": (ctypes.c_int, [_P, _P, _I64, _P, _P, _P]),
+    "sph_mlp_backward": (ctypes.c_int, [_P, _P, _P, _P, _I64, _I64, _P]),
+    "sph_mlp_adam_step": (ctypes.c_int, [_P, _P, _D, _D, _D, _D, _I32]),
+    "sph_mlp_train": (ctypes.c_int, [_P, _P, _P, _P, _I64, _I32, _I32, _D, _P]),
 }
 
-STAGES = ("cells", "hsolve", "extra", "density", "eos", "forces", "integrate")
+SPH_MLP_NPARAM = 4673
+SPH_MLP_NFEAT = 8
+# parameter layout: name -> (offset, shape)
+MLP_LAYOUT = {"W1": (0, (64, 6)), "b1": (384, (64,)), "W2": (448, (64, 64)),
+              "b2": (4544, (64,)), "W3": (4608, (1, 64)), "b3": (4672, (1,))}
+
+STAGES = ("cells", "hsolve", "extra", "density", "eos", "forces", "integrate", "mlp")
 
 # entry points of the learned / mixed forms, bound when present
 _OPTIONAL = {}
@@ -230,3 +245,67 @@ def sph_timing_read(ctx):
     cnt = (_I64 * len(STAGES))()
     check(lib().sph_timing_read(ctx, ms, cnt, len(STAGES)), ctx)
     return {s: (ms[k], cnt[k]) for k, s in enumerate(STAGES)}
+
+
+# learned smoothing length ---------------------------------------------------
+
+def _f32buf(a):
+    import numpy as np
+    a = np.ascontiguousarray(a, dtype=np.float32)
+    return a, a.ctypes.data_as(ctypes.POINTER(ctypes.c_float))
+
+
+def sph_mlp_set_weights(ctx, params, norm12=None):
+    """params: SPH_MLP_NPARAM floats (host); norm12: mean[6] + std[6] or None."""
+    import numpy as np
+    a, pa = _f32buf(params)
+    if a.size != SPH_MLP_NPARAM:
+        raise ValueError(f"expected {SPH_MLP_NPARAM} parameters, got {a.size}")
+    pn = None
+    if norm12 is not None:
+        nb = np.ascontiguousarray(norm12, dtype=np.float64)
+        if nb.size != 12:
+            raise ValueError("norm12 must hold 12 values")
+        pn = nb.ctypes.data_as(ctypes.POINTER(_D))
+    check(lib().sph_mlp_set_weights(ctx, pa, pn), ctx)
+
+
+def sph_mlp_get_weights(ctx):
+    import numpy as np
+    params = np.zeros(SPH_MLP_NPARAM, dtype=np.float32)
+    norm = np.zeros(12, dtype=np.float64)
+    check(lib().sph_mlp_get_weights(ctx, params.ctypes.data_as(ctypes.POINTER(ctypes.c_float)),
+                                    norm.ctypes.data_as(ctypes.POINTER(_D))), ctx)
+    return params, norm
+
+
+def sph_mlp_fit_norm(ctx, d_feat: int, n: int):
+    check(lib().sph_mlp_fit_norm(ctx, d_feat, n), ctx)
+
+
+def sph_get_features(ctx, s, d_dt: int, d_feat: int):
+    check(lib().sph_get_features(ctx, ctypes.byref(s), d_dt, d_feat), ctx)
+
+
+def sph_set_harvest(ctx, d_feat: int | None, d_target: int | None):
+    check(lib().sph_set_harvest(ctx, d_feat, d_target), ctx)
+
+
+def sph_mlp_forward(ctx, d_feat: int, n: int, d_y: int, d_h1: int | None = None,
+                    d_h2: int | None = None):
+    check(lib().sph_mlp_forward(ctx, d_feat, n, d_y, d_h1, d_h2), ctx)
+
+
+def sph_mlp_backward(ctx, d_feat: int, d_target: int, d_rows: int | None, row0: int, n: int,
+                     d_grad: int):
+    check(lib().sph_mlp_backward(ctx, d_feat, d_target, d_rows, row0, n, d_grad), ctx)
+
+
+def sph_mlp_adam_step(ctx, d_grad: int, lr: float, beta1: float, beta2: float, eps: float,
+                      t: int):
+    check(lib().sph_mlp_adam_step(ctx, d_grad, lr, beta1, beta2, eps, t), ctx)
+
+
+def sph_mlp_train(ctx, d_feat: int, d_target: int, d_order: int | None, n: int, batch: int,
+                  epochs: int, lr: float, d_loss: int | None):
+    check(lib().sph_mlp_train(ctx, d_feat, d_target, d_order, n, batch, epochs, lr, d_loss), ctx)

@@ -225,6 +225,11 @@ def mlp_batch(seed: int, n: int, n_in: int = 6, scale: float = 1.5) -> tuple:
     return f, y
 
 
+def shuffle_order(seed: int, n: int) -> np.ndarray:
+    """A seeded permutation of 0..n-1 (int32): the order of training rows."""
+    return np.argsort(_stream(seed, 60, n), kind="stable").astype(np.int32)
+
+
 CONFIG_SEEDS = {1: 1905033441, 2: 1905033442, 3: 1905033443, 4: 1905033444, 5: 1905033445}
 
 

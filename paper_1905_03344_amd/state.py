@@ -29,7 +29,7 @@ def choose_max_level(n: int, bbox_extent: float, h_min: float, search_div: int =
 class Simulation:
     def __init__(self, ic, params: ffi.sph_params | None = None, device="cuda", n_max=None,
                  list_stride=128, extra_per_particle=48, max_level=None, search_div=2,
-                 precision=ffi.SPH_FP64, check_finite=False):
+                 precision=ffi.SPH_FP64, check_finite=False, h_mode=ffi.SPH_H_PLAIN):
         self.device = torch.device(device)
         n = ic.n
         self.n = n
@@ -51,6 +51,7 @@ class Simulation:
         p.search_div = int(search_div)
         p.precision = int(precision)
         p.check_finite = int(bool(check_finite))
+        p.h_mode = int(h_mode)
         self.params = p
         self.ctx = ffi.sph_create(p)
         dev = self.device
@@ -165,6 +166,36 @@ class Simulation:
         """pv = v, pu = u (what sph_evaluate does before the force stages)."""
         for a, b in (("pvx", "vx"), ("pvy", "vy"), ("pvz", "vz"), ("pu", "u")):
             self.t[a].copy_(self.field(b))
+
+    # --- learned smoothing length ---------------------------------------------
+    def set_mlp(self, params, norm12=None):
+        """params: flat SPH_MLP_NPARAM floats or a dict W1, b1, W2, b2, W3, b3."""
+        from .learned import pack_params
+        flat = pack_params(params) if isinstance(params, dict) else params
+        ffi.sph_mlp_set_weights(self.ctx, flat, norm12)
+
+    def get_mlp(self):
+        """(flat FP32 parameters, norm12) from the device."""
+        return ffi.sph_mlp_get_weights(self.ctx)
+
+    def features(self):
+        """Feature rows [n, 8] of the current state (dt of the last step)."""
+        out = torch.zeros((max(self.n, 1), ffi.SPH_MLP_NFEAT), dtype=torch.float32,
+                          device=self.device)
+        ffi.sph_get_features(self.ctx, self.s, self.d_dt.data_ptr(), out.data_ptr())
+        return out[: self.n]
+
+    def set_harvest(self, feat: torch.Tensor | None, target: torch.Tensor | None):
+        """Every later step writes its (features, target) rows into these
+        device tensors ([>= n, 8] float32 and [>= n] float32); None stops."""
+        if feat is None:
+            ffi.sph_set_harvest(self.ctx, None, None)
+            return
+        assert feat.dtype == torch.float32 and target.dtype == torch.float32
+        assert feat.is_contiguous() and target.is_contiguous()
+        assert feat.shape[0] >= self.n and feat.shape[1] == ffi.SPH_MLP_NFEAT
+        assert target.shape[0] >= self.n
+        ffi.sph_set_harvest(self.ctx, feat.data_ptr(), target.data_ptr())
 
     # --- tables and lists for tests ------------------------------------------
     def cell_table(self):
