@@ -367,24 +367,34 @@ hipError_t launch_permute(sph_ctx *c, sph_particles *s, const int32_t *perm)
 
 // ---------------------------------------------------------------------------
 // cell-start table at level lmax: start[c] = first sorted index whose key is
-// in cell c (or later), for c in [0, 8^lmax]; every entry written once.
+// in cell c (or later), for c in [0, 8^lmax]; one thread per entry, by
+// binary search over the sorted keys (the table stays cheap to build where
+// most cells are empty).
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(SPH_BLOCK) void k_cell_table(const uint32_t *__restrict__ key,
                                                           int64_t n, int shift, int64_t ncell,
                                                           int32_t *__restrict__ start)
 {
-    int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (k > n) return;
-    int64_t cnow = (k < n) ? (int64_t)(key[k] >> shift) : ncell;  // k == n: sentinel past the end
-    int64_t cprev = (k > 0) ? (int64_t)(key[k - 1] >> shift) : -1;
-    for (int64_t cc = cprev + 1; cc <= cnow; ++cc) start[cc] = (int32_t)k;
+    int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (c > ncell) return;
+    int64_t lo = 0, hi = n;   // first k in [lo, hi] with key[k] >> shift >= c
+    if (c < ncell) {
+        while (lo < hi) {
+            int64_t mid = (lo + hi) >> 1;
+            if ((int64_t)(key[mid] >> shift) < c) lo = mid + 1;
+            else hi = mid;
+        }
+    } else {
+        lo = n;
+    }
+    start[c] = (int32_t)lo;
 }
 
 hipError_t launch_cell_table(sph_ctx *c, const uint32_t *sorted_key, int64_t n)
 {
     int l = c->p.max_level;
     int64_t ncell = (int64_t)1 << (3 * l);
-    hipLaunchKernelGGL(k_cell_table, dim3((unsigned)ceil_div(n + 1, SPH_BLOCK)), dim3(SPH_BLOCK), 0,
-                       c->stream, sorted_key, n, 3 * (10 - l), ncell, c->w.cell_start);
+    hipLaunchKernelGGL(k_cell_table, dim3((unsigned)ceil_div(ncell + 1, SPH_BLOCK)), dim3(SPH_BLOCK),
+                       0, c->stream, sorted_key, n, 3 * (10 - l), ncell, c->w.cell_start);
     return hipGetLastError();
 }

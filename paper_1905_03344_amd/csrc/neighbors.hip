@@ -128,28 +128,33 @@ __device__ __forceinline__ int count_fill(const Search &S, const double *__restr
 //   stop when |N - target| <= tol; below the band raise the lower bracket,
 //   above it lower the upper bracket; bisect once both are set, else
 //   h *= T[min(N, 1023)]; at most maxit counts.
+// Structure: round 0 counts every particle once with wave-cooperative
+// walks (below) and keeps iterating on the shell of that count while the
+// next h stays inside it.  Particles that need another full count, and
+// those of small (scattered) groups, which round 0 leaves alone, go to the
+// tail: one wave per particle, full counts until the iteration ends.
 // With h_try (learned mode) round 0 counts at h_try[i] and accepts it when
 // in the band.  A miss whose plain start h[i] lies inside the try's shell
 // goes on with the plain iteration from h[i] on that shell, as the plain
 // solve's round 0 would; any other miss (also one whose count is unknown
 // because the try's shell overflowed) starts the plain iteration from h[i]
-// in the worklist rounds, which get one round more.  Every particle has the
-// same budget of full walks in the rounds before the per-particle tail, so a
-// miss follows the plain solve's path: cells are walked in Morton order, so
-// its gather set does not depend on which wave counts it.
+// in one worklist round before the tail.  Groups in round 0 are formed from
+// positions and h[i] alone, and every particle gets the same budget of walks
+// before the tail, so a miss follows the plain solve's path; cells are
+// walked in Morton order, so its gather set does not depend on which wave
+// counts it.
 // The gather set of the last counted h is written (slot-major); particles
 // whose kept h is not the last counted one are rewritten by k_refill.
 //
 // Counting is wave-cooperative: a wave owns 64 particles (consecutive in
-// Morton order, or consecutive entries of a worklist), builds the union of
-// their search boxes, walks its cells in batches of 64 (one cell per lane,
-// prefix sums of the cell sizes), streams the candidates in tiles of 64
-// through LDS and lets every lane test every candidate of the tile against
-// its own particle (broadcast LDS reads).  Control flow is uniform and
-// candidate loads are coalesced.  Round 0 counts every particle once; each
-// further round counts the particles still outside the band (a compacted
-// worklist, Morton order kept) with their iteration state carried over; a
-// per-particle kernel finishes the few that remain.
+// Morton order, or consecutive entries of a worklist), split into groups of
+// nearby particles.  A large group builds the union of its search boxes,
+// walks its cells in batches of 64 (one cell per lane, prefix sums of the
+// cell sizes), streams the candidates in tiles of 64 through LDS and lets
+// every member lane test every candidate of the tile against its own
+// particle (broadcast LDS reads): control flow is uniform and candidate
+// loads are coalesced.  A small group is counted one particle at a time
+// with one candidate per lane (transposed mode).
 // ---------------------------------------------------------------------------
 struct Cand {
     double x, y, z;
@@ -275,142 +280,170 @@ struct Shell {
     int64_t sstride;
 };
 
-// One wave-cooperative count for every lane with act set at its own hc:
-// members with r^2 < A are written to idx (slot-major, at most K), shell
-// members (A <= r^2 < B) to the shell arrays (at most SPH_SHELL_SLOTS;
-// *nsh = -1 when more).  Returns the number of inner members (self
-// excluded); self is never a shell member.
-template <int PM>
-__device__ int wave_count(WaveLds &L, bool act, int64_t i, double xi, double yi, double zi,
-                          uint32_t ki, double hc, double A2, double B2,
-                          const double *__restrict__ x, const double *__restrict__ y,
-                          const double *__restrict__ z, int32_t *__restrict__ idx, int64_t stride,
-                          int K, const Shell &SH, int *nsh_out, const Search &S, const Geo &g,
-                          int64_t &tested)
+// Sub-groups of at most this many particles are counted one particle at a
+// time with the candidates spread over the lanes (transposed mode); larger
+// ones stream their union box through LDS tiles that every member tests.
+#define SPH_SMALL_GROUP 8
+
+// exact r^2 between a lane's particle and candidate coordinates (the same
+// arithmetic in both modes; PMW = 0 when the box cannot wrap, where the
+// minimum image is the plain difference)
+template <int PMW>
+__device__ __forceinline__ double pair_r2(double xi, double yi, double zi, double xj, double yj,
+                                          double zj, const Geo &g)
+{
+#pragma clang fp contract(off)
+    return exact_r2(mimg<PMW, 0>(xi, xj, g), mimg<PMW, 1>(yi, yj, g), mimg<PMW, 2>(zi, zj, g));
+}
+
+// One walk over the cells of the box covering the member lanes' search
+// spheres (radius sqrt(B)), in ascending Morton code.  Union mode: every
+// member lane tests every candidate (LDS tiles).  Transposed mode
+// (tm >= 0, one member, lane tm): lane t tests candidate t of each chunk of
+// 64 against the member, and the member's counters are kept wave-uniform.
+template <int PM, bool TRANSPOSED>
+__device__ void walk_group(WaveLds &L, uint64_t members, int tm, int64_t i, double xi, double yi,
+                           double zi, double A2, double B2, const double *__restrict__ x,
+                           const double *__restrict__ y, const double *__restrict__ z,
+                           int32_t *__restrict__ idx, int64_t stride, int K, const Shell &SH,
+                           const Search &S, const Geo &g, int &N, int &nsh, int32_t *&wp,
+                           int64_t &tested)
 {
 #pragma clang fp contract(off)
     const int lane = threadIdx.x & 63;
-    const double twoh = 2.0 * hc;
-    int N = 0, nsh = 0;
-    int32_t *wp = idx + i;   // slot N of this particle's gather set
-    uint64_t pending = __ballot(act);
-    while (pending) {
-        // sub-group: the pending lanes, split by Morton prefix while their
-        // positions spread over more than 1.5 search diameters (a group that
-        // straddles a large Morton jump would otherwise scan the gap)
-        uint64_t members = pending;
-        for (int sp = 0; sp < 32; ++sp) {
-            bool mem = (members >> lane) & 1ull;
-            double Rm = wave_max_d(mem ? twoh : 0.0);
-            double ext = 0.0;
-            const double p3[3] = {xi, yi, zi};
-            for (int d = 0; d < 3; ++d) {
-                double a = wave_min_d(mem ? p3[d] : INFINITY);
-                double b = wave_max_d(mem ? p3[d] : -INFINITY);
-                ext = fmax(ext, b - a);
-            }
-            if (!(ext > 3.0 * Rm) || __popcll(members) == 1) break;
-            uint32_t kmin = wave_min_u(mem ? ki : 0xFFFFFFFFu);
-            uint32_t kmax = wave_max_u(mem ? ki : 0u);
-            if (kmin == kmax) break;
-            int hb = 31 - __clz(kmin ^ kmax);
-            int leader = __ffsll((unsigned long long)members) - 1;
-            uint32_t lk = (uint32_t)__shfl((int)ki, leader, 64);
-            members &= __ballot(((ki ^ lk) >> hb) == 0u);
-        }
-        pending &= ~members;
-        const bool me = (members >> lane) & 1ull;
+    const bool me = (members >> lane) & 1ull;
+    const double Rout = sqrt(B2) * (1.0 + 1e-12);
 
-        // union box of the sub-group, wide enough for the shell's outer radius
-        const double Rout = sqrt(B2) * (1.0 + 1e-12);
-        double Rmax = wave_max_d(me ? Rout : 0.0);
-        double blo[3], bhi[3];
-        {
-            const double p3[3] = {xi, yi, zi};
-            for (int d = 0; d < 3; ++d) {
-                blo[d] = wave_min_d(me ? p3[d] - Rout : INFINITY) - S.margin;
-                bhi[d] = wave_max_d(me ? p3[d] + Rout : -INFINITY) + S.margin;
-            }
-        }
-        double span = fmax(fmax(bhi[0] - blo[0], bhi[1] - blo[1]), bhi[2] - blo[2]);
-        int l = S.lmax;
-        while (l > 0) {
-            bool ok = true;
-            for (int d = 0; d < 3; ++d) {
-                double cw = ldexp(S.L[d], -l);
-                if (S.L[d] > 0.0 && (cw * S.div < Rmax + S.margin || cw * 11.0 < span)) ok = false;
-            }
-            if (ok) break;
-            --l;
-        }
-        const int nl = 1 << l;
-        const int msk = nl - 1;
-        int a[3], cnt[3];
-        bool wraps = false;
+    // union box of the members, wide enough for the shell's outer radius
+    double Rmax = wave_max_d(me ? Rout : 0.0);
+    double blo[3], bhi[3];
+    {
+        const double p3[3] = {xi, yi, zi};
         for (int d = 0; d < 3; ++d) {
-            if (!(S.L[d] > 0.0)) { a[d] = 0; cnt[d] = 1; continue; }
-            double wd = ldexp(S.L[d], -l);
-            double ta = floor((blo[d] - S.lo[d]) / wd);
-            double tb = floor((bhi[d] - S.lo[d]) / wd);
-            ta = fmin(fmax(ta, -2.0 * nl), 3.0 * nl);
-            tb = fmin(fmax(tb, -2.0 * nl), 3.0 * nl);
-            int ia = (int)ta, ib = (int)tb;
-            if (S.g.per[d]) {
-                if (ib - ia + 1 >= nl) { ia = 0; ib = nl - 1; }
-                // without a wrapped cell and with the box (plus one cell of
-                // slack) under half the period, every |x_j - x_i| < L/2: the
-                // minimum image is the plain difference
-                if (ia < 0 || ib >= nl || (double)(ib - ia + 2) * wd > g.halfL[d]) wraps = true;
-            } else {
-                ia = max(ia, 0);
-                ib = min(ib, nl - 1);
-            }
-            a[d] = ia;
-            cnt[d] = max(ib - ia + 1, 0);
+            blo[d] = wave_min_d(me ? p3[d] - Rout : INFINITY) - S.margin;
+            bhi[d] = wave_max_d(me ? p3[d] + Rout : -INFINITY) + S.margin;
         }
-        const int sh = 3 * (S.lmax - l);
-        // Cells are visited in ascending Morton code, so every lane meets its
-        // candidates in ascending particle index whatever the sub-group:
-        // the gather set of a particle at a given h comes out in one order.
-        // The box is covered by aligned blocks of 4^3 cells (fewer at levels
-        // 0 and 1) whose codes are sorted across the wave (at most 64: at
-        // most 13 cells, so 4 blocks, per dimension by the level choice);
-        // inside a block lane t takes the cell of local code t.
-        const int kb = l < 2 ? l : 2;
-        const int NB = nl >> kb;   // blocks per dimension
-        int sa[3], sb[3], nbd[3];
+    }
+    double span = fmax(fmax(bhi[0] - blo[0], bhi[1] - blo[1]), bhi[2] - blo[2]);
+    int l = S.lmax;
+    while (l > 0) {
+        bool ok = true;
         for (int d = 0; d < 3; ++d) {
-            sa[d] = a[d] & msk;
-            if (cnt[d] + (1 << kb) - 1 >= nl) {
-                sb[d] = 0;
-                nbd[d] = NB;
-            } else {
-                const int e = (sa[d] + cnt[d] - 1) & msk;
-                sb[d] = sa[d] >> kb;
-                nbd[d] = (((e >> kb) - sb[d]) & (NB - 1)) + 1;
-            }
+            double cw = ldexp(S.L[d], -l);
+            if (S.L[d] > 0.0 && (cw * S.div < Rmax + S.margin || cw * 11.0 < span)) ok = false;
         }
-        const int nblk = (cnt[0] > 0 && cnt[1] > 0 && cnt[2] > 0) ? nbd[0] * nbd[1] * nbd[2] : 0;
-        const int nloc = 1 << (3 * kb);
-        const uint32_t lx = compact3((uint32_t)lane), ly = compact3((uint32_t)lane >> 1),
-                       lz = compact3((uint32_t)lane >> 2);
+        if (ok) break;
+        --l;
+    }
+    const int nl = 1 << l;
+    const int msk = nl - 1;
+    int a[3], cnt[3];
+    bool wraps = false;
+    for (int d = 0; d < 3; ++d) {
+        if (!(S.L[d] > 0.0)) { a[d] = 0; cnt[d] = 1; continue; }
+        double wd = ldexp(S.L[d], -l);
+        double ta = floor((blo[d] - S.lo[d]) / wd);
+        double tb = floor((bhi[d] - S.lo[d]) / wd);
+        ta = fmin(fmax(ta, -2.0 * nl), 3.0 * nl);
+        tb = fmin(fmax(tb, -2.0 * nl), 3.0 * nl);
+        int ia = (int)ta, ib = (int)tb;
+        if (S.g.per[d]) {
+            if (ib - ia + 1 >= nl) { ia = 0; ib = nl - 1; }
+            // without a wrapped cell and with the box (plus one cell of
+            // slack) under half the period, every |x_j - x_i| < L/2: the
+            // minimum image is the plain difference
+            if (ia < 0 || ib >= nl || (double)(ib - ia + 2) * wd > g.halfL[d]) wraps = true;
+        } else {
+            ia = max(ia, 0);
+            ib = min(ib, nl - 1);
+        }
+        a[d] = ia;
+        cnt[d] = max(ib - ia + 1, 0);
+    }
+    const int sh = 3 * (S.lmax - l);
+    // Cells are visited in ascending Morton code, so every member meets its
+    // candidates in ascending particle index whatever the group: the gather
+    // set of a particle at a given h comes out in one order.  The box is
+    // covered by aligned blocks of 4^3 cells (fewer at levels 0 and 1) whose
+    // codes are sorted across the wave (at most 64: at most 12 cells, so 4
+    // blocks, per dimension by the level choice); inside a block lane t
+    // takes the cell of local code t.
+    const int kb = l < 2 ? l : 2;
+    const int NB = nl >> kb;   // blocks per dimension
+    int sa[3], sb[3], nbd[3];
+    for (int d = 0; d < 3; ++d) {
+        sa[d] = a[d] & msk;
+        if (cnt[d] + (1 << kb) - 1 >= nl) {
+            sb[d] = 0;
+            nbd[d] = NB;
+        } else {
+            const int e = (sa[d] + cnt[d] - 1) & msk;
+            sb[d] = sa[d] >> kb;
+            nbd[d] = (((e >> kb) - sb[d]) & (NB - 1)) + 1;
+        }
+    }
+    const int nblk = (cnt[0] > 0 && cnt[1] > 0 && cnt[2] > 0) ? nbd[0] * nbd[1] * nbd[2] : 0;
+    const int nloc = 1 << (3 * kb);
+    const uint32_t lx = compact3((uint32_t)lane), ly = compact3((uint32_t)lane >> 1),
+                   lz = compact3((uint32_t)lane >> 2);
 
-        // one batch of up to 64 non-empty cells (this lane: s0, len)
-        auto batch = [&](int s0, int len) {
-            int incl = wave_incl_scan_i(len);
-            int total = __shfl(incl, 63, 64);
-            wave_lds_sync();
-            L.start[lane] = s0;
-            L.pre[lane] = incl - len;
-            wave_lds_sync();
-            if (me) tested += total;
-            for (int base = 0; base < total; base += 64) {
-                int v = base + lane;
-                if (v < total) {
-                    int r = 0;
-                    for (int st = 32; st > 0; st >>= 1)
-                        if (L.pre[r + st] <= v) r += st;
-                    int j = L.start[r] + (v - L.pre[r]);
+    // transposed mode: the member's data and counters, wave-uniform
+    const double xm = TRANSPOSED ? __shfl(xi, tm, 64) : 0.0;
+    const double ym = TRANSPOSED ? __shfl(yi, tm, 64) : 0.0;
+    const double zm = TRANSPOSED ? __shfl(zi, tm, 64) : 0.0;
+    const double A2m = TRANSPOSED ? __shfl(A2, tm, 64) : 0.0;
+    const double B2m = TRANSPOSED ? __shfl(B2, tm, 64) : 0.0;
+    const int64_t im = TRANSPOSED ? (int64_t)__shfl((int)i, tm, 64) : 0;
+    int Nm = 0, nshm = 0;
+    const uint64_t below = (1ull << lane) - 1ull;
+
+    // one batch of up to 64 non-empty cells (this lane: s0, len)
+    auto batch = [&](int s0, int len) {
+        int incl = wave_incl_scan_i(len);
+        int total = __shfl(incl, 63, 64);
+        wave_lds_sync();
+        L.start[lane] = s0;
+        L.pre[lane] = incl - len;
+        wave_lds_sync();
+        if (TRANSPOSED ? lane == tm : me) tested += total;
+        for (int base = 0; base < total; base += 64) {
+            int v = base + lane;
+            int j = -1;
+            if (v < total) {
+                int r = 0;
+                for (int st = 32; st > 0; st >>= 1)
+                    if (L.pre[r + st] <= v) r += st;
+                j = L.start[r] + (v - L.pre[r]);
+            }
+            if (TRANSPOSED) {
+                bool hin = false, hsh = false;
+                double r2 = 0.0;
+                if (j >= 0) {
+                    r2 = wraps ? pair_r2<PM>(xm, ym, zm, x[j], y[j], z[j], g)
+                               : pair_r2<0>(xm, ym, zm, x[j], y[j], z[j], g);
+                    hin = r2 < A2m && j != (int)im;
+                    hsh = !(r2 < A2m) && r2 < B2m;
+                }
+                const uint64_t bin = __ballot(hin);
+                const int pos = Nm + __popcll(bin & below);
+                if (hin && pos < K) idx[(int64_t)pos * stride + im] = j;
+                Nm += __popcll(bin);
+                const uint64_t bsh = __ballot(hsh);
+                const int c = __popcll(bsh);
+                if (c > 0 && nshm >= 0) {
+                    if (nshm + c <= SPH_SHELL_SLOTS) {
+                        const int ps = nshm + __popcll(bsh & below);
+                        if (hsh) {
+                            SH.j[(int64_t)ps * SH.sstride + im] = j;
+                            SH.r2[(int64_t)ps * SH.sstride + im] = r2;
+                        }
+                        nshm += c;
+                    } else {
+                        nshm = -1;
+                    }
+                }
+            } else {
+                if (j >= 0) {
                     Cand cd;
                     cd.x = x[j];
                     cd.y = y[j];
@@ -434,9 +467,9 @@ __device__ int wave_count(WaveLds &L, bool act, int64_t i, double xi, double yi,
                     while (hin) {
                         int t = __ffsll((unsigned long long)hin) - 1;
                         hin &= hin - 1;
-                        int j = L.c[t].j;
-                        if (j != (int)i) {
-                            if (N < K) *wp = j;
+                        int jj = L.c[t].j;
+                        if (jj != (int)i) {
+                            if (N < K) *wp = jj;
                             wp += stride;
                             ++N;
                         }
@@ -458,12 +491,13 @@ __device__ int wave_count(WaveLds &L, bool act, int64_t i, double xi, double yi,
                 }
                 wave_lds_sync();
             }
-        };
+        }
+    };
 
-        int qn = 0;   // cells waiting in the queue
-        // (more than 64 blocks cannot occur; they would still be covered,
-        // 64 at a time)
-        for (int cb = 0; cb < nblk; cb += 64) {
+    int qn = 0;   // cells waiting in the queue
+    // (more than 64 blocks cannot occur; they would still be covered, 64 at
+    // a time)
+    for (int cb = 0; cb < nblk; cb += 64) {
         const int nb = min(64, nblk - cb);
         uint32_t bcode = 0xFFFFFFFFu;
         if (lane < nb) {
@@ -491,7 +525,7 @@ __device__ int wave_count(WaveLds &L, bool act, int64_t i, double xi, double yi,
                 }
             }
             const uint64_t ne = __ballot(len > 0);
-            const int pos = qn + __popcll(ne & ((1ull << lane) - 1ull));
+            const int pos = qn + __popcll(ne & below);
             wave_lds_sync();
             if (len > 0) {
                 L.qs[pos] = s0;
@@ -513,12 +547,82 @@ __device__ int wave_count(WaveLds &L, bool act, int64_t i, double xi, double yi,
                 batch(q0, q1);
             }
         }
+    }
+    if (qn > 0) {
+        wave_lds_sync();
+        const int q0 = lane < qn ? L.qs[lane] : 0;
+        const int q1 = lane < qn ? L.ql[lane] : 0;
+        batch(q0, q1);
+    }
+    if (TRANSPOSED && lane == tm) {
+        N = Nm;
+        nsh = nshm;
+    }
+}
+
+// One wave-cooperative count for every lane with act set at its own hc:
+// members with r^2 < A are written to idx (slot-major, at most K), shell
+// members (A <= r^2 < B) to the shell arrays (at most SPH_SHELL_SLOTS;
+// *nsh = -1 when more).  Returns the number of inner members (self
+// excluded); self is never a shell member.  With A = B there is no shell and
+// the whole gather set at sqrt(A)/2 is written.  The output does not depend
+// on which lanes are counted together.  Lanes are grouped by position and by
+// hsplit (their h for that purpose); with defer_small, lanes that end up in
+// a small group are not counted and get *deferred = true (their particles
+// are better served one per wave).
+template <int PM>
+__device__ int wave_count(WaveLds &L, bool act, int64_t i, double xi, double yi, double zi,
+                          uint32_t ki, double hsplit, bool defer_small, bool *deferred,
+                          double A2, double B2, const double *__restrict__ x,
+                          const double *__restrict__ y, const double *__restrict__ z,
+                          int32_t *__restrict__ idx, int64_t stride, int K, const Shell &SH,
+                          int *nsh_out, const Search &S, const Geo &g, int64_t &tested)
+{
+#pragma clang fp contract(off)
+    const int lane = threadIdx.x & 63;
+    const double twoh = 2.0 * hsplit;
+    *deferred = false;
+    int N = 0, nsh = 0;
+    int32_t *wp = idx + i;   // slot N of this particle's gather set
+    uint64_t pending = __ballot(act);
+    while (pending) {
+        // sub-group: the pending lanes, split by Morton prefix while their
+        // positions spread over more than 1.5 search diameters (a group that
+        // straddles a large Morton jump would otherwise scan the gap)
+        uint64_t members = pending;
+        for (int sp = 0; sp < 32; ++sp) {
+            bool mem = (members >> lane) & 1ull;
+            double Rm = wave_max_d(mem ? twoh : 0.0);
+            double ext = 0.0;
+            const double p3[3] = {xi, yi, zi};
+            for (int d = 0; d < 3; ++d) {
+                double a = wave_min_d(mem ? p3[d] : INFINITY);
+                double b = wave_max_d(mem ? p3[d] : -INFINITY);
+                ext = fmax(ext, b - a);
+            }
+            if (!(ext > 3.0 * Rm) || __popcll(members) <= SPH_SMALL_GROUP) break;
+            uint32_t kmin = wave_min_u(mem ? ki : 0xFFFFFFFFu);
+            uint32_t kmax = wave_max_u(mem ? ki : 0u);
+            if (kmin == kmax) break;
+            int hb = 31 - __clz(kmin ^ kmax);
+            int leader = __ffsll((unsigned long long)members) - 1;
+            uint32_t lk = (uint32_t)__shfl((int)ki, leader, 64);
+            members &= __ballot(((ki ^ lk) >> hb) == 0u);
         }
-        if (qn > 0) {
-            wave_lds_sync();
-            const int q0 = lane < qn ? L.qs[lane] : 0;
-            const int q1 = lane < qn ? L.ql[lane] : 0;
-            batch(q0, q1);
+        pending &= ~members;
+        if (defer_small && __popcll(members) <= SPH_SMALL_GROUP) {
+            if ((members >> lane) & 1ull) *deferred = true;
+        } else if (__popcll(members) <= SPH_SMALL_GROUP) {
+            uint64_t rest = members;
+            while (rest) {
+                const int m = __ffsll((unsigned long long)rest) - 1;
+                rest &= rest - 1;
+                walk_group<PM, true>(L, 1ull << m, m, i, xi, yi, zi, A2, B2, x, y, z, idx, stride,
+                                     K, SH, S, g, N, nsh, wp, tested);
+            }
+        } else {
+            walk_group<PM, false>(L, members, -1, i, xi, yi, zi, A2, B2, x, y, z, idx, stride, K,
+                                  SH, S, g, N, nsh, wp, tested);
         }
     }
     *nsh_out = nsh;
@@ -554,7 +658,7 @@ __device__ __forceinline__ void hs_store(const HIter &H, int64_t i, const HState
 }
 
 #define HS_WALK 256        // one full walk in the bits field
-#define SPH_WAVE_ROUNDS 3  // worklist rounds after round 0 (one more after a try pass)
+#define SPH_WAVE_ROUNDS 0  // worklist rounds after round 0 (one more after a try pass)
 
 // one step of the iteration after a count N at hc.
 // returns 0 = count again at s.next, 1 = converged, 2 = stopped unconverged
@@ -684,11 +788,21 @@ __global__ __launch_bounds__(SPH_BLOCK) void k_hsolve_round(HArgs A, int64_t n,
     const double ta = 2.0 * hc * (1.0 - 1.0 / 32.0), tb = 2.0 * hc * (1.0 + 1.0 / 32.0);
     const double A2 = ta * ta, B2 = tb * tb;
     int nin = 0, nsh = 0;
-    // a wave whose slots are all past the end has nothing to do
+    bool deferred = false;
+    // a wave whose slots are all past the end has nothing to do.  Round 0
+    // groups by h_prev (the same groups with or without a learned try) and
+    // leaves particles of small groups to the per-particle tail.
     if (__ballot(valid))
-        nin = wave_count<PM>(lds[w], valid, i, xi, yi, zi, ki, hc, A2, B2, A.x, A.y, A.z, A.idx,
-                             A.stride, A.K, A.SH, &nsh, S, A.g, tested);
-    if (valid) {
+        nin = wave_count<PM>(lds[w], valid, i, xi, yi, zi, ki, wl ? hc : hprev, !wl, &deferred,
+                             A2, B2, A.x, A.y, A.z, A.idx, A.stride, A.K, A.SH, &nsh, S, A.g,
+                             tested);
+    if (valid && deferred) {
+        // no walk taken: untouched state, walk budget spent so that only
+        // the tail takes it up
+        st.bits |= (SPH_WAVE_ROUNDS + 1) * HS_WALK;
+        hs_store(A.H, i, st);
+        A.work[i] = 1;
+    } else if (valid) {
         uint8_t fl = 0;
         const int ns = nsh > 0 ? nsh : 0;
         auto shell_count = [&](double r2m) {
@@ -785,60 +899,85 @@ __global__ __launch_bounds__(SPH_BLOCK) void k_compact(int64_t n, const int32_t 
     if (i < n && work[i]) wl[woff[i]] = (int32_t)i;
 }
 
-// The particles still iterating after the wave rounds: one thread each.
+// The particles still iterating after the wave rounds: one wave each,
+// iterating to the end with full wave-cooperative counts (the whole gather
+// set written at every count, no shell).
 template <int PM>
 __global__ __launch_bounds__(SPH_BLOCK) void k_hsolve_tail(HArgs A, const int32_t *__restrict__ wl,
                                                            const int64_t *__restrict__ wcount)
 {
 #pragma clang fp contract(off)
+    __shared__ WaveLds lds[WAVES_PER_BLOCK];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int64_t gw = (int64_t)blockIdx.x * WAVES_PER_BLOCK + w;
+    const int64_t nw = (int64_t)gridDim.x * WAVES_PER_BLOCK;
     const int64_t total = *wcount;
+    const Search S = make_search(A.cs, A.lmax, A.div, A.bbox, A.g);
     int64_t counts = 0, tested = 0, nonconv = 0, overflow = 0, acc = 0, fallback = 0;
-    for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < total;
-         t += (int64_t)gridDim.x * blockDim.x) {
+    for (int64_t t = gw; t < total; t += nw) {
         const int64_t i = wl[t];
-        const Search S = make_search(A.cs, A.lmax, 1, A.bbox, A.g);
         const double xi = A.x[i], yi = A.y[i], zi = A.z[i];
+        const uint32_t ki = A.key[i];
         const double hprev = A.h[i];
         HState st = hs_load(A.H, i);
         uint8_t fl = 0;
         int res = 0;
         while (res == 0) {
             const double hc = st.next;
-            int N = count_fill<PM>(S, A.x, A.y, A.z, i, xi, yi, zi, hc, A.idx, A.stride, A.K,
-                                   true, tested);
+            const double t2 = 2.0 * hc;
+            const double r2m = t2 * t2;
+            int nsh = 0;
+            bool dfr;
+            int N = wave_count<PM>(lds[w], lane == 0, i, xi, yi, zi, ki, hc, false, &dfr, r2m, r2m,
+                                   A.x, A.y, A.z, A.idx, A.stride, A.K, A.SH, &nsh, S, A.g,
+                                   tested);
+            N = __shfl(N, 0, 64);
             ++counts;
             res = h_update(st, hc, N, hprev, A.target, A.tol, A.maxit, A.hk, fl, acc, fallback);
         }
-        h_finish(st, res, fl, i, A.h, A.nc, A.flags, A.refill, A.K, nonconv, overflow);
+        if (lane == 0) h_finish(st, res, fl, i, A.h, A.nc, A.flags, A.refill, A.K, nonconv, overflow);
     }
-    block_add_i64(counts, A.status + ST_HCOUNTS);
+    // state and counters are wave-uniform: lane 0 reports them
+    const bool rep = lane == 0;
+    block_add_i64(rep ? counts : 0, A.status + ST_HCOUNTS);
     block_add_i64(tested, A.status + ST_CANDIDATES);
-    block_add_i64(nonconv, A.status + ST_NONCONV);
-    block_add_i64(overflow, A.status + ST_LIST_OVERFLOW);
+    block_add_i64(rep ? nonconv : 0, A.status + ST_NONCONV);
+    block_add_i64(rep ? overflow : 0, A.status + ST_LIST_OVERFLOW);
     if (A.h_try) {
-        block_add_i64(acc, A.status + ST_LEARN_ACC);
-        block_add_i64(fallback, A.status + ST_LEARN_FALLBACK);
+        block_add_i64(rep ? acc : 0, A.status + ST_LEARN_ACC);
+        block_add_i64(rep ? fallback : 0, A.status + ST_LEARN_FALLBACK);
     }
 }
 
-// rewrite the gather set of particles whose kept h is not the last counted one
+// rewrite the gather set of particles whose kept h is not the last counted
+// one (wave-cooperative, the whole set at the kept h)
 template <int PM>
-__global__ __launch_bounds__(SPH_BLOCK) void k_refill(
-    int64_t n, const double *__restrict__ x, const double *__restrict__ y,
-    const double *__restrict__ z, const double *__restrict__ h, const int32_t *__restrict__ nc,
-    const uint8_t *__restrict__ refill, int32_t *__restrict__ idx, int64_t stride, int K,
-    const int32_t *__restrict__ cs, const double *__restrict__ bbox, Geo g, int lmax, int div,
-    int64_t *__restrict__ status)
+__global__ __launch_bounds__(SPH_BLOCK) void k_refill(HArgs A, int64_t n)
 {
-    int64_t i = global_index();
+#pragma clang fp contract(off)
+    __shared__ WaveLds lds[WAVES_PER_BLOCK];
+    const int w = threadIdx.x >> 6;
+    const int64_t i = global_index();
     int64_t overflow = 0, tested = 0;
-    if (i < n && refill[i]) {
-        Search S = make_search(cs, lmax, div, bbox, g);
-        int N = count_fill<PM>(S, x, y, z, i, x[i], y[i], z[i], h[i], idx, stride, K, true, tested);
-        if (N > K) ++overflow;
-        (void)nc;
+    const bool act = i < n && A.refill[i];
+    if (__ballot(act)) {
+        const Search S = make_search(A.cs, A.lmax, A.div, A.bbox, A.g);
+        double xi = 0.0, yi = 0.0, zi = 0.0, hi = 0.0;
+        uint32_t ki = 0;
+        if (i < n) {
+            xi = A.x[i]; yi = A.y[i]; zi = A.z[i];
+            hi = A.h[i];
+            ki = A.key[i];
+        }
+        const double t2 = 2.0 * hi;
+        const double r2m = t2 * t2;
+        int nsh = 0;
+        bool dfr;
+        int N = wave_count<PM>(lds[w], act, i, xi, yi, zi, ki, hi, false, &dfr, r2m, r2m, A.x, A.y,
+                               A.z, A.idx, A.stride, A.K, A.SH, &nsh, S, A.g, tested);
+        if (act && N > A.K) ++overflow;
     }
-    block_add_i64(overflow, status + ST_LIST_OVERFLOW);
+    block_add_i64(overflow, A.status + ST_LIST_OVERFLOW);
 }
 
 hipError_t launch_hsolve(sph_ctx *c, sph_particles *s, sph_nlist *nl, const double *h_try)
@@ -898,9 +1037,7 @@ hipError_t launch_hsolve(sph_ctx *c, sph_particles *s, sph_nlist *nl, const doub
         }
     }
     SPH_DISPATCH_PM(pm,
-        hipLaunchKernelGGL(k_refill<PM>, dim3(nb), dim3(SPH_BLOCK), 0, c->stream, n, A.x, A.y,
-                           A.z, A.h, A.nc, A.refill, A.idx, A.stride, A.K, A.cs, A.bbox, g,
-                           A.lmax, 1, A.status))
+        hipLaunchKernelGGL(k_refill<PM>, dim3(nb), dim3(SPH_BLOCK), 0, c->stream, A, n))
     return hipGetLastError();
 }
 
