@@ -28,8 +28,19 @@ if ROOT not in sys.path:
 # gradients 19, average 2, viscosity 10 (19 on the approaching half),
 # P/rho^2 2, sums 2, factor 2, acceleration 6, energy 6)
 FORCE_FLOPS_PER_PAIR = 67
-# per candidate of the h iteration: 3 differences, 3 squares, 2 adds, compare
-HSOLVE_FLOPS_PER_CANDIDATE = 9
+# per candidate tested by the h iteration's counting walk: 3 differences,
+# 3 squares, 2 adds (the two comparisons against the shell bounds not counted)
+HSOLVE_FLOPS_PER_CANDIDATE = 8
+# per gather-set pair of the density kernel: differences 3, r^2 5, the
+# complement test 3, sqrt 1, W 8, sum 2, dW/dr 7, /r 1, v_ij 3, dot 5, sum 2
+DENSITY_FLOPS_PER_PAIR = 40
+# algorithmic HBM bytes of the density kernel: own x y z v(3) m h (64 B),
+# nc (4 B), writes rho divv (16 B) and the E row count (4 B), plus 4 B per
+# list entry read
+DENSITY_BYTES_PER_PARTICLE = 88
+# of the first counting walk: own x y z h key (36 B) read, h nc flags state
+# (about 24 B) written, 4 B per gather-set entry written
+HWALK_BYTES_PER_PARTICLE = 60
 FP64_PEAK_TFLOPS = 78.6
 HBM_PEAK_GBS = 8000.0
 # algorithmic HBM bytes of the force kernel per particle, besides 4 B per list
@@ -37,8 +48,11 @@ HBM_PEAK_GBS = 8000.0
 # the writes a(3) du (32 B); neighbour data are re-reads of those fields
 FORCE_BYTES_PER_PARTICLE = 128
 FORCE_BYTES_PER_ENTRY = 4
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_forces_traffic.json")
-FORCE_SOURCE = os.path.join(ROOT, "paper_1905_03344_amd", "csrc", "physics.hip")
+CSRC = os.path.join(ROOT, "paper_1905_03344_amd", "csrc")
+# kernel -> (stage timed around its launch alone, source file holding it)
+KERNELS = {"k_hsolve_round": ("hwalk", "neighbors.hip"),
+           "k_forces": ("forces", "physics.hip"),
+           "k_density": ("density", "physics.hip")}
 
 CONFIG_NAMES = {
     1: "square_patch_20^3_8k_fp64",
@@ -77,15 +91,18 @@ def source_digest(path):
         return hashlib.sha256(f.read()).hexdigest()[:16]
 
 
-def measured_traffic():
-    """HBM bytes per k_forces launch from the committed PMC summary, or None
-    when the kernel source changed since the counters were taken."""
+def measured_traffic(kernel, workload):
+    """HBM bytes per launch of `kernel` on `workload` from the committed PMC
+    summary (profiles/<kernel>_<workload>_traffic.json), or None when there
+    is none or the kernel's source changed since the counters were taken."""
+    path = os.path.join(ROOT, "profiles", f"{kernel}_{workload}_traffic.json")
     try:
-        with open(TRAFFIC_FILE) as f:
+        with open(path) as f:
             t = json.load(f)
     except (OSError, ValueError):
         return None
-    if t.get("source_sha256_16") != source_digest(FORCE_SOURCE):
+    src = os.path.join(CSRC, KERNELS[kernel][1])
+    if t.get("source_sha256_16") != source_digest(src):
         return None
     return t.get("bytes_per_launch")
 
@@ -129,10 +146,42 @@ def main():
 
     torch.cuda.init()
     log(f"bench: config {args.config}, form {args.form}, building inputs")
-    ic = inputs.config_ic(args.config)
+    learned = args.form == "learned"
+    # complement rows: the clumpy mixture's density contrast needs more slots
+    extra_slots = 96 if args.config == 4 else 48
+    # the learned form is timed on seed B of the workload after training on
+    # 20 plain steps of seed A (the same distribution)
+    ic = inputs.config_ic(args.config, seed_offset=100 if learned else 0)
     n = ic.n
     precision = ffi.SPH_FP64 if args.form == "plain" else ffi.SPH_MIXED
-    sim = Simulation(ic, search_div=args.search_div, precision=precision)
+    extra = {}
+    if learned:
+        from paper_1905_03344_amd import learned as L
+        ic_a = inputs.config_ic(args.config)
+        tr = Simulation(ic_a, search_div=args.search_div, precision=precision,
+                        extra_per_particle=extra_slots)
+        tr.evaluate()
+        tr.sync()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        feat, target = L.harvest(tr, steps=20)
+        tr.sync()
+        t1 = time.perf_counter()
+        w, norm, losses = L.train(tr, feat, target, seed=inputs.CONFIG_SEEDS[args.config])
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        extra["training"] = {"harvest_steps": 20, "rows": int(feat.shape[0]),
+                             "harvest_s": round(t1 - t0, 3), "train_s": round(t2 - t1, 3),
+                             "epochs": 4, "batch": 8192,
+                             "loss_first": float(losses[0]), "loss_last": float(losses[-1]),
+                             "target_mse_zero_model": float((target.double() ** 2).mean())}
+        del feat, target, tr
+        torch.cuda.empty_cache()
+    sim = Simulation(ic, search_div=args.search_div, precision=precision,
+                     h_mode=ffi.SPH_H_LEARNED if learned else ffi.SPH_H_PLAIN,
+                     extra_per_particle=extra_slots)
+    if learned:
+        sim.set_mlp(w, norm)
     log(f"bench: n={n} max_level={sim.params.max_level} workspace={sim.ws_bytes/2**20:.1f} MiB")
     sim.evaluate()
     sim.sync()
@@ -157,29 +206,45 @@ def main():
     ms_per_step = total_ms / args.steps
     value = n * args.steps / (total_ms * 1e-3)
 
-    # work of the last step: pairs in S and candidates of the h iteration
+    # work per step: pairs in S (the last step's gather sets plus the mean
+    # complement size) and candidates of the h iteration's first walk
     nc = sim.field("nc")
     pairs_l = int(nc.sum().item())
     pairs_e = int(st.extra_total / max(1, args.steps))
     pairs = pairs_l + pairs_e
-    cand_per_step = st.candidates / args.steps
+    cand_first = st.candidates_first / args.steps
     stage_ms = {k: v[0] / max(1, args.steps) for k, v in stages.items()}
-    force_flops = FORCE_FLOPS_PER_PAIR * pairs
-    hs_flops = HSOLVE_FLOPS_PER_CANDIDATE * cand_per_step
-    t_force = stage_ms["forces"] * 1e-3
-    force_tf = force_flops / t_force / 1e12 if t_force else 0
-    hs_tf = hs_flops / (stage_ms["hsolve"] * 1e-3) / 1e12 if stage_ms["hsolve"] else 0
-    force_bytes = FORCE_BYTES_PER_PARTICLE * n + FORCE_BYTES_PER_ENTRY * pairs
-    force_gbs = force_bytes / t_force / 1e9 if t_force else 0
-    traffic = measured_traffic()
-    # the dominant kernel: k_forces has the longest single launch of the step
-    roofline = {"bound": "alu", "kernel": "k_forces", "achieved": round(force_tf, 3),
-                "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
-                "frac": round(force_tf / FP64_PEAK_TFLOPS, 4), "traffic": traffic,
-                "flops_per_launch": force_flops, "launch_ms": round(stage_ms["forces"], 4),
-                "hbm": {"algorithmic_bytes": force_bytes, "achieved": round(force_gbs, 1),
-                        "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                        "frac": round(force_gbs / HBM_PEAK_GBS, 4)}}
+    work = {
+        "k_hsolve_round": (HSOLVE_FLOPS_PER_CANDIDATE * cand_first,
+                           HWALK_BYTES_PER_PARTICLE * n + 4 * pairs_l),
+        "k_forces": (FORCE_FLOPS_PER_PAIR * pairs,
+                     FORCE_BYTES_PER_PARTICLE * n + FORCE_BYTES_PER_ENTRY * pairs),
+        "k_density": (DENSITY_FLOPS_PER_PAIR * pairs_l, DENSITY_BYTES_PER_PARTICLE * n + 4 * pairs_l),
+    }
+    workload = CONFIG_NAMES[args.config] + ("_seedB" if learned else "")
+    kernels = {}
+    for kname, (flops, nbytes) in work.items():
+        t = stage_ms[KERNELS[kname][0]] * 1e-3
+        tf = flops / t / 1e12 if t else 0.0
+        gbs = nbytes / t / 1e9 if t else 0.0
+        kernels[kname] = {"launch_ms": round(t * 1e3, 4), "flops_per_launch": int(flops),
+                          "achieved_tflops": round(tf, 3),
+                          "frac_fp64": round(tf / FP64_PEAK_TFLOPS, 4),
+                          "algorithmic_bytes": int(nbytes), "achieved_gbs": round(gbs, 1),
+                          "frac_hbm": round(gbs / HBM_PEAK_GBS, 4)}
+    # the dominant kernel: the longest launch of the step (mixed-form
+    # kernels are timed in the same stages; their FP32 work is still
+    # priced against the FP64 peak here, a conservative fraction)
+    dom = max(kernels, key=lambda k: kernels[k]["launch_ms"])
+    kd = kernels[dom]
+    roofline = {"bound": "alu", "kernel": dom, "achieved": kd["achieved_tflops"],
+                "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": kd["frac_fp64"],
+                "traffic": measured_traffic(dom, CONFIG_NAMES[args.config]) if args.form == "plain"
+                else None,
+                "flops_per_launch": kd["flops_per_launch"], "launch_ms": kd["launch_ms"],
+                "hbm": {"algorithmic_bytes": kd["algorithmic_bytes"],
+                        "achieved": kd["achieved_gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                        "frac": kd["frac_hbm"]}}
     out = {
         "metric": "particle-updates/s per full SPH step",
         "value": value,
@@ -193,16 +258,21 @@ def main():
         "vs_baseline": None,
         "dtype": "f64" if args.form == "plain" else "f32/f64",
         "data": "synthetic",
-        "config": {"workload": CONFIG_NAMES[args.config], "n": n, "form": args.form,
-                   "dt": "courant cfl 0.3"},
+        "config": {"workload": workload, "n": n, "form": args.form, "dt": "courant cfl 0.3"},
         "roofline": roofline,
+        "kernels": kernels,
         "stages_ms_per_step": {k: round(v, 4) for k, v in stage_ms.items()},
         "work_per_step": {"pairs_S": pairs, "pairs_L": pairs_l, "pairs_E": pairs_e,
-                          "hsolve_candidates": cand_per_step,
-                          "hsolve_counts_per_particle": st.h_counts / args.steps / n,
-                          "force_tflops": round(force_tf, 3), "hsolve_tflops": round(hs_tf, 3)},
+                          "hsolve_candidates_first_walk": cand_first,
+                          "hsolve_candidates_all": st.candidates / args.steps,
+                          "hsolve_counts_per_particle": st.h_counts / args.steps / n},
         "status": code,
     }
+    if learned:
+        dec = st.learned_accepted + st.learned_fallback
+        extra["accept_rate"] = st.learned_accepted / dec if dec else None
+        extra["fallback_rate"] = st.learned_fallback / dec if dec else None
+        out["learned"] = extra
     if not args.no_cpu_baseline:
         log("bench: cpu baseline (oracle)")
         out["cpu_baseline"] = cpu_baseline(args.config)

@@ -109,17 +109,21 @@ typedef struct sph_particles {
 /* Neighbour lists.  The interaction set of particle i is
  *   S_i = L_i U E_i,   L_i = { j != i : r_ij^2 < (2 h_i)^2 }  (gather set),
  *                      E_i = { j : i in L_j, j not in L_i }    (complement),
- * so that j in S_i <=> i in S_j.  Both parts are stored slot-major ("ELL")
- * with row pitch `stride`: entry k of L_i is idx[k * stride + i], k < nc[i]
- * (nc in sph_particles), in the order the cell walk met them; entry k of
- * E_i is eidx[k * stride + i], k < ecnt[i], in no particular order (the
- * force kernel visits each E_i in ascending index order, so results do not
- * depend on it).  All indices refer to the current (sorted) particle order. */
+ * so that j in S_i <=> i in S_j.  Both parts are stored particle-major: row
+ * i of L is idx[i * list_stride + k], k < nc[i] (nc in sph_particles), and
+ * row i of E is eidx[i * extra_slots + k], k < ecnt[i].  L_i comes in
+ * ascending index order, except that a set completed from the shell of an
+ * earlier count (see sph_find_neighbors) lists the members closer than the
+ * shell's inner radius first, each part ascending; the order depends only on
+ * the particle's positions and h, not on how particles were grouped.  E_i is
+ * in no particular order (the force kernel visits each E_i in ascending
+ * index order, so results do not depend on it).  All indices refer to the
+ * current (sorted) particle order. */
 typedef struct sph_nlist {
-    int32_t *idx;           /* list_stride * stride entries */
-    int64_t stride;         /* row pitch, >= n (a multiple of 64) */
+    int32_t *idx;           /* stride * list_stride entries */
+    int64_t stride;         /* rows allocated, >= n (a multiple of 64) */
     int32_t *ecnt;          /* n: |E_i| (entries beyond extra_slots are dropped and counted) */
-    int32_t *eidx;          /* extra_slots * stride entries */
+    int32_t *eidx;          /* stride * extra_slots entries */
 } sph_nlist;
 
 typedef struct sph_stats {
@@ -133,6 +137,7 @@ typedef struct sph_stats {
     int64_t learned_fallback;/* learned mode: particles that fell back to the iteration */
     int64_t candidates;      /* candidate pairs tested by the h iteration */
     double dt;               /* Courant time step of the last evaluation */
+    int64_t candidates_first;/* of those, tested by its first (all-particle) counting pass */
 } sph_stats;
 
 /* Fill *p with the defaults above (n_max and capacities set to 0). */
@@ -220,7 +225,9 @@ int sph_copy_internal(sph_ctx *ctx, int which, void *dst, size_t bytes, size_t *
  * stage of every subsequent call (overhead: two event records per stage).
  * Stages: SPH_STAGE_CELLS (A1-A4), _HSOLVE (A5 and the gather sets),
  * _EXTRA (complement E), _DENSITY (A7), _EOS (A8), _FORCES (A9 + dt),
- * _INTEGRATE (A10 kicks, drift, prediction), _MLP (learned h prediction). */
+ * _INTEGRATE (A10 kicks, drift, prediction), _MLP (learned h prediction),
+ * _HWALK (the first wave-cooperative counting pass of the h iteration, also
+ * counted in _HSOLVE). */
 #define SPH_STAGE_CELLS 0
 #define SPH_STAGE_HSOLVE 1
 #define SPH_STAGE_EXTRA 2
@@ -229,7 +236,8 @@ int sph_copy_internal(sph_ctx *ctx, int which, void *dst, size_t bytes, size_t *
 #define SPH_STAGE_FORCES 5
 #define SPH_STAGE_INTEGRATE 6
 #define SPH_STAGE_MLP 7          /* learned mode: feature build + MLP inference */
-#define SPH_NSTAGES 8
+#define SPH_STAGE_HWALK 8        /* inside _HSOLVE: the first counting pass alone */
+#define SPH_NSTAGES 9
 
 /* enable = 1 clears the accumulators and starts recording; 0 stops. */
 int sph_timing(sph_ctx *ctx, int enable);

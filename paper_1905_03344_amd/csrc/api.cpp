@@ -390,7 +390,11 @@ static int find_neighbors_impl(sph_ctx *c, sph_particles *s, sph_nlist *nl, cons
 {
     {
         StageScope scope(c, SPH_STAGE_HSOLVE);
-        TRY(launch_hsolve(c, s, nl, h_try), "h iteration");
+        {
+            StageScope walk(c, SPH_STAGE_HWALK);
+            TRY(launch_hsolve(c, s, nl, h_try, 0), "h iteration (first counts)");
+        }
+        TRY(launch_hsolve(c, s, nl, h_try, 1), "h iteration");
     }
     if (with_extra) {
         StageScope scope(c, SPH_STAGE_EXTRA);
@@ -568,6 +572,7 @@ extern "C" int sph_sync(sph_ctx *c, sph_stats *st)
         st->learned_fallback = h[ST_LEARN_FALLBACK];
         st->candidates = h[ST_CANDIDATES];
         st->extra_total = h[ST_EXTRA_TOTAL];
+        st->candidates_first = h[ST_CANDIDATES_FIRST];
     }
     if (h[ST_LIST_OVERFLOW] || h[ST_EXTRA_OVERFLOW])
         return set_err(c, SPH_ECAPACITY, "a neighbour list exceeded its capacity");

@@ -135,7 +135,7 @@ __global__ __launch_bounds__(SPH_BLOCK) void k_density_mixed(
         NeuF dv = {0.0f, 0.0f};
         int cnt = min(nc[i], K);
         for (int k = 0; k < cnt; ++k) {
-            const int j = idx[(int64_t)k * stride + i];
+            const int j = idx[(int64_t)i * K + k];
             const float4 aj = rec[j].a;
             const float4 bj = rec[j].b;
             const uint32_t gj = cell_of(aj);
@@ -161,7 +161,7 @@ __global__ __launch_bounds__(SPH_BLOCK) void k_density_mixed(
                     double twoh = 2.0 * h[j];
                     outside = !(e2 < twoh * twoh);
                 }
-                if (outside) extra_append(j, (int)i, ecnt, eidx, stride, slots, appended, dropped);
+                if (outside) extra_append(j, (int)i, ecnt, eidx, slots, appended, dropped);
             }
             float r = sqrtf(r2);
             const float mj = bj.w;
@@ -271,18 +271,11 @@ __global__ __launch_bounds__(SPH_BLOCK) void k_forces_mixed(
         ForceAccF A = {{0.f, 0.f}, {0.f, 0.f}, {0.f, 0.f}, {0.f, 0.f}, 0.f};
         int cnt = min(nc[i], K);
         for (int k = 0; k < cnt; ++k)
-            force_pair_f<PM>(ri, gi, idx[(int64_t)k * stride + i], rec, G, alpha, beta, eta2, A);
+            force_pair_f<PM>(ri, gi, idx[(int64_t)i * K + k], rec, G, alpha, beta, eta2, A);
+        // E_i in ascending index order (rows are sorted after they are built)
         const int ne = min(ecnt[i], slots);
-        int last = -1;
-        for (int q = 0; q < ne; ++q) {
-            int nxt = 0x7fffffff;
-            for (int k = 0; k < ne; ++k) {
-                int v = eidx[(int64_t)k * stride + i];
-                nxt = (v > last && v < nxt) ? v : nxt;
-            }
-            last = nxt;
-            force_pair_f<PM>(ri, gi, nxt, rec, G, alpha, beta, eta2, A);
-        }
+        const int32_t *erow = eidx + i * (int64_t)slots;
+        for (int q = 0; q < ne; ++q) force_pair_f<PM>(ri, gi, erow[q], rec, G, alpha, beta, eta2, A);
         ax[i] = neu_val(A.ax);
         ay[i] = neu_val(A.ay);
         az[i] = neu_val(A.az);
@@ -336,6 +329,8 @@ hipError_t launch_density_mixed(sph_ctx *c, sph_particles *s, const sph_nlist *n
                                c->p.list_stride, c->w.bbox, g, s->x[cur], s->y[cur], s->z[cur], s->h[cur],
                                s->rho[cur], s->divv[cur], nl->ecnt, nl->eidx, c->p.extra_slots,
                                c->w.status))
+        e = launch_sort_extra(c, nl, n);
+        if (e != hipSuccess) return e;
     } else {
         SPH_DISPATCH_PM(periodic_mask(g),
             hipLaunchKernelGGL((k_density_mixed<PM, false>), dim3(nb), dim3(SPH_BLOCK), 0,

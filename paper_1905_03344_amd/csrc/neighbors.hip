@@ -91,7 +91,7 @@ __device__ __forceinline__ void visit_ranges(const Search &S, double px, double 
 }
 
 // Count of L_i(h) = { j != i : r^2 < (2h)^2 }, writing up to K entries of
-// the set into idx (slot-major).
+// the set into row i of idx.
 template <int PM>
 __device__ __forceinline__ int count_fill(const Search &S, const double *__restrict__ x,
                                           const double *__restrict__ y,
@@ -113,7 +113,7 @@ __device__ __forceinline__ int count_fill(const Search &S, const double *__restr
             double dz = mimg<PM, 2>(zi, z[j], g);
             double r2 = exact_r2(dx, dy, dz);
             if (r2 < r2max && j != (int)i) {
-                if (write && cnt < K) idx[(int64_t)cnt * stride + i] = j;
+                if (write && cnt < K) idx[(int64_t)i * K + cnt] = j;
                 ++cnt;
             }
         }
@@ -143,7 +143,7 @@ __device__ __forceinline__ int count_fill(const Search &S, const double *__restr
 // before the tail, so a miss follows the plain solve's path; cells are
 // walked in Morton order, so its gather set does not depend on which wave
 // counts it.
-// The gather set of the last counted h is written (slot-major); particles
+// The gather set of the last counted h is written (row i of idx); particles
 // whose kept h is not the last counted one are rewritten by k_refill.
 //
 // Counting is wave-cooperative: a wave owns 64 particles (consecutive in
@@ -406,8 +406,9 @@ __device__ void walk_group(WaveLds &L, uint64_t members, int tm, int64_t i, doub
         L.pre[lane] = incl - len;
         wave_lds_sync();
         if (TRANSPOSED ? lane == tm : me) tested += total;
-        for (int base = 0; base < total; base += 64) {
-            int v = base + lane;
+        // candidate v of the batch (-1 past its end): cell by binary search
+        // over the prefix sums
+        auto cand_index = [&](int v) {
             int j = -1;
             if (v < total) {
                 int r = 0;
@@ -415,6 +416,19 @@ __device__ void walk_group(WaveLds &L, uint64_t members, int tm, int64_t i, doub
                     if (L.pre[r + st] <= v) r += st;
                 j = L.start[r] + (v - L.pre[r]);
             }
+            return j;
+        };
+        // union mode keeps the next tile's candidate in flight while the
+        // current tile is tested
+        int jn = -1;
+        double xn = 0.0, yn = 0.0, zn = 0.0;
+        if (!TRANSPOSED) {
+            jn = cand_index(lane);
+            if (jn >= 0) { xn = x[jn]; yn = y[jn]; zn = z[jn]; }
+        }
+        for (int base = 0; base < total; base += 64) {
+            int j = -1;
+            if (TRANSPOSED) j = cand_index(base + lane);
             if (TRANSPOSED) {
                 bool hin = false, hsh = false;
                 double r2 = 0.0;
@@ -426,7 +440,7 @@ __device__ void walk_group(WaveLds &L, uint64_t members, int tm, int64_t i, doub
                 }
                 const uint64_t bin = __ballot(hin);
                 const int pos = Nm + __popcll(bin & below);
-                if (hin && pos < K) idx[(int64_t)pos * stride + im] = j;
+                if (hin && pos < K) idx[(int64_t)im * K + pos] = j;
                 Nm += __popcll(bin);
                 const uint64_t bsh = __ballot(hsh);
                 const int c = __popcll(bsh);
@@ -443,16 +457,18 @@ __device__ void walk_group(WaveLds &L, uint64_t members, int tm, int64_t i, doub
                     }
                 }
             } else {
-                if (j >= 0) {
+                if (jn >= 0) {
                     Cand cd;
-                    cd.x = x[j];
-                    cd.y = y[j];
-                    cd.z = z[j];
-                    cd.j = j;
+                    cd.x = xn;
+                    cd.y = yn;
+                    cd.z = zn;
+                    cd.j = jn;
                     cd.pad = 0;
                     L.c[lane] = cd;
                 }
                 wave_lds_sync();
+                jn = cand_index(base + 64 + lane);
+                if (jn >= 0) { xn = x[jn]; yn = y[jn]; zn = z[jn]; }
                 const int m = min(64, total - base);
                 if (me) {
                     uint64_t hin, hsh;
@@ -469,8 +485,7 @@ __device__ void walk_group(WaveLds &L, uint64_t members, int tm, int64_t i, doub
                         hin &= hin - 1;
                         int jj = L.c[t].j;
                         if (jj != (int)i) {
-                            if (N < K) *wp = jj;
-                            wp += stride;
+                            if (N < K) wp[N] = jj;
                             ++N;
                         }
                     }
@@ -561,18 +576,18 @@ __device__ void walk_group(WaveLds &L, uint64_t members, int tm, int64_t i, doub
 }
 
 // One wave-cooperative count for every lane with act set at its own hc:
-// members with r^2 < A are written to idx (slot-major, at most K), shell
+// members with r^2 < A are written to row i of idx (at most K), shell
 // members (A <= r^2 < B) to the shell arrays (at most SPH_SHELL_SLOTS;
 // *nsh = -1 when more).  Returns the number of inner members (self
 // excluded); self is never a shell member.  With A = B there is no shell and
 // the whole gather set at sqrt(A)/2 is written.  The output does not depend
 // on which lanes are counted together.  Lanes are grouped by position and by
-// hsplit (their h for that purpose); with defer_small, lanes that end up in
+// hsplit (their h for that purpose); with DEFER, lanes that end up in
 // a small group are not counted and get *deferred = true (their particles
 // are better served one per wave).
-template <int PM>
+template <int PM, bool DEFER>
 __device__ int wave_count(WaveLds &L, bool act, int64_t i, double xi, double yi, double zi,
-                          uint32_t ki, double hsplit, bool defer_small, bool *deferred,
+                          uint32_t ki, double hsplit, bool *deferred,
                           double A2, double B2, const double *__restrict__ x,
                           const double *__restrict__ y, const double *__restrict__ z,
                           int32_t *__restrict__ idx, int64_t stride, int K, const Shell &SH,
@@ -583,7 +598,7 @@ __device__ int wave_count(WaveLds &L, bool act, int64_t i, double xi, double yi,
     const double twoh = 2.0 * hsplit;
     *deferred = false;
     int N = 0, nsh = 0;
-    int32_t *wp = idx + i;   // slot N of this particle's gather set
+    int32_t *wp = idx + i * (int64_t)K;   // this particle's row of the gather sets
     uint64_t pending = __ballot(act);
     while (pending) {
         // sub-group: the pending lanes, split by Morton prefix while their
@@ -610,9 +625,9 @@ __device__ int wave_count(WaveLds &L, bool act, int64_t i, double xi, double yi,
             members &= __ballot(((ki ^ lk) >> hb) == 0u);
         }
         pending &= ~members;
-        if (defer_small && __popcll(members) <= SPH_SMALL_GROUP) {
+        if (DEFER && __popcll(members) <= SPH_SMALL_GROUP) {
             if ((members >> lane) & 1ull) *deferred = true;
-        } else if (__popcll(members) <= SPH_SMALL_GROUP) {
+        } else if (!DEFER && __popcll(members) <= SPH_SMALL_GROUP) {
             uint64_t rest = members;
             while (rest) {
                 const int m = __ffsll((unsigned long long)rest) - 1;
@@ -743,8 +758,12 @@ struct HArgs {
 // (the worklist wl of wcount particles).  After its count a particle keeps
 // iterating on its shell while the next h stays inside it; particles that
 // need another full count save their state and raise work[i].
-template <int PM>
-__global__ __launch_bounds__(SPH_BLOCK) void k_hsolve_round(HArgs A, int64_t n,
+template <int PM, bool FIRST>
+#ifndef SPH_ROUND_WAVES
+#define SPH_ROUND_WAVES 4   // waves per SIMD the round kernel is compiled for (measured best)
+#endif
+__global__ __launch_bounds__(SPH_BLOCK)
+__attribute__((amdgpu_waves_per_eu(SPH_ROUND_WAVES, SPH_ROUND_WAVES))) void k_hsolve_round(HArgs A, int64_t n,
                                                             const int32_t *__restrict__ wl,
                                                             const int64_t *__restrict__ wcount)
 {
@@ -765,26 +784,19 @@ __global__ __launch_bounds__(SPH_BLOCK) void k_hsolve_round(HArgs A, int64_t n,
     const bool valid = listed && (!wl || (A.H.bits[i] >> 8) < SPH_WAVE_ROUNDS + 1);
     const Search S = make_search(A.cs, A.lmax, A.div, A.bbox, A.g);
 
-    double xi = 0.0, yi = 0.0, zi = 0.0, hprev = 0.0;
-    uint32_t ki = 0;
-    HState st = {};
+    // only what the walk needs is live across it; the iteration state is
+    // set up (round 0) or loaded (later rounds) afterwards
+    double hc = 0.0, hsplit = 0.0;
     if (valid) {
-        xi = A.x[i]; yi = A.y[i]; zi = A.z[i];
-        ki = A.key[i];
-        hprev = A.h[i];
-        if (wl) {
-            st = hs_load(A.H, i);
+        if (FIRST) {
+            hsplit = A.h[i];
+            hc = A.h_try ? A.h_try[i] : hsplit;
         } else {
-            st.next = A.h_try ? A.h_try[i] : hprev;
-            st.lo = st.hi = 0.0;
-            st.best_h = st.last_h = hprev;
-            st.best_n = -1;
-            st.itk = 0;
-            st.bits = A.h_try ? 4 : 0;
+            hc = A.H.next[i];
+            hsplit = hc;
         }
     }
     int64_t tested = 0, counts = 0, acc = 0, fallback = 0, nonconv = 0, overflow = 0;
-    const double hc = st.next;
     const double ta = 2.0 * hc * (1.0 - 1.0 / 32.0), tb = 2.0 * hc * (1.0 + 1.0 / 32.0);
     const double A2 = ta * ta, B2 = tb * tb;
     int nin = 0, nsh = 0;
@@ -792,10 +804,32 @@ __global__ __launch_bounds__(SPH_BLOCK) void k_hsolve_round(HArgs A, int64_t n,
     // a wave whose slots are all past the end has nothing to do.  Round 0
     // groups by h_prev (the same groups with or without a learned try) and
     // leaves particles of small groups to the per-particle tail.
-    if (__ballot(valid))
-        nin = wave_count<PM>(lds[w], valid, i, xi, yi, zi, ki, wl ? hc : hprev, !wl, &deferred,
-                             A2, B2, A.x, A.y, A.z, A.idx, A.stride, A.K, A.SH, &nsh, S, A.g,
-                             tested);
+    if (__ballot(valid)) {
+        double xi = 0.0, yi = 0.0, zi = 0.0;
+        uint32_t ki = 0;
+        if (valid) {
+            xi = A.x[i]; yi = A.y[i]; zi = A.z[i];
+            ki = A.key[i];
+        }
+        nin = wave_count<PM, FIRST>(lds[w], valid, i, xi, yi, zi, ki, hsplit, &deferred, A2, B2,
+                                    A.x, A.y, A.z, A.idx, A.stride, A.K, A.SH, &nsh, S, A.g,
+                                    tested);
+    }
+    double hprev = 0.0;
+    HState st = {};
+    if (valid) {
+        hprev = A.h[i];
+        if (!FIRST) {
+            st = hs_load(A.H, i);
+        } else {
+            st.next = hc;
+            st.lo = st.hi = 0.0;
+            st.best_h = st.last_h = hprev;
+            st.best_n = -1;
+            st.itk = 0;
+            st.bits = A.h_try ? 4 : 0;
+        }
+    }
     if (valid && deferred) {
         // no walk taken: untouched state, walk budget spent so that only
         // the tail takes it up
@@ -868,7 +902,7 @@ __global__ __launch_bounds__(SPH_BLOCK) void k_hsolve_round(HArgs A, int64_t n,
                 int pos = nin;
                 for (int k = 0; k < ns; ++k) {
                     if (A.SH.r2[(int64_t)k * A.SH.sstride + i] < r2k) {
-                        if (pos < A.K) A.idx[(int64_t)pos * A.stride + i] = A.SH.j[(int64_t)k * A.SH.sstride + i];
+                        if (pos < A.K) A.idx[i * (int64_t)A.K + pos] = A.SH.j[(int64_t)k * A.SH.sstride + i];
                         ++pos;
                     }
                 }
@@ -882,6 +916,7 @@ __global__ __launch_bounds__(SPH_BLOCK) void k_hsolve_round(HArgs A, int64_t n,
     }
     block_add_i64(counts, A.status + ST_HCOUNTS);
     block_add_i64(tested, A.status + ST_CANDIDATES);
+    if (!wl) block_add_i64(tested, A.status + ST_CANDIDATES_FIRST);
     block_add_i64(nonconv, A.status + ST_NONCONV);
     block_add_i64(overflow, A.status + ST_LIST_OVERFLOW);
     if (A.h_try) {
@@ -928,7 +963,7 @@ __global__ __launch_bounds__(SPH_BLOCK) void k_hsolve_tail(HArgs A, const int32_
             const double r2m = t2 * t2;
             int nsh = 0;
             bool dfr;
-            int N = wave_count<PM>(lds[w], lane == 0, i, xi, yi, zi, ki, hc, false, &dfr, r2m, r2m,
+            int N = wave_count<PM, false>(lds[w], lane == 0, i, xi, yi, zi, ki, hc, &dfr, r2m, r2m,
                                    A.x, A.y, A.z, A.idx, A.stride, A.K, A.SH, &nsh, S, A.g,
                                    tested);
             N = __shfl(N, 0, 64);
@@ -973,14 +1008,16 @@ __global__ __launch_bounds__(SPH_BLOCK) void k_refill(HArgs A, int64_t n)
         const double r2m = t2 * t2;
         int nsh = 0;
         bool dfr;
-        int N = wave_count<PM>(lds[w], act, i, xi, yi, zi, ki, hi, false, &dfr, r2m, r2m, A.x, A.y,
+        int N = wave_count<PM, false>(lds[w], act, i, xi, yi, zi, ki, hi, &dfr, r2m, r2m, A.x, A.y,
                                A.z, A.idx, A.stride, A.K, A.SH, &nsh, S, A.g, tested);
         if (act && N > A.K) ++overflow;
     }
     block_add_i64(overflow, A.status + ST_LIST_OVERFLOW);
 }
 
-hipError_t launch_hsolve(sph_ctx *c, sph_particles *s, sph_nlist *nl, const double *h_try)
+// phase 0: round 0 alone; phase 1: the worklist round, tail and refill
+hipError_t launch_hsolve(sph_ctx *c, sph_particles *s, sph_nlist *nl, const double *h_try,
+                         int phase)
 {
     int64_t n = s->n;
     if (n == 0) return hipSuccess;
@@ -1014,9 +1051,12 @@ hipError_t launch_hsolve(sph_ctx *c, sph_particles *s, sph_nlist *nl, const doub
     A.SH = {c->w.shell_j, c->w.shell_r2, c->w.shell_stride};
     A.status = c->w.status;
     const int pm = periodic_mask(g);
-    SPH_DISPATCH_PM(pm,
-        hipLaunchKernelGGL(k_hsolve_round<PM>, dim3(nb), dim3(SPH_BLOCK), 0, c->stream, A, n,
-                           (const int32_t *)nullptr, (const int64_t *)nullptr))
+    if (phase == 0) {
+        SPH_DISPATCH_PM(pm,
+            hipLaunchKernelGGL((k_hsolve_round<PM, true>), dim3(nb), dim3(SPH_BLOCK), 0, c->stream, A,
+                               n, (const int32_t *)nullptr, (const int64_t *)nullptr))
+        return hipGetLastError();
+    }
     // after a try pass the misses get the plain solve's full set of rounds
     const int rounds = SPH_WAVE_ROUNDS + (h_try ? 1 : 0);
     for (int r = 0; r <= rounds; ++r) {
@@ -1028,7 +1068,7 @@ hipError_t launch_hsolve(sph_ctx *c, sph_particles *s, sph_nlist *nl, const doub
             // the worklist size is only known on the device: launch for all
             // and let waves past its end return at once
             SPH_DISPATCH_PM(pm,
-                hipLaunchKernelGGL(k_hsolve_round<PM>, dim3(nb), dim3(SPH_BLOCK), 0, c->stream,
+                hipLaunchKernelGGL((k_hsolve_round<PM, false>), dim3(nb), dim3(SPH_BLOCK), 0, c->stream,
                                    A, n, c->w.wl, c->w.woff + n))
         } else {
             SPH_DISPATCH_PM(pm,
@@ -1072,13 +1112,13 @@ __global__ __launch_bounds__(SPH_BLOCK) void k_extra(
         double xi = x[i], yi = y[i], zi = z[i];
         int m = min(nc[i], K);
         for (int k = 0; k < m; ++k) {
-            int j = idx[(int64_t)k * stride + i];
+            int j = idx[(int64_t)i * K + k];
             double dx = mimg<PM, 0>(xi, x[j], g);
             double dy = mimg<PM, 1>(yi, y[j], g);
             double dz = mimg<PM, 2>(zi, z[j], g);
             double r2 = exact_r2(dx, dy, dz);
             double twoh = 2.0 * h[j];
-            if (!(r2 < twoh * twoh)) extra_append(j, (int)i, ecnt, eidx, stride, slots, appended, dropped);
+            if (!(r2 < twoh * twoh)) extra_append(j, (int)i, ecnt, eidx, slots, appended, dropped);
         }
     }
     block_add_i64(appended, status + ST_EXTRA_TOTAL);
@@ -1098,5 +1138,7 @@ hipError_t launch_extra(sph_ctx *c, sph_particles *s, sph_nlist *nl)
         hipLaunchKernelGGL(k_extra<PM>, dim3(nb), dim3(SPH_BLOCK), 0, c->stream, n, s->x[cur],
                            s->y[cur], s->z[cur], s->h[cur], s->nc[cur], nl->idx, nl->stride,
                            p.list_stride, g, nl->ecnt, nl->eidx, p.extra_slots, c->w.status))
-    return hipGetLastError();
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    return launch_sort_extra(c, nl, n);
 }

@@ -5,52 +5,136 @@
 // rho_i = m_i W(0,h_i) + sum_{L_i} m_j W(r_ij,h_i);
 // divv_i = (1/rho_i) sum_{L_i} m_j (v_j - v_i) . grad_i W(r_ij,h_i).
 // With EXTRA the same pass appends i to E_j for every one-sided pair.
+// Pair loops run with SPH_GROUP lanes per particle: the gather set of a
+// particle lies in ascending index order (neighbouring cells in Morton
+// order), so the lanes of a group load short runs of consecutive particles
+// and each load touches a few cache lines instead of one per lane.  Each
+// lane sums its share of the pairs (k = lane, lane + SPH_GROUP, ...) and the
+// group adds the partial sums in a fixed butterfly order, so results are
+// reproducible.  Block b treats particles [SPH_BLOCK b, SPH_BLOCK (b+1)):
+// in round r its 16 groups take particles SPH_BLOCK b + 16 r + group.
+#define SPH_GROUP 16
+#define SPH_BATCH 4
+#define SPH_FBATCH 2
+
+__device__ __forceinline__ double group_sum(double v)
+{
+    for (int o = SPH_GROUP / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, SPH_GROUP);
+    return v;
+}
+__device__ __forceinline__ double group_max(double v)
+{
+    for (int o = SPH_GROUP / 2; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, SPH_GROUP));
+    return v;
+}
+
 template <int PM, bool EXTRA>
 __global__ __launch_bounds__(SPH_BLOCK) void k_density(
     int64_t n, const double *__restrict__ x, const double *__restrict__ y,
     const double *__restrict__ z, const double *__restrict__ vx, const double *__restrict__ vy,
     const double *__restrict__ vz, const double *__restrict__ m, const double *__restrict__ h,
-    const int32_t *__restrict__ nc, const int32_t *__restrict__ idx, int64_t stride, int K,
-    Geo g, double *__restrict__ rho, double *__restrict__ divv, int32_t *__restrict__ ecnt,
+    const int32_t *__restrict__ nc, const int32_t *__restrict__ idx, int K, Geo g,
+    double *__restrict__ rho, double *__restrict__ divv, int32_t *__restrict__ ecnt,
     int32_t *__restrict__ eidx, int slots, int64_t *__restrict__ status)
 {
-    int64_t i = global_index();
+    const int lane = threadIdx.x & (SPH_GROUP - 1);
+    const int grp = threadIdx.x / SPH_GROUP;
+    const int64_t base = (int64_t)xcd_block(blockIdx.x, gridDim.x) * SPH_BLOCK;
     int64_t appended = 0, dropped = 0;
-    if (i < n) {
-        double xi = x[i], yi = y[i], zi = z[i];
-        double vxi = vx[i], vyi = vy[i], vzi = vz[i];
-        double inv_h = 1.0 / h[i];
-        double s = m[i] * kern_w(0.0, inv_h);
-        double dv = 0.0;
-        int cnt = min(nc[i], K);
-        for (int k = 0; k < cnt; ++k) {
-            int j = idx[(int64_t)k * stride + i];
-            double dx = mimg<PM, 0>(xi, x[j], g);
-            double dy = mimg<PM, 1>(yi, y[j], g);
-            double dz = mimg<PM, 2>(zi, z[j], g);
-            double r2 = exact_r2(dx, dy, dz);
-            if (EXTRA) {
+    for (int r = 0; r < SPH_BLOCK / SPH_GROUP; ++r) {
+        const int64_t i = base + (int64_t)r * (SPH_BLOCK / SPH_GROUP) + grp;
+        double s = 0.0, dv = 0.0, inv_h = 0.0;
+        if (i < n) {
+            const double xi = x[i], yi = y[i], zi = z[i];
+            const double vxi = vx[i], vyi = vy[i], vzi = vz[i];
+            inv_h = 1.0 / h[i];
+            const int cnt = min(nc[i], K);
+            const int32_t *row = idx + i * (int64_t)K;
+            // batches of SPH_BATCH pairs per lane: indices first, then every
+            // gather of the batch, then the arithmetic (slots past the end
+            // point at particle i itself and are skipped)
+            for (int k0 = lane; k0 < cnt; k0 += SPH_BATCH * SPH_GROUP) {
+                int jb[SPH_BATCH];
+#pragma unroll
+                for (int q = 0; q < SPH_BATCH; ++q) {
+                    const int k = k0 + q * SPH_GROUP;
+                    jb[q] = k < cnt ? row[k] : (int)i;
+                }
+                double xb[SPH_BATCH], yb[SPH_BATCH], zb[SPH_BATCH], hb[SPH_BATCH], mb[SPH_BATCH];
+                double ub[SPH_BATCH], vb[SPH_BATCH], wb[SPH_BATCH];
+#pragma unroll
+                for (int q = 0; q < SPH_BATCH; ++q) {
+                    const int j = jb[q];
+                    xb[q] = x[j]; yb[q] = y[j]; zb[q] = z[j];
+                    if (EXTRA) hb[q] = h[j];
+                    mb[q] = m[j];
+                    ub[q] = vx[j]; vb[q] = vy[j]; wb[q] = vz[j];
+                }
+#pragma unroll
+                for (int q = 0; q < SPH_BATCH; ++q) {
+                    if (k0 + q * SPH_GROUP >= cnt) break;
+                    const int j = jb[q];
+                    double dx = mimg<PM, 0>(xi, xb[q], g);
+                    double dy = mimg<PM, 1>(yi, yb[q], g);
+                    double dz = mimg<PM, 2>(zi, zb[q], g);
+                    double r2 = exact_r2(dx, dy, dz);
+                    if (EXTRA) {
 #pragma clang fp contract(off)
-                double twoh = 2.0 * h[j];
-                if (!(r2 < twoh * twoh))
-                    extra_append(j, (int)i, ecnt, eidx, stride, slots, appended, dropped);
-            }
-            double r = sqrt(r2);
-            double mj = m[j];
-            s += mj * kern_w(r, inv_h);
-            if (r > 0.0) {
-                double gw = kern_dwdr(r, inv_h) / r;
-                double vdot = (vx[j] - vxi) * (-dx) + (vy[j] - vyi) * (-dy) + (vz[j] - vzi) * (-dz);
-                dv += mj * vdot * gw;
+                        double twoh = 2.0 * hb[q];
+                        if (!(r2 < twoh * twoh))
+                            extra_append(j, (int)i, ecnt, eidx, slots, appended, dropped);
+                    }
+                    double rr = sqrt(r2);
+                    double mj = mb[q];
+                    s += mj * kern_w(rr, inv_h);
+                    if (rr > 0.0) {
+                        double gw = kern_dwdr(rr, inv_h) / rr;
+                        double vdot = (ub[q] - vxi) * (-dx) + (vb[q] - vyi) * (-dy) + (wb[q] - vzi) * (-dz);
+                        dv += mj * vdot * gw;
+                    }
+                }
             }
         }
-        rho[i] = s;
-        divv[i] = dv / s;
+        s = group_sum(s);
+        dv = group_sum(dv);
+        if (i < n && lane == 0) {
+            const double rh = m[i] * kern_w(0.0, inv_h) + s;
+            rho[i] = rh;
+            divv[i] = dv / rh;
+        }
     }
     if (EXTRA) {
         block_add_i64(appended, status + ST_EXTRA_TOTAL);
         block_add_i64(dropped, status + ST_EXTRA_OVERFLOW);
     }
+}
+
+// E rows in ascending order (their slots were taken by atomics), one thread
+// per row, insertion sort in place
+__global__ __launch_bounds__(SPH_BLOCK) void k_sort_extra(int64_t n, const int32_t *__restrict__ ecnt,
+                                                          int32_t *__restrict__ eidx, int slots)
+{
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int ne = min(ecnt[i], slots);
+    int32_t *row = eidx + i * (int64_t)slots;
+    for (int a = 1; a < ne; ++a) {
+        const int v = row[a];
+        int b = a - 1;
+        while (b >= 0 && row[b] > v) {
+            row[b + 1] = row[b];
+            --b;
+        }
+        row[b + 1] = v;
+    }
+}
+
+hipError_t launch_sort_extra(sph_ctx *c, const sph_nlist *nl, int64_t n)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_sort_extra, dim3((unsigned)ceil_div(n, SPH_BLOCK)), dim3(SPH_BLOCK), 0,
+                       c->stream, n, nl->ecnt, nl->eidx, c->p.extra_slots);
+    return hipGetLastError();
 }
 
 hipError_t launch_density(sph_ctx *c, sph_particles *s, const sph_nlist *nl, bool build_extra)
@@ -68,14 +152,16 @@ hipError_t launch_density(sph_ctx *c, sph_particles *s, const sph_nlist *nl, boo
         SPH_DISPATCH_PM(periodic_mask(g),
             hipLaunchKernelGGL((k_density<PM, true>), dim3(nb), dim3(SPH_BLOCK), 0, c->stream, n,
                                s->x[cur], s->y[cur], s->z[cur], s->pvx, s->pvy, s->pvz, s->m[cur],
-                               s->h[cur], s->nc[cur], nl->idx, nl->stride, c->p.list_stride, g,
+                               s->h[cur], s->nc[cur], nl->idx, c->p.list_stride, g,
                                s->rho[cur], s->divv[cur], nl->ecnt, nl->eidx, c->p.extra_slots,
                                c->w.status))
+        hipError_t e = launch_sort_extra(c, nl, n);
+        if (e != hipSuccess) return e;
     } else {
         SPH_DISPATCH_PM(periodic_mask(g),
             hipLaunchKernelGGL((k_density<PM, false>), dim3(nb), dim3(SPH_BLOCK), 0, c->stream, n,
                                s->x[cur], s->y[cur], s->z[cur], s->pvx, s->pvy, s->pvz, s->m[cur],
-                               s->h[cur], s->nc[cur], nl->idx, nl->stride, c->p.list_stride, g,
+                               s->h[cur], s->nc[cur], nl->idx, c->p.list_stride, g,
                                s->rho[cur], s->divv[cur], nl->ecnt, nl->eidx, c->p.extra_slots,
                                c->w.status))
     }
@@ -117,50 +203,64 @@ struct ForceAcc {
     double ax, ay, az, du, mumax;
 };
 
-template <int PM>
-__device__ __forceinline__ void force_pair(int j, double xi, double yi, double zi, double vxi,
-                                           double vyi, double vzi, double hi, double inv_hi,
-                                           double rhoi, double ci, double pi_term,
-                                           const double *__restrict__ x,
-                                           const double *__restrict__ y,
-                                           const double *__restrict__ z,
-                                           const double *__restrict__ vx,
-                                           const double *__restrict__ vy,
-                                           const double *__restrict__ vz,
-                                           const double *__restrict__ m,
-                                           const double *__restrict__ h,
-                                           const double *__restrict__ rho,
-                                           const double *__restrict__ p,
-                                           const double *__restrict__ c, const Geo &g,
-                                           double alpha, double beta, double eta2, ForceAcc &A)
+// neighbour fields of one pair, gathered ahead of the arithmetic
+struct NbrF {
+    double x, y, z, vx, vy, vz, m, h, rho, p, c;
+};
+
+__device__ __forceinline__ NbrF load_nbr(int j, const double *__restrict__ x,
+                                         const double *__restrict__ y,
+                                         const double *__restrict__ z,
+                                         const double *__restrict__ vx,
+                                         const double *__restrict__ vy,
+                                         const double *__restrict__ vz,
+                                         const double *__restrict__ m,
+                                         const double *__restrict__ h,
+                                         const double *__restrict__ rho,
+                                         const double *__restrict__ p,
+                                         const double *__restrict__ c)
 {
-    double dx = mimg<PM, 0>(xi, x[j], g);
-    double dy = mimg<PM, 1>(yi, y[j], g);
-    double dz = mimg<PM, 2>(zi, z[j], g);
+    NbrF b;
+    b.x = x[j]; b.y = y[j]; b.z = z[j];
+    b.vx = vx[j]; b.vy = vy[j]; b.vz = vz[j];
+    b.m = m[j]; b.h = h[j]; b.rho = rho[j]; b.p = p[j]; b.c = c[j];
+    return b;
+}
+
+template <int PM>
+__device__ __forceinline__ void force_pair(const NbrF &b, double xi, double yi, double zi,
+                                           double vxi, double vyi, double vzi, double hi,
+                                           double inv_hi, double rhoi, double ci, double pi_term,
+                                           const Geo &g, double alpha, double beta, double eta2,
+                                           ForceAcc &A)
+{
+    double dx = mimg<PM, 0>(xi, b.x, g);
+    double dy = mimg<PM, 1>(yi, b.y, g);
+    double dz = mimg<PM, 2>(zi, b.z, g);
     double r2 = dx * dx + dy * dy + dz * dz;
     if (!(r2 > 0.0)) return;
     double r = sqrt(r2);
     double inv_r = 1.0 / r;
-    double hj = h[j];
+    double hj = b.h;
     double xij = -dx, yij = -dy, zij = -dz;
-    double vxij = vxi - vx[j], vyij = vyi - vy[j], vzij = vzi - vz[j];
+    double vxij = vxi - b.vx, vyij = vyi - b.vy, vzij = vzi - b.vz;
     double w = vxij * xij + vyij * yij + vzij * zij;
     double gwi = kern_dwdr(r, inv_hi) * inv_r;
     double gwj = kern_dwdr(r, 1.0 / hj) * inv_r;
     double gbar = 0.5 * (gwi + gwj);
-    double rhoj = rho[j];
+    double rhoj = b.rho;
     double Pi = 0.0;
     if (w < 0.0) {
         double hb = 0.5 * (hi + hj);
-        double cb = 0.5 * (ci + c[j]);
+        double cb = 0.5 * (ci + b.c);
         double rb = 0.5 * (rhoi + rhoj);
         double mu = hb * w / (r2 + eta2 * hb * hb);
         Pi = (-alpha * cb * mu + beta * mu * mu) / rb;
         A.mumax = fmax(A.mumax, fabs(mu));
     }
-    double pj_term = p[j] / (rhoj * rhoj);
+    double pj_term = b.p / (rhoj * rhoj);
     double sfac = (pi_term + pj_term) + Pi;
-    double mj = m[j];
+    double mj = b.m;
     double f = mj * sfac * gbar;
     A.ax -= f * xij;
     A.ay -= f * yij;
@@ -168,48 +268,71 @@ __device__ __forceinline__ void force_pair(int j, double xi, double yi, double z
     A.du += mj * (pi_term + 0.5 * Pi) * gbar * w;
 }
 
+// S_i = L_i (row order) then E_i (ascending) in groups of SPH_GROUP lanes
 template <int PM>
 __global__ __launch_bounds__(SPH_BLOCK) void k_forces(
     int64_t n, const double *__restrict__ x, const double *__restrict__ y,
     const double *__restrict__ z, const double *__restrict__ vx, const double *__restrict__ vy,
     const double *__restrict__ vz, const double *__restrict__ m, const double *__restrict__ h,
     const double *__restrict__ rho, const double *__restrict__ p, const double *__restrict__ c,
-    const int32_t *__restrict__ nc, const int32_t *__restrict__ idx, int64_t stride, int K,
+    const int32_t *__restrict__ nc, const int32_t *__restrict__ idx, int K,
     const int32_t *__restrict__ ecnt, const int32_t *__restrict__ eidx, int slots, Geo g,
     double alpha, double beta, double eta2, double cfl, double *__restrict__ ax,
     double *__restrict__ ay, double *__restrict__ az, double *__restrict__ du,
     double *__restrict__ dt_part)
 {
-    int64_t i = global_index();
+    const int lane = threadIdx.x & (SPH_GROUP - 1);
+    const int grp = threadIdx.x / SPH_GROUP;
+    const int64_t blk = xcd_block(blockIdx.x, gridDim.x);
+    const int64_t base = blk * SPH_BLOCK;
     double dti = INFINITY;
-    if (i < n) {
-        double xi = x[i], yi = y[i], zi = z[i];
-        double vxi = vx[i], vyi = vy[i], vzi = vz[i];
-        double hi = h[i], inv_hi = 1.0 / hi, rhoi = rho[i], ci = c[i];
-        double pi_term = p[i] / (rhoi * rhoi);
+    for (int r = 0; r < SPH_BLOCK / SPH_GROUP; ++r) {
+        const int64_t i = base + (int64_t)r * (SPH_BLOCK / SPH_GROUP) + grp;
         ForceAcc A = {0.0, 0.0, 0.0, 0.0, 0.0};
-        int cnt = min(nc[i], K);
-        for (int k = 0; k < cnt; ++k)
-            force_pair<PM>(idx[(int64_t)k * stride + i], xi, yi, zi, vxi, vyi, vzi, hi, inv_hi, rhoi,
-                       ci, pi_term, x, y, z, vx, vy, vz, m, h, rho, p, c, g, alpha, beta, eta2, A);
-        // E_i in ascending index order (its slots were filled by atomics)
-        const int ne = min(ecnt[i], slots);
-        int last = -1;
-        for (int q = 0; q < ne; ++q) {
-            int nxt = 0x7fffffff;
-            for (int k = 0; k < ne; ++k) {
-                int v = eidx[(int64_t)k * stride + i];
-                nxt = (v > last && v < nxt) ? v : nxt;
+        double hi = 0.0, ci = 0.0;
+        if (i < n) {
+            const double xi = x[i], yi = y[i], zi = z[i];
+            const double vxi = vx[i], vyi = vy[i], vzi = vz[i];
+            hi = h[i];
+            const double inv_hi = 1.0 / hi, rhoi = rho[i];
+            ci = c[i];
+            const double pi_term = p[i] / (rhoi * rhoi);
+            const int cnt = min(nc[i], K);
+            const int ne = min(ecnt[i], slots);
+            const int32_t *lrow = idx + i * (int64_t)K;
+            const int32_t *erow = eidx + i * (int64_t)slots;
+            const int tot = cnt + ne;
+            for (int k0 = lane; k0 < tot; k0 += SPH_FBATCH * SPH_GROUP) {
+                int jb[SPH_FBATCH];
+#pragma unroll
+                for (int q = 0; q < SPH_FBATCH; ++q) {
+                    const int k = k0 + q * SPH_GROUP;
+                    jb[q] = k < cnt ? lrow[k] : (k < tot ? erow[k - cnt] : (int)i);
+                }
+                NbrF nb[SPH_FBATCH];
+#pragma unroll
+                for (int q = 0; q < SPH_FBATCH; ++q)
+                    nb[q] = load_nbr(jb[q], x, y, z, vx, vy, vz, m, h, rho, p, c);
+#pragma unroll
+                for (int q = 0; q < SPH_FBATCH; ++q) {
+                    if (k0 + q * SPH_GROUP >= tot) break;
+                    force_pair<PM>(nb[q], xi, yi, zi, vxi, vyi, vzi, hi, inv_hi, rhoi, ci,
+                                   pi_term, g, alpha, beta, eta2, A);
+                }
             }
-            last = nxt;
-            force_pair<PM>(nxt, xi, yi, zi, vxi, vyi, vzi, hi, inv_hi, rhoi, ci, pi_term, x, y, z,
-                       vx, vy, vz, m, h, rho, p, c, g, alpha, beta, eta2, A);
         }
-        ax[i] = A.ax;
-        ay[i] = A.ay;
-        az[i] = A.az;
-        du[i] = A.du;
-        dti = cfl * hi / (ci + 1.2 * (alpha * ci + beta * A.mumax));
+        A.ax = group_sum(A.ax);
+        A.ay = group_sum(A.ay);
+        A.az = group_sum(A.az);
+        A.du = group_sum(A.du);
+        A.mumax = group_max(A.mumax);
+        if (i < n && lane == 0) {
+            ax[i] = A.ax;
+            ay[i] = A.ay;
+            az[i] = A.az;
+            du[i] = A.du;
+            dti = fmin(dti, cfl * hi / (ci + 1.2 * (alpha * ci + beta * A.mumax)));
+        }
     }
     // block minimum of dt_i (min is exact and order independent)
     __shared__ double sh[SPH_BLOCK];
@@ -219,7 +342,7 @@ __global__ __launch_bounds__(SPH_BLOCK) void k_forces(
         if ((int)threadIdx.x < s) sh[threadIdx.x] = fmin(sh[threadIdx.x], sh[threadIdx.x + s]);
         __syncthreads();
     }
-    if (threadIdx.x == 0) dt_part[blockIdx.x] = sh[0];
+    if (threadIdx.x == 0) dt_part[blk] = sh[0];
 }
 
 __global__ __launch_bounds__(SPH_BLOCK) void k_min_final(const double *__restrict__ part, int64_t nb,
@@ -249,7 +372,7 @@ hipError_t launch_forces(sph_ctx *c, sph_particles *s, const sph_nlist *nl, doub
     SPH_DISPATCH_PM(periodic_mask(g),
         hipLaunchKernelGGL(k_forces<PM>, dim3((unsigned)nb), dim3(SPH_BLOCK), 0, c->stream, n,
                            s->x[cur], s->y[cur], s->z[cur], s->pvx, s->pvy, s->pvz, s->m[cur],
-                           s->h[cur], s->rho[cur], s->p, s->c, s->nc[cur], nl->idx, nl->stride,
+                           s->h[cur], s->rho[cur], s->p, s->c, s->nc[cur], nl->idx,
                            p.list_stride, nl->ecnt, nl->eidx, p.extra_slots, g, p.av_alpha, p.av_beta,
                            p.av_eta2, p.cfl, s->ax[cur], s->ay[cur], s->az[cur], s->du[cur], part))
     return hipGetLastError();

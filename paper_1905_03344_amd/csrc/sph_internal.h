@@ -27,6 +27,7 @@ enum {
     ST_LEARN_FALLBACK = 6,
     ST_CANDIDATES = 7,
     ST_EXTRA_TOTAL = 8,
+    ST_CANDIDATES_FIRST = 9,   // candidates tested by round 0 of the h iteration
     ST_COUNT = 16
 };
 
@@ -106,8 +107,10 @@ hipError_t launch_cell_table(sph_ctx *c, const uint32_t *sorted_key, int64_t n);
 hipError_t launch_scan_i32_to_i64(sph_ctx *c, const int32_t *in, int64_t *out, int64_t n);
 hipError_t launch_scan_u32(sph_ctx *c, const uint32_t *in, uint32_t *out, int64_t n);
 
-hipError_t launch_hsolve(sph_ctx *c, sph_particles *s, sph_nlist *nl, const double *h_try);
+hipError_t launch_hsolve(sph_ctx *c, sph_particles *s, sph_nlist *nl, const double *h_try,
+                         int phase);
 hipError_t launch_extra(sph_ctx *c, sph_particles *s, sph_nlist *nl);
+hipError_t launch_sort_extra(sph_ctx *c, const sph_nlist *nl, int64_t n);
 hipError_t launch_density(sph_ctx *c, sph_particles *s, const sph_nlist *nl, bool build_extra);
 hipError_t launch_zero_i32(sph_ctx *c, int32_t *a, int64_t n);
 hipError_t launch_eos(sph_ctx *c, sph_particles *s);
@@ -218,13 +221,14 @@ static inline int periodic_mask(const Geo &g) { return g.per[0] | (g.per[1] << 1
 
 // Complement rows: i goes into E_j when j is in L_i but i is not in L_j,
 // i.e. r_ij^2 >= (2 h_j)^2 (the same exact test j's own gather used).
-// Slots come from an integer atomic; rows past `slots` are counted.
+// Slots come from an integer atomic (row j at eidx + j * slots); rows past
+// `slots` are counted.
 __device__ __forceinline__ void extra_append(int j, int i, int32_t *__restrict__ ecnt,
-                                             int32_t *__restrict__ eidx, int64_t stride, int slots,
+                                             int32_t *__restrict__ eidx, int slots,
                                              int64_t &appended, int64_t &dropped)
 {
     int k = atomicAdd(&ecnt[j], 1);
-    if (k < slots) eidx[(int64_t)k * stride + j] = i;
+    if (k < slots) eidx[(int64_t)j * slots + k] = i;
     else if (k == slots) ++dropped;   // count each overflowing row once
     ++appended;
 }

@@ -63,7 +63,7 @@ class sph_stats(ctypes.Structure):
     _fields_ = [("nonconverged", _I64), ("list_overflow", _I64), ("extra_total", _I64),
                 ("extra_overflow", _I64), ("nonfinite", _I64), ("h_counts", _I64),
                 ("learned_accepted", _I64), ("learned_fallback", _I64), ("candidates", _I64),
-                ("dt", _D)]
+                ("dt", _D), ("candidates_first", _I64)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -115,7 +115,7 @@ SPH_MLP_NFEAT = 8
 MLP_LAYOUT = {"W1": (0, (64, 6)), "b1": (384, (64,)), "W2": (448, (64, 64)),
               "b2": (4544, (64,)), "W3": (4608, (1, 64)), "b3": (4672, (1,))}
 
-STAGES = ("cells", "hsolve", "extra", "density", "eos", "forces", "integrate", "mlp")
+STAGES = ("cells", "hsolve", "extra", "density", "eos", "forces", "integrate", "mlp", "hwalk")
 
 # entry points of the learned / mixed forms, bound when present
 _OPTIONAL = {}

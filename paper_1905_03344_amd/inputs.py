@@ -233,17 +233,19 @@ def shuffle_order(seed: int, n: int) -> np.ndarray:
 CONFIG_SEEDS = {1: 1905033441, 2: 1905033442, 3: 1905033443, 4: 1905033444, 5: 1905033445}
 
 
-def config_ic(cfg: int) -> ParticleSet:
+def config_ic(cfg: int, seed_offset: int = 0) -> ParticleSet:
     """Initial conditions of the five workloads (square patch 20^3, 100^3,
-    200^3, clumpy 1M, square patch 400^3)."""
+    200^3, clumpy 1M, square patch 400^3); seed_offset draws another sample
+    of the same distribution (100: the learned form's evaluation seed)."""
+    if cfg not in CONFIG_SEEDS:
+        raise ValueError(f"unknown config {cfg}")
+    seed = CONFIG_SEEDS[cfg] + seed_offset
     if cfg == 1:
-        return square_patch(20, CONFIG_SEEDS[1])
+        return square_patch(20, seed)
     if cfg == 2:
-        return square_patch(100, CONFIG_SEEDS[2])
+        return square_patch(100, seed)
     if cfg == 3:
-        return square_patch(200, CONFIG_SEEDS[3])
+        return square_patch(200, seed)
     if cfg == 4:
-        return clumpy(seed=CONFIG_SEEDS[4])
-    if cfg == 5:
-        return square_patch(400, CONFIG_SEEDS[5])
-    raise ValueError(f"unknown config {cfg}")
+        return clumpy(seed=seed)
+    return square_patch(400, seed)

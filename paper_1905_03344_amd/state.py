@@ -214,21 +214,21 @@ class Simulation:
         n = self.n
         nc = self.numpy("nc")
         K = self.params.list_stride
-        idx = self.nl_idx.view(K, self.stride)[:, :n].cpu().numpy()
+        idx = self.nl_idx.view(self.stride, K)[:n].cpu().numpy().T
         return nc, [idx[:min(int(nc[i]), K), i] for i in range(n)]
 
     def gather_dense(self):
         """(nc, idx[K, n]) numpy view of the gather sets."""
         n = self.n
         K = self.params.list_stride
-        return self.numpy("nc"), self.nl_idx.view(K, self.stride)[:, :n].cpu().numpy()
+        return self.numpy("nc"), self.nl_idx.view(self.stride, K)[:n].cpu().numpy().T
 
     def extra_lists(self):
         """(eoff, eidx): the complement rows as CSR with ascending rows."""
         n = self.n
         ke = self.params.extra_slots
         ecnt = np.minimum(self.nl_ecnt[:n].cpu().numpy(), ke)
-        e = self.nl_eidx.view(ke, self.stride)[:, :n].cpu().numpy()
+        e = self.nl_eidx.view(self.stride, ke)[:n].cpu().numpy().T
         mask = np.arange(ke)[:, None] < ecnt[None, :]
         kk, ii = np.nonzero(mask)
         code = np.sort(ii.astype(np.int64) * max(n, 1) + e[kk, ii].astype(np.int64))
