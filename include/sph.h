@@ -258,8 +258,7 @@ int sph_timing_read(sph_ctx *ctx, double *ms, int64_t *count, int nstages);
  *   f4 = dt (div v)_i, f5 = dt |v_i| / h_i, f6 = dt c_i / h_i,
  * taken from the previous evaluation (h, N, rho, div v) and the predicted
  * state of this step (v = pv, c = sqrt(gamma (gamma-1) pu), dt of the step),
- * to y ~ log(h_c / h_i), h_c the centre of the band of solutions (targets
- * below).  In sph_step (and sph_find_neighbors) the first
+ * to y ~ log(h_new / h_i) (training targets below).  In sph_step (and sph_find_neighbors) the first
  * count of particle i is taken at h_i exp(clamp(y, -1/2, 1/2)); within
  * n_tol of n_target it is accepted (SPH_FLAG_LEARNED), otherwise the plain
  * iteration runs from h_i exactly as in SPH_H_PLAIN.  sph_evaluate always
@@ -303,11 +302,17 @@ int sph_get_features(sph_ctx *ctx, const sph_particles *s, const double *d_dt, f
 /* Training sink: while set (both non-NULL), every sph_step writes, in the
  * particle order of that step, the feature rows of its start into
  * d_feat[n][SPH_MLP_NFEAT] and the targets into d_target[n] (n = particles
- * of the step; device arrays of at least n_max rows).  The target is
- * log(h_c) - f1 with h_c = h_new (n_target / N_new)^(1/3): the solved h moved
- * to the centre of the band by the h^3 scaling of the count (N_new > 0).
- * NULL, NULL turns it off. */
-int sph_set_harvest(sph_ctx *ctx, float *d_feat, float *d_target);
+ * of the step; device arrays of at least n_max rows).  Target modes:
+ *   SPH_TARGET_SOLVED:  log(h_new) - f1, the h the iteration settled on;
+ *   SPH_TARGET_CENTRED: log(h_c) - f1, h_c = h_new (n_target / N_new)^(1/3),
+ *     the solved h moved to the band centre by the h^3 scaling of the count.
+ * Any h in the band solves the problem; the centred target leaves the widest
+ * margin where the count grows smoothly with h (irregular particle
+ * distributions), the solved one suits near-lattice distributions, whose
+ * count grows in whole neighbour shells.  NULL, NULL turns the sink off. */
+#define SPH_TARGET_SOLVED 0
+#define SPH_TARGET_CENTRED 1
+int sph_set_harvest(sph_ctx *ctx, float *d_feat, float *d_target, int32_t target_mode);
 
 /* Inference on n device feature rows: y[n] (device), and, when non-NULL,
  * the bfloat16 bit patterns of the two hidden layers' rounded activations

@@ -534,7 +534,8 @@ extern "C" int sph_step(sph_ctx *c, sph_particles *s, sph_nlist *nl, double dt, 
     if (r) return r;
     if (c->harvest_feat) {
         StageScope scope(c, SPH_STAGE_MLP);
-        TRY(launch_mlp_targets(c, s, c->harvest_feat, c->harvest_target), "harvest targets");
+        TRY(launch_mlp_targets(c, s, c->harvest_feat, c->harvest_target,
+                               c->harvest_mode == SPH_TARGET_CENTRED), "harvest targets");
     }
     {
         StageScope scope(c, SPH_STAGE_INTEGRATE);
@@ -672,14 +673,17 @@ extern "C" int sph_get_features(sph_ctx *c, const sph_particles *s, const double
     return SPH_OK;
 }
 
-extern "C" int sph_set_harvest(sph_ctx *c, float *d_feat, float *d_target)
+extern "C" int sph_set_harvest(sph_ctx *c, float *d_feat, float *d_target, int32_t target_mode)
 {
     int r = check_bound(c);
     if (r) return r;
     if ((d_feat == nullptr) != (d_target == nullptr))
         return set_err(c, SPH_EINVAL, "harvest needs both arrays or neither");
+    if (target_mode != SPH_TARGET_SOLVED && target_mode != SPH_TARGET_CENTRED)
+        return set_err(c, SPH_EINVAL, "unknown target mode");
     c->harvest_feat = d_feat;
     c->harvest_target = d_target;
+    c->harvest_mode = target_mode;
     return SPH_OK;
 }
 

@@ -5,15 +5,31 @@
 // an FP32 prefilter with an FP64 test for the ambiguous band.
 #include "sph_internal.h"
 
-// Per-particle FP32 record, 64 bytes:
-//   a = {delta_x, delta_y, delta_z, cell}   cell = gx | gy << 10 | gz << 20
-//   b = {vx, vy, vz, m}
-//   c = {h, 1/h, rho, P/rho^2}
-//   d = {c_sound, 0, 0, 0}
+// Per-particle FP32 fields, four float4 arrays (one 16-byte quad per
+// particle each, so that a group of lanes reading consecutive particles
+// touches consecutive memory):
+//   A = {delta_x, delta_y, delta_z, cell}   cell = gx | gy << 10 | gz << 20
+//   B = {vx, vy, vz, m}
+//   C = {h, 1/h, rho, P/rho^2}
+//   D = {c_sound, 0, 0, 0}
 // with x = lo + g * w + delta, w = L/1024 the key-cell width.
-struct __align__(16) MixRec {
-    float4 a, b, c, d;
+struct MixQ {
+    float4 *A, *B, *C, *D;
 };
+__host__ __device__ static inline MixQ mix_quads(void *base, int64_t n_max)
+{
+    float4 *q = (float4 *)base;
+    return MixQ{q, q + n_max, q + 2 * n_max, q + 3 * n_max};
+}
+
+// lanes per particle in the pair loops, and their partial sums combined in a
+// fixed butterfly order (Neumaier steps: the same value in every lane)
+#define SPH_MGROUP 16
+__device__ __forceinline__ float mgroup_max(float v)
+{
+    for (int o = SPH_MGROUP / 2; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o, SPH_MGROUP));
+    return v;
+}
 
 struct MixGeo {
     float w[3];    // key-cell width per dimension
@@ -32,6 +48,15 @@ __device__ __forceinline__ void neu_add(NeuF &a, float v)
     a.s = t;
 }
 __device__ __forceinline__ double neu_val(const NeuF &a) { return (double)a.s + (double)a.c; }
+__device__ __forceinline__ NeuF mgroup_neu(NeuF a)
+{
+    for (int o = SPH_MGROUP / 2; o > 0; o >>= 1) {
+        const float os = __shfl_xor(a.s, o, SPH_MGROUP), oc = __shfl_xor(a.c, o, SPH_MGROUP);
+        neu_add(a, os);
+        a.c += oc;
+    }
+    return a;
+}
 
 __device__ __forceinline__ uint32_t cell_of(float4 a) { return __float_as_uint(a.w); }
 
@@ -79,7 +104,7 @@ __global__ __launch_bounds__(SPH_BLOCK) void k_pack_mixed(
     int64_t n, const double *__restrict__ x, const double *__restrict__ y,
     const double *__restrict__ z, const double *__restrict__ vx, const double *__restrict__ vy,
     const double *__restrict__ vz, const double *__restrict__ m, const double *__restrict__ h,
-    const double *__restrict__ bbox, MixRec *__restrict__ rec)
+    const double *__restrict__ bbox, MixQ Q)
 {
     int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (i >= n) return;
@@ -93,13 +118,11 @@ __global__ __launch_bounds__(SPH_BLOCK) void k_pack_mixed(
         dl[d] = (float)((p[d] - lo) - (double)g * w);
         cell |= (uint32_t)g << (10 * d);
     }
-    MixRec r;
-    r.a = make_float4(dl[0], dl[1], dl[2], __uint_as_float(cell));
-    r.b = make_float4((float)vx[i], (float)vy[i], (float)vz[i], (float)m[i]);
+    Q.A[i] = make_float4(dl[0], dl[1], dl[2], __uint_as_float(cell));
+    Q.B[i] = make_float4((float)vx[i], (float)vy[i], (float)vz[i], (float)m[i]);
     double hi = h[i];
-    r.c = make_float4((float)hi, (float)(1.0 / hi), 0.0f, 0.0f);
-    r.d = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-    rec[i] = r;
+    Q.C[i] = make_float4((float)hi, (float)(1.0 / hi), 0.0f, 0.0f);
+    Q.D[i] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
 }
 
 // ---------------------------------------------------------------------------
@@ -117,64 +140,79 @@ __device__ __forceinline__ MixGeo mix_geo(const double *__restrict__ bbox, const
 
 template <int PM, bool EXTRA>
 __global__ __launch_bounds__(SPH_BLOCK) void k_density_mixed(
-    int64_t n, const MixRec *__restrict__ rec, const int32_t *__restrict__ nc,
-    const int32_t *__restrict__ idx, int64_t stride, int K, const double *__restrict__ bbox, Geo g,
-    const double *__restrict__ x, const double *__restrict__ y, const double *__restrict__ z,
-    const double *__restrict__ h, double *__restrict__ rho, double *__restrict__ divv,
-    int32_t *__restrict__ ecnt, int32_t *__restrict__ eidx, int slots,
-    int64_t *__restrict__ status)
+    int64_t n, MixQ Q, const int32_t *__restrict__ nc, const int32_t *__restrict__ idx, int K,
+    const double *__restrict__ bbox, Geo g, const double *__restrict__ x,
+    const double *__restrict__ y, const double *__restrict__ z, const double *__restrict__ h,
+    double *__restrict__ rho, double *__restrict__ divv, int32_t *__restrict__ ecnt,
+    int32_t *__restrict__ eidx, int slots, int64_t *__restrict__ status)
 {
-    int64_t i = global_index();
+    const int lane = threadIdx.x & (SPH_MGROUP - 1);
+    const int grp = threadIdx.x / SPH_MGROUP;
+    const int64_t base = (int64_t)xcd_block(blockIdx.x, gridDim.x) * SPH_BLOCK;
     int64_t appended = 0, dropped = 0;
     const MixGeo G = mix_geo(bbox, g);
-    if (i < n) {
-        const MixRec ri = rec[i];
-        const uint32_t gi = cell_of(ri.a);
-        const float inv_h = ri.c.y;
-        NeuF s = {ri.b.w * kern_w_f(0.0f, inv_h), 0.0f};
-        NeuF dv = {0.0f, 0.0f};
-        int cnt = min(nc[i], K);
-        for (int k = 0; k < cnt; ++k) {
-            const int j = idx[(int64_t)i * K + k];
-            const float4 aj = rec[j].a;
-            const float4 bj = rec[j].b;
-            const uint32_t gj = cell_of(aj);
-            float dx = split_diff<PM, 0>(gi, gj, ri.a.x, aj.x, G);
-            float dy = split_diff<PM, 1>(gi, gj, ri.a.y, aj.y, G);
-            float dz = split_diff<PM, 2>(gi, gj, ri.a.z, aj.z, G);
-            float r2 = dx * dx + dy * dy + dz * dz;
-            if (EXTRA) {
-                // is i outside j's gather sphere?  FP32 decides clear cases
-                // (|error| of r2 is below 1e-6 relative), FP64 the band
-                const float hj = rec[j].c.x;
-                const float lim = 4.0f * hj * hj;
-                bool outside;
-                if (r2 > lim * (1.0f + 1e-5f)) {
-                    outside = true;
-                } else if (r2 < lim * (1.0f - 1e-5f)) {
-                    outside = false;
-                } else {
+    for (int rr = 0; rr < SPH_BLOCK / SPH_MGROUP; ++rr) {
+        const int64_t i = base + (int64_t)rr * (SPH_BLOCK / SPH_MGROUP) + grp;
+        NeuF s = {0.0f, 0.0f}, dv = {0.0f, 0.0f};
+        float4 ai = make_float4(0.f, 0.f, 0.f, 0.f), bi = ai;
+        float inv_h = 0.0f;
+        if (i < n) {
+            ai = Q.A[i];
+            bi = Q.B[i];
+            inv_h = Q.C[i].y;
+            const uint32_t gi = cell_of(ai);
+            const int cnt = min(nc[i], K);
+            const int32_t *row = idx + i * (int64_t)K;
+            for (int k = lane; k < cnt; k += SPH_MGROUP) {
+                const int j = row[k];
+                const float4 aj = Q.A[j];
+                const float4 bj = Q.B[j];
+                const uint32_t gj = cell_of(aj);
+                float dx = split_diff<PM, 0>(gi, gj, ai.x, aj.x, G);
+                float dy = split_diff<PM, 1>(gi, gj, ai.y, aj.y, G);
+                float dz = split_diff<PM, 2>(gi, gj, ai.z, aj.z, G);
+                float r2 = dx * dx + dy * dy + dz * dz;
+                if (EXTRA) {
+                    // is i outside j's gather sphere?  FP32 decides clear
+                    // cases (|error| of r2 is below 1e-6 relative), FP64 the
+                    // band
+                    const float hj = Q.C[j].x;
+                    const float lim = 4.0f * hj * hj;
+                    bool outside;
+                    if (r2 > lim * (1.0f + 1e-5f)) {
+                        outside = true;
+                    } else if (r2 < lim * (1.0f - 1e-5f)) {
+                        outside = false;
+                    } else {
 #pragma clang fp contract(off)
-                    double ex = mimg<PM, 0>(x[i], x[j], g), ey = mimg<PM, 1>(y[i], y[j], g),
-                           ez = mimg<PM, 2>(z[i], z[j], g);
-                    double e2 = exact_r2(ex, ey, ez);
-                    double twoh = 2.0 * h[j];
-                    outside = !(e2 < twoh * twoh);
+                        double ex = mimg<PM, 0>(x[i], x[j], g), ey = mimg<PM, 1>(y[i], y[j], g),
+                               ez = mimg<PM, 2>(z[i], z[j], g);
+                        double e2 = exact_r2(ex, ey, ez);
+                        double twoh = 2.0 * h[j];
+                        outside = !(e2 < twoh * twoh);
+                    }
+                    if (outside) extra_append(j, (int)i, ecnt, eidx, slots, appended, dropped);
                 }
-                if (outside) extra_append(j, (int)i, ecnt, eidx, slots, appended, dropped);
-            }
-            float r = sqrtf(r2);
-            const float mj = bj.w;
-            neu_add(s, mj * kern_w_f(r, inv_h));
-            if (r > 0.0f) {
-                float gw = kern_dwdr_f(r, inv_h) / r;
-                float vdot = (bj.x - ri.b.x) * (-dx) + (bj.y - ri.b.y) * (-dy) + (bj.z - ri.b.z) * (-dz);
-                neu_add(dv, mj * vdot * gw);
+                float r = sqrtf(r2);
+                const float mj = bj.w;
+                neu_add(s, mj * kern_w_f(r, inv_h));
+                if (r > 0.0f) {
+                    float gw = kern_dwdr_f(r, inv_h) / r;
+                    float vdot = (bj.x - bi.x) * (-dx) + (bj.y - bi.y) * (-dy) + (bj.z - bi.z) * (-dz);
+                    neu_add(dv, mj * vdot * gw);
+                }
             }
         }
-        double sd = neu_val(s);
-        rho[i] = sd;
-        divv[i] = neu_val(dv) / sd;
+        s = mgroup_neu(s);
+        dv = mgroup_neu(dv);
+        if (i < n && lane == 0) {
+            NeuF tot = {bi.w * kern_w_f(0.0f, inv_h), 0.0f};
+            neu_add(tot, s.s);
+            tot.c += s.c;
+            const double sd = neu_val(tot);
+            rho[i] = sd;
+            divv[i] = neu_val(dv) / sd;
+        }
     }
     if (EXTRA) {
         block_add_i64(appended, status + ST_EXTRA_TOTAL);
@@ -187,7 +225,7 @@ __global__ __launch_bounds__(SPH_BLOCK) void k_eos_mixed(int64_t n, const double
                                                          const double *__restrict__ u, double gamma,
                                                          double *__restrict__ p,
                                                          double *__restrict__ c,
-                                                         MixRec *__restrict__ rec, int check,
+                                                         MixQ Q, int check,
                                                          int64_t *__restrict__ status)
 {
     int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
@@ -198,9 +236,9 @@ __global__ __launch_bounds__(SPH_BLOCK) void k_eos_mixed(int64_t n, const double
         double cv = sqrt(gamma * (gamma - 1.0) * u[i]);
         p[i] = pv;
         c[i] = cv;
-        rec[i].c.z = (float)rh;
-        rec[i].c.w = (float)(pv / (rh * rh));
-        rec[i].d.x = (float)cv;
+        Q.C[i].z = (float)rh;
+        Q.C[i].w = (float)(pv / (rh * rh));
+        Q.D[i].x = (float)cv;
         if (check && !(isfinite(pv) && isfinite(cv) && isfinite(rh))) bad = 1;
     }
     if (check) block_add_i64(bad, status + ST_NONFINITE);
@@ -214,12 +252,16 @@ struct ForceAccF {
     float mumax;
 };
 
+// own fields of particle i (a, b, c, d) and the gathered fields of j
+struct QuadF {
+    float4 a, b, c, d;
+};
+
 template <int PM>
-__device__ __forceinline__ void force_pair_f(const MixRec &ri, uint32_t gi, int j,
-                                             const MixRec *__restrict__ rec, const MixGeo &G,
-                                             float alpha, float beta, float eta2, ForceAccF &A)
+__device__ __forceinline__ void force_pair_f(const QuadF &ri, uint32_t gi, const QuadF &rj,
+                                             const MixGeo &G, float alpha, float beta,
+                                             float eta2, ForceAccF &A)
 {
-    const MixRec rj = rec[j];
     const uint32_t gj = cell_of(rj.a);
     float dx = split_diff<PM, 0>(gi, gj, ri.a.x, rj.a.x, G);
     float dy = split_diff<PM, 1>(gi, gj, ri.a.y, rj.a.y, G);
@@ -252,36 +294,58 @@ __device__ __forceinline__ void force_pair_f(const MixRec &ri, uint32_t gi, int 
     neu_add(A.du, mj * (ri.c.w + 0.5f * Pi) * gbar * w);
 }
 
+// S_i = L_i (row order) then E_i (ascending), SPH_MGROUP lanes per particle
 template <int PM>
 __global__ __launch_bounds__(SPH_BLOCK) void k_forces_mixed(
-    int64_t n, const MixRec *__restrict__ rec, const int32_t *__restrict__ nc,
-    const int32_t *__restrict__ idx, int64_t stride, int K, const int32_t *__restrict__ ecnt,
-    const int32_t *__restrict__ eidx, int slots, const double *__restrict__ bbox, Geo g,
-    float alpha, float beta, float eta2, double alpha_d, double beta_d, double cfl,
-    const double *__restrict__ h,
-    const double *__restrict__ c, double *__restrict__ ax, double *__restrict__ ay,
-    double *__restrict__ az, double *__restrict__ du, double *__restrict__ dt_part)
+    int64_t n, MixQ Q, const int32_t *__restrict__ nc, const int32_t *__restrict__ idx, int K,
+    const int32_t *__restrict__ ecnt, const int32_t *__restrict__ eidx, int slots,
+    const double *__restrict__ bbox, Geo g, float alpha, float beta, float eta2, double alpha_d,
+    double beta_d, double cfl, const double *__restrict__ h, const double *__restrict__ c,
+    double *__restrict__ ax, double *__restrict__ ay, double *__restrict__ az,
+    double *__restrict__ du, double *__restrict__ dt_part)
 {
-    int64_t i = global_index();
+    const int lane = threadIdx.x & (SPH_MGROUP - 1);
+    const int grp = threadIdx.x / SPH_MGROUP;
+    const int64_t blk = xcd_block(blockIdx.x, gridDim.x);
+    const int64_t base = blk * SPH_BLOCK;
     double dti = INFINITY;
     const MixGeo G = mix_geo(bbox, g);
-    if (i < n) {
-        const MixRec ri = rec[i];
-        const uint32_t gi = cell_of(ri.a);
+    for (int rr = 0; rr < SPH_BLOCK / SPH_MGROUP; ++rr) {
+        const int64_t i = base + (int64_t)rr * (SPH_BLOCK / SPH_MGROUP) + grp;
         ForceAccF A = {{0.f, 0.f}, {0.f, 0.f}, {0.f, 0.f}, {0.f, 0.f}, 0.f};
-        int cnt = min(nc[i], K);
-        for (int k = 0; k < cnt; ++k)
-            force_pair_f<PM>(ri, gi, idx[(int64_t)i * K + k], rec, G, alpha, beta, eta2, A);
-        // E_i in ascending index order (rows are sorted after they are built)
-        const int ne = min(ecnt[i], slots);
-        const int32_t *erow = eidx + i * (int64_t)slots;
-        for (int q = 0; q < ne; ++q) force_pair_f<PM>(ri, gi, erow[q], rec, G, alpha, beta, eta2, A);
-        ax[i] = neu_val(A.ax);
-        ay[i] = neu_val(A.ay);
-        az[i] = neu_val(A.az);
-        du[i] = neu_val(A.du);
-        double ci = c[i];
-        dti = cfl * h[i] / (ci + 1.2 * (alpha_d * ci + beta_d * (double)A.mumax));
+        if (i < n) {
+            QuadF ri;
+            ri.a = Q.A[i]; ri.b = Q.B[i]; ri.c = Q.C[i]; ri.d = Q.D[i];
+            const uint32_t gi = cell_of(ri.a);
+            const int cnt = min(nc[i], K);
+            const int ne = min(ecnt[i], slots);
+            const int tot = cnt + ne;
+            const int32_t *lrow = idx + i * (int64_t)K;
+            const int32_t *erow = eidx + i * (int64_t)slots;
+            for (int k0 = lane; k0 < tot; k0 += 2 * SPH_MGROUP) {
+                const int k1 = k0 + SPH_MGROUP;
+                const int j0 = k0 < cnt ? lrow[k0] : erow[k0 - cnt];
+                const int j1 = k1 < cnt ? lrow[k1] : (k1 < tot ? erow[k1 - cnt] : (int)i);
+                QuadF r0, r1;
+                r0.a = Q.A[j0]; r0.b = Q.B[j0]; r0.c = Q.C[j0]; r0.d = Q.D[j0];
+                r1.a = Q.A[j1]; r1.b = Q.B[j1]; r1.c = Q.C[j1]; r1.d = Q.D[j1];
+                force_pair_f<PM>(ri, gi, r0, G, alpha, beta, eta2, A);
+                if (k1 < tot) force_pair_f<PM>(ri, gi, r1, G, alpha, beta, eta2, A);
+            }
+        }
+        A.ax = mgroup_neu(A.ax);
+        A.ay = mgroup_neu(A.ay);
+        A.az = mgroup_neu(A.az);
+        A.du = mgroup_neu(A.du);
+        A.mumax = mgroup_max(A.mumax);
+        if (i < n && lane == 0) {
+            ax[i] = neu_val(A.ax);
+            ay[i] = neu_val(A.ay);
+            az[i] = neu_val(A.az);
+            du[i] = neu_val(A.du);
+            const double ci = c[i];
+            dti = fmin(dti, cfl * h[i] / (ci + 1.2 * (alpha_d * ci + beta_d * (double)A.mumax)));
+        }
     }
     __shared__ double sh[SPH_BLOCK];
     sh[threadIdx.x] = dti;
@@ -290,12 +354,18 @@ __global__ __launch_bounds__(SPH_BLOCK) void k_forces_mixed(
         if ((int)threadIdx.x < s) sh[threadIdx.x] = fmin(sh[threadIdx.x], sh[threadIdx.x + s]);
         __syncthreads();
     }
-    if (threadIdx.x == 0) dt_part[blockIdx.x] = sh[0];
+    if (threadIdx.x == 0) dt_part[blk] = sh[0];
 }
 
 // ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
+// the record area holds n_max particles (at least one) of each quad array
+static MixQ ctx_quads(sph_ctx *c)
+{
+    return mix_quads(c->w.mixrec, c->p.n_max > 0 ? c->p.n_max : 1);
+}
+
 hipError_t launch_pack_mixed(sph_ctx *c, sph_particles *s)
 {
     int64_t n = s->n;
@@ -303,7 +373,7 @@ hipError_t launch_pack_mixed(sph_ctx *c, sph_particles *s)
     int k = s->cur;
     hipLaunchKernelGGL(k_pack_mixed, dim3((unsigned)ceil_div(n, SPH_BLOCK)), dim3(SPH_BLOCK), 0,
                        c->stream, n, s->x[k], s->y[k], s->z[k], s->pvx, s->pvy, s->pvz, s->m[k],
-                       s->h[k], c->w.bbox, (MixRec *)c->w.mixrec);
+                       s->h[k], c->w.bbox, ctx_quads(c));
     return hipGetLastError();
 }
 
@@ -321,11 +391,11 @@ hipError_t launch_density_mixed(sph_ctx *c, sph_particles *s, const sph_nlist *n
     int cur = s->cur;
     Geo g = make_geo(c->p);
     unsigned nb = (unsigned)ceil_div(n, SPH_BLOCK);
-    const MixRec *rec = (const MixRec *)c->w.mixrec;
+    const MixQ Q = ctx_quads(c);
     if (build_extra) {
         SPH_DISPATCH_PM(periodic_mask(g),
             hipLaunchKernelGGL((k_density_mixed<PM, true>), dim3(nb), dim3(SPH_BLOCK), 0,
-                               c->stream, n, rec, s->nc[cur], nl->idx, nl->stride,
+                               c->stream, n, Q, s->nc[cur], nl->idx,
                                c->p.list_stride, c->w.bbox, g, s->x[cur], s->y[cur], s->z[cur], s->h[cur],
                                s->rho[cur], s->divv[cur], nl->ecnt, nl->eidx, c->p.extra_slots,
                                c->w.status))
@@ -334,7 +404,7 @@ hipError_t launch_density_mixed(sph_ctx *c, sph_particles *s, const sph_nlist *n
     } else {
         SPH_DISPATCH_PM(periodic_mask(g),
             hipLaunchKernelGGL((k_density_mixed<PM, false>), dim3(nb), dim3(SPH_BLOCK), 0,
-                               c->stream, n, rec, s->nc[cur], nl->idx, nl->stride,
+                               c->stream, n, Q, s->nc[cur], nl->idx,
                                c->p.list_stride, c->w.bbox, g, s->x[cur], s->y[cur], s->z[cur], s->h[cur],
                                s->rho[cur], s->divv[cur], nl->ecnt, nl->eidx, c->p.extra_slots,
                                c->w.status))
@@ -348,7 +418,7 @@ hipError_t launch_eos_mixed(sph_ctx *c, sph_particles *s)
     if (n == 0) return hipSuccess;
     hipLaunchKernelGGL(k_eos_mixed, dim3((unsigned)ceil_div(n, SPH_BLOCK)), dim3(SPH_BLOCK), 0,
                        c->stream, n, s->rho[s->cur], s->pu, c->p.gamma, s->p, s->c,
-                       (MixRec *)c->w.mixrec, c->p.check_finite, c->w.status);
+                       ctx_quads(c), c->p.check_finite, c->w.status);
     return hipGetLastError();
 }
 
@@ -361,7 +431,7 @@ hipError_t launch_forces_mixed(sph_ctx *c, sph_particles *s, const sph_nlist *nl
     Geo g = make_geo(p);
     SPH_DISPATCH_PM(periodic_mask(g),
         hipLaunchKernelGGL(k_forces_mixed<PM>, dim3((unsigned)nb), dim3(SPH_BLOCK), 0, c->stream,
-                           n, (const MixRec *)c->w.mixrec, s->nc[cur], nl->idx, nl->stride,
+                           n, ctx_quads(c), s->nc[cur], nl->idx,
                            p.list_stride, nl->ecnt, nl->eidx, p.extra_slots, c->w.bbox, g,
                            (float)p.av_alpha,
                            (float)p.av_beta, (float)p.av_eta2, p.av_alpha, p.av_beta, p.cfl,

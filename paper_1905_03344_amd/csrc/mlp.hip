@@ -214,20 +214,20 @@ __global__ __launch_bounds__(SPH_BLOCK) void k_mlp_features(
     feat[i * 8 + 7] = 0.0f;
 }
 
-// training targets: y = log(h_c / h_then), h_then = exp(feature 1), where
-// h_c = h_now (n_target / N_now)^(1/3) is the band centre estimated from the
-// solved h and its count (counts scale with h^3 at fixed density): any h in
-// the band is a solution, the centre leaves the widest margin for a try
+// training targets: y = log(h_now / h_then), h_then = exp(feature 1); with
+// centre, h_now is replaced by h_c = h_now (n_target / N_now)^(1/3), the
+// band centre estimated from the solved h and its count (counts scale with
+// h^3 where the particle distribution is smooth on the scale of h)
 __global__ __launch_bounds__(SPH_BLOCK) void k_mlp_targets(int64_t n, const double *__restrict__ h,
                                                            const int32_t *__restrict__ nc,
-                                                           int n_target,
+                                                           int n_target, int centre,
                                                            const float *__restrict__ feat,
                                                            float *__restrict__ target)
 {
     int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (i >= n) return;
     double y = log(h[i]) - (double)feat[i * 8];
-    if (nc[i] > 0) y += log((double)n_target / (double)nc[i]) / 3.0;
+    if (centre && nc[i] > 0) y += log((double)n_target / (double)nc[i]) / 3.0;
     target[i] = (float)y;
 }
 
@@ -605,12 +605,13 @@ hipError_t launch_mlp_features(sph_ctx *c, const sph_particles *s, const double 
 }
 
 hipError_t launch_mlp_targets(sph_ctx *c, const sph_particles *s, const float *feat,
-                              float *target)
+                              float *target, int centre)
 {
     int64_t n = s->n;
     if (n == 0) return hipSuccess;
     hipLaunchKernelGGL(k_mlp_targets, dim3((unsigned)ceil_div(n, SPH_BLOCK)), dim3(SPH_BLOCK), 0,
-                       c->stream, n, s->h[s->cur], s->nc[s->cur], c->p.n_target, feat, target);
+                       c->stream, n, s->h[s->cur], s->nc[s->cur], c->p.n_target, centre, feat,
+                       target);
     return hipGetLastError();
 }
 

@@ -754,14 +754,73 @@ struct HArgs {
     int64_t *status;
 };
 
+// After a walk at hc that wrote the nin members closer than sqrt(A)/2 to
+// row i and the nsh shell members (A <= r^2 < B; -1 when they overflowed)
+// to the shell arrays: one iteration step at hc, then more while the next h
+// stays inside the shell, all counted exactly from the shell.  Returns the
+// h_update result; 0 leaves st.next for the next full count (hc itself after
+// an overflow).  When the iteration ends, the kept h's gather set is
+// completed in the row (writer) if it lies in this shell, else
+// st.last_h = -1 marks the row for rewriting.
+__device__ int shell_iterate(const HArgs &A, int64_t i, HState &st, double hc, double hprev,
+                             int nin, int nsh, double A2, double B2, bool writer, uint8_t &fl,
+                             int64_t &counts, int64_t &acc, int64_t &fallback)
+{
+#pragma clang fp contract(off)
+    if (nsh < 0) {
+        st.next = hc;   // shell overflow: the exact count needs a full walk
+        return 0;
+    }
+    auto shell_count = [&](double r2m) {
+        int c = nin;
+        for (int k = 0; k < nsh; ++k) c += A.SH.r2[(int64_t)k * A.SH.sstride + i] < r2m ? 1 : 0;
+        return c;
+    };
+    auto in_shell = [&](double r2m) { return r2m >= A2 && r2m <= B2; };
+    const double t0 = 2.0 * hc;
+    ++counts;
+    int res = h_update(st, hc, shell_count(t0 * t0), hprev, A.target, A.tol, A.maxit, A.hk, fl,
+                       acc, fallback);
+    while (res == 0) {
+        const double tn = 2.0 * st.next;
+        const double r2n = tn * tn;
+        if (!in_shell(r2n)) break;
+        const double hn = st.next;
+        ++counts;
+        res = h_update(st, hn, shell_count(r2n), hprev, A.target, A.tol, A.maxit, A.hk, fl, acc,
+                       fallback);
+    }
+    if (res != 0) {
+        // the gather set of the kept h: inner members are in place when the
+        // kept h lies in this shell; append its shell members
+        const double tk = 2.0 * st.best_h;
+        const double r2k = tk * tk;
+        if (in_shell(r2k) && st.best_n == shell_count(r2k)) {
+            if (writer) {
+                int pos = nin;
+                for (int k = 0; k < nsh; ++k) {
+                    if (A.SH.r2[(int64_t)k * A.SH.sstride + i] < r2k) {
+                        if (pos < A.K) A.idx[i * (int64_t)A.K + pos] = A.SH.j[(int64_t)k * A.SH.sstride + i];
+                        ++pos;
+                    }
+                }
+            }
+            st.last_h = st.best_h;
+        } else {
+            st.last_h = -1.0;   // the kept h lies outside this shell: rewrite its set
+        }
+    }
+    return res;
+}
+
+#ifndef SPH_ROUND_WAVES
+#define SPH_ROUND_WAVES 4   // waves per SIMD the round kernel is compiled for (measured best)
+#endif
 // Round 0 (wl == nullptr: every particle, grouped by index) and later rounds
 // (the worklist wl of wcount particles).  After its count a particle keeps
 // iterating on its shell while the next h stays inside it; particles that
 // need another full count save their state and raise work[i].
 template <int PM, bool FIRST>
-#ifndef SPH_ROUND_WAVES
-#define SPH_ROUND_WAVES 4   // waves per SIMD the round kernel is compiled for (measured best)
-#endif
 __global__ __launch_bounds__(SPH_BLOCK)
 __attribute__((amdgpu_waves_per_eu(SPH_ROUND_WAVES, SPH_ROUND_WAVES))) void k_hsolve_round(HArgs A, int64_t n,
                                                             const int32_t *__restrict__ wl,
@@ -832,35 +891,27 @@ __attribute__((amdgpu_waves_per_eu(SPH_ROUND_WAVES, SPH_ROUND_WAVES))) void k_hs
     }
     if (valid && deferred) {
         // no walk taken: untouched state, walk budget spent so that only
-        // the tail takes it up
+        // the tail takes it up (with full counts)
         st.bits |= (SPH_WAVE_ROUNDS + 1) * HS_WALK;
         hs_store(A.H, i, st);
         A.work[i] = 1;
     } else if (valid) {
         uint8_t fl = 0;
-        const int ns = nsh > 0 ? nsh : 0;
-        auto shell_count = [&](double r2m) {
-            int c = nin;
-            for (int k = 0; k < ns; ++k) c += A.SH.r2[(int64_t)k * A.SH.sstride + i] < r2m ? 1 : 0;
-            return c;
-        };
-        auto in_shell = [&](double r2m) { return nsh >= 0 && r2m >= A2 && r2m <= B2; };
-        const double t0 = 2.0 * hc;
-        int N = nsh >= 0 ? shell_count(t0 * t0) : -1;
         int res;
         st.bits += HS_WALK;
         const double tp = 2.0 * hprev;
-        if (A.h_try && !wl && (N < 0 || !in_shell(tp * tp))) {
+        const double tp2 = tp * tp;
+        if (FIRST && A.h_try && (nsh < 0 || !(tp2 >= A2 && tp2 <= B2))) {
             // the try pass, for a particle whose plain start h_prev lies
             // outside the try's shell (or whose count is unknown because the
             // shell overflowed): accept the predicted h when in band,
-            // otherwise the plain iteration starts from h_prev in the
-            // worklist rounds, with the plain start's state and walk budget
-            ++counts;
-            if (N >= 0) {
-                res = h_update(st, hc, N, hprev, A.target, A.tol, A.maxit, A.hk, fl, acc,
-                               fallback);
+            // otherwise the plain iteration starts from h_prev in the tail,
+            // with the plain start's state (no walk taken yet)
+            if (nsh >= 0) {
+                res = shell_iterate(A, i, st, hc, hprev, nin, nsh, A2, B2, true, fl, counts, acc,
+                                    fallback);
             } else {
+                ++counts;
                 ++fallback;
                 res = 0;
             }
@@ -872,44 +923,14 @@ __attribute__((amdgpu_waves_per_eu(SPH_ROUND_WAVES, SPH_ROUND_WAVES))) void k_hs
                 st.itk = 0;
                 st.bits = 0;
             }
-            N = 0;   // state already set for the next round
-        } else if (N < 0) {
-            // shell overflow: the exact count needs a full pass (next round)
-            res = 0;
         } else {
-            ++counts;
-            res = h_update(st, hc, N, hprev, A.target, A.tol, A.maxit, A.hk, fl, acc, fallback);
-            while (res == 0) {
-                const double tn = 2.0 * st.next;
-                const double r2n = tn * tn;
-                if (!in_shell(r2n)) break;
-                const double hn = st.next;
-                int Nn = shell_count(r2n);
-                ++counts;
-                res = h_update(st, hn, Nn, hprev, A.target, A.tol, A.maxit, A.hk, fl, acc, fallback);
-            }
+            res = shell_iterate(A, i, st, hc, hprev, nin, nsh, A2, B2, true, fl, counts, acc,
+                                fallback);
         }
         if (res == 0) {
-            if (N < 0) st.next = hc;   // count again in full
             hs_store(A.H, i, st);
             A.work[i] = 1;
         } else {
-            // the gather set of the kept h: inner members are in place when
-            // the kept h lies in this shell; append its shell members
-            const double tk = 2.0 * st.best_h;
-            const double r2k = tk * tk;
-            if (in_shell(r2k) && st.best_n == shell_count(r2k)) {
-                int pos = nin;
-                for (int k = 0; k < ns; ++k) {
-                    if (A.SH.r2[(int64_t)k * A.SH.sstride + i] < r2k) {
-                        if (pos < A.K) A.idx[i * (int64_t)A.K + pos] = A.SH.j[(int64_t)k * A.SH.sstride + i];
-                        ++pos;
-                    }
-                }
-                st.last_h = st.best_h;
-            } else {
-                st.last_h = -1.0;   // the kept h lies outside this shell: rewrite its set
-            }
             h_finish(st, res, fl, i, A.h, A.nc, A.flags, A.refill, A.K, nonconv, overflow);
             A.work[i] = 0;
         }
@@ -938,7 +959,7 @@ __global__ __launch_bounds__(SPH_BLOCK) void k_compact(int64_t n, const int32_t 
 // iterating to the end with full wave-cooperative counts (the whole gather
 // set written at every count, no shell).
 template <int PM>
-__global__ __launch_bounds__(SPH_BLOCK) void k_hsolve_tail(HArgs A, const int32_t *__restrict__ wl,
+__global__ __launch_bounds__(SPH_BLOCK) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_hsolve_tail(HArgs A, const int32_t *__restrict__ wl,
                                                            const int64_t *__restrict__ wcount)
 {
 #pragma clang fp contract(off)
@@ -957,12 +978,31 @@ __global__ __launch_bounds__(SPH_BLOCK) void k_hsolve_tail(HArgs A, const int32_
         HState st = hs_load(A.H, i);
         uint8_t fl = 0;
         int res = 0;
+        // a particle that has not been walked yet (a learned miss restarted
+        // from h_prev) gets the plain solve's first walk: with a shell and
+        // the iteration on it, so that it follows the plain path
+        bool shell_walk = (st.bits >> 8) == 0;
         while (res == 0) {
             const double hc = st.next;
-            const double t2 = 2.0 * hc;
-            const double r2m = t2 * t2;
             int nsh = 0;
             bool dfr;
+            if (shell_walk) {
+                shell_walk = false;
+                const double ta = 2.0 * hc * (1.0 - 1.0 / 32.0), tb = 2.0 * hc * (1.0 + 1.0 / 32.0);
+                const double A2 = ta * ta, B2 = tb * tb;
+                int nin = wave_count<PM, false>(lds[w], lane == 0, i, xi, yi, zi, ki, hc, &dfr, A2,
+                                                B2, A.x, A.y, A.z, A.idx, A.stride, A.K, A.SH, &nsh,
+                                                S, A.g, tested);
+                nin = __shfl(nin, 0, 64);
+                nsh = __shfl(nsh, 0, 64);
+                // the shell arrays were written by other lanes: make them visible
+                __threadfence_block();
+                res = shell_iterate(A, i, st, hc, hprev, nin, nsh, A2, B2, lane == 0, fl, counts,
+                                    acc, fallback);
+                continue;
+            }
+            const double t2 = 2.0 * hc;
+            const double r2m = t2 * t2;
             int N = wave_count<PM, false>(lds[w], lane == 0, i, xi, yi, zi, ki, hc, &dfr, r2m, r2m,
                                    A.x, A.y, A.z, A.idx, A.stride, A.K, A.SH, &nsh, S, A.g,
                                    tested);
@@ -1057,8 +1097,7 @@ hipError_t launch_hsolve(sph_ctx *c, sph_particles *s, sph_nlist *nl, const doub
                                n, (const int32_t *)nullptr, (const int64_t *)nullptr))
         return hipGetLastError();
     }
-    // after a try pass the misses get the plain solve's full set of rounds
-    const int rounds = SPH_WAVE_ROUNDS + (h_try ? 1 : 0);
+    const int rounds = SPH_WAVE_ROUNDS;
     for (int r = 0; r <= rounds; ++r) {
         hipError_t e = launch_scan_i32_to_i64(c, c->w.work, c->w.woff, n);
         if (e != hipSuccess) return e;

@@ -91,6 +91,7 @@ struct sph_ctx {
     int mlp_t;             // Adam step counter of sph_mlp_train
     float *harvest_feat;   // step sink of (features, target) rows, or NULL
     float *harvest_target;
+    int harvest_mode;      // SPH_TARGET_*
     char err[512];
 };
 
@@ -125,7 +126,7 @@ hipError_t launch_mlp_predict(sph_ctx *c, sph_particles *s, double *h_try);
 hipError_t launch_mlp_features(sph_ctx *c, const sph_particles *s, const double *d_dt,
                                float *feat);
 hipError_t launch_mlp_targets(sph_ctx *c, const sph_particles *s, const float *feat,
-                              float *target);
+                              float *target, int centre);
 hipError_t launch_mlp_forward(sph_ctx *c, const float *feat, int64_t n, float *y, uint16_t *h1,
                               uint16_t *h2);
 hipError_t launch_mlp_grad(sph_ctx *c, const float *feat, const float *target,

@@ -102,7 +102,7 @@ _SIGS = {
     "sph_mlp_get_weights": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_float), ctypes.POINTER(_D)]),
     "sph_mlp_fit_norm": (ctypes.c_int, [_P, _P, _I64]),
     "sph_get_features": (ctypes.c_int, [_P, ctypes.POINTER(sph_particles), _P, _P]),
-    "sph_set_harvest": (ctypes.c_int, [_P, _P, _P]),
+    "sph_set_harvest": (ctypes.c_int, [_P, _P, _P, _I32]),
     "sph_mlp_forward": (ctypes.c_int, [_P, _P, _I64, _P, _P, _P]),
     "sph_mlp_backward": (ctypes.c_int, [_P, _P, _P, _P, _I64, _I64, _P]),
     "sph_mlp_adam_step": (ctypes.c_int, [_P, _P, _D, _D, _D, _D, _I32]),
@@ -287,8 +287,13 @@ def sph_get_features(ctx, s, d_dt: int, d_feat: int):
     check(lib().sph_get_features(ctx, ctypes.byref(s), d_dt, d_feat), ctx)
 
 
-def sph_set_harvest(ctx, d_feat: int | None, d_target: int | None):
-    check(lib().sph_set_harvest(ctx, d_feat, d_target), ctx)
+SPH_TARGET_SOLVED = 0
+SPH_TARGET_CENTRED = 1
+
+
+def sph_set_harvest(ctx, d_feat: int | None, d_target: int | None,
+                    target_mode: int = SPH_TARGET_SOLVED):
+    check(lib().sph_set_harvest(ctx, d_feat, d_target, target_mode), ctx)
 
 
 def sph_mlp_forward(ctx, d_feat: int, n: int, d_y: int, d_h1: int | None = None,

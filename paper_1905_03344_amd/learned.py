@@ -41,16 +41,16 @@ def unpack_params(flat) -> dict:
             for name, (off, shape) in ffi.MLP_LAYOUT.items()}
 
 
-def harvest(sim, steps: int = 20, dt: float = 0.0):
+def harvest(sim, steps: int = 20, dt: float = 0.0, target_mode: int = ffi.SPH_TARGET_SOLVED):
     """Run `steps` KDK steps and collect one (features, target) row per
-    particle and step.  Returns device tensors feat [steps*n, 8] and target
-    [steps*n] (float32)."""
+    particle and step (target_mode: ffi.SPH_TARGET_SOLVED or _CENTRED).
+    Returns device tensors feat [steps*n, 8] and target [steps*n] (float32)."""
     n = sim.n
     feat = torch.zeros((steps * n, ffi.SPH_MLP_NFEAT), dtype=torch.float32, device=sim.device)
     target = torch.zeros(steps * n, dtype=torch.float32, device=sim.device)
     try:
         for k in range(steps):
-            sim.set_harvest(feat[k * n:(k + 1) * n], target[k * n:(k + 1) * n])
+            sim.set_harvest(feat[k * n:(k + 1) * n], target[k * n:(k + 1) * n], target_mode)
             sim.step(dt)
     finally:
         sim.set_harvest(None, None)

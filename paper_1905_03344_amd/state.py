@@ -185,7 +185,8 @@ class Simulation:
         ffi.sph_get_features(self.ctx, self.s, self.d_dt.data_ptr(), out.data_ptr())
         return out[: self.n]
 
-    def set_harvest(self, feat: torch.Tensor | None, target: torch.Tensor | None):
+    def set_harvest(self, feat: torch.Tensor | None, target: torch.Tensor | None,
+                    target_mode: int = ffi.SPH_TARGET_SOLVED):
         """Every later step writes its (features, target) rows into these
         device tensors ([>= n, 8] float32 and [>= n] float32); None stops."""
         if feat is None:
@@ -195,7 +196,7 @@ class Simulation:
         assert feat.is_contiguous() and target.is_contiguous()
         assert feat.shape[0] >= self.n and feat.shape[1] == ffi.SPH_MLP_NFEAT
         assert target.shape[0] >= self.n
-        ffi.sph_set_harvest(self.ctx, feat.data_ptr(), target.data_ptr())
+        ffi.sph_set_harvest(self.ctx, feat.data_ptr(), target.data_ptr(), target_mode)
 
     # --- tables and lists for tests ------------------------------------------
     def cell_table(self):

@@ -313,9 +313,21 @@ def test_features_and_harvest():
                                rtol=3e-7, atol=1e-12)
     c = np.sqrt(g * (g - 1.0) * sim.numpy("pu"))
     np.testing.assert_allclose(F[:, 5], (dt * c / b["h"]).astype(np.float32), rtol=3e-7, atol=1e-12)
-    # target = log(h_new (100 / N_new)^(1/3)) - f1, the band centre
-    yc = np.log(sim.numpy("h")) - F[:, 0].astype(np.float64) + np.log(100.0 / sim.numpy("nc")) / 3.0
-    np.testing.assert_allclose(T, yc.astype(np.float32), rtol=1e-6, atol=1e-7)
+    # solved target: log(h_new) - f1
+    ys = np.log(sim.numpy("h")) - F[:, 0].astype(np.float64)
+    np.testing.assert_allclose(T, ys.astype(np.float32), rtol=1e-6, atol=1e-7)
+    # centred target: log(h_new (100 / N_new)^(1/3)) - f1, on the next step
+    from paper_1905_03344_amd import ffi
+    F2 = torch.zeros((ic.n, 8), dtype=torch.float32, device=sim.device)
+    T2 = torch.zeros(ic.n, dtype=torch.float32, device=sim.device)
+    sim.set_harvest(F2, T2, ffi.SPH_TARGET_CENTRED)
+    sim.step(0.0)
+    sim.set_harvest(None, None)
+    sim.sync()
+    F2 = F2.cpu().numpy()
+    yc = (np.log(sim.numpy("h")) - F2[:, 0].astype(np.float64)
+          + np.log(100.0 / sim.numpy("nc")) / 3.0)
+    np.testing.assert_allclose(T2.cpu().numpy(), yc.astype(np.float32), rtol=1e-6, atol=1e-7)
 
 
 # ---------------------------------------------------------------------------
