@@ -76,12 +76,14 @@ def cpu_baseline(config: int):
     ic = inputs.config_ic(config)
     st = O.State(ic)
     st.evaluate(method=1)
+    steps = 4 if ic.n <= 2_000_000 else 1
     t0 = time.perf_counter()
-    st.step(None, method=1)
+    for _ in range(steps):
+        st.step(None, method=1)
     dt = time.perf_counter() - t0
-    return {"value": ic.n / dt, "unit": "particle-updates/s", "cores": O.num_threads(),
+    return {"value": ic.n * steps / dt, "unit": "particle-updates/s", "cores": O.num_threads(),
             "kind": "oracle",
-            "sample": f"one KDK step (Courant dt) of the full {ic.n}-particle workload "
+            "sample": f"{steps} KDK steps (Courant dt) of the full {ic.n}-particle workload "
                       f"after an untimed t=0 evaluation, {dt:.2f} s"}
 
 

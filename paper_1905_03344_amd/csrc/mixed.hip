@@ -294,7 +294,7 @@ __device__ __forceinline__ void force_pair_f(const QuadF &ri, uint32_t gi, const
     neu_add(A.du, mj * (ri.c.w + 0.5f * Pi) * gbar * w);
 }
 
-// S_i = L_i (row order) then E_i (ascending), SPH_MGROUP lanes per particle
+// S_i = L_i (row order) then E_i (ascending; rows sorted once built), SPH_MGROUP lanes per particle
 template <int PM>
 __global__ __launch_bounds__(SPH_BLOCK) void k_forces_mixed(
     int64_t n, MixQ Q, const int32_t *__restrict__ nc, const int32_t *__restrict__ idx, int K,

@@ -110,22 +110,70 @@ __global__ __launch_bounds__(SPH_BLOCK) void k_density(
 }
 
 // E rows in ascending order (their slots were taken by atomics), one thread
-// per row, insertion sort in place
+// per row: rows of up to 16 entries through a sorting network in registers,
+// longer ones (rare) by insertion sort in place
+#define SPH_ESORT 16
+__device__ __forceinline__ void cmp_swap(int &a, int &b)
+{
+    const int lo = min(a, b), hi = max(a, b);
+    a = lo;
+    b = hi;
+}
+
 __global__ __launch_bounds__(SPH_BLOCK) void k_sort_extra(int64_t n, const int32_t *__restrict__ ecnt,
                                                           int32_t *__restrict__ eidx, int slots)
 {
     const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (i >= n) return;
     const int ne = min(ecnt[i], slots);
+    if (ne < 2) return;
     int32_t *row = eidx + i * (int64_t)slots;
+    if (ne <= SPH_ESORT && (((uintptr_t)row) & 15) == 0) {
+        int v[SPH_ESORT];
+        // 16-byte loads of the row's first ceil(ne/4) quads
+#pragma unroll
+        for (int q = 0; q < SPH_ESORT / 4; ++q) {
+            int4 w = make_int4(0x7fffffff, 0x7fffffff, 0x7fffffff, 0x7fffffff);
+            if (4 * q < ne) w = reinterpret_cast<const int4 *>(row)[q];
+            v[4 * q] = 4 * q < ne ? w.x : 0x7fffffff;
+            v[4 * q + 1] = 4 * q + 1 < ne ? w.y : 0x7fffffff;
+            v[4 * q + 2] = 4 * q + 2 < ne ? w.z : 0x7fffffff;
+            v[4 * q + 3] = 4 * q + 3 < ne ? w.w : 0x7fffffff;
+        }
+        // bitonic sorting network on 16 values
+#pragma unroll
+        for (int sz = 2; sz <= SPH_ESORT; sz <<= 1)
+#pragma unroll
+            for (int st = sz >> 1; st > 0; st >>= 1)
+#pragma unroll
+                for (int k = 0; k < SPH_ESORT; ++k) {
+                    const int l = k ^ st;
+                    if (l > k) {
+                        if ((k & sz) == 0) cmp_swap(v[k], v[l]);
+                        else cmp_swap(v[l], v[k]);
+                    }
+                }
+#pragma unroll
+        for (int q = 0; q < SPH_ESORT / 4; ++q) {
+            if (4 * q + 3 < ne) {
+                reinterpret_cast<int4 *>(row)[q] = make_int4(v[4 * q], v[4 * q + 1], v[4 * q + 2],
+                                                             v[4 * q + 3]);
+            } else {
+#pragma unroll
+                for (int k = 4 * q; k < 4 * q + 4; ++k)
+                    if (k < ne) row[k] = v[k];
+            }
+        }
+        return;
+    }
     for (int a = 1; a < ne; ++a) {
-        const int v = row[a];
+        const int x = row[a];
         int b = a - 1;
-        while (b >= 0 && row[b] > v) {
+        while (b >= 0 && row[b] > x) {
             row[b + 1] = row[b];
             --b;
         }
-        row[b + 1] = v;
+        row[b + 1] = x;
     }
 }
 
