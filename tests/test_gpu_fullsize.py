@@ -1,0 +1,172 @@
+"""Parity at the full sizes of the benchmark workloads, in the launch
+configuration bench.py times.
+
+* 1,000,000-particle patch: the whole state against the oracle, at t = 0 and
+  after one step at the Courant dt (plain FP64), and the mixed form at t = 0.
+* 8,000,000 (mixed form) and 64,000,000 (plain FP64 and mixed): sampled
+  outputs.  The oracle evaluates a cube of the patch at the GPU's own
+  smoothing lengths and compares the particles at least 4 h_max inside it
+  (density, divergence, acceleration and du of a particle depend only on
+  particles within 4 h of it, so the cube holds all they need), matched by
+  particle id; plus properties that hold at any size: every h in band or
+  flagged, the interaction sets symmetric on a sample, the total momentum
+  change zero to rounding."""
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_1905_03344_amd import inputs
+
+pytestmark = [pytest.mark.gpu, pytest.mark.slow]
+
+TOL = 1e-12
+TOL_MIXED = 1e-5
+
+
+def _sim(ic, **kw):
+    from paper_1905_03344_amd.state import Simulation
+    return Simulation(ic, **kw)
+
+
+def test_patch_1M_evaluate_and_step():
+    from test_gpu_parity import (_upload_oracle_state, compare_cells, compare_fields,
+                                 compare_neighbors)
+    ic = inputs.config_ic(2)
+    print("1M: oracle evaluate", flush=True)
+    st = O.State(ic.copy())
+    st.keep_gather = True
+    st.evaluate(method=1)
+    print("1M: gpu evaluate", flush=True)
+    sim = _sim(ic)
+    sim.evaluate()
+    sim.sync()
+    compare_cells(sim, st)
+    compare_neighbors(sim, st)
+    compare_fields(sim, st)
+    # the step starts from identical state on both sides (the evaluation's
+    # accelerations agree to 1e-12, not bit for bit)
+    _upload_oracle_state(sim, st)
+    dt = st.dt_next
+    print("1M: oracle step", flush=True)
+    st.step(dt, method=1)
+    print("1M: gpu step", flush=True)
+    sim.step(dt)
+    sim.sync()
+    compare_cells(sim, st)
+    compare_neighbors(sim, st)
+    compare_fields(sim, st)
+
+
+def test_patch_1M_mixed_evaluate():
+    from paper_1905_03344_amd import ffi
+    from test_gpu_mixed import check_mixed_fields
+    from test_gpu_parity import compare_neighbors
+    ic = inputs.config_ic(2)
+    st = O.State(ic.copy())
+    st.keep_gather = True
+    st.evaluate(method=1)
+    sim = _sim(ic, precision=ffi.SPH_MIXED)
+    sim.evaluate()
+    sim.sync()
+    compare_neighbors(sim, st)
+    check_mixed_fields(sim, st)
+
+
+def _sampled_check(sim, tol, half=0.05):
+    """Oracle on the cube |x|,|y|,|z| < half at the GPU's h, with the
+    velocity and energy the evaluation used; compare the particles 4 h_max
+    inside it.  Selection happens on the device."""
+    import torch
+    x, y, z = sim.field("x"), sim.field("y"), sim.field("z")
+    sel = (x.abs() < half) & (y.abs() < half) & (z.abs() < half)
+    names = {"x": "x", "y": "y", "z": "z", "vx": "pvx", "vy": "pvy", "vz": "pvz", "m": "m",
+             "h": "h", "u": "pu", "rho": "rho", "divv": "divv", "ax": "ax", "ay": "ay",
+             "az": "az", "du": "du", "nc": "nc"}
+    f = {k: sim.field(v)[sel].cpu().numpy() for k, v in names.items()}
+    hmax = float(f["h"].max())
+    inner = half - 4.0 * hmax * 1.01
+    assert inner > 0, (half, hmax)
+    print(f"sampled cube: {len(f['x'])} particles, h_max {hmax:.4g}", flush=True)
+    per, lo, hi = (0, 0, 0), (-half, -half, -half), (half, half, half)
+    nc = O.count(f["x"], f["y"], f["z"], f["h"], per, lo, hi, 1)
+    off, idx = O.lists(f["x"], f["y"], f["z"], f["h"], per, lo, hi, 1)
+    rho, divv, dvmag = O.density(f["x"], f["y"], f["z"], f["vx"], f["vy"], f["vz"], f["m"], f["h"],
+                                 per, lo, hi, off, idx, with_mag=True)
+    P, c = O.eos(rho, f["u"])
+    ax, ay, az, du, dt_i, amag, dumag = O.forces(f["x"], f["y"], f["z"], f["vx"], f["vy"], f["vz"],
+                                                 f["m"], f["h"], rho, P, c, per, lo, hi, off, idx,
+                                                 1.0, 2.0, 0.01, 0.3, with_mag=True)
+    deep = (np.abs(f["x"]) < inner) & (np.abs(f["y"]) < inner) & (np.abs(f["z"]) < inner)
+    assert deep.sum() > 100
+    np.testing.assert_array_equal(f["nc"][deep], nc[deep])
+    assert np.max(np.abs(f["rho"][deep] - rho[deep]) / rho[deep]) <= tol
+    assert np.all(np.abs(f["divv"][deep] - divv[deep]) <= tol * dvmag[deep] + 1e-300)
+    for k, ref in (("ax", ax), ("ay", ay), ("az", az)):
+        d = np.abs(f[k][deep] - ref[deep])
+        assert np.all(d <= tol * amag[deep] + 1e-300), (k, np.max(d / (amag[deep] + 1e-300)))
+    d = np.abs(f["du"][deep] - du[deep])
+    assert np.all(d <= tol * dumag[deep] + 1e-300)
+    return int(deep.sum())
+
+
+def _rows(sim, ii):
+    """gather set and complement rows of particles ii (read on the device)"""
+    import torch
+    K, S = sim.params.list_stride, sim.params.extra_slots
+    t = torch.as_tensor(np.asarray(ii, dtype=np.int64), device=sim.device)
+    nc = sim.field("nc")[t].cpu().numpy()
+    L = sim.nl_idx.view(sim.stride, K)[t].cpu().numpy()
+    ne = np.minimum(sim.nl_ecnt[t].cpu().numpy(), S)
+    E = sim.nl_eidx.view(sim.stride, S)[t].cpu().numpy()
+    return [set(L[r, :nc[r]].tolist()) | set(E[r, :ne[r]].tolist()) for r in range(len(ii))]
+
+
+def _properties(sim, momentum_tol):
+    from paper_1905_03344_amd import ffi
+    nc = sim.field("nc")
+    flags = sim.field("flags").int()
+    ok = ((nc - 100).abs() <= 5) | ((flags & ffi.SPH_FLAG_NOCONV) != 0)
+    assert bool(ok.all())
+    # momentum change: sum m a vanishes (exactly antisymmetric pairs in FP64)
+    m = sim.field("m")
+    for k in ("ax", "ay", "az"):
+        a = sim.field(k)
+        assert abs(float((m * a).sum())) <= momentum_tol * float((m * a.abs()).sum())
+    # symmetric interaction sets on a sample: j in S_i => i in S_j
+    rng = np.random.default_rng(7)
+    ii = rng.choice(sim.n, 200, replace=False)
+    rows = _rows(sim, ii)
+    for i, si in zip(ii, rows):
+        jj = sorted(si)[:20]
+        for j, sj in zip(jj, _rows(sim, jj)):
+            assert int(i) in sj
+
+
+@pytest.mark.parametrize("precision", ["mixed"])
+def test_patch_8M_sampled(precision):
+    from paper_1905_03344_amd import ffi
+    ic = inputs.config_ic(3)
+    sim = _sim(ic, precision=ffi.SPH_MIXED)
+    print("8M: gpu evaluate + step", flush=True)
+    sim.evaluate()
+    sim.step(0.0)
+    sim.sync()
+    n = _sampled_check(sim, TOL_MIXED)
+    print(f"8M: {n} sampled particles agree", flush=True)
+    _properties(sim, 1e-5)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_patch_64M_sampled(precision):
+    from paper_1905_03344_amd import ffi
+    ic = inputs.config_ic(5)
+    prec = ffi.SPH_FP64 if precision == "fp64" else ffi.SPH_MIXED
+    sim = _sim(ic, precision=prec)
+    del ic
+    print(f"64M {precision}: gpu evaluate + step", flush=True)
+    sim.evaluate()
+    sim.step(0.0)
+    sim.sync()
+    n = _sampled_check(sim, TOL if precision == "fp64" else TOL_MIXED, half=0.03)
+    print(f"64M {precision}: {n} sampled particles agree", flush=True)
+    _properties(sim, 1e-9 if precision == "fp64" else 1e-5)
