@@ -170,13 +170,15 @@ def main():
         # band centre; the square patch is a jittered lattice whose count
         # grows in whole shells: train towards the solved h
         mode = ffi.SPH_TARGET_CENTRED if args.config == 4 else ffi.SPH_TARGET_SOLVED
-        feat, target = L.harvest(tr, steps=20, target_mode=mode)
+        # 20 harvested plain steps; at 64M rows of 2 steps (128M rows, 4.6 GB)
+        harvest_steps = 20 if n <= 8_000_000 else 2
+        feat, target = L.harvest(tr, steps=harvest_steps, target_mode=mode)
         tr.sync()
         t1 = time.perf_counter()
         w, norm, losses = L.train(tr, feat, target, seed=inputs.CONFIG_SEEDS[args.config])
         torch.cuda.synchronize()
         t2 = time.perf_counter()
-        extra["training"] = {"harvest_steps": 20, "rows": int(feat.shape[0]),
+        extra["training"] = {"harvest_steps": harvest_steps, "rows": int(feat.shape[0]),
                              "target": "centred" if mode == ffi.SPH_TARGET_CENTRED else "solved",
                              "harvest_s": round(t1 - t0, 3), "train_s": round(t2 - t1, 3),
                              "epochs": 4, "batch": 8192,

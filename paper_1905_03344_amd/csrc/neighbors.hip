@@ -284,6 +284,16 @@ struct Shell {
 // time with the candidates spread over the lanes (transposed mode); larger
 // ones stream their union box through LDS tiles that every member tests.
 #define SPH_SMALL_GROUP 8
+// a group is split by Morton prefix while its positions spread over more than
+// this many search diameters (3: measured best of 1.5, 2, 3, 5)
+#ifndef SPH_SPLIT_SPREAD
+#define SPH_SPLIT_SPREAD 3.0
+#endif
+// lanes whose search radius exceeds this multiple of the group's smallest
+// form a later group (2: measured best of 1.5, 2, 3 and no split)
+#ifndef SPH_SPLIT_H
+#define SPH_SPLIT_H 2.0
+#endif
 
 // exact r^2 between a lane's particle and candidate coordinates (the same
 // arithmetic in both modes; PMW = 0 when the box cannot wrap, where the
@@ -601,9 +611,10 @@ __device__ int wave_count(WaveLds &L, bool act, int64_t i, double xi, double yi,
     int32_t *wp = idx + i * (int64_t)K;   // this particle's row of the gather sets
     uint64_t pending = __ballot(act);
     while (pending) {
-        // sub-group: the pending lanes, split by Morton prefix while their
-        // positions spread over more than 1.5 search diameters (a group that
-        // straddles a large Morton jump would otherwise scan the gap)
+        // sub-group: the pending lanes, split by search radius, then by
+        // Morton prefix while their positions spread over more than
+        // SPH_SPLIT_SPREAD search diameters (a group that straddles a large
+        // Morton jump would otherwise scan the gap)
         uint64_t members = pending;
         for (int sp = 0; sp < 32; ++sp) {
             bool mem = (members >> lane) & 1ull;
@@ -615,7 +626,15 @@ __device__ int wave_count(WaveLds &L, bool act, int64_t i, double xi, double yi,
                 double b = wave_max_d(mem ? p3[d] : -INFINITY);
                 ext = fmax(ext, b - a);
             }
-            if (!(ext > 3.0 * Rm) || __popcll(members) <= SPH_SMALL_GROUP) break;
+            // lanes whose search radius exceeds SPH_SPLIT_H times the group's
+            // smallest wait for a later group (one large-h particle would
+            // size the box and its cells for every member)
+            const double Rlo = wave_min_d(mem ? twoh : INFINITY);
+            if (Rm > SPH_SPLIT_H * Rlo) {
+                members &= __ballot(twoh <= SPH_SPLIT_H * Rlo);
+                continue;
+            }
+            if (!(ext > SPH_SPLIT_SPREAD * Rm) || __popcll(members) <= SPH_SMALL_GROUP) break;
             uint32_t kmin = wave_min_u(mem ? ki : 0xFFFFFFFFu);
             uint32_t kmax = wave_max_u(mem ? ki : 0u);
             if (kmin == kmax) break;
