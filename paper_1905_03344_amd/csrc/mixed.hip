@@ -294,8 +294,9 @@ __device__ __forceinline__ void force_pair_f(const QuadF &ri, uint32_t gi, const
     neu_add(A.du, mj * (ri.c.w + 0.5f * Pi) * gbar * w);
 }
 
-// S_i = L_i (row order) then E_i (ascending; rows sorted once built), SPH_MGROUP lanes per particle
-template <int PM>
+// S_i = L_i (row order) then E_i (ascending), SPH_MGROUP lanes per particle;
+// ELDS: E rows ranked in LDS here (capacity <= SPH_ELDS), else sorted already
+template <int PM, bool ELDS>
 __global__ __launch_bounds__(SPH_BLOCK) void k_forces_mixed(
     int64_t n, MixQ Q, const int32_t *__restrict__ nc, const int32_t *__restrict__ idx, int K,
     const int32_t *__restrict__ ecnt, const int32_t *__restrict__ eidx, int slots,
@@ -310,6 +311,8 @@ __global__ __launch_bounds__(SPH_BLOCK) void k_forces_mixed(
     const int64_t base = blk * SPH_BLOCK;
     double dti = INFINITY;
     const MixGeo G = mix_geo(bbox, g);
+    __shared__ int32_t e_raw[ELDS ? SPH_BLOCK / SPH_MGROUP : 1][ELDS ? SPH_ELDS : 1];
+    __shared__ int32_t e_srt[ELDS ? SPH_BLOCK / SPH_MGROUP : 1][ELDS ? SPH_ELDS : 1];
     for (int rr = 0; rr < SPH_BLOCK / SPH_MGROUP; ++rr) {
         const int64_t i = base + (int64_t)rr * (SPH_BLOCK / SPH_MGROUP) + grp;
         ForceAccF A = {{0.f, 0.f}, {0.f, 0.f}, {0.f, 0.f}, {0.f, 0.f}, 0.f};
@@ -322,10 +325,12 @@ __global__ __launch_bounds__(SPH_BLOCK) void k_forces_mixed(
             const int tot = cnt + ne;
             const int32_t *lrow = idx + i * (int64_t)K;
             const int32_t *erow = eidx + i * (int64_t)slots;
+            if (ELDS && ne > 0) erow_sort_lds<SPH_MGROUP>(erow, ne, lane, e_raw[grp], e_srt[grp]);
+            const int32_t *es = ELDS ? e_srt[grp] : erow;
             for (int k0 = lane; k0 < tot; k0 += 2 * SPH_MGROUP) {
                 const int k1 = k0 + SPH_MGROUP;
-                const int j0 = k0 < cnt ? lrow[k0] : erow[k0 - cnt];
-                const int j1 = k1 < cnt ? lrow[k1] : (k1 < tot ? erow[k1 - cnt] : (int)i);
+                const int j0 = k0 < cnt ? lrow[k0] : es[k0 - cnt];
+                const int j1 = k1 < cnt ? lrow[k1] : (k1 < tot ? es[k1 - cnt] : (int)i);
                 QuadF r0, r1;
                 r0.a = Q.A[j0]; r0.b = Q.B[j0]; r0.c = Q.C[j0]; r0.d = Q.D[j0];
                 r1.a = Q.A[j1]; r1.b = Q.B[j1]; r1.c = Q.C[j1]; r1.d = Q.D[j1];
@@ -399,8 +404,6 @@ hipError_t launch_density_mixed(sph_ctx *c, sph_particles *s, const sph_nlist *n
                                c->p.list_stride, c->w.bbox, g, s->x[cur], s->y[cur], s->z[cur], s->h[cur],
                                s->rho[cur], s->divv[cur], nl->ecnt, nl->eidx, c->p.extra_slots,
                                c->w.status))
-        e = launch_sort_extra(c, nl, n);
-        if (e != hipSuccess) return e;
     } else {
         SPH_DISPATCH_PM(periodic_mask(g),
             hipLaunchKernelGGL((k_density_mixed<PM, false>), dim3(nb), dim3(SPH_BLOCK), 0,
@@ -429,13 +432,20 @@ hipError_t launch_forces_mixed(sph_ctx *c, sph_particles *s, const sph_nlist *nl
     const sph_params &p = c->p;
     int64_t nb = ceil_div(n > 0 ? n : 1, SPH_BLOCK);
     Geo g = make_geo(p);
-    SPH_DISPATCH_PM(periodic_mask(g),
-        hipLaunchKernelGGL(k_forces_mixed<PM>, dim3((unsigned)nb), dim3(SPH_BLOCK), 0, c->stream,
-                           n, ctx_quads(c), s->nc[cur], nl->idx,
-                           p.list_stride, nl->ecnt, nl->eidx, p.extra_slots, c->w.bbox, g,
-                           (float)p.av_alpha,
-                           (float)p.av_beta, (float)p.av_eta2, p.av_alpha, p.av_beta, p.cfl,
-                           s->h[cur], s->c, s->ax[cur], s->ay[cur], s->az[cur], s->du[cur],
-                           c->w.red_part))
+#define SPH_FORCE_ARGS                                                                        \
+    dim3((unsigned)nb), dim3(SPH_BLOCK), 0, c->stream, n, ctx_quads(c), s->nc[cur], nl->idx,   \
+        p.list_stride, nl->ecnt, nl->eidx, p.extra_slots, c->w.bbox, g, (float)p.av_alpha,     \
+        (float)p.av_beta, (float)p.av_eta2, p.av_alpha, p.av_beta, p.cfl, s->h[cur], s->c,     \
+        s->ax[cur], s->ay[cur], s->az[cur], s->du[cur], c->w.red_part
+    if (p.extra_slots <= SPH_ELDS) {
+        SPH_DISPATCH_PM(periodic_mask(g),
+                        hipLaunchKernelGGL((k_forces_mixed<PM, true>), SPH_FORCE_ARGS))
+    } else {
+        hipError_t e = launch_sort_extra(c, nl, n);
+        if (e != hipSuccess) return e;
+        SPH_DISPATCH_PM(periodic_mask(g),
+                        hipLaunchKernelGGL((k_forces_mixed<PM, false>), SPH_FORCE_ARGS))
+    }
+#undef SPH_FORCE_ARGS
     return hipGetLastError();
 }

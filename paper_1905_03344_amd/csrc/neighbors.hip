@@ -191,15 +191,6 @@ __device__ __forceinline__ int wave_incl_scan_i(int v)
     }
     return v;
 }
-// orders this wave's LDS writes before its later LDS reads (LDS is in order
-// within a wave; this keeps the compiler from moving accesses across)
-__device__ __forceinline__ void wave_lds_sync()
-{
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
-
 #define WAVES_PER_BLOCK (SPH_BLOCK / 64)
 
 struct WaveLds {
@@ -1196,7 +1187,5 @@ hipError_t launch_extra(sph_ctx *c, sph_particles *s, sph_nlist *nl)
         hipLaunchKernelGGL(k_extra<PM>, dim3(nb), dim3(SPH_BLOCK), 0, c->stream, n, s->x[cur],
                            s->y[cur], s->z[cur], s->h[cur], s->nc[cur], nl->idx, nl->stride,
                            p.list_stride, g, nl->ecnt, nl->eidx, p.extra_slots, c->w.status))
-    e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    return launch_sort_extra(c, nl, n);
+    return hipGetLastError();
 }

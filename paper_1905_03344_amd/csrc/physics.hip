@@ -110,8 +110,9 @@ __global__ __launch_bounds__(SPH_BLOCK) void k_density(
 }
 
 // E rows in ascending order (their slots were taken by atomics), one thread
-// per row: rows of up to 16 entries through a sorting network in registers,
-// longer ones (rare) by insertion sort in place
+// per row, for row capacities above SPH_ELDS (the force kernels rank shorter
+// rows themselves): rows of up to 16 entries through a sorting network in
+// registers, longer ones by insertion sort in place
 #define SPH_ESORT 16
 __device__ __forceinline__ void cmp_swap(int &a, int &b)
 {
@@ -203,8 +204,6 @@ hipError_t launch_density(sph_ctx *c, sph_particles *s, const sph_nlist *nl, boo
                                s->h[cur], s->nc[cur], nl->idx, c->p.list_stride, g,
                                s->rho[cur], s->divv[cur], nl->ecnt, nl->eidx, c->p.extra_slots,
                                c->w.status))
-        hipError_t e = launch_sort_extra(c, nl, n);
-        if (e != hipSuccess) return e;
     } else {
         SPH_DISPATCH_PM(periodic_mask(g),
             hipLaunchKernelGGL((k_density<PM, false>), dim3(nb), dim3(SPH_BLOCK), 0, c->stream, n,
@@ -220,15 +219,18 @@ hipError_t launch_density(sph_ctx *c, sph_particles *s, const sph_nlist *nl, boo
 __global__ __launch_bounds__(SPH_BLOCK) void k_eos(int64_t n, const double *__restrict__ rho,
                                                    const double *__restrict__ u, double gamma,
                                                    double *__restrict__ p, double *__restrict__ c,
-                                                   int check, int64_t *__restrict__ status)
+                                                   double *__restrict__ pr2, int check,
+                                                   int64_t *__restrict__ status)
 {
     int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     int64_t bad = 0;
     if (i < n) {
-        double pv = (gamma - 1.0) * rho[i] * u[i];
+        const double rh = rho[i];
+        double pv = (gamma - 1.0) * rh * u[i];
         double cv = sqrt(gamma * (gamma - 1.0) * u[i]);
         p[i] = pv;
         c[i] = cv;
+        pr2[i] = pv / (rh * rh);   // the pressure term of the force sum, once per particle
         if (check && !(isfinite(pv) && isfinite(cv) && isfinite(rho[i]))) bad = 1;
     }
     if (check) block_add_i64(bad, status + ST_NONFINITE);
@@ -239,7 +241,7 @@ hipError_t launch_eos(sph_ctx *c, sph_particles *s)
     int64_t n = s->n;
     if (n == 0) return hipSuccess;
     hipLaunchKernelGGL(k_eos, dim3((unsigned)ceil_div(n, SPH_BLOCK)), dim3(SPH_BLOCK), 0,
-                       c->stream, n, s->rho[s->cur], s->pu, c->p.gamma, s->p, s->c,
+                       c->stream, n, s->rho[s->cur], s->pu, c->p.gamma, s->p, s->c, c->w.pr2,
                        c->p.check_finite, c->w.status);
     return hipGetLastError();
 }
@@ -253,7 +255,7 @@ struct ForceAcc {
 
 // neighbour fields of one pair, gathered ahead of the arithmetic
 struct NbrF {
-    double x, y, z, vx, vy, vz, m, h, rho, p, c;
+    double x, y, z, vx, vy, vz, m, h, rho, p, c;   // p holds P / rho^2
 };
 
 __device__ __forceinline__ NbrF load_nbr(int j, const double *__restrict__ x,
@@ -265,13 +267,13 @@ __device__ __forceinline__ NbrF load_nbr(int j, const double *__restrict__ x,
                                          const double *__restrict__ m,
                                          const double *__restrict__ h,
                                          const double *__restrict__ rho,
-                                         const double *__restrict__ p,
+                                         const double *__restrict__ pr2,
                                          const double *__restrict__ c)
 {
     NbrF b;
     b.x = x[j]; b.y = y[j]; b.z = z[j];
     b.vx = vx[j]; b.vy = vy[j]; b.vz = vz[j];
-    b.m = m[j]; b.h = h[j]; b.rho = rho[j]; b.p = p[j]; b.c = c[j];
+    b.m = m[j]; b.h = h[j]; b.rho = rho[j]; b.p = pr2[j]; b.c = c[j];
     return b;
 }
 
@@ -306,7 +308,7 @@ __device__ __forceinline__ void force_pair(const NbrF &b, double xi, double yi, 
         Pi = (-alpha * cb * mu + beta * mu * mu) / rb;
         A.mumax = fmax(A.mumax, fabs(mu));
     }
-    double pj_term = b.p / (rhoj * rhoj);
+    double pj_term = b.p;
     double sfac = (pi_term + pj_term) + Pi;
     double mj = b.m;
     double f = mj * sfac * gbar;
@@ -316,13 +318,14 @@ __device__ __forceinline__ void force_pair(const NbrF &b, double xi, double yi, 
     A.du += mj * (pi_term + 0.5 * Pi) * gbar * w;
 }
 
-// S_i = L_i (row order) then E_i (ascending) in groups of SPH_GROUP lanes
-template <int PM>
+// S_i = L_i (row order) then E_i (ascending) in groups of SPH_GROUP lanes;
+// ELDS: E rows ranked in LDS here (capacity <= SPH_ELDS), else sorted already
+template <int PM, bool ELDS>
 __global__ __launch_bounds__(SPH_BLOCK) void k_forces(
     int64_t n, const double *__restrict__ x, const double *__restrict__ y,
     const double *__restrict__ z, const double *__restrict__ vx, const double *__restrict__ vy,
     const double *__restrict__ vz, const double *__restrict__ m, const double *__restrict__ h,
-    const double *__restrict__ rho, const double *__restrict__ p, const double *__restrict__ c,
+    const double *__restrict__ rho, const double *__restrict__ pr2, const double *__restrict__ c,
     const int32_t *__restrict__ nc, const int32_t *__restrict__ idx, int K,
     const int32_t *__restrict__ ecnt, const int32_t *__restrict__ eidx, int slots, Geo g,
     double alpha, double beta, double eta2, double cfl, double *__restrict__ ax,
@@ -333,6 +336,8 @@ __global__ __launch_bounds__(SPH_BLOCK) void k_forces(
     const int grp = threadIdx.x / SPH_GROUP;
     const int64_t blk = xcd_block(blockIdx.x, gridDim.x);
     const int64_t base = blk * SPH_BLOCK;
+    __shared__ int32_t e_raw[ELDS ? SPH_BLOCK / SPH_GROUP : 1][ELDS ? SPH_ELDS : 1];
+    __shared__ int32_t e_srt[ELDS ? SPH_BLOCK / SPH_GROUP : 1][ELDS ? SPH_ELDS : 1];
     double dti = INFINITY;
     for (int r = 0; r < SPH_BLOCK / SPH_GROUP; ++r) {
         const int64_t i = base + (int64_t)r * (SPH_BLOCK / SPH_GROUP) + grp;
@@ -344,23 +349,25 @@ __global__ __launch_bounds__(SPH_BLOCK) void k_forces(
             hi = h[i];
             const double inv_hi = 1.0 / hi, rhoi = rho[i];
             ci = c[i];
-            const double pi_term = p[i] / (rhoi * rhoi);
+            const double pi_term = pr2[i];
             const int cnt = min(nc[i], K);
             const int ne = min(ecnt[i], slots);
             const int32_t *lrow = idx + i * (int64_t)K;
             const int32_t *erow = eidx + i * (int64_t)slots;
+            if (ELDS && ne > 0) erow_sort_lds<SPH_GROUP>(erow, ne, lane, e_raw[grp], e_srt[grp]);
             const int tot = cnt + ne;
             for (int k0 = lane; k0 < tot; k0 += SPH_FBATCH * SPH_GROUP) {
                 int jb[SPH_FBATCH];
 #pragma unroll
                 for (int q = 0; q < SPH_FBATCH; ++q) {
                     const int k = k0 + q * SPH_GROUP;
-                    jb[q] = k < cnt ? lrow[k] : (k < tot ? erow[k - cnt] : (int)i);
+                    jb[q] = k < cnt ? lrow[k]
+                                    : (k < tot ? (ELDS ? e_srt[grp][k - cnt] : erow[k - cnt]) : (int)i);
                 }
                 NbrF nb[SPH_FBATCH];
 #pragma unroll
                 for (int q = 0; q < SPH_FBATCH; ++q)
-                    nb[q] = load_nbr(jb[q], x, y, z, vx, vy, vz, m, h, rho, p, c);
+                    nb[q] = load_nbr(jb[q], x, y, z, vx, vy, vz, m, h, rho, pr2, c);
 #pragma unroll
                 for (int q = 0; q < SPH_FBATCH; ++q) {
                     if (k0 + q * SPH_GROUP >= tot) break;
@@ -417,12 +424,19 @@ hipError_t launch_forces(sph_ctx *c, sph_particles *s, const sph_nlist *nl, doub
     // dt partials live in the reduction area sized for n_max / SPH_BLOCK blocks
     double *part = c->w.red_part;
     Geo g = make_geo(p);
-    SPH_DISPATCH_PM(periodic_mask(g),
-        hipLaunchKernelGGL(k_forces<PM>, dim3((unsigned)nb), dim3(SPH_BLOCK), 0, c->stream, n,
-                           s->x[cur], s->y[cur], s->z[cur], s->pvx, s->pvy, s->pvz, s->m[cur],
-                           s->h[cur], s->rho[cur], s->p, s->c, s->nc[cur], nl->idx,
-                           p.list_stride, nl->ecnt, nl->eidx, p.extra_slots, g, p.av_alpha, p.av_beta,
-                           p.av_eta2, p.cfl, s->ax[cur], s->ay[cur], s->az[cur], s->du[cur], part))
+#define SPH_FORCE_ARGS                                                                          \
+    dim3((unsigned)nb), dim3(SPH_BLOCK), 0, c->stream, n, s->x[cur], s->y[cur], s->z[cur],       \
+        s->pvx, s->pvy, s->pvz, s->m[cur], s->h[cur], s->rho[cur], c->w.pr2, s->c, s->nc[cur],   \
+        nl->idx, p.list_stride, nl->ecnt, nl->eidx, p.extra_slots, g, p.av_alpha, p.av_beta,     \
+        p.av_eta2, p.cfl, s->ax[cur], s->ay[cur], s->az[cur], s->du[cur], part
+    if (p.extra_slots <= SPH_ELDS) {
+        SPH_DISPATCH_PM(periodic_mask(g), hipLaunchKernelGGL((k_forces<PM, true>), SPH_FORCE_ARGS))
+    } else {
+        hipError_t e = launch_sort_extra(c, nl, n);
+        if (e != hipSuccess) return e;
+        SPH_DISPATCH_PM(periodic_mask(g), hipLaunchKernelGGL((k_forces<PM, false>), SPH_FORCE_ARGS))
+    }
+#undef SPH_FORCE_ARGS
     return hipGetLastError();
 }
 

@@ -71,6 +71,7 @@ struct Workspace {
     double *mlp_norm;      // feature mean[6], std[6]
     float *mlp_part;       // per-wave gradient partial rows
     double *h_try;         // n_max predicted smoothing lengths (learned mode)
+    double *pr2;           // n_max: P / rho^2 from the last EOS (read by the force kernel)
     int64_t nb_red;
     int64_t nb_sort;
     int64_t scan_part_len;
@@ -219,6 +220,39 @@ static inline int periodic_mask(const Geo &g) { return g.per[0] | (g.per[1] << 1
     case 6: { constexpr int PM = 6; LAUNCH; } break; \
     default: { constexpr int PM = 7; LAUNCH; } break; \
     }
+
+// orders this wave's LDS writes before its later LDS reads (LDS is in order
+// within a wave; this keeps the compiler from moving accesses across)
+__device__ __forceinline__ void wave_lds_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Force kernels visit E_i in ascending index order (so that sums do not
+// depend on the order atomics filled the row).  Rows of up to SPH_ELDS
+// entries are ranked in LDS by the particle's lane group inside the force
+// kernel; with more slots the rows are sorted in memory beforehand.
+#define SPH_ELDS 128
+template <int G>
+__device__ __forceinline__ void erow_sort_lds(const int32_t *__restrict__ erow, int ne, int lane,
+                                              int32_t *raw, int32_t *srt)
+{
+    wave_lds_sync();   // the group's reads of the previous row are behind us
+    for (int e = lane; e < ne; e += G) raw[e] = erow[e];
+    wave_lds_sync();
+    for (int e = lane; e < ne; e += G) {
+        const int v = raw[e];
+        int rank = 0;
+        for (int f = 0; f < ne; ++f) {
+            const int u = raw[f];
+            rank += (u < v) | ((u == v) & (f < e));
+        }
+        srt[rank] = v;
+    }
+    wave_lds_sync();
+}
 
 // Complement rows: i goes into E_j when j is in L_i but i is not in L_j,
 // i.e. r_ij^2 >= (2 h_j)^2 (the same exact test j's own gather used).

@@ -181,6 +181,26 @@ def test_deterministic_runs():
         np.testing.assert_array_equal(outs[0][f], outs[1][f])
 
 
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_complement_order_paths(precision):
+    """Complement rows ranked inside the force kernel (row capacity up to
+    128) and rows sorted in memory first (larger capacity) are visited in the
+    same ascending order, so the sums agree bit for bit."""
+    from paper_1905_03344_amd import ffi
+    ic = inputs.clumpy(n_clumps=3, per_clump=2000, n_background=1500, seed=21)
+    prec = ffi.SPH_FP64 if precision == "fp64" else ffi.SPH_MIXED
+    outs = []
+    for slots in (96, 160):
+        sim = _sim(ic, extra_per_particle=slots, precision=prec)
+        sim.evaluate()
+        sim.step(0.0)
+        sim.sync()
+        assert int((sim.nl_ecnt[:sim.n] > 16).sum()) > 100   # rows that span several lane rounds
+        outs.append({f: sim.numpy(f).copy() for f in ("ax", "ay", "az", "du", "x", "u")})
+    for f in outs[0]:
+        np.testing.assert_array_equal(outs[0][f], outs[1][f])
+
+
 def test_lattice_nonconvergence_reported():
     from paper_1905_03344_amd import ffi
     ic = inputs.perfect_lattice(16)
