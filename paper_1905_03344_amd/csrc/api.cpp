@@ -193,7 +193,7 @@ size_t sph_layout(const sph_params *p, void *base, Workspace *w)
     t.mlp_norm = (double *)take(12 * sizeof(double));
     t.mlp_part = (float *)take((size_t)SPH_MLP_TRAIN_WAVES * SPH_MLP_ROW * sizeof(float));
     t.h_try = p->h_mode == SPH_H_LEARNED ? (double *)take(n * sizeof(double)) : nullptr;
-    t.pr2 = (double *)take(n * sizeof(double));
+    t.pk64 = p->precision == SPH_FP64 ? take(n * 80) : nullptr;
     t.nb_red = nb_red;
     t.nb_sort = nb_sort;
     t.scan_part_len = scan_part;

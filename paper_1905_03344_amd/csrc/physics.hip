@@ -28,12 +28,30 @@ __device__ __forceinline__ double group_max(double v)
     return v;
 }
 
+static Pk64 ctx_pk64(sph_ctx *c)
+{
+    const int64_t n = c->p.n_max;
+    double2 *b = (double2 *)c->w.pk64;
+    return Pk64{b, b + n, b + 2 * n, b + 3 * n, b + 4 * n};
+}
+
+__global__ __launch_bounds__(SPH_BLOCK) void k_pack64(
+    int64_t n, const double *__restrict__ x, const double *__restrict__ y,
+    const double *__restrict__ z, const double *__restrict__ h, const double *__restrict__ vx,
+    const double *__restrict__ vy, const double *__restrict__ vz, const double *__restrict__ m,
+    Pk64 P)
+{
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    P.xy[i] = make_double2(x[i], y[i]);
+    P.zh[i] = make_double2(z[i], h[i]);
+    P.vxy[i] = make_double2(vx[i], vy[i]);
+    P.vzm[i] = make_double2(vz[i], m[i]);
+}
+
 template <int PM, bool EXTRA>
 __global__ __launch_bounds__(SPH_BLOCK) void k_density(
-    int64_t n, const double *__restrict__ x, const double *__restrict__ y,
-    const double *__restrict__ z, const double *__restrict__ vx, const double *__restrict__ vy,
-    const double *__restrict__ vz, const double *__restrict__ m, const double *__restrict__ h,
-    const int32_t *__restrict__ nc, const int32_t *__restrict__ idx, int K, Geo g,
+    int64_t n, Pk64 P, const int32_t *__restrict__ nc, const int32_t *__restrict__ idx, int K, Geo g,
     double *__restrict__ rho, double *__restrict__ divv, int32_t *__restrict__ ecnt,
     int32_t *__restrict__ eidx, int slots, int64_t *__restrict__ status)
 {
@@ -43,11 +61,13 @@ __global__ __launch_bounds__(SPH_BLOCK) void k_density(
     int64_t appended = 0, dropped = 0;
     for (int r = 0; r < SPH_BLOCK / SPH_GROUP; ++r) {
         const int64_t i = base + (int64_t)r * (SPH_BLOCK / SPH_GROUP) + grp;
-        double s = 0.0, dv = 0.0, inv_h = 0.0;
+        double s = 0.0, dv = 0.0, inv_h = 0.0, mi = 0.0;
         if (i < n) {
-            const double xi = x[i], yi = y[i], zi = z[i];
-            const double vxi = vx[i], vyi = vy[i], vzi = vz[i];
-            inv_h = 1.0 / h[i];
+            const double2 pxy = P.xy[i], pzh = P.zh[i], pv = P.vxy[i], pvm = P.vzm[i];
+            const double xi = pxy.x, yi = pxy.y, zi = pzh.x;
+            const double vxi = pv.x, vyi = pv.y, vzi = pvm.x;
+            mi = pvm.y;
+            inv_h = 1.0 / pzh.y;
             const int cnt = min(nc[i], K);
             const int32_t *row = idx + i * (int64_t)K;
             // batches of SPH_BATCH pairs per lane: indices first, then every
@@ -65,10 +85,9 @@ __global__ __launch_bounds__(SPH_BLOCK) void k_density(
 #pragma unroll
                 for (int q = 0; q < SPH_BATCH; ++q) {
                     const int j = jb[q];
-                    xb[q] = x[j]; yb[q] = y[j]; zb[q] = z[j];
-                    if (EXTRA) hb[q] = h[j];
-                    mb[q] = m[j];
-                    ub[q] = vx[j]; vb[q] = vy[j]; wb[q] = vz[j];
+                    const double2 a = P.xy[j], b = P.zh[j], cv = P.vxy[j], d = P.vzm[j];
+                    xb[q] = a.x; yb[q] = a.y; zb[q] = b.x; hb[q] = b.y;
+                    ub[q] = cv.x; vb[q] = cv.y; wb[q] = d.x; mb[q] = d.y;
                 }
 #pragma unroll
                 for (int q = 0; q < SPH_BATCH; ++q) {
@@ -98,7 +117,7 @@ __global__ __launch_bounds__(SPH_BLOCK) void k_density(
         s = group_sum(s);
         dv = group_sum(dv);
         if (i < n && lane == 0) {
-            const double rh = m[i] * kern_w(0.0, inv_h) + s;
+            const double rh = mi * kern_w(0.0, inv_h) + s;
             rho[i] = rh;
             divv[i] = dv / rh;
         }
@@ -197,20 +216,19 @@ hipError_t launch_density(sph_ctx *c, sph_particles *s, const sph_nlist *nl, boo
     int cur = s->cur;
     Geo g = make_geo(c->p);
     unsigned nb = (unsigned)ceil_div(n, SPH_BLOCK);
+    const Pk64 P = ctx_pk64(c);
+    hipLaunchKernelGGL(k_pack64, dim3(nb), dim3(SPH_BLOCK), 0, c->stream, n, s->x[cur], s->y[cur],
+                       s->z[cur], s->h[cur], s->pvx, s->pvy, s->pvz, s->m[cur], P);
     if (build_extra) {
         SPH_DISPATCH_PM(periodic_mask(g),
             hipLaunchKernelGGL((k_density<PM, true>), dim3(nb), dim3(SPH_BLOCK), 0, c->stream, n,
-                               s->x[cur], s->y[cur], s->z[cur], s->pvx, s->pvy, s->pvz, s->m[cur],
-                               s->h[cur], s->nc[cur], nl->idx, c->p.list_stride, g,
-                               s->rho[cur], s->divv[cur], nl->ecnt, nl->eidx, c->p.extra_slots,
-                               c->w.status))
+                               P, s->nc[cur], nl->idx, c->p.list_stride, g, s->rho[cur],
+                               s->divv[cur], nl->ecnt, nl->eidx, c->p.extra_slots, c->w.status))
     } else {
         SPH_DISPATCH_PM(periodic_mask(g),
             hipLaunchKernelGGL((k_density<PM, false>), dim3(nb), dim3(SPH_BLOCK), 0, c->stream, n,
-                               s->x[cur], s->y[cur], s->z[cur], s->pvx, s->pvy, s->pvz, s->m[cur],
-                               s->h[cur], s->nc[cur], nl->idx, c->p.list_stride, g,
-                               s->rho[cur], s->divv[cur], nl->ecnt, nl->eidx, c->p.extra_slots,
-                               c->w.status))
+                               P, s->nc[cur], nl->idx, c->p.list_stride, g, s->rho[cur],
+                               s->divv[cur], nl->ecnt, nl->eidx, c->p.extra_slots, c->w.status))
     }
     return hipGetLastError();
 }
@@ -219,7 +237,7 @@ hipError_t launch_density(sph_ctx *c, sph_particles *s, const sph_nlist *nl, boo
 __global__ __launch_bounds__(SPH_BLOCK) void k_eos(int64_t n, const double *__restrict__ rho,
                                                    const double *__restrict__ u, double gamma,
                                                    double *__restrict__ p, double *__restrict__ c,
-                                                   double *__restrict__ pr2, int check,
+                                                   double2 *__restrict__ rp, int check,
                                                    int64_t *__restrict__ status)
 {
     int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
@@ -230,7 +248,7 @@ __global__ __launch_bounds__(SPH_BLOCK) void k_eos(int64_t n, const double *__re
         double cv = sqrt(gamma * (gamma - 1.0) * u[i]);
         p[i] = pv;
         c[i] = cv;
-        pr2[i] = pv / (rh * rh);   // the pressure term of the force sum, once per particle
+        rp[i] = make_double2(rh, pv / (rh * rh));   // P / rho^2 once per particle
         if (check && !(isfinite(pv) && isfinite(cv) && isfinite(rho[i]))) bad = 1;
     }
     if (check) block_add_i64(bad, status + ST_NONFINITE);
@@ -241,7 +259,7 @@ hipError_t launch_eos(sph_ctx *c, sph_particles *s)
     int64_t n = s->n;
     if (n == 0) return hipSuccess;
     hipLaunchKernelGGL(k_eos, dim3((unsigned)ceil_div(n, SPH_BLOCK)), dim3(SPH_BLOCK), 0,
-                       c->stream, n, s->rho[s->cur], s->pu, c->p.gamma, s->p, s->c, c->w.pr2,
+                       c->stream, n, s->rho[s->cur], s->pu, c->p.gamma, s->p, s->c, ctx_pk64(c).rp,
                        c->p.check_finite, c->w.status);
     return hipGetLastError();
 }
@@ -258,22 +276,13 @@ struct NbrF {
     double x, y, z, vx, vy, vz, m, h, rho, p, c;   // p holds P / rho^2
 };
 
-__device__ __forceinline__ NbrF load_nbr(int j, const double *__restrict__ x,
-                                         const double *__restrict__ y,
-                                         const double *__restrict__ z,
-                                         const double *__restrict__ vx,
-                                         const double *__restrict__ vy,
-                                         const double *__restrict__ vz,
-                                         const double *__restrict__ m,
-                                         const double *__restrict__ h,
-                                         const double *__restrict__ rho,
-                                         const double *__restrict__ pr2,
-                                         const double *__restrict__ c)
+__device__ __forceinline__ NbrF load_nbr(int j, const Pk64 &P, const double *__restrict__ c)
 {
     NbrF b;
-    b.x = x[j]; b.y = y[j]; b.z = z[j];
-    b.vx = vx[j]; b.vy = vy[j]; b.vz = vz[j];
-    b.m = m[j]; b.h = h[j]; b.rho = rho[j]; b.p = pr2[j]; b.c = c[j];
+    const double2 a = P.xy[j], zh = P.zh[j], v = P.vxy[j], vm = P.vzm[j], rp = P.rp[j];
+    b.x = a.x; b.y = a.y; b.z = zh.x; b.h = zh.y;
+    b.vx = v.x; b.vy = v.y; b.vz = vm.x; b.m = vm.y;
+    b.rho = rp.x; b.p = rp.y; b.c = c[j];
     return b;
 }
 
@@ -322,11 +331,7 @@ __device__ __forceinline__ void force_pair(const NbrF &b, double xi, double yi, 
 // ELDS: E rows ranked in LDS here (capacity <= SPH_ELDS), else sorted already
 template <int PM, bool ELDS>
 __global__ __launch_bounds__(SPH_BLOCK) void k_forces(
-    int64_t n, const double *__restrict__ x, const double *__restrict__ y,
-    const double *__restrict__ z, const double *__restrict__ vx, const double *__restrict__ vy,
-    const double *__restrict__ vz, const double *__restrict__ m, const double *__restrict__ h,
-    const double *__restrict__ rho, const double *__restrict__ pr2, const double *__restrict__ c,
-    const int32_t *__restrict__ nc, const int32_t *__restrict__ idx, int K,
+    int64_t n, Pk64 P, const double *__restrict__ c, const int32_t *__restrict__ nc, const int32_t *__restrict__ idx, int K,
     const int32_t *__restrict__ ecnt, const int32_t *__restrict__ eidx, int slots, Geo g,
     double alpha, double beta, double eta2, double cfl, double *__restrict__ ax,
     double *__restrict__ ay, double *__restrict__ az, double *__restrict__ du,
@@ -344,12 +349,13 @@ __global__ __launch_bounds__(SPH_BLOCK) void k_forces(
         ForceAcc A = {0.0, 0.0, 0.0, 0.0, 0.0};
         double hi = 0.0, ci = 0.0;
         if (i < n) {
-            const double xi = x[i], yi = y[i], zi = z[i];
-            const double vxi = vx[i], vyi = vy[i], vzi = vz[i];
-            hi = h[i];
-            const double inv_hi = 1.0 / hi, rhoi = rho[i];
-            ci = c[i];
-            const double pi_term = pr2[i];
+            const NbrF me = load_nbr((int)i, P, c);
+            const double xi = me.x, yi = me.y, zi = me.z;
+            const double vxi = me.vx, vyi = me.vy, vzi = me.vz;
+            hi = me.h;
+            const double inv_hi = 1.0 / hi, rhoi = me.rho;
+            ci = me.c;
+            const double pi_term = me.p;
             const int cnt = min(nc[i], K);
             const int ne = min(ecnt[i], slots);
             const int32_t *lrow = idx + i * (int64_t)K;
@@ -367,7 +373,7 @@ __global__ __launch_bounds__(SPH_BLOCK) void k_forces(
                 NbrF nb[SPH_FBATCH];
 #pragma unroll
                 for (int q = 0; q < SPH_FBATCH; ++q)
-                    nb[q] = load_nbr(jb[q], x, y, z, vx, vy, vz, m, h, rho, pr2, c);
+                    nb[q] = load_nbr(jb[q], P, c);
 #pragma unroll
                 for (int q = 0; q < SPH_FBATCH; ++q) {
                     if (k0 + q * SPH_GROUP >= tot) break;
@@ -425,8 +431,7 @@ hipError_t launch_forces(sph_ctx *c, sph_particles *s, const sph_nlist *nl, doub
     double *part = c->w.red_part;
     Geo g = make_geo(p);
 #define SPH_FORCE_ARGS                                                                          \
-    dim3((unsigned)nb), dim3(SPH_BLOCK), 0, c->stream, n, s->x[cur], s->y[cur], s->z[cur],       \
-        s->pvx, s->pvy, s->pvz, s->m[cur], s->h[cur], s->rho[cur], c->w.pr2, s->c, s->nc[cur],   \
+    dim3((unsigned)nb), dim3(SPH_BLOCK), 0, c->stream, n, ctx_pk64(c), s->c, s->nc[cur],         \
         nl->idx, p.list_stride, nl->ecnt, nl->eidx, p.extra_slots, g, p.av_alpha, p.av_beta,     \
         p.av_eta2, p.cfl, s->ax[cur], s->ay[cur], s->az[cur], s->du[cur], part
     if (p.extra_slots <= SPH_ELDS) {

@@ -38,6 +38,15 @@ struct Geo {
     double halfL[3];  // 0.5 * L
 };
 
+// FP64 neighbour records read by the pair kernels, two fields per 16-byte
+// load (a gather's cost follows the cache lines it touches, and lines of
+// 16-byte pairs hold runs of neighbours almost as well as lines of single
+// fields): xy = (x, y), zh = (z, h), vxy / vzm = (v*x, v*y) / (v*z, m)
+// from the pack before density, rp = (rho, P / rho^2) from the EOS.
+struct Pk64 {
+    double2 *xy, *zh, *vxy, *vzm, *rp;
+};
+
 // Workspace carve-up.
 struct Workspace {
     double *bbox;          // 6: lo[3], hi[3]
@@ -71,7 +80,7 @@ struct Workspace {
     double *mlp_norm;      // feature mean[6], std[6]
     float *mlp_part;       // per-wave gradient partial rows
     double *h_try;         // n_max predicted smoothing lengths (learned mode)
-    double *pr2;           // n_max: P / rho^2 from the last EOS (read by the force kernel)
+    void *pk64;            // n_max * 80 bytes: FP64 neighbour records (Pk64, FP64 form)
     int64_t nb_red;
     int64_t nb_sort;
     int64_t scan_part_len;
