@@ -5,16 +5,16 @@
 // an FP32 prefilter with an FP64 test for the ambiguous band.
 #include "sph_internal.h"
 
-// Per-particle FP32 fields, four float4 arrays (one 16-byte quad per
+// Per-particle FP32 fields, three float4 arrays (one 16-byte quad per
 // particle each, so that a group of lanes reading consecutive particles
-// touches consecutive memory):
+// touches consecutive memory; a pair costs three loads):
 //   A = {delta_x, delta_y, delta_z, cell}   cell = gx | gy << 10 | gz << 20
 //   B = {vx, vy, vz, m}
-//   C = {h, 1/h, rho, P/rho^2}
-//   D = {c_sound, 0, 0, 0}
-// with x = lo + g * w + delta, w = L/1024 the key-cell width.
+//   C = {h, c_sound, rho, P/rho^2}
+// with x = lo + g * w + delta, w = L/1024 the key-cell width.  1/h of a
+// neighbour is formed in the pair (hardware reciprocal, 1 ulp).
 struct MixQ {
-    float4 *A, *B, *C, *D;
+    float4 *A, *B, *C, *D;   // D: unused fourth quad of the 64-byte record
 };
 __host__ __device__ static inline MixQ mix_quads(void *base, int64_t n_max)
 {
@@ -121,8 +121,7 @@ __global__ __launch_bounds__(SPH_BLOCK) void k_pack_mixed(
     Q.A[i] = make_float4(dl[0], dl[1], dl[2], __uint_as_float(cell));
     Q.B[i] = make_float4((float)vx[i], (float)vy[i], (float)vz[i], (float)m[i]);
     double hi = h[i];
-    Q.C[i] = make_float4((float)hi, (float)(1.0 / hi), 0.0f, 0.0f);
-    Q.D[i] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    Q.C[i] = make_float4((float)hi, 0.0f, 0.0f, 0.0f);
 }
 
 // ---------------------------------------------------------------------------
@@ -159,7 +158,7 @@ __global__ __launch_bounds__(SPH_BLOCK) void k_density_mixed(
         if (i < n) {
             ai = Q.A[i];
             bi = Q.B[i];
-            inv_h = Q.C[i].y;
+            inv_h = (float)(1.0 / h[i]);
             const uint32_t gi = cell_of(ai);
             const int cnt = min(nc[i], K);
             const int32_t *row = idx + i * (int64_t)K;
@@ -236,9 +235,9 @@ __global__ __launch_bounds__(SPH_BLOCK) void k_eos_mixed(int64_t n, const double
         double cv = sqrt(gamma * (gamma - 1.0) * u[i]);
         p[i] = pv;
         c[i] = cv;
+        Q.C[i].y = (float)cv;
         Q.C[i].z = (float)rh;
         Q.C[i].w = (float)(pv / (rh * rh));
-        Q.D[i].x = (float)cv;
         if (check && !(isfinite(pv) && isfinite(cv) && isfinite(rh))) bad = 1;
     }
     if (check) block_add_i64(bad, status + ST_NONFINITE);
@@ -252,15 +251,15 @@ struct ForceAccF {
     float mumax;
 };
 
-// own fields of particle i (a, b, c, d) and the gathered fields of j
+// own fields of particle i (a, b, c) and the gathered fields of j
 struct QuadF {
-    float4 a, b, c, d;
+    float4 a, b, c;
 };
 
 template <int PM>
-__device__ __forceinline__ void force_pair_f(const QuadF &ri, uint32_t gi, const QuadF &rj,
-                                             const MixGeo &G, float alpha, float beta,
-                                             float eta2, ForceAccF &A)
+__device__ __forceinline__ void force_pair_f(const QuadF &ri, float inv_hi, uint32_t gi,
+                                             const QuadF &rj, const MixGeo &G, float alpha,
+                                             float beta, float eta2, ForceAccF &A)
 {
     const uint32_t gj = cell_of(rj.a);
     float dx = split_diff<PM, 0>(gi, gj, ri.a.x, rj.a.x, G);
@@ -273,13 +272,13 @@ __device__ __forceinline__ void force_pair_f(const QuadF &ri, uint32_t gi, const
     float xij = -dx, yij = -dy, zij = -dz;
     float vxij = ri.b.x - rj.b.x, vyij = ri.b.y - rj.b.y, vzij = ri.b.z - rj.b.z;
     float w = vxij * xij + vyij * yij + vzij * zij;
-    float gwi = kern_dwdr_f(r, ri.c.y) * inv_r;
-    float gwj = kern_dwdr_f(r, rj.c.y) * inv_r;
+    float gwi = kern_dwdr_f(r, inv_hi) * inv_r;
+    float gwj = kern_dwdr_f(r, __builtin_amdgcn_rcpf(rj.c.x)) * inv_r;
     float gbar = 0.5f * (gwi + gwj);
     float Pi = 0.0f;
     if (w < 0.0f) {
         float hb = 0.5f * (ri.c.x + rj.c.x);
-        float cb = 0.5f * (ri.d.x + rj.d.x);
+        float cb = 0.5f * (ri.c.y + rj.c.y);
         float rb = 0.5f * (ri.c.z + rj.c.z);
         float mu = hb * w / (r2 + eta2 * hb * hb);
         Pi = (-alpha * cb * mu + beta * mu * mu) / rb;
@@ -318,7 +317,8 @@ __global__ __launch_bounds__(SPH_BLOCK) void k_forces_mixed(
         ForceAccF A = {{0.f, 0.f}, {0.f, 0.f}, {0.f, 0.f}, {0.f, 0.f}, 0.f};
         if (i < n) {
             QuadF ri;
-            ri.a = Q.A[i]; ri.b = Q.B[i]; ri.c = Q.C[i]; ri.d = Q.D[i];
+            ri.a = Q.A[i]; ri.b = Q.B[i]; ri.c = Q.C[i];
+            const float inv_hi = (float)(1.0 / h[i]);
             const uint32_t gi = cell_of(ri.a);
             const int cnt = min(nc[i], K);
             const int ne = min(ecnt[i], slots);
@@ -332,10 +332,10 @@ __global__ __launch_bounds__(SPH_BLOCK) void k_forces_mixed(
                 const int j0 = k0 < cnt ? lrow[k0] : es[k0 - cnt];
                 const int j1 = k1 < cnt ? lrow[k1] : (k1 < tot ? es[k1 - cnt] : (int)i);
                 QuadF r0, r1;
-                r0.a = Q.A[j0]; r0.b = Q.B[j0]; r0.c = Q.C[j0]; r0.d = Q.D[j0];
-                r1.a = Q.A[j1]; r1.b = Q.B[j1]; r1.c = Q.C[j1]; r1.d = Q.D[j1];
-                force_pair_f<PM>(ri, gi, r0, G, alpha, beta, eta2, A);
-                if (k1 < tot) force_pair_f<PM>(ri, gi, r1, G, alpha, beta, eta2, A);
+                r0.a = Q.A[j0]; r0.b = Q.B[j0]; r0.c = Q.C[j0];
+                r1.a = Q.A[j1]; r1.b = Q.B[j1]; r1.c = Q.C[j1];
+                force_pair_f<PM>(ri, inv_hi, gi, r0, G, alpha, beta, eta2, A);
+                if (k1 < tot) force_pair_f<PM>(ri, inv_hi, gi, r1, G, alpha, beta, eta2, A);
             }
         }
         A.ax = mgroup_neu(A.ax);
