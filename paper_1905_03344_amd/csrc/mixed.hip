@@ -25,6 +25,9 @@ __host__ __device__ static inline MixQ mix_quads(void *base, int64_t n_max)
 // lanes per particle in the pair loops, and their partial sums combined in a
 // fixed butterfly order (Neumaier steps: the same value in every lane)
 #define SPH_MGROUP 16
+#ifndef SPH_MBATCH
+#define SPH_MBATCH 4
+#endif
 __device__ __forceinline__ float mgroup_max(float v)
 {
     for (int o = SPH_MGROUP / 2; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o, SPH_MGROUP));
@@ -162,43 +165,64 @@ __global__ __launch_bounds__(SPH_BLOCK) void k_density_mixed(
             const uint32_t gi = cell_of(ai);
             const int cnt = min(nc[i], K);
             const int32_t *row = idx + i * (int64_t)K;
-            for (int k = lane; k < cnt; k += SPH_MGROUP) {
-                const int j = row[k];
-                const float4 aj = Q.A[j];
-                const float4 bj = Q.B[j];
-                const uint32_t gj = cell_of(aj);
-                float dx = split_diff<PM, 0>(gi, gj, ai.x, aj.x, G);
-                float dy = split_diff<PM, 1>(gi, gj, ai.y, aj.y, G);
-                float dz = split_diff<PM, 2>(gi, gj, ai.z, aj.z, G);
-                float r2 = dx * dx + dy * dy + dz * dz;
-                if (EXTRA) {
-                    // is i outside j's gather sphere?  FP32 decides clear
-                    // cases (|error| of r2 is below 1e-6 relative), FP64 the
-                    // band
-                    const float hj = Q.C[j].x;
-                    const float lim = 4.0f * hj * hj;
-                    bool outside;
-                    if (r2 > lim * (1.0f + 1e-5f)) {
-                        outside = true;
-                    } else if (r2 < lim * (1.0f - 1e-5f)) {
-                        outside = false;
-                    } else {
-#pragma clang fp contract(off)
-                        double ex = mimg<PM, 0>(x[i], x[j], g), ey = mimg<PM, 1>(y[i], y[j], g),
-                               ez = mimg<PM, 2>(z[i], z[j], g);
-                        double e2 = exact_r2(ex, ey, ez);
-                        double twoh = 2.0 * h[j];
-                        outside = !(e2 < twoh * twoh);
-                    }
-                    if (outside) extra_append(j, (int)i, ecnt, eidx, slots, appended, dropped);
+            // batches of SPH_MBATCH pairs per lane: indices, then the
+            // gathers, then the arithmetic (slots past the end are skipped)
+            for (int k0 = lane; k0 < cnt; k0 += SPH_MBATCH * SPH_MGROUP) {
+                int jb[SPH_MBATCH];
+#pragma unroll
+                for (int q = 0; q < SPH_MBATCH; ++q) {
+                    const int k = k0 + q * SPH_MGROUP;
+                    jb[q] = k < cnt ? row[k] : (int)i;
                 }
-                float r = sqrtf(r2);
-                const float mj = bj.w;
-                neu_add(s, mj * kern_w_f(r, inv_h));
-                if (r > 0.0f) {
-                    float gw = kern_dwdr_f(r, inv_h) / r;
-                    float vdot = (bj.x - bi.x) * (-dx) + (bj.y - bi.y) * (-dy) + (bj.z - bi.z) * (-dz);
-                    neu_add(dv, mj * vdot * gw);
+                float4 ab[SPH_MBATCH], bb[SPH_MBATCH];
+                float hb[SPH_MBATCH];
+#pragma unroll
+                for (int q = 0; q < SPH_MBATCH; ++q) {
+                    ab[q] = Q.A[jb[q]];
+                    bb[q] = Q.B[jb[q]];
+                    if (EXTRA) hb[q] = Q.C[jb[q]].x;
+                }
+#pragma unroll
+                for (int q = 0; q < SPH_MBATCH; ++q) {
+                    if (k0 + q * SPH_MGROUP >= cnt) break;
+                    const int j = jb[q];
+                    const float4 aj = ab[q], bj = bb[q];
+                    const uint32_t gj = cell_of(aj);
+                    float dx = split_diff<PM, 0>(gi, gj, ai.x, aj.x, G);
+                    float dy = split_diff<PM, 1>(gi, gj, ai.y, aj.y, G);
+                    float dz = split_diff<PM, 2>(gi, gj, ai.z, aj.z, G);
+                    float r2 = dx * dx + dy * dy + dz * dz;
+                    if (EXTRA) {
+                        // is i outside j's gather sphere?  FP32 decides clear
+                        // cases (|error| of r2 is below 1e-6 relative), FP64
+                        // the band
+                        const float hj = hb[q];
+                        const float lim = 4.0f * hj * hj;
+                        bool outside;
+                        if (r2 > lim * (1.0f + 1e-5f)) {
+                            outside = true;
+                        } else if (r2 < lim * (1.0f - 1e-5f)) {
+                            outside = false;
+                        } else {
+#pragma clang fp contract(off)
+                            double ex = mimg<PM, 0>(x[i], x[j], g),
+                                   ey = mimg<PM, 1>(y[i], y[j], g),
+                                   ez = mimg<PM, 2>(z[i], z[j], g);
+                            double e2 = exact_r2(ex, ey, ez);
+                            double twoh = 2.0 * h[j];
+                            outside = !(e2 < twoh * twoh);
+                        }
+                        if (outside) extra_append(j, (int)i, ecnt, eidx, slots, appended, dropped);
+                    }
+                    float r = sqrtf(r2);
+                    const float mj = bj.w;
+                    neu_add(s, mj * kern_w_f(r, inv_h));
+                    if (r > 0.0f) {
+                        float gw = kern_dwdr_f(r, inv_h) / r;
+                        float vdot = (bj.x - bi.x) * (-dx) + (bj.y - bi.y) * (-dy) +
+                                     (bj.z - bi.z) * (-dz);
+                        neu_add(dv, mj * vdot * gw);
+                    }
                 }
             }
         }
