@@ -28,6 +28,9 @@ __host__ __device__ static inline MixQ mix_quads(void *base, int64_t n_max)
 #ifndef SPH_MBATCH
 #define SPH_MBATCH 4
 #endif
+#ifndef SPH_MFBATCH
+#define SPH_MFBATCH 4
+#endif
 __device__ __forceinline__ float mgroup_max(float v)
 {
     for (int o = SPH_MGROUP / 2; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o, SPH_MGROUP));
@@ -351,15 +354,23 @@ __global__ __launch_bounds__(SPH_BLOCK) void k_forces_mixed(
             const int32_t *erow = eidx + i * (int64_t)slots;
             if (ELDS && ne > 0) erow_sort_lds<SPH_MGROUP>(erow, ne, lane, e_raw[grp], e_srt[grp]);
             const int32_t *es = ELDS ? e_srt[grp] : erow;
-            for (int k0 = lane; k0 < tot; k0 += 2 * SPH_MGROUP) {
-                const int k1 = k0 + SPH_MGROUP;
-                const int j0 = k0 < cnt ? lrow[k0] : es[k0 - cnt];
-                const int j1 = k1 < cnt ? lrow[k1] : (k1 < tot ? es[k1 - cnt] : (int)i);
-                QuadF r0, r1;
-                r0.a = Q.A[j0]; r0.b = Q.B[j0]; r0.c = Q.C[j0];
-                r1.a = Q.A[j1]; r1.b = Q.B[j1]; r1.c = Q.C[j1];
-                force_pair_f<PM>(ri, inv_hi, gi, r0, G, alpha, beta, eta2, A);
-                if (k1 < tot) force_pair_f<PM>(ri, inv_hi, gi, r1, G, alpha, beta, eta2, A);
+            for (int k0 = lane; k0 < tot; k0 += SPH_MFBATCH * SPH_MGROUP) {
+                int jb[SPH_MFBATCH];
+#pragma unroll
+                for (int q = 0; q < SPH_MFBATCH; ++q) {
+                    const int k = k0 + q * SPH_MGROUP;
+                    jb[q] = k < cnt ? lrow[k] : (k < tot ? es[k - cnt] : (int)i);
+                }
+                QuadF rb[SPH_MFBATCH];
+#pragma unroll
+                for (int q = 0; q < SPH_MFBATCH; ++q) {
+                    rb[q].a = Q.A[jb[q]]; rb[q].b = Q.B[jb[q]]; rb[q].c = Q.C[jb[q]];
+                }
+#pragma unroll
+                for (int q = 0; q < SPH_MFBATCH; ++q) {
+                    if (k0 + q * SPH_MGROUP >= tot) break;
+                    force_pair_f<PM>(ri, inv_hi, gi, rb[q], G, alpha, beta, eta2, A);
+                }
             }
         }
         A.ax = mgroup_neu(A.ax);

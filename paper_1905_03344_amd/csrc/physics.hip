@@ -14,8 +14,12 @@
 // reproducible.  Block b treats particles [SPH_BLOCK b, SPH_BLOCK (b+1)):
 // in round r its 16 groups take particles SPH_BLOCK b + 16 r + group.
 #define SPH_GROUP 16
+#ifndef SPH_BATCH
 #define SPH_BATCH 4
+#endif
+#ifndef SPH_FBATCH
 #define SPH_FBATCH 2
+#endif
 
 __device__ __forceinline__ double group_sum(double v)
 {
