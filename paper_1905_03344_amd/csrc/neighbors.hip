@@ -199,7 +199,172 @@ struct WaveLds {
     int pre[64];
     int qs[128];   // queue of non-empty cells in Morton order: first particle
     int ql[128];   // and particle count
+    uint32_t cf[64][8];   // Gram features of the tile's candidates (16 bf16 each)
+    uint32_t mf[64][8];   // Gram features of the members, outer threshold
+    uint32_t ma[64];      // the two features that differ for the inner threshold
 };
+
+// ---------------------------------------------------------------------------
+// Gram prefilter of a union tile on the matrix cores.  With u = s (x - c)
+// (c the box centre, s a power of two with s R_max in [1/2, 1)), the squared
+// distance of member i and candidate j minus a threshold T_i is the dot
+// product of two 16-vectors:
+//   member    M = (-2a_i, -2a_i, -2b_i, 1, 1, hi(|u_i|^2 - T_i), lo(..), 0, 0, 0)
+//   candidate C = ( a_j,   b_j,   a_j,  hi(|u_j|^2), lo(|u_j|^2), 1, 1, 0, 0, 0)
+// where a + b is a two-term bfloat16 split of u (the dropped b_i b_j and the
+// split remainders are below 2^-17 U^2) and the products are exact in the
+// FP32 accumulator.  With U^2 >= |u|^2 over the whole cell box, every error
+// term together stays below 2^-14 (U^2 + T_max) (2^-16 observed on random
+// boxes), so with the band delta = 2^-11 (U^2 + T_max):
+//   D < 0 for T = B + delta  keeps every candidate with r^2 < B  (a superset),
+//   D < 0 for T = A - delta  holds only candidates with r^2 < A  (certainly inner),
+// and the candidates between the two are decided by the exact FP64 r^2.
+// One 16x16x16 MFMA covers 16 candidates x 16 members; a 64 x 64 tile takes
+// 16 per threshold.
+// ---------------------------------------------------------------------------
+typedef short gs4_t __attribute__((ext_vector_type(4)));
+typedef float gf4_t __attribute__((ext_vector_type(4)));
+
+struct Gram {
+    bool ok;
+    double c[3];
+    double s, s2, delta;
+    int wrap[3];
+    double L[3], halfL[3];
+};
+
+__device__ __forceinline__ uint32_t bf16_rne(float f)
+{
+    const uint32_t b = __float_as_uint(f);
+    return (b + 0x7FFFu + ((b >> 16) & 1u)) >> 16;
+}
+__device__ __forceinline__ float bf16_float(uint32_t h) { return __uint_as_float(h << 16); }
+__device__ __forceinline__ void bf16_split(double v, uint32_t &hi, uint32_t &lo)
+{
+    hi = bf16_rne((float)v);
+    lo = bf16_rne((float)(v - (double)bf16_float(hi)));
+}
+
+__device__ __forceinline__ double gram_rel(const Gram &G, int d, double x)
+{
+    double r = x - G.c[d];
+    if (G.wrap[d]) {
+        if (r > G.halfL[d]) r -= G.L[d];
+        else if (r < -G.halfL[d]) r += G.L[d];
+    }
+    return r * G.s;
+}
+
+// candidate features into f[0..7] (pairs of bf16, element 2k in the low half)
+__device__ __forceinline__ void gram_cand(const Gram &G, double x, double y, double z, uint32_t *f)
+{
+    const double u[3] = {gram_rel(G, 0, x), gram_rel(G, 1, y), gram_rel(G, 2, z)};
+    uint32_t a[3], b[3], nh, nl;
+    for (int d = 0; d < 3; ++d) bf16_split(u[d], a[d], b[d]);
+    bf16_split(u[0] * u[0] + u[1] * u[1] + u[2] * u[2], nh, nl);
+    const uint32_t one = 0x3F80u;
+    f[0] = a[0] | a[1] << 16;
+    f[1] = a[2] | b[0] << 16;
+    f[2] = b[1] | b[2] << 16;
+    f[3] = a[0] | a[1] << 16;
+    f[4] = a[2] | nh << 16;
+    f[5] = nl | one << 16;
+    f[6] = one;
+    f[7] = 0u;
+}
+
+// member features for thresholds TB (all eight words) and TA (words 5 and 6
+// differ: ma = hi | lo << 16 of |u|^2 - TA)
+__device__ __forceinline__ void gram_member(const Gram &G, double x, double y, double z, double TB,
+                                            double TA, uint32_t *f, uint32_t &ma)
+{
+    const double u[3] = {gram_rel(G, 0, x), gram_rel(G, 1, y), gram_rel(G, 2, z)};
+    uint32_t m2a[3], m2b[3];
+    for (int d = 0; d < 3; ++d) {
+        uint32_t a, b;
+        bf16_split(u[d], a, b);
+        m2a[d] = bf16_rne(-2.0f * bf16_float(a));   // exact
+        m2b[d] = bf16_rne(-2.0f * bf16_float(b));
+    }
+    const double n = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+    uint32_t bh, bl, ah, al;
+    bf16_split(n - TB, bh, bl);
+    bf16_split(n - TA, ah, al);
+    const uint32_t one = 0x3F80u;
+    f[0] = m2a[0] | m2a[1] << 16;
+    f[1] = m2a[2] | m2a[0] << 16;
+    f[2] = m2a[1] | m2a[2] << 16;
+    f[3] = m2b[0] | m2b[1] << 16;
+    f[4] = m2b[2] | one << 16;
+    f[5] = one | bh << 16;
+    f[6] = bl;
+    f[7] = 0u;
+    ma = ah | al << 16;
+}
+
+__device__ __forceinline__ gs4_t gram_op(uint32_t w0, uint32_t w1)
+{
+    gs4_t r;
+    r[0] = (short)(w0 & 0xFFFFu);
+    r[1] = (short)(w0 >> 16);
+    r[2] = (short)(w1 & 0xFFFFu);
+    r[3] = (short)(w1 >> 16);
+    return r;
+}
+
+// nibble rb of a 16-bit word to bits rb*16 + sh .. +3 of a 64-bit mask
+__device__ __forceinline__ uint64_t gram_expand(uint32_t w, int sh)
+{
+    const uint32_t lo = ((w & 0xFu) | ((w & 0xF0u) << 12)) << sh;
+    const uint32_t hi = (((w >> 8) & 0xFu) | ((w & 0xF000u) << 4)) << sh;
+    return (uint64_t)lo | ((uint64_t)hi << 32);
+}
+
+// All 64 lanes: this lane's masks over the tile (lane = member): bit t of hb
+// when D_B(t) < 0, of ha when D_A(t) < 0.
+__device__ __forceinline__ void gram_tile(const WaveLds &L, int lane, uint64_t &hb, uint64_t &ha)
+{
+    const int q = lane >> 4, j = lane & 15;
+    gs4_t A[4];
+#pragma unroll
+    for (int rb = 0; rb < 4; ++rb) {
+        const uint2 w = *reinterpret_cast<const uint2 *>(&L.cf[rb * 16 + j][2 * q]);
+        A[rb] = gram_op(w.x, w.y);
+    }
+    const gf4_t zero = {0.0f, 0.0f, 0.0f, 0.0f};
+    hb = 0;
+    ha = 0;
+#pragma unroll
+    for (int cb = 0; cb < 4; ++cb) {
+        const int m = cb * 16 + j;
+        const uint2 w = *reinterpret_cast<const uint2 *>(&L.mf[m][2 * q]);
+        const uint32_t mav = L.ma[m];
+        uint2 wa = w;
+        if (q == 2) wa.y = (w.y & 0xFFFFu) | (mav << 16);          // element 11
+        if (q == 3) wa.x = (w.x & 0xFFFF0000u) | (mav >> 16);      // element 12
+        const gs4_t MB = gram_op(w.x, w.y), MA = gram_op(wa.x, wa.y);
+        uint32_t wb = 0, wa_ = 0;
+#pragma unroll
+        for (int rb = 3; rb >= 0; --rb) {
+            const gf4_t db = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(A[rb], MB, zero, 0, 0, 0);
+            const gf4_t da = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(A[rb], MA, zero, 0, 0, 0);
+#pragma unroll
+            for (int v = 3; v >= 0; --v) {
+                wb = __builtin_amdgcn_alignbit(wb, __float_as_uint(db[v]), 31);
+                wa_ = __builtin_amdgcn_alignbit(wa_, __float_as_uint(da[v]), 31);
+            }
+        }
+        uint64_t pb = gram_expand(wb, 4 * q), pa = gram_expand(wa_, 4 * q);
+        pb |= (uint64_t)__shfl_xor((long long)pb, 16, 64);
+        pa |= (uint64_t)__shfl_xor((long long)pa, 16, 64);
+        pb |= (uint64_t)__shfl_xor((long long)pb, 32, 64);
+        pa |= (uint64_t)__shfl_xor((long long)pa, 32, 64);
+        if (cb == q) {
+            hb = pb;
+            ha = pa;
+        }
+    }
+}
 
 // ascending bitonic sort of one value per lane across the wave
 __device__ __forceinline__ uint32_t wave_sort_u32(uint32_t v)
@@ -362,6 +527,45 @@ __device__ void walk_group(WaveLds &L, uint64_t members, int tm, int64_t i, doub
         cnt[d] = max(ib - ia + 1, 0);
     }
     const int sh = 3 * (S.lmax - l);
+
+    // Gram prefilter of the union tiles (see gram_tile): relative coordinates
+    // to the box centre stay minimum images while the cell box spans under
+    // half of every periodic length it wraps in
+    Gram G;
+    G.ok = false;
+    if (!TRANSPOSED) {
+        double U2 = 0.0;
+        bool ok = Rmax > 0.0 && Rmax < INFINITY;
+        for (int d = 0; d < 3; ++d) {
+            const double cwd = ldexp(S.L[d], -l);
+            G.c[d] = 0.5 * (blo[d] + bhi[d]);
+            G.wrap[d] = wraps && S.g.per[d];
+            G.L[d] = g.L[d];
+            G.halfL[d] = g.halfL[d];
+            if (S.g.per[d] && (double)cnt[d] * cwd > 0.45 * g.L[d]) ok = false;
+            const double e0 = fabs(S.lo[d] + (double)a[d] * cwd - G.c[d]);
+            const double e1 = fabs(S.lo[d] + (double)(a[d] + cnt[d]) * cwd - G.c[d]);
+            const double e = fmax(fmax(e0, e1), fabs(bhi[d] - G.c[d]));
+            U2 += e * e;
+        }
+        if (ok) {
+            G.s = ldexp(1.0, -(ilogb(Rmax) + 1));
+            G.s2 = G.s * G.s;
+            U2 *= G.s2;
+            G.delta = ldexp(U2 + Rmax * Rmax * G.s2, -11);
+            G.ok = U2 < 1e30;
+        }
+        if (G.ok) {
+            uint32_t f[8], ma = 0;
+            if (me) {
+                gram_member(G, xi, yi, zi, B2 * G.s2 + G.delta, A2 * G.s2 - G.delta, f, ma);
+            } else {
+                for (int k = 0; k < 8; ++k) f[k] = 0u;
+            }
+            for (int k = 0; k < 8; ++k) L.mf[lane][k] = f[k];
+            L.ma[lane] = ma;
+        }
+    }
     // Cells are visited in ascending Morton code, so every member meets its
     // candidates in ascending particle index whatever the group: the gather
     // set of a particle at a given h comes out in one order.  The box is
@@ -466,14 +670,36 @@ __device__ void walk_group(WaveLds &L, uint64_t members, int tm, int64_t i, doub
                     cd.j = jn;
                     cd.pad = 0;
                     L.c[lane] = cd;
+                    if (G.ok) {
+                        uint32_t f[8];
+                        gram_cand(G, xn, yn, zn, f);
+                        for (int k = 0; k < 8; ++k) L.cf[lane][k] = f[k];
+                    }
                 }
                 wave_lds_sync();
                 jn = cand_index(base + 64 + lane);
                 if (jn >= 0) { xn = x[jn]; yn = y[jn]; zn = z[jn]; }
                 const int m = min(64, total - base);
+                uint64_t gb = 0, ga = 0;
+                if (G.ok) gram_tile(L, lane, gb, ga);   // all lanes (matrix cores)
                 if (me) {
                     uint64_t hin, hsh;
-                    if (m == 64) {
+                    if (G.ok) {
+                        // certainly inner from the prefilter; the band and the
+                        // shell by the exact r^2
+                        const uint64_t valid = m == 64 ? ~0ull : ((1ull << m) - 1ull);
+                        hin = ga & valid;
+                        hsh = 0;
+                        uint64_t chk = gb & ~ga & valid;
+                        while (chk) {
+                            const int t = __ffsll((unsigned long long)chk) - 1;
+                            chk &= chk - 1;
+                            const double r2 = wraps ? tile_r2<PM>(L, t, xi, yi, zi, g)
+                                                    : tile_r2<0>(L, t, xi, yi, zi, g);
+                            if (r2 < A2) hin |= 1ull << t;
+                            else if (r2 < B2) hsh |= 1ull << t;
+                        }
+                    } else if (m == 64) {
                         if (wraps) tile_hits<PM, true>(L, m, xi, yi, zi, A2, B2, g, &hin, &hsh);
                         else tile_hits<0, true>(L, m, xi, yi, zi, A2, B2, g, &hin, &hsh);
                     } else {
