@@ -312,58 +312,70 @@ __device__ __forceinline__ gs4_t gram_op(uint32_t w0, uint32_t w1)
     return r;
 }
 
-// nibble rb of a 16-bit word to bits rb*16 + sh .. +3 of a 64-bit mask
-__device__ __forceinline__ uint64_t gram_expand(uint32_t w, int sh)
-{
-    const uint32_t lo = ((w & 0xFu) | ((w & 0xF0u) << 12)) << sh;
-    const uint32_t hi = (((w >> 8) & 0xFu) | ((w & 0xF000u) << 4)) << sh;
-    return (uint64_t)lo | ((uint64_t)hi << 32);
-}
-
-// All 64 lanes: this lane's masks over the tile (lane = member): bit t of hb
-// when D_B(t) < 0, of ha when D_A(t) < 0.
+// All 64 lanes: this lane's masks over the tile's candidates (lane = member):
+// bit t of hb when D_B(t) < 0, of ha when D_A(t) < 0.
+// Lane (q, j) = (lane / 16, lane % 16) feeds row j of each row block rb with
+// candidate 16 (j / 4) + 4 rb + j % 4, so that the D rows it holds (4q + v)
+// are the candidates 16q + 4rb + v: its sign bits, collected rb- and v-major
+// by alignbit, are bits 16q .. 16q + 15 of the mask of member cb*16 + j.  A
+// 4 x 4 transpose over the lanes (q, j), q = 0..3, in two exchange steps
+// then gives every lane the four words of its own member.
 __device__ __forceinline__ void gram_tile(const WaveLds &L, int lane, uint64_t &hb, uint64_t &ha)
 {
     const int q = lane >> 4, j = lane & 15;
+    const int cbase = 16 * (j >> 2) + (j & 3);
     gs4_t A[4];
 #pragma unroll
     for (int rb = 0; rb < 4; ++rb) {
-        const uint2 w = *reinterpret_cast<const uint2 *>(&L.cf[rb * 16 + j][2 * q]);
+        const uint2 w = *reinterpret_cast<const uint2 *>(&L.cf[cbase + 4 * rb][2 * q]);
         A[rb] = gram_op(w.x, w.y);
     }
     const gf4_t zero = {0.0f, 0.0f, 0.0f, 0.0f};
-    hb = 0;
-    ha = 0;
+    uint32_t w[4];   // per column block: outer bits | inner bits << 16
 #pragma unroll
     for (int cb = 0; cb < 4; ++cb) {
         const int m = cb * 16 + j;
-        const uint2 w = *reinterpret_cast<const uint2 *>(&L.mf[m][2 * q]);
+        const uint2 mw = *reinterpret_cast<const uint2 *>(&L.mf[m][2 * q]);
         const uint32_t mav = L.ma[m];
-        uint2 wa = w;
-        if (q == 2) wa.y = (w.y & 0xFFFFu) | (mav << 16);          // element 11
-        if (q == 3) wa.x = (w.x & 0xFFFF0000u) | (mav >> 16);      // element 12
-        const gs4_t MB = gram_op(w.x, w.y), MA = gram_op(wa.x, wa.y);
-        uint32_t wb = 0, wa_ = 0;
+        uint2 wa = mw;
+        if (q == 2) wa.y = (mw.y & 0xFFFFu) | (mav << 16);        // element 11
+        if (q == 3) wa.x = (mw.x & 0xFFFF0000u) | (mav >> 16);    // element 12
+        const gs4_t MB = gram_op(mw.x, mw.y), MA = gram_op(wa.x, wa.y);
+        uint32_t ob = 0, ib = 0;
 #pragma unroll
         for (int rb = 3; rb >= 0; --rb) {
             const gf4_t db = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(A[rb], MB, zero, 0, 0, 0);
             const gf4_t da = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(A[rb], MA, zero, 0, 0, 0);
 #pragma unroll
             for (int v = 3; v >= 0; --v) {
-                wb = __builtin_amdgcn_alignbit(wb, __float_as_uint(db[v]), 31);
-                wa_ = __builtin_amdgcn_alignbit(wa_, __float_as_uint(da[v]), 31);
+                ob = __builtin_amdgcn_alignbit(ob, __float_as_uint(db[v]), 31);
+                ib = __builtin_amdgcn_alignbit(ib, __float_as_uint(da[v]), 31);
             }
         }
-        uint64_t pb = gram_expand(wb, 4 * q), pa = gram_expand(wa_, 4 * q);
-        pb |= (uint64_t)__shfl_xor((long long)pb, 16, 64);
-        pa |= (uint64_t)__shfl_xor((long long)pa, 16, 64);
-        pb |= (uint64_t)__shfl_xor((long long)pb, 32, 64);
-        pa |= (uint64_t)__shfl_xor((long long)pa, 32, 64);
-        if (cb == q) {
-            hb = pb;
-            ha = pa;
-        }
+        w[cb] = (ob & 0xFFFFu) | (ib << 16);
     }
+    // step 1, partner q ^ 1: keep the columns of this lane's parity
+    const bool odd = (q & 1) != 0, upper = (q & 2) != 0;
+    const uint32_t keep0 = odd ? w[1] : w[0], keep2 = odd ? w[3] : w[2];
+    const uint32_t r0 = (uint32_t)__shfl_xor((int)(odd ? w[0] : w[1]), 16, 64);
+    const uint32_t r2 = (uint32_t)__shfl_xor((int)(odd ? w[2] : w[3]), 16, 64);
+    // step 2, partner q ^ 2: keep this lane's column
+    const uint32_t u0 = (uint32_t)__shfl_xor((int)(upper ? keep0 : keep2), 32, 64);
+    const uint32_t u1 = (uint32_t)__shfl_xor((int)(upper ? r0 : r2), 32, 64);
+    // rows q, q^1, q^2, q^3 of column q, put in row order (index xor q)
+    uint32_t e0 = upper ? keep2 : keep0, e1 = upper ? r2 : r0, e2 = u0, e3 = u1;
+    if (odd) {
+        const uint32_t t0 = e0, t2 = e2;
+        e0 = e1; e1 = t0; e2 = e3; e3 = t2;
+    }
+    if (upper) {
+        const uint32_t t0 = e0, t1 = e1;
+        e0 = e2; e1 = e3; e2 = t0; e3 = t1;
+    }
+    const uint32_t blo = (e0 & 0xFFFFu) | (e1 << 16), bhi = (e2 & 0xFFFFu) | (e3 << 16);
+    const uint32_t alo = (e0 >> 16) | (e1 & 0xFFFF0000u), ahi = (e2 >> 16) | (e3 & 0xFFFF0000u);
+    hb = (uint64_t)blo | ((uint64_t)bhi << 32);
+    ha = (uint64_t)alo | ((uint64_t)ahi << 32);
 }
 
 // ascending bitonic sort of one value per lane across the wave
