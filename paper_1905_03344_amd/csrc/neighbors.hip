@@ -451,7 +451,9 @@ struct Shell {
 // Sub-groups of at most this many particles are counted one particle at a
 // time with the candidates spread over the lanes (transposed mode); larger
 // ones stream their union box through LDS tiles that every member tests.
+#ifndef SPH_SMALL_GROUP
 #define SPH_SMALL_GROUP 8
+#endif
 // a group is split by Morton prefix while its positions spread over more than
 // this many search diameters (3: measured best of 1.5, 2, 3, 5)
 #ifndef SPH_SPLIT_SPREAD
@@ -698,7 +700,8 @@ __device__ void walk_group(WaveLds &L, uint64_t members, int tm, int64_t i, doub
                     uint64_t hin, hsh;
                     if (G.ok) {
                         // certainly inner from the prefilter; the band and the
-                        // shell by the exact r^2
+                        // shell by the exact r^2, shell members recorded here
+                        // (in candidate order)
                         const uint64_t valid = m == 64 ? ~0ull : ((1ull << m) - 1ull);
                         hin = ga & valid;
                         hsh = 0;
@@ -708,8 +711,17 @@ __device__ void walk_group(WaveLds &L, uint64_t members, int tm, int64_t i, doub
                             chk &= chk - 1;
                             const double r2 = wraps ? tile_r2<PM>(L, t, xi, yi, zi, g)
                                                     : tile_r2<0>(L, t, xi, yi, zi, g);
-                            if (r2 < A2) hin |= 1ull << t;
-                            else if (r2 < B2) hsh |= 1ull << t;
+                            if (r2 < A2) {
+                                hin |= 1ull << t;
+                            } else if (r2 < B2) {
+                                if (nsh >= 0 && nsh < SPH_SHELL_SLOTS) {
+                                    SH.j[(int64_t)nsh * SH.sstride + i] = L.c[t].j;
+                                    SH.r2[(int64_t)nsh * SH.sstride + i] = r2;
+                                    ++nsh;
+                                } else {
+                                    nsh = -1;
+                                }
+                            }
                         }
                     } else if (m == 64) {
                         if (wraps) tile_hits<PM, true>(L, m, xi, yi, zi, A2, B2, g, &hin, &hsh);
