@@ -129,6 +129,9 @@ def main():
     ap.add_argument("--form", default="plain", choices=["plain", "mixed", "learned"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--search-div", type=int, default=2)
+    ap.add_argument("--walk-prefilter", default="matrix", choices=["matrix", "none"],
+                    help="candidate test of the h-iteration walk: bf16 Gram prefilter on the "
+                         "matrix cores with an exact FP64 band, or FP64 for every candidate")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a 1 GiB device copy (PMC byte-counter calibration)")
     args = ap.parse_args()
@@ -156,12 +159,14 @@ def main():
     ic = inputs.config_ic(args.config, seed_offset=100 if learned else 0)
     n = ic.n
     precision = ffi.SPH_FP64 if args.form == "plain" else ffi.SPH_MIXED
+    prefilter = (ffi.SPH_PREFILTER_MATRIX if args.walk_prefilter == "matrix"
+                 else ffi.SPH_PREFILTER_NONE)
     extra = {}
     if learned:
         from paper_1905_03344_amd import learned as L
         ic_a = inputs.config_ic(args.config)
         tr = Simulation(ic_a, search_div=args.search_div, precision=precision,
-                        extra_per_particle=extra_slots)
+                        extra_per_particle=extra_slots, walk_prefilter=prefilter)
         tr.evaluate()
         tr.sync()
         torch.cuda.synchronize()
@@ -188,7 +193,7 @@ def main():
         torch.cuda.empty_cache()
     sim = Simulation(ic, search_div=args.search_div, precision=precision,
                      h_mode=ffi.SPH_H_LEARNED if learned else ffi.SPH_H_PLAIN,
-                     extra_per_particle=extra_slots)
+                     extra_per_particle=extra_slots, walk_prefilter=prefilter)
     if learned:
         sim.set_mlp(w, norm)
     log(f"bench: n={n} max_level={sim.params.max_level} workspace={sim.ws_bytes/2**20:.1f} MiB")
@@ -267,7 +272,8 @@ def main():
         "vs_baseline": None,
         "dtype": "f64" if args.form == "plain" else "f32/f64",
         "data": "synthetic",
-        "config": {"workload": workload, "n": n, "form": args.form, "dt": "courant cfl 0.3"},
+        "config": {"workload": workload, "n": n, "form": args.form, "dt": "courant cfl 0.3",
+                   "walk_prefilter": args.walk_prefilter},
         "roofline": roofline,
         "kernels": kernels,
         "stages_ms_per_step": {k: round(v, 4) for k, v in stage_ms.items()},

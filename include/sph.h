@@ -57,12 +57,22 @@ extern "C" {
 
 typedef struct sph_ctx sph_ctx;
 
+/* Candidate test of the group walk in the neighbour search.  NONE: every
+ * candidate of a union tile gets the FP64 r^2 test.  MATRIX: a 64 x 64
+ * tile's r^2 - threshold values are first formed as Gram products on the
+ * matrix cores (bfloat16 hi/lo splits, FP32 sums) with a band of
+ * 2^-11 (U^2 + T) around each threshold; only candidates inside the band
+ * or the shell get the FP64 test.  Both give the same sets, counts, order
+ * and h bit for bit. */
+#define SPH_PREFILTER_NONE 0
+#define SPH_PREFILTER_MATRIX 1
+
 typedef struct sph_params {
     int64_t n_max;          /* largest particle count the workspace is sized for */
     int32_t list_stride;    /* K: capacity of each gather set L_i (default 128) */
     int32_t pad0;
     int32_t extra_slots;    /* capacity of each complement row E_i (default 48) */
-    int32_t pad1;
+    int32_t walk_prefilter; /* SPH_PREFILTER_MATRIX (default) or SPH_PREFILTER_NONE */
     int32_t periodic[3];    /* 1 = periodic dimension (minimum image, wrap) */
     int32_t kernel;         /* SPH_KERNEL_M4 */
     double box_lo[3];       /* box of the periodic dimensions */

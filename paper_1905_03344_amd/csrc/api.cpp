@@ -112,6 +112,7 @@ extern "C" void sph_default_params(sph_params *p)
     p->check_finite = 0;
     p->max_level = 6;
     p->search_div = 2;
+    p->walk_prefilter = SPH_PREFILTER_MATRIX;
 }
 
 extern "C" const char *sph_params_error(void) { return g_params_error; }
@@ -129,6 +130,8 @@ static const char *validate(const sph_params *p)
     if (p->h_mode != SPH_H_PLAIN && p->h_mode != SPH_H_LEARNED) return "unknown h_mode";
     if (p->max_level < 1 || p->max_level > 8) return "max_level must be in 1..8";
     if (p->search_div < 1 || p->search_div > 4) return "search_div must be in 1..4";
+    if (p->walk_prefilter != SPH_PREFILTER_NONE && p->walk_prefilter != SPH_PREFILTER_MATRIX)
+        return "walk_prefilter must be SPH_PREFILTER_NONE or SPH_PREFILTER_MATRIX";
     if (!(p->gamma > 1.0)) return "gamma must exceed 1";
     if (!(p->cfl > 0.0)) return "cfl must be positive";
     if (!(p->av_eta2 > 0.0)) return "av_eta2 must be positive";

@@ -10,18 +10,20 @@ struct Search {
     const int32_t *cs;
     int lmax;
     int div;
+    int prefilter;   // SPH_PREFILTER_*
     double lo[3], L[3];
     double margin;
     Geo g;
 };
 
-__device__ __forceinline__ Search make_search(const int32_t *cs, int lmax, int div,
+__device__ __forceinline__ Search make_search(const int32_t *cs, int lmax, int div, int prefilter,
                                               const double *bbox, Geo g)
 {
     Search S;
     S.cs = cs;
     S.lmax = lmax;
     S.div = div;
+    S.prefilter = prefilter;
     double mx = 0.0;
     for (int d = 0; d < 3; ++d) {
         S.lo[d] = bbox[d];
@@ -549,7 +551,7 @@ __device__ void walk_group(WaveLds &L, uint64_t members, int tm, int64_t i, doub
     G.ok = false;
     if (!TRANSPOSED) {
         double U2 = 0.0;
-        bool ok = Rmax > 0.0 && Rmax < INFINITY;
+        bool ok = S.prefilter == SPH_PREFILTER_MATRIX && Rmax > 0.0 && Rmax < INFINITY;
         for (int d = 0; d < 3; ++d) {
             const double cwd = ldexp(S.L[d], -l);
             G.c[d] = 0.5 * (blo[d] + bhi[d]);
@@ -1008,7 +1010,7 @@ struct HArgs {
     const double *bbox;
     const double *hk;
     Geo g;
-    int lmax, div, target, tol, maxit;
+    int lmax, div, prefilter, target, tol, maxit;
     HIter H;
     Shell SH;
     int64_t *status;
@@ -1101,7 +1103,7 @@ __attribute__((amdgpu_waves_per_eu(SPH_ROUND_WAVES, SPH_ROUND_WAVES))) void k_hs
     // rounds (a learned try that is left behind does not count); one that
     // has used them waits, still listed, for the per-particle tail
     const bool valid = listed && (!wl || (A.H.bits[i] >> 8) < SPH_WAVE_ROUNDS + 1);
-    const Search S = make_search(A.cs, A.lmax, A.div, A.bbox, A.g);
+    const Search S = make_search(A.cs, A.lmax, A.div, A.prefilter, A.bbox, A.g);
 
     // only what the walk needs is live across it; the iteration state is
     // set up (round 0) or loaded (later rounds) afterwards
@@ -1228,7 +1230,7 @@ __global__ __launch_bounds__(SPH_BLOCK) __attribute__((amdgpu_waves_per_eu(2, 2)
     const int64_t gw = (int64_t)blockIdx.x * WAVES_PER_BLOCK + w;
     const int64_t nw = (int64_t)gridDim.x * WAVES_PER_BLOCK;
     const int64_t total = *wcount;
-    const Search S = make_search(A.cs, A.lmax, A.div, A.bbox, A.g);
+    const Search S = make_search(A.cs, A.lmax, A.div, A.prefilter, A.bbox, A.g);
     int64_t counts = 0, tested = 0, nonconv = 0, overflow = 0, acc = 0, fallback = 0;
     for (int64_t t = gw; t < total; t += nw) {
         const int64_t i = wl[t];
@@ -1296,7 +1298,7 @@ __global__ __launch_bounds__(SPH_BLOCK) void k_refill(HArgs A, int64_t n)
     int64_t overflow = 0, tested = 0;
     const bool act = i < n && A.refill[i];
     if (__ballot(act)) {
-        const Search S = make_search(A.cs, A.lmax, A.div, A.bbox, A.g);
+        const Search S = make_search(A.cs, A.lmax, A.div, A.prefilter, A.bbox, A.g);
         double xi = 0.0, yi = 0.0, zi = 0.0, hi = 0.0;
         uint32_t ki = 0;
         if (i < n) {
@@ -1343,6 +1345,7 @@ hipError_t launch_hsolve(sph_ctx *c, sph_particles *s, sph_nlist *nl, const doub
     A.g = g;
     A.lmax = p.max_level;
     A.div = p.search_div;
+    A.prefilter = p.walk_prefilter;
     A.target = p.n_target;
     A.tol = p.n_tol;
     A.maxit = p.h_max_iter;

@@ -21,6 +21,8 @@ SPH_WNOCONV = 1
 SPH_KERNEL_M4 = 0
 SPH_FP64 = 0
 SPH_MIXED = 1
+SPH_PREFILTER_NONE = 0
+SPH_PREFILTER_MATRIX = 1
 SPH_H_PLAIN = 0
 SPH_H_LEARNED = 1
 SPH_FLAG_NOCONV = 1
@@ -34,7 +36,7 @@ _D = ctypes.c_double
 
 class sph_params(ctypes.Structure):
     _fields_ = [("n_max", _I64), ("list_stride", _I32), ("pad0", _I32),
-                ("extra_slots", _I32), ("pad1", _I32), ("periodic", _I32 * 3), ("kernel", _I32),
+                ("extra_slots", _I32), ("walk_prefilter", _I32), ("periodic", _I32 * 3), ("kernel", _I32),
                 ("box_lo", _D * 3), ("box_hi", _D * 3), ("n_target", _I32), ("n_tol", _I32),
                 ("h_max_iter", _I32), ("precision", _I32), ("gamma", _D), ("av_alpha", _D),
                 ("av_beta", _D), ("av_eta2", _D), ("cfl", _D), ("h_mode", _I32),

@@ -29,7 +29,8 @@ def choose_max_level(n: int, bbox_extent: float, h_min: float, search_div: int =
 class Simulation:
     def __init__(self, ic, params: ffi.sph_params | None = None, device="cuda", n_max=None,
                  list_stride=128, extra_per_particle=48, max_level=None, search_div=2,
-                 precision=ffi.SPH_FP64, check_finite=False, h_mode=ffi.SPH_H_PLAIN):
+                 precision=ffi.SPH_FP64, check_finite=False, h_mode=ffi.SPH_H_PLAIN,
+                 walk_prefilter=None):
         self.device = torch.device(device)
         n = ic.n
         self.n = n
@@ -49,6 +50,8 @@ class Simulation:
                 max_level = 1
         p.max_level = int(max_level)
         p.search_div = int(search_div)
+        if walk_prefilter is not None:
+            p.walk_prefilter = int(walk_prefilter)
         p.precision = int(precision)
         p.check_finite = int(bool(check_finite))
         p.h_mode = int(h_mode)

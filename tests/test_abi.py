@@ -61,6 +61,12 @@ def test_params_validation(lib):
     bad.periodic[2] = 1
     with pytest.raises(ffi.SphError):
         ffi.sph_create(bad)
+    assert p.walk_prefilter == ffi.SPH_PREFILTER_MATRIX
+    bad = ffi.default_params()
+    bad.walk_prefilter = 2
+    with pytest.raises(ffi.SphError) as e:
+        ffi.sph_create(bad)
+    assert "walk_prefilter" in str(e.value)
 
 
 def test_workspace_size_grows_with_n(lib):
