@@ -618,25 +618,36 @@ __device__ void walk_group(WaveLds &L, uint64_t members, int tm, int64_t i, doub
     int Nm = 0, nshm = 0;
     const uint64_t below = (1ull << lane) - 1ull;
 
+    int wtag = 0;   // window tags of this walk
+    L.pre[lane] = -1;
     // one batch of up to 64 non-empty cells (this lane: s0, len)
     auto batch = [&](int s0, int len) {
         int incl = wave_incl_scan_i(len);
         int total = __shfl(incl, 63, 64);
         wave_lds_sync();
-        L.start[lane] = s0;
-        L.pre[lane] = incl - len;
+        const int pre_me = incl - len;   // this cell-lane's first candidate in the batch
+        L.start[lane] = s0 - pre_me;     // candidate v of cell r is particle start[r] + v
         wave_lds_sync();
         if (TRANSPOSED ? lane == tm : me) tested += total;
-        // candidate v of the batch (-1 past its end): cell by binary search
-        // over the prefix sums
-        auto cand_index = [&](int v) {
+        // Candidates of the window [w0, w0 + 64), one per lane (-1 past the
+        // batch's end), windows taken in order.  rw is the cell holding
+        // candidate w0; the cells starting inside the window are flagged at
+        // their offsets with the window's tag (unique in this walk, the
+        // flags were cleared at its start), so a lane's cell is rw plus the
+        // starts at or before it (non-empty cells start at distinct
+        // candidates).
+        int rw = 0;
+        auto window = [&](int w0) {
+            const int k = pre_me - w0;
+            const int tag = wtag++;
+            wave_lds_sync();
+            if (len > 0 && k > 0 && k < 64) L.pre[k] = tag;
+            wave_lds_sync();
+            const uint64_t starts = __ballot(L.pre[lane] == tag);
+            const int v = w0 + lane;
             int j = -1;
-            if (v < total) {
-                int r = 0;
-                for (int st = 32; st > 0; st >>= 1)
-                    if (L.pre[r + st] <= v) r += st;
-                j = L.start[r] + (v - L.pre[r]);
-            }
+            if (v < total) j = L.start[rw + __popcll(starts & ((2ull << lane) - 1ull))] + v;
+            rw += __popcll(starts) + (__ballot(len > 0 && k == 64) != 0 ? 1 : 0);
             return j;
         };
         // union mode keeps the next tile's candidate in flight while the
@@ -644,12 +655,12 @@ __device__ void walk_group(WaveLds &L, uint64_t members, int tm, int64_t i, doub
         int jn = -1;
         double xn = 0.0, yn = 0.0, zn = 0.0;
         if (!TRANSPOSED) {
-            jn = cand_index(lane);
+            jn = window(0);
             if (jn >= 0) { xn = x[jn]; yn = y[jn]; zn = z[jn]; }
         }
         for (int base = 0; base < total; base += 64) {
             int j = -1;
-            if (TRANSPOSED) j = cand_index(base + lane);
+            if (TRANSPOSED) j = window(base);
             if (TRANSPOSED) {
                 bool hin = false, hsh = false;
                 double r2 = 0.0;
@@ -693,7 +704,7 @@ __device__ void walk_group(WaveLds &L, uint64_t members, int tm, int64_t i, doub
                     }
                 }
                 wave_lds_sync();
-                jn = cand_index(base + 64 + lane);
+                jn = window(base + 64);
                 if (jn >= 0) { xn = x[jn]; yn = y[jn]; zn = z[jn]; }
                 const int m = min(64, total - base);
                 uint64_t gb = 0, ga = 0;
