@@ -22,9 +22,12 @@ __host__ __device__ static inline MixQ mix_quads(void *base, int64_t n_max)
     return MixQ{q, q + n_max, q + 2 * n_max, q + 3 * n_max};
 }
 
-// lanes per particle in the pair loops, and their partial sums combined in a
-// fixed butterfly order (Neumaier steps: the same value in every lane)
-#define SPH_MGROUP 16
+// lanes per particle in the pair loops (8: measured best of 4, 8, 16, 32, 64),
+// and their partial sums combined in a fixed butterfly order (Neumaier
+// steps: the same value in every lane)
+#ifndef SPH_MGROUP
+#define SPH_MGROUP 8
+#endif
 #ifndef SPH_MBATCH
 #define SPH_MBATCH 4
 #endif
@@ -156,7 +159,7 @@ __global__ __launch_bounds__(SPH_BLOCK) void k_density_mixed(
     const int64_t base = (int64_t)xcd_block(blockIdx.x, gridDim.x) * SPH_BLOCK;
     int64_t appended = 0, dropped = 0;
     const MixGeo G = mix_geo(bbox, g);
-    for (int rr = 0; rr < SPH_BLOCK / SPH_MGROUP; ++rr) {
+    for (int rr = 0; rr < SPH_MGROUP; ++rr) {   // SPH_BLOCK / SPH_MGROUP groups, SPH_MGROUP rounds
         const int64_t i = base + (int64_t)rr * (SPH_BLOCK / SPH_MGROUP) + grp;
         NeuF s = {0.0f, 0.0f}, dv = {0.0f, 0.0f};
         float4 ai = make_float4(0.f, 0.f, 0.f, 0.f), bi = ai;
@@ -339,7 +342,7 @@ __global__ __launch_bounds__(SPH_BLOCK) void k_forces_mixed(
     const MixGeo G = mix_geo(bbox, g);
     __shared__ int32_t e_raw[ELDS ? SPH_BLOCK / SPH_MGROUP : 1][ELDS ? SPH_ELDS : 1];
     __shared__ int32_t e_srt[ELDS ? SPH_BLOCK / SPH_MGROUP : 1][ELDS ? SPH_ELDS : 1];
-    for (int rr = 0; rr < SPH_BLOCK / SPH_MGROUP; ++rr) {
+    for (int rr = 0; rr < SPH_MGROUP; ++rr) {   // SPH_BLOCK / SPH_MGROUP groups, SPH_MGROUP rounds
         const int64_t i = base + (int64_t)rr * (SPH_BLOCK / SPH_MGROUP) + grp;
         ForceAccF A = {{0.f, 0.f}, {0.f, 0.f}, {0.f, 0.f}, {0.f, 0.f}, 0.f};
         if (i < n) {

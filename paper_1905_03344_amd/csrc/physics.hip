@@ -12,8 +12,14 @@
 // lane sums its share of the pairs (k = lane, lane + SPH_GROUP, ...) and the
 // group adds the partial sums in a fixed butterfly order, so results are
 // reproducible.  Block b treats particles [SPH_BLOCK b, SPH_BLOCK (b+1)):
-// in round r its 16 groups take particles SPH_BLOCK b + 16 r + group.
-#define SPH_GROUP 16
+// in round r its G = SPH_BLOCK / SPH_GROUP groups take particles
+// SPH_BLOCK b + G r + group.  Eight lanes per particle (eight particles per
+// wave) measured best of 4, 8, 16, 32 and 64: a wave load then spans the
+// short row segments of eight consecutive particles, whose neighbours
+// overlap, and rows of ~100 entries keep the lanes busy.
+#ifndef SPH_GROUP
+#define SPH_GROUP 8
+#endif
 #ifndef SPH_BATCH
 #define SPH_BATCH 4
 #endif
@@ -63,7 +69,7 @@ __global__ __launch_bounds__(SPH_BLOCK) void k_density(
     const int grp = threadIdx.x / SPH_GROUP;
     const int64_t base = (int64_t)xcd_block(blockIdx.x, gridDim.x) * SPH_BLOCK;
     int64_t appended = 0, dropped = 0;
-    for (int r = 0; r < SPH_BLOCK / SPH_GROUP; ++r) {
+    for (int r = 0; r < SPH_GROUP; ++r) {   // SPH_BLOCK / SPH_GROUP groups, SPH_GROUP rounds
         const int64_t i = base + (int64_t)r * (SPH_BLOCK / SPH_GROUP) + grp;
         double s = 0.0, dv = 0.0, inv_h = 0.0, mi = 0.0;
         if (i < n) {
@@ -348,7 +354,7 @@ __global__ __launch_bounds__(SPH_BLOCK) void k_forces(
     __shared__ int32_t e_raw[ELDS ? SPH_BLOCK / SPH_GROUP : 1][ELDS ? SPH_ELDS : 1];
     __shared__ int32_t e_srt[ELDS ? SPH_BLOCK / SPH_GROUP : 1][ELDS ? SPH_ELDS : 1];
     double dti = INFINITY;
-    for (int r = 0; r < SPH_BLOCK / SPH_GROUP; ++r) {
+    for (int r = 0; r < SPH_GROUP; ++r) {   // SPH_BLOCK / SPH_GROUP groups, SPH_GROUP rounds
         const int64_t i = base + (int64_t)r * (SPH_BLOCK / SPH_GROUP) + grp;
         ForceAcc A = {0.0, 0.0, 0.0, 0.0, 0.0};
         double hi = 0.0, ci = 0.0;
