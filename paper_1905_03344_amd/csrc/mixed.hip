@@ -147,7 +147,7 @@ __device__ __forceinline__ MixGeo mix_geo(const double *__restrict__ bbox, const
 }
 
 template <int PM, bool EXTRA>
-__global__ __launch_bounds__(SPH_BLOCK) void k_density_mixed(
+__global__ __launch_bounds__(SPH_BLOCK) SPH_PAIR_WAVES_D void k_density_mixed(
     int64_t n, MixQ Q, const int32_t *__restrict__ nc, const int32_t *__restrict__ idx, int K,
     const double *__restrict__ bbox, Geo g, const double *__restrict__ x,
     const double *__restrict__ y, const double *__restrict__ z, const double *__restrict__ h,
@@ -326,7 +326,7 @@ __device__ __forceinline__ void force_pair_f(const QuadF &ri, float inv_hi, uint
 // S_i = L_i (row order) then E_i (ascending), SPH_MGROUP lanes per particle;
 // ELDS: E rows ranked in LDS here (capacity <= SPH_ELDS), else sorted already
 template <int PM, bool ELDS>
-__global__ __launch_bounds__(SPH_BLOCK) void k_forces_mixed(
+__global__ __launch_bounds__(SPH_BLOCK) SPH_PAIR_WAVES_F void k_forces_mixed(
     int64_t n, MixQ Q, const int32_t *__restrict__ nc, const int32_t *__restrict__ idx, int K,
     const int32_t *__restrict__ ecnt, const int32_t *__restrict__ eidx, int slots,
     const double *__restrict__ bbox, Geo g, float alpha, float beta, float eta2, double alpha_d,

@@ -60,7 +60,7 @@ __global__ __launch_bounds__(SPH_BLOCK) void k_pack64(
 }
 
 template <int PM, bool EXTRA>
-__global__ __launch_bounds__(SPH_BLOCK) void k_density(
+__global__ __launch_bounds__(SPH_BLOCK) SPH_PAIR_WAVES_D void k_density(
     int64_t n, Pk64 P, const int32_t *__restrict__ nc, const int32_t *__restrict__ idx, int K, Geo g,
     double *__restrict__ rho, double *__restrict__ divv, int32_t *__restrict__ ecnt,
     int32_t *__restrict__ eidx, int slots, int64_t *__restrict__ status)
@@ -340,7 +340,7 @@ __device__ __forceinline__ void force_pair(const NbrF &b, double xi, double yi, 
 // S_i = L_i (row order) then E_i (ascending) in groups of SPH_GROUP lanes;
 // ELDS: E rows ranked in LDS here (capacity <= SPH_ELDS), else sorted already
 template <int PM, bool ELDS>
-__global__ __launch_bounds__(SPH_BLOCK) void k_forces(
+__global__ __launch_bounds__(SPH_BLOCK) SPH_PAIR_WAVES_F void k_forces(
     int64_t n, Pk64 P, const double *__restrict__ c, const int32_t *__restrict__ nc, const int32_t *__restrict__ idx, int K,
     const int32_t *__restrict__ ecnt, const int32_t *__restrict__ eidx, int slots, Geo g,
     double alpha, double beta, double eta2, double cfl, double *__restrict__ ax,

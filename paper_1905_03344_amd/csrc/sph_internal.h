@@ -7,7 +7,21 @@
 #include "../../include/sph.h"
 
 #define SPH_BLOCK 256
+// waves per SIMD the pair kernels are compiled for (empty: the compiler's
+// choice)
+#ifdef SPH_DENSITY_WAVES
+#define SPH_PAIR_WAVES_D __attribute__((amdgpu_waves_per_eu(SPH_DENSITY_WAVES, SPH_DENSITY_WAVES)))
+#else
+#define SPH_PAIR_WAVES_D
+#endif
+#ifdef SPH_FORCE_WAVES
+#define SPH_PAIR_WAVES_F __attribute__((amdgpu_waves_per_eu(SPH_FORCE_WAVES, SPH_FORCE_WAVES)))
+#else
+#define SPH_PAIR_WAVES_F
+#endif
+#ifndef SPH_SORT_ITEMS
 #define SPH_SORT_ITEMS 16                      // keys per thread per sort tile
+#endif
 #define SPH_SORT_TILE (SPH_BLOCK * SPH_SORT_ITEMS)
 #define SPH_SCAN_ITEMS 8
 #define SPH_SCAN_TILE (SPH_BLOCK * SPH_SCAN_ITEMS)
