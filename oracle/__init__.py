@@ -56,8 +56,12 @@ def lib():
         L.or_kernel_w.argtypes = [ctypes.c_double, ctypes.c_double]
         L.or_kernel_dwdr.restype = ctypes.c_double
         L.or_kernel_dwdr.argtypes = [ctypes.c_double, ctypes.c_double]
-        L.or_kernel_wendland.restype = ctypes.c_double
-        L.or_kernel_wendland.argtypes = [ctypes.c_double, ctypes.c_double]
+        for nm in ("or_kernel_wendland", "or_kernel_wendland_dwdr", "or_kernel_sinc",
+                   "or_kernel_sinc_dwdr"):
+            getattr(L, nm).restype = ctypes.c_double
+            getattr(L, nm).argtypes = [ctypes.c_double, ctypes.c_double]
+        L.or_sinc_norm.restype = ctypes.c_double
+        L.or_sinc_norm.argtypes = []
         L.or_hsolve.restype = ctypes.c_int64
         L.or_lists.restype = ctypes.c_int64
         L.or_mlp_loss_grad.restype = ctypes.c_double
@@ -88,6 +92,28 @@ def kernel_dwdr(r, h):
 
 def kernel_wendland(r, h):
     return lib().or_kernel_wendland(float(r), float(h))
+
+
+def kernel_wendland_dwdr(r, h):
+    return lib().or_kernel_wendland_dwdr(float(r), float(h))
+
+
+def kernel_sinc(r, h):
+    """sinc kernel, exponent 5 (kernel section; B_5 by normalisation)"""
+    return lib().or_kernel_sinc(float(r), float(h))
+
+
+def kernel_sinc_dwdr(r, h):
+    return lib().or_kernel_sinc_dwdr(float(r), float(h))
+
+
+def sinc_norm():
+    return lib().or_sinc_norm()
+
+
+# kernel ids of the density and force sums (same numbering as the library's
+# sph_params.kernel)
+KERNEL_M4, KERNEL_WENDLAND, KERNEL_SINC5 = 0, 1, 2
 
 
 def hk_table(n_target=100):
@@ -182,7 +208,8 @@ def lists(x, y, z, h, periodic, box_lo, box_hi, method=1, symmetric=True):
 # fields
 # ---------------------------------------------------------------------------
 
-def density(x, y, z, vx, vy, vz, m, h, periodic, box_lo, box_hi, off, idx, with_mag=False):
+def density(x, y, z, vx, vy, vz, m, h, periodic, box_lo, box_hi, off, idx, with_mag=False,
+            kernel=0):
     """rho, divv (and, with_mag, (1/rho) sum |m_j (v_j - v_i).grad W|, the scale
     of the divergence sum used for conditioning-aware comparisons)."""
     arr = [_f64(a) for a in (x, y, z, vx, vy, vz, m, h)]
@@ -193,7 +220,8 @@ def density(x, y, z, vx, vy, vz, m, h, periodic, box_lo, box_hi, off, idx, with_
     off = np.ascontiguousarray(off, dtype=np.int64)
     idx = np.ascontiguousarray(idx, dtype=np.int32)
     lib().or_density(ctypes.c_int64(n), *[_p(a) for a in arr], _int3(*periodic), _dbl3(*box_lo),
-                     _dbl3(*box_hi), _p(off, _i64), _p(idx, _i32), _p(rho), _p(divv), _p(mag))
+                     _dbl3(*box_hi), _p(off, _i64), _p(idx, _i32), _p(rho), _p(divv), _p(mag),
+                     ctypes.c_int(kernel))
     return (rho, divv, mag) if with_mag else (rho, divv)
 
 
@@ -206,7 +234,7 @@ def eos(rho, u, gamma=5.0 / 3.0):
 
 
 def forces(x, y, z, vx, vy, vz, m, h, rho, p, c, periodic, box_lo, box_hi, off, idx,
-           alpha=1.0, beta=2.0, eta2=0.01, cfl=0.3, with_mag=False):
+           alpha=1.0, beta=2.0, eta2=0.01, cfl=0.3, with_mag=False, kernel=0):
     """a, du, per-particle dt, sum_j m_j |f_ij| (and with_mag sum_j m_j |de_ij|)."""
     arr = [_f64(a) for a in (x, y, z, vx, vy, vz, m, h, rho, p, c)]
     n = len(arr[0])
@@ -216,7 +244,7 @@ def forces(x, y, z, vx, vy, vz, m, h, rho, p, c, periodic, box_lo, box_hi, off, 
     lib().or_forces(ctypes.c_int64(n), *[_p(a) for a in arr], _int3(*periodic), _dbl3(*box_lo),
                     _dbl3(*box_hi), _p(off, _i64), _p(idx, _i32), ctypes.c_double(alpha),
                     ctypes.c_double(beta), ctypes.c_double(eta2), ctypes.c_double(cfl),
-                    *[_p(a) for a in out])
+                    *[_p(a) for a in out], ctypes.c_int(kernel))
     ax, ay, az, du, dt_i, amag, dumag = out
     if with_mag:
         return ax, ay, az, du, dt_i, amag, dumag
@@ -224,13 +252,13 @@ def forces(x, y, z, vx, vy, vz, m, h, rho, p, c, periodic, box_lo, box_hi, off, 
 
 
 def pair_term(x, y, z, vx, vy, vz, m, h, rho, p, c, periodic, box_lo, box_hi, i, j,
-              alpha=1.0, beta=2.0, eta2=0.01):
+              alpha=1.0, beta=2.0, eta2=0.01, kernel=0):
     arr = [_f64(a) for a in (x, y, z, vx, vy, vz, m, h, rho, p, c)]
     out = np.zeros(4)
     lib().or_pair_term(ctypes.c_int64(len(arr[0])), *[_p(a) for a in arr], _int3(*periodic),
                        _dbl3(*box_lo), _dbl3(*box_hi), ctypes.c_int64(i), ctypes.c_int64(j),
                        ctypes.c_double(alpha), ctypes.c_double(beta), ctypes.c_double(eta2),
-                       _p(out))
+                       _p(out), ctypes.c_int(kernel))
     return out
 
 
@@ -259,6 +287,7 @@ class Params:
     beta: float = 2.0
     eta2: float = 0.01
     cfl: float = 0.3
+    kernel: int = 0   # KERNEL_M4, KERNEL_WENDLAND or KERNEL_SINC5
 
 
 class State:
@@ -367,7 +396,7 @@ class State:
         self.pv = (vel, u)
         self.find_neighbors(method)
         rho, divv, dvmag = density(f["x"], f["y"], f["z"], *vel, f["m"], f["h"], *self.geom(),
-                                   self.off, self.idx, with_mag=True)
+                                   self.off, self.idx, with_mag=True, kernel=self.p.kernel)
         f["rho"], f["divv"] = rho, divv
         self.divv_mag = dvmag
         P, c = eos(rho, u, self.p.gamma)
@@ -375,7 +404,7 @@ class State:
         ax, ay, az, du, dt_i, amag, dumag = forces(f["x"], f["y"], f["z"], *vel, f["m"], f["h"],
                                                    rho, P, c, *self.geom(), self.off, self.idx,
                                                    self.p.alpha, self.p.beta, self.p.eta2,
-                                                   self.p.cfl, with_mag=True)
+                                                   self.p.cfl, with_mag=True, kernel=self.p.kernel)
         f["ax"], f["ay"], f["az"], f["du"] = ax, ay, az, du
         self.amag, self.dumag, self.dt_i = amag, dumag, dt_i
         self.dt_next = float(dt_i.min()) if len(dt_i) else np.inf

@@ -11,7 +11,8 @@
  * textbook form of the works the paper names, as listed per function):
  *   - M4 cubic-spline kernel and its radial derivative (kernel section,
  *     support 0 <= v <= 2 as in the Sinc and Wendland equations; M4 is the
- *     spline listed for ChaNGa in Table 1);
+ *     spline listed for ChaNGa in Table 1), and the kernel section's own
+ *     two kernels: Wendland C2 and the sinc family (exponent 5);
  *   - cell keys: 10-bit-per-dimension Morton interleave of the cell index in
  *     the bounding box, stable sort by key (replaces the tree walk of
  *     Table 1 by a cell list);
@@ -84,6 +85,100 @@ double or_kernel_wendland(double r, double h)
     if (v >= 2.0) return 0.0;
     double t = 1.0 - 0.5 * v;
     return 21.0 / (16.0 * OR_PI * h * h * h) * (t * t * t * t) * (2.0 * v + 1.0);
+}
+
+/* dW/dr of the Wendland C2 kernel: d/dv [(1 - v/2)^4 (2v + 1)] = -5 v (1 - v/2)^3 */
+double or_kernel_wendland_dwdr(double r, double h)
+{
+    double v = r / h;
+    if (v >= 2.0) return 0.0;
+    double t = 1.0 - 0.5 * v;
+    return 21.0 / (16.0 * OR_PI * h * h * h * h) * (-5.0 * v) * (t * t * t);
+}
+
+/* Sinc kernel of the kernel section, W = B_n / h^3 sinc^n(pi v / 2), 0 <= v <= 2,
+ * sinc(x) = sin(x) / x.  The paper gives neither n nor B_n: n = 5 here, and B_n
+ * follows from normalisation, B_n = 1 / (4 pi int_0^2 sinc^n(pi v/2) v^2 dv),
+ * the integral by composite Simpson on 2^16 intervals.                       */
+#define OR_SINC_N 5
+static double sinc_val(double x)
+{
+    /* Taylor series below 1/2 (terms to x^16), sin(x)/x above */
+    if (x < 0.5) {
+        double x2 = x * x, term = 1.0, s = 1.0;
+        for (int k = 1; k <= 8; ++k) {
+            term *= -x2 / ((2.0 * k) * (2.0 * k + 1.0));
+            s += term;
+        }
+        return s;
+    }
+    return sin(x) / x;
+}
+static double sinc_deriv(double x)
+{
+    /* d/dx sin(x)/x = (x cos x - sin x) / x^2; series -x/3 + x^3/30 - ... below 1/2 */
+    if (x < 0.5) {
+        double x2 = x * x, term = 1.0, s = 0.0;
+        for (int k = 1; k <= 8; ++k) {
+            term *= -x2 / ((2.0 * k) * (2.0 * k + 1.0));   /* (-1)^k x^2k / (2k+1)! */
+            s += 2.0 * k * term;
+        }
+        return s / x;   /* x > 0 here: callers handle x = 0 */
+    }
+    return (x * cos(x) - sin(x)) / (x * x);
+}
+static double sinc_pow(double s)
+{
+    double s2 = s * s;
+    return s2 * s2 * s;   /* n = 5 */
+}
+double or_sinc_norm(void)
+{
+    static double bn = 0.0;
+    if (bn == 0.0) {
+        const int m = 1 << 16;
+        const double dv = 2.0 / m;
+        double acc = 0.0;
+        for (int k = 0; k <= m; ++k) {
+            double v = k * dv;
+            double f = sinc_pow(sinc_val(0.5 * OR_PI * v)) * v * v;
+            double wgt = (k == 0 || k == m) ? 1.0 : ((k & 1) ? 4.0 : 2.0);
+            acc += wgt * f;
+        }
+        double integral = acc * dv / 3.0;
+        bn = 1.0 / (4.0 * OR_PI * integral);
+    }
+    return bn;
+}
+double or_kernel_sinc(double r, double h)
+{
+    double v = r / h;
+    if (v >= 2.0) return 0.0;
+    return or_sinc_norm() / (h * h * h) * sinc_pow(sinc_val(0.5 * OR_PI * v));
+}
+/* dW/dr = B_n / h^4 * n sinc^(n-1)(x) sinc'(x) * pi/2,  x = pi v / 2 */
+double or_kernel_sinc_dwdr(double r, double h)
+{
+    double v = r / h;
+    if (v >= 2.0 || v <= 0.0) return 0.0;
+    double x = 0.5 * OR_PI * v;
+    double s = sinc_val(x);
+    double s4 = (s * s) * (s * s);
+    return or_sinc_norm() / (h * h * h * h) * (OR_SINC_N * s4 * sinc_deriv(x) * (0.5 * OR_PI));
+}
+
+/* kernel selection: 0 = M4, 1 = Wendland C2, 2 = sinc (n = 5) */
+static double kern(int kernel, double r, double h)
+{
+    if (kernel == 1) return or_kernel_wendland(r, h);
+    if (kernel == 2) return or_kernel_sinc(r, h);
+    return or_kernel_w(r, h);
+}
+static double kern_dr(int kernel, double r, double h)
+{
+    if (kernel == 1) return or_kernel_wendland_dwdr(r, h);
+    if (kernel == 2) return or_kernel_sinc_dwdr(r, h);
+    return or_kernel_dwdr(r, h);
 }
 
 /* ------------------------------------------------------------------------ */
@@ -561,7 +656,7 @@ void or_density(int64_t n, const double *x, const double *y, const double *z,
                 const double *vx, const double *vy, const double *vz, const double *m,
                 const double *h, const int *periodic, const double *box_lo,
                 const double *box_hi, const int64_t *off, const int32_t *idx,
-                double *rho, double *divv, double *divv_mag)
+                double *rho, double *divv, double *divv_mag, int kernel)
 {
     or_geom g;
     geom_init(&g, x, y, z, periodic, box_lo, box_hi);
@@ -570,7 +665,7 @@ void or_density(int64_t n, const double *x, const double *y, const double *z,
         double hi = h[i];
         double twoh = 2.0 * hi;
         double r2max = twoh * twoh;
-        double s = m[i] * or_kernel_w(0.0, hi);
+        double s = m[i] * kern(kernel, 0.0, hi);
         double dv = 0.0, dvm = 0.0;
         for (int64_t k = off[i]; k < off[i + 1]; ++k) {
             int64_t j = idx[k];
@@ -578,10 +673,10 @@ void or_density(int64_t n, const double *x, const double *y, const double *z,
             double r2 = pair_r2(&g, i, j, &dx, &dy, &dz);
             if (!(r2 < r2max)) continue;
             double r = sqrt(r2);
-            s += m[j] * or_kernel_w(r, hi);
+            s += m[j] * kern(kernel, r, hi);
             if (r > 0.0) {
                 /* grad_i W = dW/dr (x_i - x_j)/r, and x_i - x_j = -(dx,dy,dz) */
-                double gw = or_kernel_dwdr(r, hi) / r;
+                double gw = kern_dr(kernel, r, hi) / r;
                 double vdot = (vx[j] - vx[i]) * (-dx) + (vy[j] - vy[i]) * (-dy) + (vz[j] - vz[i]) * (-dz);
                 dv += m[j] * vdot * gw;
                 /* condition of the dot product: sum of |component products| */
@@ -617,6 +712,7 @@ void or_eos(int64_t n, const double *rho, const double *u, double gamma, double 
 /* ------------------------------------------------------------------------ */
 typedef struct {
     double gamma, alpha, beta, eta2, cfl;
+    int kernel;
 } or_phys;
 
 /* the pair term of particle i from neighbour j: writes the acceleration
@@ -636,8 +732,8 @@ static void pair_force(const or_geom *g, int64_t i, int64_t j, const double *vx,
     double xij = -dx, yij = -dy, zij = -dz;
     double vxij = vx[i] - vx[j], vyij = vy[i] - vy[j], vzij = vz[i] - vz[j];
     double w = vxij * xij + vyij * yij + vzij * zij;
-    double gwi = or_kernel_dwdr(r, h[i]) / r;
-    double gwj = or_kernel_dwdr(r, h[j]) / r;
+    double gwi = kern_dr(ph->kernel, r, h[i]) / r;
+    double gwj = kern_dr(ph->kernel, r, h[j]) / r;
     double gbar = 0.5 * (gwi + gwj);
     double Pi = 0.0;
     if (w < 0.0) {
@@ -667,11 +763,11 @@ void or_forces(int64_t n, const double *x, const double *y, const double *z,
                const int *periodic, const double *box_lo, const double *box_hi,
                const int64_t *off, const int32_t *idx, double alpha, double beta, double eta2,
                double cfl, double *ax, double *ay, double *az, double *du, double *dt_i,
-               double *amag, double *dumag)
+               double *amag, double *dumag, int kernel)
 {
     or_geom g;
     geom_init(&g, x, y, z, periodic, box_lo, box_hi);
-    or_phys ph = {0.0, alpha, beta, eta2, cfl};
+    or_phys ph = {0.0, alpha, beta, eta2, cfl, kernel};
 #pragma omp parallel for schedule(dynamic, 256)
     for (int64_t i = 0; i < n; ++i) {
         double sx = 0.0, sy = 0.0, sz = 0.0, se = 0.0, mumax = 0.0, mag = 0.0, emag = 0.0;
@@ -700,12 +796,13 @@ void or_pair_term(int64_t n, const double *x, const double *y, const double *z,
                   const double *vx, const double *vy, const double *vz, const double *m,
                   const double *h, const double *rho, const double *p, const double *c,
                   const int *periodic, const double *box_lo, const double *box_hi,
-                  int64_t i, int64_t j, double alpha, double beta, double eta2, double *out4)
+                  int64_t i, int64_t j, double alpha, double beta, double eta2, double *out4,
+                  int kernel)
 {
     (void)n;
     or_geom g;
     geom_init(&g, x, y, z, periodic, box_lo, box_hi);
-    or_phys ph = {0.0, alpha, beta, eta2, 0.0};
+    or_phys ph = {0.0, alpha, beta, eta2, 0.0, kernel};
     double fx, fy, fz, de, mua;
     pair_force(&g, i, j, vx, vy, vz, h, rho, p, c, &ph, &fx, &fy, &fz, &de, &mua, NULL);
     double mm = m[i] * m[j];

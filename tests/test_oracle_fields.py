@@ -43,6 +43,33 @@ def test_lattice_density_equals_lattice_sum(h_over_s):
     assert np.all(divv == 0.0)
 
 
+@pytest.mark.parametrize("kernel,wfun", [(O.KERNEL_WENDLAND, O.kernel_wendland),
+                                         (O.KERNEL_SINC5, O.kernel_sinc)])
+def test_lattice_density_other_kernels(kernel, wfun):
+    # the density sum with the kernel section's kernels: the lattice sum of
+    # that kernel, uniform, and near the continuum density 1
+    h_over_s = 1.6
+    ps = inputs.perfect_lattice(16, h_over_s)
+    off, idx = O.lists(ps.x, ps.y, ps.z, ps.h, ps.periodic, ps.box_lo, ps.box_hi)
+    rho, divv = O.density(ps.x, ps.y, ps.z, ps.vx, ps.vy, ps.vz, ps.m, ps.h, ps.periodic,
+                          ps.box_lo, ps.box_hi, off, idx, kernel=kernel)
+    assert rho.std() / rho.mean() < 1e-14
+    ref = _lattice_sum(h_over_s, lambda r: wfun(r, h_over_s))
+    assert rho.mean() == pytest.approx(ref, rel=1e-13)
+    assert abs(rho.mean() - 1.0) < 2e-2
+    assert np.all(divv == 0.0)
+
+
+def test_two_particle_density_wendland_closed_form():
+    # m = h = 1 at distance 1.5 h: rho = sigma_W (1 + (1 - 0.75)^4 (2 * 1.5 + 1))
+    x = np.array([0.0, 1.5]); z = np.zeros(2)
+    one = np.ones(2)
+    off, idx = O.lists(x, z, z, one, (0, 0, 0), (0, 0, 0), (0, 0, 0), method=0)
+    rho, _ = O.density(x, z, z, z, z, z, one, one, (0, 0, 0), (0, 0, 0), (0, 0, 0), off, idx,
+                       kernel=O.KERNEL_WENDLAND)
+    assert rho[0] == pytest.approx(21.0 / (16.0 * math.pi) * (1 + 0.25 ** 4 * 4.0), rel=1e-15)
+
+
 def test_two_particle_density_closed_form():
     # m = h = 1 at distance 1.5 h: rho = (1 + 0.25 * 0.5^3) / pi
     x = np.array([0.0, 1.5]); z = np.zeros(2)
@@ -115,21 +142,26 @@ def _forces(ps, off, idx, rho, P, c, **kw):
                     ps.box_lo, ps.box_hi, off, idx, **kw)
 
 
-def test_pair_term_bitwise_antisymmetric():
+KERNEL_IDS = [O.KERNEL_M4, O.KERNEL_WENDLAND, O.KERNEL_SINC5]
+
+
+@pytest.mark.parametrize("kernel", KERNEL_IDS)
+def test_pair_term_bitwise_antisymmetric(kernel):
     ps, off, idx, rho, P, c = _patch_state()
     args = (ps.x, ps.y, ps.z, ps.vx, ps.vy, ps.vz, ps.m, ps.h, rho, P, c, ps.periodic,
             ps.box_lo, ps.box_hi)
     rng = np.random.default_rng(0)
     for i in rng.integers(0, ps.n, 60):
         for j in idx[off[i]:off[i + 1]][:20]:
-            a = O.pair_term(*args, int(i), int(j))
-            b = O.pair_term(*args, int(j), int(i))
+            a = O.pair_term(*args, int(i), int(j), kernel=kernel)
+            b = O.pair_term(*args, int(j), int(i), kernel=kernel)
             assert np.array_equal(a[:3], -b[:3]) and a[3] == b[3]
 
 
-def test_momentum_angular_momentum_energy_conservation():
+@pytest.mark.parametrize("kernel", KERNEL_IDS)
+def test_momentum_angular_momentum_energy_conservation(kernel):
     ps, off, idx, rho, P, c = _patch_state(periodic=False)
-    ax, ay, az, du, dt_i, amag = _forces(ps, off, idx, rho, P, c)
+    ax, ay, az, du, dt_i, amag = _forces(ps, off, idx, rho, P, c, kernel=kernel)
     m = ps.m
     scale = np.sum(m * amag)
     assert abs(np.sum(m * ax)) < 1e-13 * scale
