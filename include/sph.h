@@ -45,7 +45,17 @@ extern "C" {
 #define SPH_ENONFINITE (-5)  /* non-finite field value (only with check_finite) */
 #define SPH_WNOCONV 1        /* warning: some smoothing lengths did not converge */
 
+/* Smoothing kernels of the density and force sums (support 2h, 0 <= v <= 2):
+ *   M4        cubic spline, 1/(pi h^3) {1 - 1.5v^2 + 0.75v^3; 0.25(2-v)^3}
+ *   WENDLAND  Wendland C2 of the paper's kernel section,
+ *             21/(16 pi h^3) (1 - v/2)^4 (2v + 1)
+ *   SINC5     the section's sinc family with exponent 5,
+ *             B_5/h^3 sinc^5(pi v/2), sinc(x) = sin(x)/x, B_5 normalising
+ *             the kernel to one (computed by the library at sph_create)
+ * The neighbour search and h iteration do not depend on the kernel. */
 #define SPH_KERNEL_M4 0
+#define SPH_KERNEL_WENDLAND 1
+#define SPH_KERNEL_SINC5 2
 #define SPH_FP64 0
 #define SPH_MIXED 1
 #define SPH_H_PLAIN 0
@@ -74,7 +84,7 @@ typedef struct sph_params {
     int32_t extra_slots;    /* capacity of each complement row E_i (default 48) */
     int32_t walk_prefilter; /* SPH_PREFILTER_MATRIX (default) or SPH_PREFILTER_NONE */
     int32_t periodic[3];    /* 1 = periodic dimension (minimum image, wrap) */
-    int32_t kernel;         /* SPH_KERNEL_M4 */
+    int32_t kernel;         /* SPH_KERNEL_M4 (default), _WENDLAND or _SINC5 */
     double box_lo[3];       /* box of the periodic dimensions */
     double box_hi[3];
     int32_t n_target;       /* target neighbour count (100) */

@@ -122,7 +122,8 @@ static const char *validate(const sph_params *p)
     if (p->n_max < 0 || p->n_max > (int64_t)INT32_MAX - 1) return "n_max out of range";
     if (p->list_stride < 1 || p->list_stride > 4096) return "list_stride out of range";
     if (p->extra_slots < 1 || p->extra_slots > 4096) return "extra_slots out of range";
-    if (p->kernel != SPH_KERNEL_M4) return "unsupported kernel";
+    if (p->kernel != SPH_KERNEL_M4 && p->kernel != SPH_KERNEL_WENDLAND && p->kernel != SPH_KERNEL_SINC5)
+        return "kernel must be SPH_KERNEL_M4, SPH_KERNEL_WENDLAND or SPH_KERNEL_SINC5";
     if (p->n_target < 1 || p->n_target > 1000) return "n_target out of range";
     if (p->n_tol < 0 || p->n_tol >= p->n_target) return "n_tol out of range";
     if (p->h_max_iter < 1 || p->h_max_iter > 256) return "h_max_iter out of range";
@@ -204,6 +205,31 @@ size_t sph_layout(const sph_params *p, void *base, Workspace *w)
     return off + 256;
 }
 
+// B_5 = 1 / (4 pi int_0^2 sinc^5(pi v / 2) v^2 dv): the normalisation of the
+// sinc kernel (its volume integral is one), by 5-point Gauss-Legendre on 64
+// equal subintervals
+static double sinc5_norm()
+{
+    const double a = 2.0 * sqrt(10.0 / 7.0);
+    const double xg[5] = {-sqrt(5.0 + a) / 3.0, -sqrt(5.0 - a) / 3.0, 0.0, sqrt(5.0 - a) / 3.0,
+                          sqrt(5.0 + a) / 3.0};
+    const double wo = (322.0 - 13.0 * sqrt(70.0)) / 900.0, wi = (322.0 + 13.0 * sqrt(70.0)) / 900.0;
+    const double wg[5] = {wo, wi, 128.0 / 225.0, wi, wo};
+    const int m = 64;
+    const double hsub = 2.0 / m;
+    double acc = 0.0;
+    for (int k = 0; k < m; ++k) {
+        const double mid = (k + 0.5) * hsub;
+        for (int g = 0; g < 5; ++g) {
+            const double v = mid + 0.5 * hsub * xg[g];
+            const double xx = 0.5 * M_PI * v;
+            const double sc = xx == 0.0 ? 1.0 : sin(xx) / xx;
+            acc += wg[g] * 0.5 * hsub * (sc * sc * sc * sc * sc) * v * v;
+        }
+    }
+    return 1.0 / (4.0 * M_PI * acc);
+}
+
 extern "C" int sph_create(const sph_params *p, sph_ctx **out)
 {
     if (!p || !out) return SPH_EINVAL;
@@ -217,6 +243,7 @@ extern "C" int sph_create(const sph_params *p, sph_ctx **out)
     if (!c) return SPH_ENOMEM;
     memset(c, 0, sizeof(*c));
     c->p = *p;
+    c->knorm = sinc5_norm();
     *out = c;
     return SPH_OK;
 }

@@ -83,27 +83,63 @@ __device__ __forceinline__ float split_diff(uint32_t gi, uint32_t gj, float di, 
     return (float)dg * G.w[D] + (dj - di);
 }
 
-// M4 kernel and derivative in FP32
-__device__ __forceinline__ float kern_w_f(float r, float inv_h)
+// kernel and derivative in FP32 (SPH_KERNEL_*; knorm = B_5 of the sinc kernel)
+__device__ __forceinline__ float sinc_f(float x, float &deriv)
 {
-    float q = r * inv_h;
-    float norm = (float)(1.0 / SPH_PI) * inv_h * inv_h * inv_h;
-    float w;
-    if (q < 1.0f) w = 1.0f - 1.5f * q * q + 0.75f * q * q * q;
-    else if (q < 2.0f) { float t = 2.0f - q; w = 0.25f * t * t * t; }
-    else w = 0.0f;
-    return norm * w;
+    // sin(x)/x and its derivative for 0 <= x <= pi: series below 1/2
+    if (x < 0.5f) {
+        const float x2 = x * x;
+        deriv = x * (-1.0f / 3.0f + x2 * (1.0f / 30.0f + x2 * (-1.0f / 840.0f + x2 * (1.0f / 45360.0f))));
+        return 1.0f + x2 * (-1.0f / 6.0f + x2 * (1.0f / 120.0f + x2 * (-1.0f / 5040.0f + x2 * (1.0f / 362880.0f))));
+    }
+    float sx, cx;
+    sincosf(x, &sx, &cx);
+    deriv = (x * cx - sx) / (x * x);
+    return sx / x;
 }
-__device__ __forceinline__ float kern_dwdr_f(float r, float inv_h)
+template <int KER>
+__device__ __forceinline__ float kern_w_f(float r, float inv_h, float knorm)
 {
-    float q = r * inv_h;
-    float ih2 = inv_h * inv_h;
-    float norm = (float)(1.0 / SPH_PI) * ih2 * ih2;
-    float w;
-    if (q < 1.0f) w = q * (-3.0f + 2.25f * q);
-    else if (q < 2.0f) { float t = 2.0f - q; w = -0.75f * t * t; }
-    else w = 0.0f;
-    return norm * w;
+    const float q = r * inv_h;
+    const float ih3 = inv_h * inv_h * inv_h;
+    if constexpr (KER == SPH_KERNEL_WENDLAND) {
+        if (!(q < 2.0f)) return 0.0f;
+        const float t = 1.0f - 0.5f * q, t2 = t * t;
+        return (float)(21.0 / (16.0 * SPH_PI)) * ih3 * (t2 * t2) * (2.0f * q + 1.0f);
+    } else if constexpr (KER == SPH_KERNEL_SINC5) {
+        if (!(q < 2.0f)) return 0.0f;
+        float d;
+        const float s = sinc_f((float)(0.5 * SPH_PI) * q, d), s2 = s * s;
+        return knorm * ih3 * (s2 * s2 * s);
+    } else {
+        float w;
+        if (q < 1.0f) w = 1.0f - 1.5f * q * q + 0.75f * q * q * q;
+        else if (q < 2.0f) { float t = 2.0f - q; w = 0.25f * t * t * t; }
+        else w = 0.0f;
+        return (float)(1.0 / SPH_PI) * ih3 * w;
+    }
+}
+template <int KER>
+__device__ __forceinline__ float kern_dwdr_f(float r, float inv_h, float knorm)
+{
+    const float q = r * inv_h;
+    const float ih2 = inv_h * inv_h;
+    if constexpr (KER == SPH_KERNEL_WENDLAND) {
+        if (!(q < 2.0f)) return 0.0f;
+        const float t = 1.0f - 0.5f * q;
+        return (float)(21.0 / (16.0 * SPH_PI)) * (ih2 * ih2) * (-5.0f * q) * (t * t * t);
+    } else if constexpr (KER == SPH_KERNEL_SINC5) {
+        if (!(q < 2.0f)) return 0.0f;
+        float d;
+        const float s = sinc_f((float)(0.5 * SPH_PI) * q, d), s2 = s * s;
+        return knorm * (ih2 * ih2) * (5.0f * (s2 * s2) * d * (float)(0.5 * SPH_PI));
+    } else {
+        float w;
+        if (q < 1.0f) w = q * (-3.0f + 2.25f * q);
+        else if (q < 2.0f) { float t = 2.0f - q; w = -0.75f * t * t; }
+        else w = 0.0f;
+        return (float)(1.0 / SPH_PI) * (ih2 * ih2) * w;
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -146,10 +182,10 @@ __device__ __forceinline__ MixGeo mix_geo(const double *__restrict__ bbox, const
     return G;
 }
 
-template <int PM, bool EXTRA>
+template <int PM, bool EXTRA, int KER>
 __global__ __launch_bounds__(SPH_BLOCK) SPH_PAIR_WAVES_D void k_density_mixed(
     int64_t n, MixQ Q, const int32_t *__restrict__ nc, const int32_t *__restrict__ idx, int K,
-    const double *__restrict__ bbox, Geo g, const double *__restrict__ x,
+    const double *__restrict__ bbox, Geo g, float knorm, const double *__restrict__ x,
     const double *__restrict__ y, const double *__restrict__ z, const double *__restrict__ h,
     double *__restrict__ rho, double *__restrict__ divv, int32_t *__restrict__ ecnt,
     int32_t *__restrict__ eidx, int slots, int64_t *__restrict__ status)
@@ -222,9 +258,9 @@ __global__ __launch_bounds__(SPH_BLOCK) SPH_PAIR_WAVES_D void k_density_mixed(
                     }
                     float r = sqrtf(r2);
                     const float mj = bj.w;
-                    neu_add(s, mj * kern_w_f(r, inv_h));
+                    neu_add(s, mj * kern_w_f<KER>(r, inv_h, knorm));
                     if (r > 0.0f) {
-                        float gw = kern_dwdr_f(r, inv_h) / r;
+                        float gw = kern_dwdr_f<KER>(r, inv_h, knorm) / r;
                         float vdot = (bj.x - bi.x) * (-dx) + (bj.y - bi.y) * (-dy) +
                                      (bj.z - bi.z) * (-dz);
                         neu_add(dv, mj * vdot * gw);
@@ -235,7 +271,7 @@ __global__ __launch_bounds__(SPH_BLOCK) SPH_PAIR_WAVES_D void k_density_mixed(
         s = mgroup_neu(s);
         dv = mgroup_neu(dv);
         if (i < n && lane == 0) {
-            NeuF tot = {bi.w * kern_w_f(0.0f, inv_h), 0.0f};
+            NeuF tot = {bi.w * kern_w_f<KER>(0.0f, inv_h, knorm), 0.0f};
             neu_add(tot, s.s);
             tot.c += s.c;
             const double sd = neu_val(tot);
@@ -286,10 +322,10 @@ struct QuadF {
     float4 a, b, c;
 };
 
-template <int PM>
+template <int PM, int KER>
 __device__ __forceinline__ void force_pair_f(const QuadF &ri, float inv_hi, uint32_t gi,
-                                             const QuadF &rj, const MixGeo &G, float alpha,
-                                             float beta, float eta2, ForceAccF &A)
+                                             const QuadF &rj, const MixGeo &G, float knorm,
+                                             float alpha, float beta, float eta2, ForceAccF &A)
 {
     const uint32_t gj = cell_of(rj.a);
     float dx = split_diff<PM, 0>(gi, gj, ri.a.x, rj.a.x, G);
@@ -302,8 +338,8 @@ __device__ __forceinline__ void force_pair_f(const QuadF &ri, float inv_hi, uint
     float xij = -dx, yij = -dy, zij = -dz;
     float vxij = ri.b.x - rj.b.x, vyij = ri.b.y - rj.b.y, vzij = ri.b.z - rj.b.z;
     float w = vxij * xij + vyij * yij + vzij * zij;
-    float gwi = kern_dwdr_f(r, inv_hi) * inv_r;
-    float gwj = kern_dwdr_f(r, __builtin_amdgcn_rcpf(rj.c.x)) * inv_r;
+    float gwi = kern_dwdr_f<KER>(r, inv_hi, knorm) * inv_r;
+    float gwj = kern_dwdr_f<KER>(r, __builtin_amdgcn_rcpf(rj.c.x), knorm) * inv_r;
     float gbar = 0.5f * (gwi + gwj);
     float Pi = 0.0f;
     if (w < 0.0f) {
@@ -325,11 +361,12 @@ __device__ __forceinline__ void force_pair_f(const QuadF &ri, float inv_hi, uint
 
 // S_i = L_i (row order) then E_i (ascending), SPH_MGROUP lanes per particle;
 // ELDS: E rows ranked in LDS here (capacity <= SPH_ELDS), else sorted already
-template <int PM, bool ELDS>
+template <int PM, bool ELDS, int KER>
 __global__ __launch_bounds__(SPH_BLOCK) SPH_PAIR_WAVES_F void k_forces_mixed(
     int64_t n, MixQ Q, const int32_t *__restrict__ nc, const int32_t *__restrict__ idx, int K,
     const int32_t *__restrict__ ecnt, const int32_t *__restrict__ eidx, int slots,
-    const double *__restrict__ bbox, Geo g, float alpha, float beta, float eta2, double alpha_d,
+    const double *__restrict__ bbox, Geo g, float knorm, float alpha, float beta, float eta2,
+    double alpha_d,
     double beta_d, double cfl, const double *__restrict__ h, const double *__restrict__ c,
     double *__restrict__ ax, double *__restrict__ ay, double *__restrict__ az,
     double *__restrict__ du, double *__restrict__ dt_part)
@@ -372,7 +409,7 @@ __global__ __launch_bounds__(SPH_BLOCK) SPH_PAIR_WAVES_F void k_forces_mixed(
 #pragma unroll
                 for (int q = 0; q < SPH_MFBATCH; ++q) {
                     if (k0 + q * SPH_MGROUP >= tot) break;
-                    force_pair_f<PM>(ri, inv_hi, gi, rb[q], G, alpha, beta, eta2, A);
+                    force_pair_f<PM, KER>(ri, inv_hi, gi, rb[q], G, knorm, alpha, beta, eta2, A);
                 }
             }
         }
@@ -435,21 +472,18 @@ hipError_t launch_density_mixed(sph_ctx *c, sph_particles *s, const sph_nlist *n
     Geo g = make_geo(c->p);
     unsigned nb = (unsigned)ceil_div(n, SPH_BLOCK);
     const MixQ Q = ctx_quads(c);
+#define SPH_DENSITY_ARGS                                                                      \
+    dim3(nb), dim3(SPH_BLOCK), 0, c->stream, n, Q, s->nc[cur], nl->idx, c->p.list_stride,      \
+        c->w.bbox, g, (float)c->knorm, s->x[cur], s->y[cur], s->z[cur], s->h[cur], s->rho[cur], \
+        s->divv[cur], nl->ecnt, nl->eidx, c->p.extra_slots, c->w.status
     if (build_extra) {
-        SPH_DISPATCH_PM(periodic_mask(g),
-            hipLaunchKernelGGL((k_density_mixed<PM, true>), dim3(nb), dim3(SPH_BLOCK), 0,
-                               c->stream, n, Q, s->nc[cur], nl->idx,
-                               c->p.list_stride, c->w.bbox, g, s->x[cur], s->y[cur], s->z[cur], s->h[cur],
-                               s->rho[cur], s->divv[cur], nl->ecnt, nl->eidx, c->p.extra_slots,
-                               c->w.status))
+        SPH_DISPATCH_KER(c->p.kernel, SPH_DISPATCH_PM(periodic_mask(g),
+            hipLaunchKernelGGL((k_density_mixed<PM, true, KER>), SPH_DENSITY_ARGS)))
     } else {
-        SPH_DISPATCH_PM(periodic_mask(g),
-            hipLaunchKernelGGL((k_density_mixed<PM, false>), dim3(nb), dim3(SPH_BLOCK), 0,
-                               c->stream, n, Q, s->nc[cur], nl->idx,
-                               c->p.list_stride, c->w.bbox, g, s->x[cur], s->y[cur], s->z[cur], s->h[cur],
-                               s->rho[cur], s->divv[cur], nl->ecnt, nl->eidx, c->p.extra_slots,
-                               c->w.status))
+        SPH_DISPATCH_KER(c->p.kernel, SPH_DISPATCH_PM(periodic_mask(g),
+            hipLaunchKernelGGL((k_density_mixed<PM, false, KER>), SPH_DENSITY_ARGS)))
     }
+#undef SPH_DENSITY_ARGS
     return hipGetLastError();
 }
 
@@ -472,17 +506,17 @@ hipError_t launch_forces_mixed(sph_ctx *c, sph_particles *s, const sph_nlist *nl
     Geo g = make_geo(p);
 #define SPH_FORCE_ARGS                                                                        \
     dim3((unsigned)nb), dim3(SPH_BLOCK), 0, c->stream, n, ctx_quads(c), s->nc[cur], nl->idx,   \
-        p.list_stride, nl->ecnt, nl->eidx, p.extra_slots, c->w.bbox, g, (float)p.av_alpha,     \
-        (float)p.av_beta, (float)p.av_eta2, p.av_alpha, p.av_beta, p.cfl, s->h[cur], s->c,     \
-        s->ax[cur], s->ay[cur], s->az[cur], s->du[cur], c->w.red_part
+        p.list_stride, nl->ecnt, nl->eidx, p.extra_slots, c->w.bbox, g, (float)c->knorm,       \
+        (float)p.av_alpha, (float)p.av_beta, (float)p.av_eta2, p.av_alpha, p.av_beta, p.cfl,   \
+        s->h[cur], s->c, s->ax[cur], s->ay[cur], s->az[cur], s->du[cur], c->w.red_part
     if (p.extra_slots <= SPH_ELDS) {
-        SPH_DISPATCH_PM(periodic_mask(g),
-                        hipLaunchKernelGGL((k_forces_mixed<PM, true>), SPH_FORCE_ARGS))
+        SPH_DISPATCH_KER(p.kernel, SPH_DISPATCH_PM(periodic_mask(g),
+            hipLaunchKernelGGL((k_forces_mixed<PM, true, KER>), SPH_FORCE_ARGS)))
     } else {
         hipError_t e = launch_sort_extra(c, nl, n);
         if (e != hipSuccess) return e;
-        SPH_DISPATCH_PM(periodic_mask(g),
-                        hipLaunchKernelGGL((k_forces_mixed<PM, false>), SPH_FORCE_ARGS))
+        SPH_DISPATCH_KER(p.kernel, SPH_DISPATCH_PM(periodic_mask(g),
+            hipLaunchKernelGGL((k_forces_mixed<PM, false, KER>), SPH_FORCE_ARGS)))
     }
 #undef SPH_FORCE_ARGS
     return hipGetLastError();

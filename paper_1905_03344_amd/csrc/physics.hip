@@ -59,9 +59,10 @@ __global__ __launch_bounds__(SPH_BLOCK) void k_pack64(
     P.vzm[i] = make_double2(vz[i], m[i]);
 }
 
-template <int PM, bool EXTRA>
+template <int PM, bool EXTRA, int KER>
 __global__ __launch_bounds__(SPH_BLOCK) SPH_PAIR_WAVES_D void k_density(
     int64_t n, Pk64 P, const int32_t *__restrict__ nc, const int32_t *__restrict__ idx, int K, Geo g,
+    double knorm,
     double *__restrict__ rho, double *__restrict__ divv, int32_t *__restrict__ ecnt,
     int32_t *__restrict__ eidx, int slots, int64_t *__restrict__ status)
 {
@@ -115,9 +116,9 @@ __global__ __launch_bounds__(SPH_BLOCK) SPH_PAIR_WAVES_D void k_density(
                     }
                     double rr = sqrt(r2);
                     double mj = mb[q];
-                    s += mj * kern_w(rr, inv_h);
+                    s += mj * kern_w<KER>(rr, inv_h, knorm);
                     if (rr > 0.0) {
-                        double gw = kern_dwdr(rr, inv_h) / rr;
+                        double gw = kern_dwdr<KER>(rr, inv_h, knorm) / rr;
                         double vdot = (ub[q] - vxi) * (-dx) + (vb[q] - vyi) * (-dy) + (wb[q] - vzi) * (-dz);
                         dv += mj * vdot * gw;
                     }
@@ -127,7 +128,7 @@ __global__ __launch_bounds__(SPH_BLOCK) SPH_PAIR_WAVES_D void k_density(
         s = group_sum(s);
         dv = group_sum(dv);
         if (i < n && lane == 0) {
-            const double rh = mi * kern_w(0.0, inv_h) + s;
+            const double rh = mi * kern_w<KER>(0.0, inv_h, knorm) + s;
             rho[i] = rh;
             divv[i] = dv / rh;
         }
@@ -229,17 +230,17 @@ hipError_t launch_density(sph_ctx *c, sph_particles *s, const sph_nlist *nl, boo
     const Pk64 P = ctx_pk64(c);
     hipLaunchKernelGGL(k_pack64, dim3(nb), dim3(SPH_BLOCK), 0, c->stream, n, s->x[cur], s->y[cur],
                        s->z[cur], s->h[cur], s->pvx, s->pvy, s->pvz, s->m[cur], P);
+#define SPH_DENSITY_ARGS                                                                        \
+    dim3(nb), dim3(SPH_BLOCK), 0, c->stream, n, P, s->nc[cur], nl->idx, c->p.list_stride, g,     \
+        c->knorm, s->rho[cur], s->divv[cur], nl->ecnt, nl->eidx, c->p.extra_slots, c->w.status
     if (build_extra) {
-        SPH_DISPATCH_PM(periodic_mask(g),
-            hipLaunchKernelGGL((k_density<PM, true>), dim3(nb), dim3(SPH_BLOCK), 0, c->stream, n,
-                               P, s->nc[cur], nl->idx, c->p.list_stride, g, s->rho[cur],
-                               s->divv[cur], nl->ecnt, nl->eidx, c->p.extra_slots, c->w.status))
+        SPH_DISPATCH_KER(c->p.kernel, SPH_DISPATCH_PM(periodic_mask(g),
+            hipLaunchKernelGGL((k_density<PM, true, KER>), SPH_DENSITY_ARGS)))
     } else {
-        SPH_DISPATCH_PM(periodic_mask(g),
-            hipLaunchKernelGGL((k_density<PM, false>), dim3(nb), dim3(SPH_BLOCK), 0, c->stream, n,
-                               P, s->nc[cur], nl->idx, c->p.list_stride, g, s->rho[cur],
-                               s->divv[cur], nl->ecnt, nl->eidx, c->p.extra_slots, c->w.status))
+        SPH_DISPATCH_KER(c->p.kernel, SPH_DISPATCH_PM(periodic_mask(g),
+            hipLaunchKernelGGL((k_density<PM, false, KER>), SPH_DENSITY_ARGS)))
     }
+#undef SPH_DENSITY_ARGS
     return hipGetLastError();
 }
 
@@ -296,12 +297,12 @@ __device__ __forceinline__ NbrF load_nbr(int j, const Pk64 &P, const double *__r
     return b;
 }
 
-template <int PM>
+template <int PM, int KER>
 __device__ __forceinline__ void force_pair(const NbrF &b, double xi, double yi, double zi,
                                            double vxi, double vyi, double vzi, double hi,
                                            double inv_hi, double rhoi, double ci, double pi_term,
-                                           const Geo &g, double alpha, double beta, double eta2,
-                                           ForceAcc &A)
+                                           const Geo &g, double knorm, double alpha, double beta,
+                                           double eta2, ForceAcc &A)
 {
     double dx = mimg<PM, 0>(xi, b.x, g);
     double dy = mimg<PM, 1>(yi, b.y, g);
@@ -314,8 +315,8 @@ __device__ __forceinline__ void force_pair(const NbrF &b, double xi, double yi, 
     double xij = -dx, yij = -dy, zij = -dz;
     double vxij = vxi - b.vx, vyij = vyi - b.vy, vzij = vzi - b.vz;
     double w = vxij * xij + vyij * yij + vzij * zij;
-    double gwi = kern_dwdr(r, inv_hi) * inv_r;
-    double gwj = kern_dwdr(r, 1.0 / hj) * inv_r;
+    double gwi = kern_dwdr<KER>(r, inv_hi, knorm) * inv_r;
+    double gwj = kern_dwdr<KER>(r, 1.0 / hj, knorm) * inv_r;
     double gbar = 0.5 * (gwi + gwj);
     double rhoj = b.rho;
     double Pi = 0.0;
@@ -339,11 +340,11 @@ __device__ __forceinline__ void force_pair(const NbrF &b, double xi, double yi, 
 
 // S_i = L_i (row order) then E_i (ascending) in groups of SPH_GROUP lanes;
 // ELDS: E rows ranked in LDS here (capacity <= SPH_ELDS), else sorted already
-template <int PM, bool ELDS>
+template <int PM, bool ELDS, int KER>
 __global__ __launch_bounds__(SPH_BLOCK) SPH_PAIR_WAVES_F void k_forces(
     int64_t n, Pk64 P, const double *__restrict__ c, const int32_t *__restrict__ nc, const int32_t *__restrict__ idx, int K,
     const int32_t *__restrict__ ecnt, const int32_t *__restrict__ eidx, int slots, Geo g,
-    double alpha, double beta, double eta2, double cfl, double *__restrict__ ax,
+    double knorm, double alpha, double beta, double eta2, double cfl, double *__restrict__ ax,
     double *__restrict__ ay, double *__restrict__ az, double *__restrict__ du,
     double *__restrict__ dt_part)
 {
@@ -387,8 +388,8 @@ __global__ __launch_bounds__(SPH_BLOCK) SPH_PAIR_WAVES_F void k_forces(
 #pragma unroll
                 for (int q = 0; q < SPH_FBATCH; ++q) {
                     if (k0 + q * SPH_GROUP >= tot) break;
-                    force_pair<PM>(nb[q], xi, yi, zi, vxi, vyi, vzi, hi, inv_hi, rhoi, ci,
-                                   pi_term, g, alpha, beta, eta2, A);
+                    force_pair<PM, KER>(nb[q], xi, yi, zi, vxi, vyi, vzi, hi, inv_hi, rhoi, ci,
+                                        pi_term, g, knorm, alpha, beta, eta2, A);
                 }
             }
         }
@@ -442,14 +443,16 @@ hipError_t launch_forces(sph_ctx *c, sph_particles *s, const sph_nlist *nl, doub
     Geo g = make_geo(p);
 #define SPH_FORCE_ARGS                                                                          \
     dim3((unsigned)nb), dim3(SPH_BLOCK), 0, c->stream, n, ctx_pk64(c), s->c, s->nc[cur],         \
-        nl->idx, p.list_stride, nl->ecnt, nl->eidx, p.extra_slots, g, p.av_alpha, p.av_beta,     \
-        p.av_eta2, p.cfl, s->ax[cur], s->ay[cur], s->az[cur], s->du[cur], part
+        nl->idx, p.list_stride, nl->ecnt, nl->eidx, p.extra_slots, g, c->knorm, p.av_alpha,     \
+        p.av_beta, p.av_eta2, p.cfl, s->ax[cur], s->ay[cur], s->az[cur], s->du[cur], part
     if (p.extra_slots <= SPH_ELDS) {
-        SPH_DISPATCH_PM(periodic_mask(g), hipLaunchKernelGGL((k_forces<PM, true>), SPH_FORCE_ARGS))
+        SPH_DISPATCH_KER(p.kernel, SPH_DISPATCH_PM(periodic_mask(g),
+            hipLaunchKernelGGL((k_forces<PM, true, KER>), SPH_FORCE_ARGS)))
     } else {
         hipError_t e = launch_sort_extra(c, nl, n);
         if (e != hipSuccess) return e;
-        SPH_DISPATCH_PM(periodic_mask(g), hipLaunchKernelGGL((k_forces<PM, false>), SPH_FORCE_ARGS))
+        SPH_DISPATCH_KER(p.kernel, SPH_DISPATCH_PM(periodic_mask(g),
+            hipLaunchKernelGGL((k_forces<PM, false, KER>), SPH_FORCE_ARGS)))
     }
 #undef SPH_FORCE_ARGS
     return hipGetLastError();

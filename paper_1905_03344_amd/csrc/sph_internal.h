@@ -116,6 +116,7 @@ struct sph_ctx {
     float *harvest_feat;   // step sink of (features, target) rows, or NULL
     float *harvest_target;
     int harvest_mode;      // SPH_TARGET_*
+    double knorm;          // B_5 of the sinc kernel (sph_create)
     char err[512];
 };
 
@@ -342,29 +343,98 @@ __device__ __forceinline__ uint32_t compact3(uint32_t v)
 
 #define SPH_PI 3.14159265358979323846
 
-// M4 cubic spline W(r, h) and dW/dr (fields; rounding order free)
-__device__ __forceinline__ double kern_w(double r, double inv_h)
+// sinc(x) = sin(x)/x and its derivative for 0 <= x <= pi: Horner series in
+// x^2 (terms to x^16, coefficients (-1)^k / (2k+1)!) below x = 1/2, the
+// closed forms above
+__device__ __forceinline__ double sinc_series(double x2)
 {
-    double q = r * inv_h;
-    double norm = (1.0 / SPH_PI) * inv_h * inv_h * inv_h;
-    double w;
-    if (q < 1.0) w = 1.0 - 1.5 * q * q + 0.75 * q * q * q;
-    else if (q < 2.0) { double t = 2.0 - q; w = 0.25 * t * t * t; }
-    else w = 0.0;
-    return norm * w;
+    double s = 1.0 / 355687428096000.0;
+    s = s * x2 - 1.0 / 1307674368000.0;
+    s = s * x2 + 1.0 / 6227020800.0;
+    s = s * x2 - 1.0 / 39916800.0;
+    s = s * x2 + 1.0 / 362880.0;
+    s = s * x2 - 1.0 / 5040.0;
+    s = s * x2 + 1.0 / 120.0;
+    s = s * x2 - 1.0 / 6.0;
+    return s * x2 + 1.0;
+}
+__device__ __forceinline__ double sinc_d(double x)
+{
+    return x < 0.5 ? sinc_series(x * x) : sin(x) / x;
+}
+__device__ __forceinline__ double sinc_deriv_d(double x)
+{
+    if (x < 0.5) {
+        // sum_k>=1 (-1)^k 2k x^(2k-1) / (2k+1)!
+        const double x2 = x * x;
+        double s = 16.0 / 355687428096000.0;
+        s = s * x2 - 14.0 / 1307674368000.0;
+        s = s * x2 + 12.0 / 6227020800.0;
+        s = s * x2 - 10.0 / 39916800.0;
+        s = s * x2 + 8.0 / 362880.0;
+        s = s * x2 - 6.0 / 5040.0;
+        s = s * x2 + 4.0 / 120.0;
+        s = s * x2 - 2.0 / 6.0;
+        return s * x;
+    }
+    double sx, cx;
+    sincos(x, &sx, &cx);
+    return (x * cx - sx) / (x * x);
 }
 
-__device__ __forceinline__ double kern_dwdr(double r, double inv_h)
+// Kernel W(r, h) and dW/dr from r and 1/h (fields; rounding order free);
+// knorm is B_5 of the sinc kernel (unused by the others)
+template <int KER>
+__device__ __forceinline__ double kern_w(double r, double inv_h, double knorm)
 {
-    double q = r * inv_h;
-    double ih2 = inv_h * inv_h;
-    double norm = (1.0 / SPH_PI) * ih2 * ih2;
-    double w;
-    if (q < 1.0) w = q * (-3.0 + 2.25 * q);
-    else if (q < 2.0) { double t = 2.0 - q; w = -0.75 * t * t; }
-    else w = 0.0;
-    return norm * w;
+    const double q = r * inv_h;
+    const double ih3 = inv_h * inv_h * inv_h;
+    if constexpr (KER == SPH_KERNEL_WENDLAND) {
+        if (!(q < 2.0)) return 0.0;
+        const double t = 1.0 - 0.5 * q, t2 = t * t;
+        return (21.0 / (16.0 * SPH_PI)) * ih3 * (t2 * t2) * (2.0 * q + 1.0);
+    } else if constexpr (KER == SPH_KERNEL_SINC5) {
+        if (!(q < 2.0)) return 0.0;
+        const double s = sinc_d(0.5 * SPH_PI * q), s2 = s * s;
+        return knorm * ih3 * (s2 * s2 * s);
+    } else {
+        double w;
+        if (q < 1.0) w = 1.0 - 1.5 * q * q + 0.75 * q * q * q;
+        else if (q < 2.0) { double t = 2.0 - q; w = 0.25 * t * t * t; }
+        else w = 0.0;
+        return (1.0 / SPH_PI) * ih3 * w;
+    }
 }
+
+template <int KER>
+__device__ __forceinline__ double kern_dwdr(double r, double inv_h, double knorm)
+{
+    const double q = r * inv_h;
+    const double ih2 = inv_h * inv_h;
+    if constexpr (KER == SPH_KERNEL_WENDLAND) {
+        if (!(q < 2.0)) return 0.0;
+        const double t = 1.0 - 0.5 * q;
+        return (21.0 / (16.0 * SPH_PI)) * (ih2 * ih2) * (-5.0 * q) * (t * t * t);
+    } else if constexpr (KER == SPH_KERNEL_SINC5) {
+        if (!(q < 2.0)) return 0.0;
+        const double x = 0.5 * SPH_PI * q;
+        const double s = sinc_d(x), s2 = s * s;
+        return knorm * (ih2 * ih2) * (5.0 * (s2 * s2) * sinc_deriv_d(x) * (0.5 * SPH_PI));
+    } else {
+        double w;
+        if (q < 1.0) w = q * (-3.0 + 2.25 * q);
+        else if (q < 2.0) { double t = 2.0 - q; w = -0.75 * t * t; }
+        else w = 0.0;
+        return (1.0 / SPH_PI) * (ih2 * ih2) * w;
+    }
+}
+
+#define SPH_DISPATCH_KER(k, LAUNCH)                                              \
+    switch (k) {                                                                 \
+    case SPH_KERNEL_WENDLAND: { constexpr int KER = SPH_KERNEL_WENDLAND; LAUNCH; } break; \
+    case SPH_KERNEL_SINC5: { constexpr int KER = SPH_KERNEL_SINC5; LAUNCH; } break;       \
+    default: { constexpr int KER = SPH_KERNEL_M4; LAUNCH; } break;                        \
+    }
 
 // wave and block reductions
 __device__ __forceinline__ int64_t wave_sum_i64(int64_t v)

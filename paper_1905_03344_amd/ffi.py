@@ -19,6 +19,8 @@ SPH_ENONFINITE = -5
 SPH_WNOCONV = 1
 
 SPH_KERNEL_M4 = 0
+SPH_KERNEL_WENDLAND = 1
+SPH_KERNEL_SINC5 = 2
 SPH_FP64 = 0
 SPH_MIXED = 1
 SPH_PREFILTER_NONE = 0

@@ -64,6 +64,21 @@ def test_mixed_evaluate_parity(case):
     assert stats.extra_total == st.off[-1] - st.loff[-1]
 
 
+@pytest.mark.parametrize("kernel", ["wendland", "sinc5"])
+def test_mixed_kernel_variants(kernel):
+    from test_gpu_parity import _kernel_id, compare_neighbors
+    kid = _kernel_id(kernel)
+    ic = CASES["clumpy_12k"]()
+    st = O.State(ic.copy(), O.Params(kernel=kid))
+    st.keep_gather = True
+    st.evaluate(method=1)
+    sim = _sim(ic, extra_per_particle=96, kernel=kid)
+    sim.evaluate()
+    sim.sync()
+    compare_neighbors(sim, st)
+    check_mixed_fields(sim, st)
+
+
 def test_mixed_step_parity():
     from test_gpu_parity import _upload_oracle_state, compare_cells, compare_neighbors
     ic = inputs.square_patch(20, inputs.CONFIG_SEEDS[1])
