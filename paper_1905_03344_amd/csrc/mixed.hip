@@ -86,16 +86,30 @@ __device__ __forceinline__ float split_diff(uint32_t gi, uint32_t gj, float di, 
 // kernel and derivative in FP32 (SPH_KERNEL_*; knorm = B_5 of the sinc kernel)
 __device__ __forceinline__ float sinc_f(float x, float &deriv)
 {
-    // sin(x)/x and its derivative for 0 <= x <= pi: series below 1/2
-    if (x < 0.5f) {
-        const float x2 = x * x;
-        deriv = x * (-1.0f / 3.0f + x2 * (1.0f / 30.0f + x2 * (-1.0f / 840.0f + x2 * (1.0f / 45360.0f))));
-        return 1.0f + x2 * (-1.0f / 6.0f + x2 * (1.0f / 120.0f + x2 * (-1.0f / 5040.0f + x2 * (1.0f / 362880.0f))));
-    }
-    float sx, cx;
-    sincosf(x, &sx, &cx);
-    deriv = (x * cx - sx) / (x * x);
-    return sx / x;
+    // sin(x)/x and its derivative on 0 <= x <= pi: series in x^2 to x^18
+    // (the next terms are below 2e-10 at x = pi)
+    const float x2 = x * x;
+    float d = -1.4797143443923793e-16f;
+    d = d * x2 + 4.498331606952833e-14f;
+    d = d * x2 + -1.0706029224547743e-11f;
+    d = d * x2 + 1.9270852604185937e-09f;
+    d = d * x2 + -2.505210838544172e-07f;
+    d = d * x2 + 2.2045855379188714e-05f;
+    d = d * x2 + -0.0011904761904761906f;
+    d = d * x2 + 0.03333333333333333f;
+    d = d * x2 + -0.3333333333333333f;
+    deriv = d * x;
+    float s = -8.22063524662433e-18f;
+    s = s * x2 + 2.8114572543455206e-15f;
+    s = s * x2 + -7.647163731819816e-13f;
+    s = s * x2 + 1.6059043836821613e-10f;
+    s = s * x2 + -2.505210838544172e-08f;
+    s = s * x2 + 2.7557319223985893e-06f;
+    s = s * x2 + -0.0001984126984126984f;
+    s = s * x2 + 0.008333333333333333f;
+    s = s * x2 + -0.16666666666666666f;
+    s = s * x2 + 1.0f;
+    return s;
 }
 template <int KER>
 __device__ __forceinline__ float kern_w_f(float r, float inv_h, float knorm)

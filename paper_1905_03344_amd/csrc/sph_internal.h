@@ -343,43 +343,47 @@ __device__ __forceinline__ uint32_t compact3(uint32_t v)
 
 #define SPH_PI 3.14159265358979323846
 
-// sinc(x) = sin(x)/x and its derivative for 0 <= x <= pi: Horner series in
-// x^2 (terms to x^16, coefficients (-1)^k / (2k+1)!) below x = 1/2, the
-// closed forms above
-__device__ __forceinline__ double sinc_series(double x2)
-{
-    double s = 1.0 / 355687428096000.0;
-    s = s * x2 - 1.0 / 1307674368000.0;
-    s = s * x2 + 1.0 / 6227020800.0;
-    s = s * x2 - 1.0 / 39916800.0;
-    s = s * x2 + 1.0 / 362880.0;
-    s = s * x2 - 1.0 / 5040.0;
-    s = s * x2 + 1.0 / 120.0;
-    s = s * x2 - 1.0 / 6.0;
-    return s * x2 + 1.0;
-}
+// sinc(x) = sin(x)/x and its derivative on 0 <= x <= pi as series in x^2,
+// sum_k (-1)^k x^2k / (2k+1)! and sum_k>=1 (-1)^k 2k x^(2k-1) / (2k+1)!,
+// terms to k = 13 and 14 (the next term is below 1e-17 at x = pi): no
+// division or trigonometric call in the pair loops
 __device__ __forceinline__ double sinc_d(double x)
 {
-    return x < 0.5 ? sinc_series(x * x) : sin(x) / x;
+    const double x2 = x * x;
+    double s = -9.183689863795546e-29;
+    s = s * x2 + 6.446950284384474e-26;
+    s = s * x2 + -3.868170170630684e-23;
+    s = s * x2 + 1.9572941063391263e-20;
+    s = s * x2 + -8.22063524662433e-18;
+    s = s * x2 + 2.8114572543455206e-15;
+    s = s * x2 + -7.647163731819816e-13;
+    s = s * x2 + 1.6059043836821613e-10;
+    s = s * x2 + -2.505210838544172e-08;
+    s = s * x2 + 2.7557319223985893e-06;
+    s = s * x2 + -0.0001984126984126984;
+    s = s * x2 + 0.008333333333333333;
+    s = s * x2 + -0.16666666666666666;
+    s = s * x2 + 1.0;
+    return s;
 }
 __device__ __forceinline__ double sinc_deriv_d(double x)
 {
-    if (x < 0.5) {
-        // sum_k>=1 (-1)^k 2k x^(2k-1) / (2k+1)!
-        const double x2 = x * x;
-        double s = 16.0 / 355687428096000.0;
-        s = s * x2 - 14.0 / 1307674368000.0;
-        s = s * x2 + 12.0 / 6227020800.0;
-        s = s * x2 - 10.0 / 39916800.0;
-        s = s * x2 + 8.0 / 362880.0;
-        s = s * x2 - 6.0 / 5040.0;
-        s = s * x2 + 4.0 / 120.0;
-        s = s * x2 - 2.0 / 6.0;
-        return s * x;
-    }
-    double sx, cx;
-    sincos(x, &sx, &cx);
-    return (x * cx - sx) / (x * x);
+    const double x2 = x * x;
+    double d = 3.166789608205361e-30;
+    d = d * x2 + -2.387759364586842e-27;
+    d = d * x2 + 1.5472680682522736e-24;
+    d = d * x2 + -8.509974375387505e-22;
+    d = d * x2 + 3.9145882126782523e-19;
+    d = d * x2 + -1.4797143443923793e-16;
+    d = d * x2 + 4.498331606952833e-14;
+    d = d * x2 + -1.0706029224547743e-11;
+    d = d * x2 + 1.9270852604185937e-09;
+    d = d * x2 + -2.505210838544172e-07;
+    d = d * x2 + 2.2045855379188714e-05;
+    d = d * x2 + -0.0011904761904761906;
+    d = d * x2 + 0.03333333333333333;
+    d = d * x2 + -0.3333333333333333;
+    return d * x;
 }
 
 // Kernel W(r, h) and dW/dr from r and 1/h (fields; rounding order free);
