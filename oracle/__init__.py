@@ -114,6 +114,19 @@ def sinc_norm():
 # kernel ids of the density and force sums (same numbering as the library's
 # sph_params.kernel)
 KERNEL_M4, KERNEL_WENDLAND, KERNEL_SINC5 = 0, 1, 2
+# integrators: kick-drift-kick leapfrog; KDK positions and velocities with
+# the energy by second-order Adams-Bashforth
+INTEGRATOR_KDK, INTEGRATOR_AB2 = 0, 1
+
+
+def ab2_energy(u, du, du_prev, dt, dt_prev, hist):
+    """u after one Adams-Bashforth step (Euler without history)."""
+    u = _f64(u).copy()
+    du = _f64(du)
+    dup = _f64(du_prev if du_prev is not None else du)
+    lib().or_ab2_energy(ctypes.c_int64(len(u)), ctypes.c_double(dt), ctypes.c_double(dt_prev),
+                        ctypes.c_int(int(hist)), _p(u), _p(du), _p(dup))
+    return u
 
 
 def hk_table(n_target=100):
@@ -288,6 +301,7 @@ class Params:
     eta2: float = 0.01
     cfl: float = 0.3
     kernel: int = 0   # KERNEL_M4, KERNEL_WENDLAND or KERNEL_SINC5
+    integrator: int = 0   # INTEGRATOR_KDK or INTEGRATOR_AB2
 
 
 class State:
@@ -317,6 +331,7 @@ class State:
         # the order after the next sort); used to check a form that chose
         # its own in-band h against these same stages at that h
         self.h_given = None
+        self.dt_prev = None     # the previous step's dt (Adams-Bashforth energy)
 
     @property
     def n(self):
@@ -331,7 +346,7 @@ class State:
         lo, hi = bbox(f["x"], f["y"], f["z"], *self.geom())
         key = cell_keys(f["x"], f["y"], f["z"], lo, hi)
         perm = sort_perm(key)
-        for k in CARRIED:
+        for k in CARRIED + (("du_prev",) if "du_prev" in f else ()):
             f[k] = f[k][perm].copy()
         self.keys = key[perm]
         self.perm = perm
@@ -361,6 +376,8 @@ class State:
         """Cells, neighbours, density, EOS and forces at the stored state
         (the force evaluation at t = 0).  Returns the Courant dt."""
         f = self.f
+        f.pop("du_prev", None)   # an evaluation starts the integrator afresh
+        self.dt_prev = None
         self.build_cells()
         self._evaluate_sorted((f["vx"], f["vy"], f["vz"]), f["u"], method)
         return self.dt_next
@@ -371,6 +388,12 @@ class State:
         if dt is None or dt <= 0:
             dt = self.dt_next
         f = self.f
+        ab2 = self.p.integrator == INTEGRATOR_AB2
+        if ab2:
+            hist = "du_prev" in f
+            u_new = ab2_energy(f["u"], f["du"], f.get("du_prev"), dt,
+                               self.dt_prev if hist else 0.0, hist)
+            du_n = f["du"].copy()
         vx, vy, vz, u = f["vx"].copy(), f["vy"].copy(), f["vz"].copy(), f["u"].copy()
         x, y, z = f["x"].copy(), f["y"].copy(), f["z"].copy()
         n = self.n
@@ -378,6 +401,9 @@ class State:
                             _p(vy), _p(vz), _p(u), _p(f["ax"]), _p(f["ay"]), _p(f["az"]),
                             _p(f["du"]), _int3(*self.periodic), _dbl3(*self.box_lo),
                             _dbl3(*self.box_hi))
+        if ab2:
+            u = u_new   # the energy is final at the step's start: no half kicks
+            f["du_prev"] = du_n
         f["x"], f["y"], f["z"], f["vx"], f["vy"], f["vz"], f["u"] = x, y, z, vx, vy, vz, u
         # permutation happens inside evaluate; predicted values use the
         # permuted half-step state and old accelerations
@@ -386,9 +412,15 @@ class State:
         lib().or_predict(ctypes.c_int64(n), ctypes.c_double(dt), _p(f["vx"]), _p(f["vy"]),
                          _p(f["vz"]), _p(f["u"]), _p(f["ax"]), _p(f["ay"]), _p(f["az"]),
                          _p(f["du"]), _p(pvx), _p(pvy), _p(pvz), _p(pu))
+        if ab2:
+            pu = f["u"].copy()
         self._evaluate_sorted((pvx, pvy, pvz), pu, method)
+        u_keep = f["u"].copy()
         lib().or_kick(ctypes.c_int64(n), ctypes.c_double(dt), _p(f["vx"]), _p(f["vy"]),
                       _p(f["vz"]), _p(f["u"]), _p(f["ax"]), _p(f["ay"]), _p(f["az"]), _p(f["du"]))
+        if ab2:
+            f["u"] = u_keep
+            self.dt_prev = dt
         return dt
 
     def _evaluate_sorted(self, vel, u, method):

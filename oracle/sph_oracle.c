@@ -25,7 +25,9 @@
  *   - momentum equation (Rosswog 2009 kernel-averaged form, cited in the
  *     co-design section), Monaghan-Gingold artificial viscosity (Monaghan
  *     1983, same section), energy equation and a Courant time step;
- *   - kick-drift-kick leapfrog update and conservation sums (Neumaier).
+ *   - kick-drift-kick leapfrog update and conservation sums (Neumaier);
+ *     the paper's own energy update (second-order Adams-Bashforth) as the
+ *     alternative integrator, positions and velocities as in KDK.
  *   - the learned smoothing-length MLP (6-64-64-1, tanh, bf16 operands)
  *     forward, analytic backward and Adam, in FP64 on bf16-rounded operands.
  *
@@ -895,6 +897,24 @@ void or_kick(int64_t n, double dt, double *vx, double *vy, double *vz, double *u
         vz[i] = vz[i] + hdt * az[i];
         u[i] = u[i] + hdt * du[i];
     }
+}
+
+/* Energy by the second-order Adams-Bashforth method with a variable step
+ * (the paper names Adams-Bashforth for the energy update next to the
+ * Courant step; it prints no formula):
+ *   u^{n+1} = u^n + dt_n [(1 + r/2) du^n - (r/2) du^{n-1}],  r = dt_n / dt_{n-1},
+ * i.e. du extrapolated linearly to the middle of the step; with no previous
+ * step (hist = 0) the Euler step u^{n+1} = u^n + dt_n du^n.                 */
+void or_ab2_energy(int64_t n, double dt, double dt_prev, int hist, double *u, const double *du,
+                   const double *du_prev)
+{
+    if (!hist) {
+        for (int64_t i = 0; i < n; ++i) u[i] = u[i] + dt * du[i];
+        return;
+    }
+    double r = dt / dt_prev;
+    double c1 = 1.0 + 0.5 * r, c0 = 0.5 * r;
+    for (int64_t i = 0; i < n; ++i) u[i] = u[i] + dt * (c1 * du[i] - c0 * du_prev[i]);
 }
 
 int or_num_threads(void)
