@@ -77,10 +77,21 @@ typedef struct sph_ctx sph_ctx;
 #define SPH_PREFILTER_NONE 0
 #define SPH_PREFILTER_MATRIX 1
 
+/* Time integrators of sph_step.  KDK: kick-drift-kick leapfrog (positions,
+ * velocities and energy).  AB2: the same positions and velocities, the
+ * energy by second-order Adams-Bashforth with a variable step (the paper's
+ * energy update, the co-design section names it without a formula):
+ *   u^{n+1} = u^n + dt_n [(1 + r/2) du^n - (r/2) du^{n-1}],  r = dt_n/dt_{n-1},
+ * computed at the step's start and used as the energy of the force
+ * evaluation; the first step after sph_bind or sph_evaluate is the Euler
+ * step u + dt du.  du^{n-1} and dt_{n-1} live in the workspace. */
+#define SPH_INTEGRATOR_KDK 0
+#define SPH_INTEGRATOR_AB2 1
+
 typedef struct sph_params {
     int64_t n_max;          /* largest particle count the workspace is sized for */
     int32_t list_stride;    /* K: capacity of each gather set L_i (default 128) */
-    int32_t pad0;
+    int32_t integrator;     /* SPH_INTEGRATOR_KDK (default) or SPH_INTEGRATOR_AB2 */
     int32_t extra_slots;    /* capacity of each complement row E_i (default 48) */
     int32_t walk_prefilter; /* SPH_PREFILTER_MATRIX (default) or SPH_PREFILTER_NONE */
     int32_t periodic[3];    /* 1 = periodic dimension (minimum image, wrap) */

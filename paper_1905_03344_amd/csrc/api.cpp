@@ -113,6 +113,7 @@ extern "C" void sph_default_params(sph_params *p)
     p->max_level = 6;
     p->search_div = 2;
     p->walk_prefilter = SPH_PREFILTER_MATRIX;
+    p->integrator = SPH_INTEGRATOR_KDK;
 }
 
 extern "C" const char *sph_params_error(void) { return g_params_error; }
@@ -131,6 +132,8 @@ static const char *validate(const sph_params *p)
     if (p->h_mode != SPH_H_PLAIN && p->h_mode != SPH_H_LEARNED) return "unknown h_mode";
     if (p->max_level < 1 || p->max_level > 8) return "max_level must be in 1..8";
     if (p->search_div < 1 || p->search_div > 4) return "search_div must be in 1..4";
+    if (p->integrator != SPH_INTEGRATOR_KDK && p->integrator != SPH_INTEGRATOR_AB2)
+        return "integrator must be SPH_INTEGRATOR_KDK or SPH_INTEGRATOR_AB2";
     if (p->walk_prefilter != SPH_PREFILTER_NONE && p->walk_prefilter != SPH_PREFILTER_MATRIX)
         return "walk_prefilter must be SPH_PREFILTER_NONE or SPH_PREFILTER_MATRIX";
     if (!(p->gamma > 1.0)) return "gamma must exceed 1";
@@ -198,6 +201,10 @@ size_t sph_layout(const sph_params *p, void *base, Workspace *w)
     t.mlp_part = (float *)take((size_t)SPH_MLP_TRAIN_WAVES * SPH_MLP_ROW * sizeof(float));
     t.h_try = p->h_mode == SPH_H_LEARNED ? (double *)take(n * sizeof(double)) : nullptr;
     t.pk64 = p->precision == SPH_FP64 ? take(n * 80) : nullptr;
+    const bool ab2 = p->integrator == SPH_INTEGRATOR_AB2;
+    t.du_prev[0] = ab2 ? (double *)take(n * sizeof(double)) : nullptr;
+    t.du_prev[1] = ab2 ? (double *)take(n * sizeof(double)) : nullptr;
+    t.dt_prev = (double *)take(sizeof(double));
     t.nb_red = nb_red;
     t.nb_sort = nb_sort;
     t.scan_part_len = scan_part;
@@ -339,6 +346,8 @@ extern "C" int sph_bind(sph_ctx *c, void *workspace, size_t bytes, void *stream)
     if (r) return r;
     r = hip_check(c, hipMemsetAsync(c->w.dt_cur, 0, sizeof(double), c->stream), "clear dt");
     if (r) return r;
+    r = hip_check(c, hipMemsetAsync(c->w.dt_prev, 0, sizeof(double), c->stream), "clear dt_prev");
+    if (r) return r;
     // MLP state: zero parameters and moments, standardisation (0, 1)
     const double norm0[12] = {0, 0, 0, 0, 0, 0, 1, 1, 1, 1, 1, 1};
     r = hip_check(c, hipMemcpyAsync(c->w.mlp_norm, norm0, sizeof(norm0), hipMemcpyHostToDevice,
@@ -352,6 +361,7 @@ extern "C" int sph_bind(sph_ctx *c, void *workspace, size_t bytes, void *stream)
                   "clear MLP");
     if (r) return r;
     c->mlp_ready = 0;
+    c->ab2_hist = 0;
     c->mlp_t = 0;
     c->harvest_feat = nullptr;
     c->harvest_target = nullptr;
@@ -532,6 +542,7 @@ extern "C" int sph_evaluate(sph_ctx *c, sph_particles *s, sph_nlist *nl, double 
     r = sph_build_cells(c, s);
     if (r) return r;
     TRY(launch_copy_pred(c, s), "copy prediction");
+    c->ab2_hist = 0;   // the integrator starts afresh from this state
     return evaluate_sorted(c, s, nl, d_dt, nullptr);
 }
 
@@ -572,6 +583,7 @@ extern "C" int sph_step(sph_ctx *c, sph_particles *s, sph_nlist *nl, double dt, 
         StageScope scope(c, SPH_STAGE_INTEGRATE);
         TRY(launch_kick(c, s), "kick");
     }
+    c->ab2_hist = 1;
     return SPH_OK;
 }
 

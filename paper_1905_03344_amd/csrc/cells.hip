@@ -328,9 +328,11 @@ hipError_t launch_radix_sort(sph_ctx *c, int64_t n, uint32_t *key_out, int32_t *
 // ---------------------------------------------------------------------------
 // permutation of every carried field from buffer cur into 1 - cur
 // ---------------------------------------------------------------------------
+#define SPH_PERM_MAX 16
 struct PermArgs {
-    const double *src[15];
-    double *dst[15];
+    int nf;   // double fields in use (15, or 16 with the Adams-Bashforth du_prev)
+    const double *src[SPH_PERM_MAX];
+    double *dst[SPH_PERM_MAX];
     const int32_t *isrc[2];
     int32_t *idst[2];
 };
@@ -342,7 +344,8 @@ __global__ __launch_bounds__(SPH_BLOCK) void k_permute(PermArgs a, const int32_t
     if (k >= n) return;
     int64_t s = perm[k];
 #pragma unroll
-    for (int f = 0; f < 15; ++f) a.dst[f][k] = a.src[f][s];
+    for (int f = 0; f < SPH_PERM_MAX; ++f)
+        if (f < a.nf) a.dst[f][k] = a.src[f][s];
     a.idst[0][k] = a.isrc[0][s];
     a.idst[1][k] = a.isrc[1][s];
 }
@@ -357,6 +360,12 @@ hipError_t launch_permute(sph_ctx *c, sph_particles *s, const int32_t *perm)
     for (int f = 0; f < 15; ++f) {
         pa.src[f] = fields[f][a];
         pa.dst[f] = fields[f][b];
+    }
+    pa.nf = 15;
+    if (c->p.integrator == SPH_INTEGRATOR_AB2) {
+        pa.src[15] = c->w.du_prev[a];
+        pa.dst[15] = c->w.du_prev[b];
+        pa.nf = 16;
     }
     pa.isrc[0] = s->nc[a]; pa.idst[0] = s->nc[b];
     pa.isrc[1] = s->id[a]; pa.idst[1] = s->id[b];

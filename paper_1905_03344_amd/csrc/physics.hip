@@ -481,12 +481,16 @@ hipError_t launch_set_dt(sph_ctx *c, double dt, const double *d_dt)
     return hipGetLastError();
 }
 
+// ab2: 0 = KDK half kick of u; 1 = Euler u + dt du; 2 = Adams-Bashforth
+// u + dt [(1 + r/2) du - (r/2) du_prev], r = dt / dt_prev.  With ab2 > 0 the
+// kernel also moves du into du_prev (the previous step's du is read first).
 __global__ __launch_bounds__(SPH_BLOCK) void k_kick_drift(
     int64_t n, const double *__restrict__ dtp, double *__restrict__ x, double *__restrict__ y,
     double *__restrict__ z, double *__restrict__ vx, double *__restrict__ vy,
     double *__restrict__ vz, double *__restrict__ u, const double *__restrict__ ax,
     const double *__restrict__ ay, const double *__restrict__ az, const double *__restrict__ du,
-    Geo g, double lo0, double lo1, double lo2, double hi0, double hi1, double hi2)
+    Geo g, double lo0, double lo1, double lo2, double hi0, double hi1, double hi2, int ab2,
+    double *__restrict__ du_prev, const double *__restrict__ dt_prev)
 {
 #pragma clang fp contract(off)
     int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
@@ -508,7 +512,19 @@ __global__ __launch_bounds__(SPH_BLOCK) void k_kick_drift(
         }
         pos[d][i] = q;
     }
-    u[i] = u[i] + hdt * du[i];
+    if (ab2 == 0) {
+        u[i] = u[i] + hdt * du[i];
+    } else {
+        const double dun = du[i];
+        if (ab2 == 1) {
+            u[i] = u[i] + dt * dun;
+        } else {
+            const double r = dt / *dt_prev;
+            const double c1 = 1.0 + 0.5 * r, c0 = 0.5 * r;
+            u[i] = u[i] + dt * (c1 * dun - c0 * du_prev[i]);
+        }
+        du_prev[i] = dun;
+    }
 }
 
 hipError_t launch_kick_drift(sph_ctx *c, sph_particles *s)
@@ -521,12 +537,14 @@ hipError_t launch_kick_drift(sph_ctx *c, sph_particles *s)
                        c->stream, n, c->w.dt_cur, s->x[k], s->y[k], s->z[k], s->vx[k], s->vy[k],
                        s->vz[k], s->u[k], s->ax[k], s->ay[k], s->az[k], s->du[k], make_geo(p),
                        p.box_lo[0], p.box_lo[1], p.box_lo[2], p.box_hi[0], p.box_hi[1],
-                       p.box_hi[2]);
+                       p.box_hi[2], p.integrator == SPH_INTEGRATOR_AB2 ? (c->ab2_hist ? 2 : 1) : 0,
+                       c->w.du_prev[k], c->w.dt_prev);
     return hipGetLastError();
 }
 
 // pv = v + dt/2 a, pu = u + dt/2 du   (mode 0)
 // pv = v, pu = u                      (mode 1: evaluation at the stored state)
+// pv = v + dt/2 a, pu = u             (mode 2: Adams-Bashforth energy, final)
 __global__ __launch_bounds__(SPH_BLOCK) void k_predict(
     int64_t n, const double *__restrict__ dtp, int mode, const double *__restrict__ vx,
     const double *__restrict__ vy, const double *__restrict__ vz, const double *__restrict__ u,
@@ -545,7 +563,7 @@ __global__ __launch_bounds__(SPH_BLOCK) void k_predict(
     pvx[i] = vx[i] + hdt * ax[i];
     pvy[i] = vy[i] + hdt * ay[i];
     pvz[i] = vz[i] + hdt * az[i];
-    pu[i] = u[i] + hdt * du[i];
+    pu[i] = mode == 2 ? u[i] : u[i] + hdt * du[i];
 }
 
 static hipError_t predict(sph_ctx *c, sph_particles *s, int mode)
@@ -559,9 +577,14 @@ static hipError_t predict(sph_ctx *c, sph_particles *s, int mode)
     return hipGetLastError();
 }
 
-hipError_t launch_predict(sph_ctx *c, sph_particles *s) { return predict(c, s, 0); }
+hipError_t launch_predict(sph_ctx *c, sph_particles *s)
+{
+    return predict(c, s, c->p.integrator == SPH_INTEGRATOR_AB2 ? 2 : 0);
+}
 hipError_t launch_copy_pred(sph_ctx *c, sph_particles *s) { return predict(c, s, 1); }
 
+// second half kick; with ab2 the energy is already final, and the step's dt
+// is kept for the next Adams-Bashforth step
 __global__ __launch_bounds__(SPH_BLOCK) void k_kick(int64_t n, const double *__restrict__ dtp,
                                                     double *__restrict__ vx,
                                                     double *__restrict__ vy,
@@ -570,16 +593,18 @@ __global__ __launch_bounds__(SPH_BLOCK) void k_kick(int64_t n, const double *__r
                                                     const double *__restrict__ ax,
                                                     const double *__restrict__ ay,
                                                     const double *__restrict__ az,
-                                                    const double *__restrict__ du)
+                                                    const double *__restrict__ du, int ab2,
+                                                    double *__restrict__ dt_prev)
 {
 #pragma clang fp contract(off)
     int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (ab2 && i == 0) *dt_prev = *dtp;
     if (i >= n) return;
     double hdt = 0.5 * (*dtp);
     vx[i] = vx[i] + hdt * ax[i];
     vy[i] = vy[i] + hdt * ay[i];
     vz[i] = vz[i] + hdt * az[i];
-    u[i] = u[i] + hdt * du[i];
+    if (!ab2) u[i] = u[i] + hdt * du[i];
 }
 
 hipError_t launch_kick(sph_ctx *c, sph_particles *s)
@@ -589,7 +614,8 @@ hipError_t launch_kick(sph_ctx *c, sph_particles *s)
     int k = s->cur;
     hipLaunchKernelGGL(k_kick, dim3((unsigned)ceil_div(n, SPH_BLOCK)), dim3(SPH_BLOCK), 0,
                        c->stream, n, c->w.dt_cur, s->vx[k], s->vy[k], s->vz[k], s->u[k], s->ax[k],
-                       s->ay[k], s->az[k], s->du[k]);
+                       s->ay[k], s->az[k], s->du[k], c->p.integrator == SPH_INTEGRATOR_AB2 ? 1 : 0,
+                       c->w.dt_prev);
     return hipGetLastError();
 }
 

@@ -95,6 +95,8 @@ struct Workspace {
     float *mlp_part;       // per-wave gradient partial rows
     double *h_try;         // n_max predicted smoothing lengths (learned mode)
     void *pk64;            // n_max * 80 bytes: FP64 neighbour records (Pk64, FP64 form)
+    double *du_prev[2];    // AB2: du of the previous evaluation, ping-pong like the state
+    double *dt_prev;       // AB2: the previous step's dt
     int64_t nb_red;
     int64_t nb_sort;
     int64_t scan_part_len;
@@ -117,6 +119,7 @@ struct sph_ctx {
     float *harvest_target;
     int harvest_mode;      // SPH_TARGET_*
     double knorm;          // B_5 of the sinc kernel (sph_create)
+    int ab2_hist;          // AB2: a step since the last bind / evaluation
     char err[512];
 };
 

@@ -18,6 +18,8 @@ SPH_EHIP = -4
 SPH_ENONFINITE = -5
 SPH_WNOCONV = 1
 
+SPH_INTEGRATOR_KDK = 0
+SPH_INTEGRATOR_AB2 = 1
 SPH_KERNEL_M4 = 0
 SPH_KERNEL_WENDLAND = 1
 SPH_KERNEL_SINC5 = 2
@@ -37,7 +39,7 @@ _D = ctypes.c_double
 
 
 class sph_params(ctypes.Structure):
-    _fields_ = [("n_max", _I64), ("list_stride", _I32), ("pad0", _I32),
+    _fields_ = [("n_max", _I64), ("list_stride", _I32), ("integrator", _I32),
                 ("extra_slots", _I32), ("walk_prefilter", _I32), ("periodic", _I32 * 3), ("kernel", _I32),
                 ("box_lo", _D * 3), ("box_hi", _D * 3), ("n_target", _I32), ("n_tol", _I32),
                 ("h_max_iter", _I32), ("precision", _I32), ("gamma", _D), ("av_alpha", _D),

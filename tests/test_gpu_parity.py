@@ -155,6 +155,29 @@ def test_step_parity(dt):
         assert np.max(np.abs(sim.numpy(f) - st.f[f])) <= TOL * scale
 
 
+def test_ab2_step_parity():
+    """The Adams-Bashforth energy integrator: an Euler first step and an AB2
+    second step with a different dt, each from the oracle's state."""
+    from paper_1905_03344_amd import ffi
+    ic = inputs.square_patch(20, inputs.CONFIG_SEEDS[1])
+    st = O.State(ic.copy(), O.Params(integrator=O.INTEGRATOR_AB2))
+    st.keep_gather = True
+    st.evaluate(method=1)
+    sim = _sim(ic, integrator=ffi.SPH_INTEGRATOR_AB2)
+    sim.evaluate()
+    for k, dt in enumerate((1e-4, 1.5e-4)):
+        _upload_oracle_state(sim, st)
+        st.step(dt, method=1)
+        sim.step(dt)
+        sim.sync()
+        compare_cells(sim, st)
+        compare_neighbors(sim, st)
+        compare_fields(sim, st)
+        for f in ("vx", "vy", "vz", "u"):
+            scale = np.max(np.abs(st.f[f]))
+            assert np.max(np.abs(sim.numpy(f) - st.f[f])) <= TOL * scale, (k, f)
+
+
 def test_conservation_parity():
     ic = inputs.square_patch(21, 9)
     st = O.State(ic.copy())
