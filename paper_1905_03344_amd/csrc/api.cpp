@@ -189,8 +189,8 @@ size_t sph_layout(const sph_params *p, void *base, Workspace *w)
     t.hs_itk = (int32_t *)take(n * sizeof(int32_t));
     t.hs_bits = (int32_t *)take(n * sizeof(int32_t));
     t.shell_stride = ceil_div(n, 64) * 64;
-    t.shell_j = (int32_t *)take(48 * t.shell_stride * sizeof(int32_t));
-    t.shell_r2 = (double *)take(48 * t.shell_stride * sizeof(double));
+    t.shell_j = (int32_t *)take(SPH_SHELL_SLOTS * t.shell_stride * sizeof(int32_t));
+    t.shell_r2 = (double *)take(SPH_SHELL_SLOTS * t.shell_stride * sizeof(double));
     t.mixrec = p->precision == SPH_MIXED ? take(n * 64) : nullptr;
     t.mlp_master = (float *)take(SPH_MLP_ROW * sizeof(float));
     t.mlp_m = (float *)take(SPH_MLP_ROW * sizeof(float));

@@ -440,10 +440,16 @@ __device__ __forceinline__ double tile_r2(const WaveLds &L, int t, double xi, do
 }
 
 // Shell around a counted h: members with A <= r^2 < B, A = (2h(1-d))^2,
-// B = (2h(1+d))^2, d = 1/32.  For any h' with A <= (2h')^2 <= B the count
+// B = (2h(1+d))^2, d = 1/SPH_SHELL_D.  For any h' with A <= (2h')^2 <= B the count
 // is exactly N_inner + #{shell: r^2 < (2h')^2}: both sides use the same
 // rounded r^2 and the same rounded (2h')^2.
-#define SPH_SHELL_SLOTS 48
+// the shell is |r - 2h| < 2h / SPH_SHELL_D.  Its width only trades shell
+// records against new walks (results do not depend on it): measured 1/24
+// best on the jittered lattice (of 1/16 .. 1/64; the lattice's count moves
+// by whole shells), 1/48 .. 1/64 on the smooth clumpy mixture (2% there)
+#ifndef SPH_SHELL_D
+#define SPH_SHELL_D 24.0
+#endif
 struct Shell {
     int32_t *j;     // SPH_SHELL_SLOTS * sstride
     double *r2;     // SPH_SHELL_SLOTS * sstride
@@ -1129,7 +1135,7 @@ __attribute__((amdgpu_waves_per_eu(SPH_ROUND_WAVES, SPH_ROUND_WAVES))) void k_hs
         }
     }
     int64_t tested = 0, counts = 0, acc = 0, fallback = 0, nonconv = 0, overflow = 0;
-    const double ta = 2.0 * hc * (1.0 - 1.0 / 32.0), tb = 2.0 * hc * (1.0 + 1.0 / 32.0);
+    const double ta = 2.0 * hc * (1.0 - 1.0 / SPH_SHELL_D), tb = 2.0 * hc * (1.0 + 1.0 / SPH_SHELL_D);
     const double A2 = ta * ta, B2 = tb * tb;
     int nin = 0, nsh = 0;
     bool deferred = false;
@@ -1261,7 +1267,7 @@ __global__ __launch_bounds__(SPH_BLOCK) __attribute__((amdgpu_waves_per_eu(2, 2)
             bool dfr;
             if (shell_walk) {
                 shell_walk = false;
-                const double ta = 2.0 * hc * (1.0 - 1.0 / 32.0), tb = 2.0 * hc * (1.0 + 1.0 / 32.0);
+                const double ta = 2.0 * hc * (1.0 - 1.0 / SPH_SHELL_D), tb = 2.0 * hc * (1.0 + 1.0 / SPH_SHELL_D);
                 const double A2 = ta * ta, B2 = tb * tb;
                 int nin = wave_count<PM, false>(lds[w], lane == 0, i, xi, yi, zi, ki, hc, &dfr, A2,
                                                 B2, A.x, A.y, A.z, A.idx, A.stride, A.K, A.SH, &nsh,

@@ -19,6 +19,10 @@
 #else
 #define SPH_PAIR_WAVES_F
 #endif
+// shell records of the h iteration: slots per particle
+#ifndef SPH_SHELL_SLOTS
+#define SPH_SHELL_SLOTS 48
+#endif
 #ifndef SPH_SORT_ITEMS
 #define SPH_SORT_ITEMS 16                      // keys per thread per sort tile
 #endif
@@ -82,7 +86,7 @@ struct Workspace {
     int32_t *wl;           // n_max: the worklist
     double *hs_next, *hs_lo, *hs_hi, *hs_best_h, *hs_last_h;  // h iteration state, n_max each
     int32_t *hs_best_n, *hs_itk, *hs_bits;
-    int32_t *shell_j;      // 48 slots per particle, slot-major with shell_stride
+    int32_t *shell_j;      // SPH_SHELL_SLOTS per particle, slot-major with shell_stride
     double *shell_r2;
     int64_t shell_stride;
     void *mixrec;          // n_max records of 64 bytes (mixed form)
