@@ -62,6 +62,8 @@ def lib():
             getattr(L, nm).argtypes = [ctypes.c_double, ctypes.c_double]
         L.or_sinc_norm.restype = ctypes.c_double
         L.or_sinc_norm.argtypes = []
+        L.or_kernel_dwdh.restype = ctypes.c_double
+        L.or_kernel_dwdh.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_double]
         L.or_hsolve.restype = ctypes.c_int64
         L.or_lists.restype = ctypes.c_int64
         L.or_mlp_loss_grad.restype = ctypes.c_double
@@ -109,6 +111,11 @@ def kernel_sinc_dwdr(r, h):
 
 def sinc_norm():
     return lib().or_sinc_norm()
+
+
+def kernel_dwdh(r, h, kernel=0):
+    """dW/dh at fixed r (grad-h factor)"""
+    return lib().or_kernel_dwdh(int(kernel), float(r), float(h))
 
 
 # kernel ids of the density and force sums (same numbering as the library's
@@ -222,20 +229,23 @@ def lists(x, y, z, h, periodic, box_lo, box_hi, method=1, symmetric=True):
 # ---------------------------------------------------------------------------
 
 def density(x, y, z, vx, vy, vz, m, h, periodic, box_lo, box_hi, off, idx, with_mag=False,
-            kernel=0):
+            kernel=0, with_omega=False):
     """rho, divv (and, with_mag, (1/rho) sum |m_j (v_j - v_i).grad W|, the scale
-    of the divergence sum used for conditioning-aware comparisons)."""
+    of the divergence sum used for conditioning-aware comparisons; with_omega
+    also the grad-h factors Omega, appended last)."""
     arr = [_f64(a) for a in (x, y, z, vx, vy, vz, m, h)]
     n = len(arr[0])
     rho = np.zeros(n)
     divv = np.zeros(n)
     mag = np.zeros(n)
+    om = np.zeros(n)
     off = np.ascontiguousarray(off, dtype=np.int64)
     idx = np.ascontiguousarray(idx, dtype=np.int32)
     lib().or_density(ctypes.c_int64(n), *[_p(a) for a in arr], _int3(*periodic), _dbl3(*box_lo),
                      _dbl3(*box_hi), _p(off, _i64), _p(idx, _i32), _p(rho), _p(divv), _p(mag),
-                     ctypes.c_int(kernel))
-    return (rho, divv, mag) if with_mag else (rho, divv)
+                     ctypes.c_int(kernel), _p(om))
+    out = (rho, divv, mag) if with_mag else (rho, divv)
+    return out + (om,) if with_omega else out
 
 
 def eos(rho, u, gamma=5.0 / 3.0):
@@ -247,7 +257,7 @@ def eos(rho, u, gamma=5.0 / 3.0):
 
 
 def forces(x, y, z, vx, vy, vz, m, h, rho, p, c, periodic, box_lo, box_hi, off, idx,
-           alpha=1.0, beta=2.0, eta2=0.01, cfl=0.3, with_mag=False, kernel=0):
+           alpha=1.0, beta=2.0, eta2=0.01, cfl=0.3, with_mag=False, kernel=0, omega=None):
     """a, du, per-particle dt, sum_j m_j |f_ij| (and with_mag sum_j m_j |de_ij|)."""
     arr = [_f64(a) for a in (x, y, z, vx, vy, vz, m, h, rho, p, c)]
     n = len(arr[0])
@@ -257,7 +267,8 @@ def forces(x, y, z, vx, vy, vz, m, h, rho, p, c, periodic, box_lo, box_hi, off, 
     lib().or_forces(ctypes.c_int64(n), *[_p(a) for a in arr], _int3(*periodic), _dbl3(*box_lo),
                     _dbl3(*box_hi), _p(off, _i64), _p(idx, _i32), ctypes.c_double(alpha),
                     ctypes.c_double(beta), ctypes.c_double(eta2), ctypes.c_double(cfl),
-                    *[_p(a) for a in out], ctypes.c_int(kernel))
+                    *[_p(a) for a in out], ctypes.c_int(kernel),
+                    _p(_f64(omega)) if omega is not None else None)
     ax, ay, az, du, dt_i, amag, dumag = out
     if with_mag:
         return ax, ay, az, du, dt_i, amag, dumag
@@ -265,13 +276,14 @@ def forces(x, y, z, vx, vy, vz, m, h, rho, p, c, periodic, box_lo, box_hi, off, 
 
 
 def pair_term(x, y, z, vx, vy, vz, m, h, rho, p, c, periodic, box_lo, box_hi, i, j,
-              alpha=1.0, beta=2.0, eta2=0.01, kernel=0):
+              alpha=1.0, beta=2.0, eta2=0.01, kernel=0, omega=None):
     arr = [_f64(a) for a in (x, y, z, vx, vy, vz, m, h, rho, p, c)]
     out = np.zeros(4)
     lib().or_pair_term(ctypes.c_int64(len(arr[0])), *[_p(a) for a in arr], _int3(*periodic),
                        _dbl3(*box_lo), _dbl3(*box_hi), ctypes.c_int64(i), ctypes.c_int64(j),
                        ctypes.c_double(alpha), ctypes.c_double(beta), ctypes.c_double(eta2),
-                       _p(out), ctypes.c_int(kernel))
+                       _p(out), ctypes.c_int(kernel),
+                       _p(_f64(omega)) if omega is not None else None)
     return out
 
 
@@ -302,6 +314,7 @@ class Params:
     cfl: float = 0.3
     kernel: int = 0   # KERNEL_M4, KERNEL_WENDLAND or KERNEL_SINC5
     integrator: int = 0   # INTEGRATOR_KDK or INTEGRATOR_AB2
+    grad_h: bool = False  # grad-h correction terms in the momentum and energy equations
 
 
 class State:
@@ -427,8 +440,10 @@ class State:
         f = self.f
         self.pv = (vel, u)
         self.find_neighbors(method)
-        rho, divv, dvmag = density(f["x"], f["y"], f["z"], *vel, f["m"], f["h"], *self.geom(),
-                                   self.off, self.idx, with_mag=True, kernel=self.p.kernel)
+        rho, divv, dvmag, omega = density(f["x"], f["y"], f["z"], *vel, f["m"], f["h"],
+                                          *self.geom(), self.off, self.idx, with_mag=True,
+                                          kernel=self.p.kernel, with_omega=True)
+        self.omega = omega
         f["rho"], f["divv"] = rho, divv
         self.divv_mag = dvmag
         P, c = eos(rho, u, self.p.gamma)
@@ -436,7 +451,8 @@ class State:
         ax, ay, az, du, dt_i, amag, dumag = forces(f["x"], f["y"], f["z"], *vel, f["m"], f["h"],
                                                    rho, P, c, *self.geom(), self.off, self.idx,
                                                    self.p.alpha, self.p.beta, self.p.eta2,
-                                                   self.p.cfl, with_mag=True, kernel=self.p.kernel)
+                                                   self.p.cfl, with_mag=True, kernel=self.p.kernel,
+                                                   omega=omega if self.p.grad_h else None)
         f["ax"], f["ay"], f["az"], f["du"] = ax, ay, az, du
         self.amag, self.dumag, self.dt_i = amag, dumag, dt_i
         self.dt_next = float(dt_i.min()) if len(dt_i) else np.inf

@@ -183,6 +183,12 @@ static double kern_dr(int kernel, double r, double h)
     return or_kernel_dwdr(r, h);
 }
 
+/* dW/dh at fixed r: W = h^-3 w(r/h) gives dW/dh = -(3 W + r dW/dr) / h */
+double or_kernel_dwdh(int kernel, double r, double h)
+{
+    return -(3.0 * kern(kernel, r, h) + r * kern_dr(kernel, r, h)) / h;
+}
+
 /* ------------------------------------------------------------------------ */
 /* Geometry helpers                                                           */
 /* ------------------------------------------------------------------------ */
@@ -658,7 +664,7 @@ void or_density(int64_t n, const double *x, const double *y, const double *z,
                 const double *vx, const double *vy, const double *vz, const double *m,
                 const double *h, const int *periodic, const double *box_lo,
                 const double *box_hi, const int64_t *off, const int32_t *idx,
-                double *rho, double *divv, double *divv_mag, int kernel)
+                double *rho, double *divv, double *divv_mag, int kernel, double *omega)
 {
     or_geom g;
     geom_init(&g, x, y, z, periodic, box_lo, box_hi);
@@ -668,6 +674,7 @@ void or_density(int64_t n, const double *x, const double *y, const double *z,
         double twoh = 2.0 * hi;
         double r2max = twoh * twoh;
         double s = m[i] * kern(kernel, 0.0, hi);
+        double sh = m[i] * or_kernel_dwdh(kernel, 0.0, hi);   /* sum of m_j dW/dh */
         double dv = 0.0, dvm = 0.0;
         for (int64_t k = off[i]; k < off[i + 1]; ++k) {
             int64_t j = idx[k];
@@ -676,6 +683,7 @@ void or_density(int64_t n, const double *x, const double *y, const double *z,
             if (!(r2 < r2max)) continue;
             double r = sqrt(r2);
             s += m[j] * kern(kernel, r, hi);
+            sh += m[j] * or_kernel_dwdh(kernel, r, hi);
             if (r > 0.0) {
                 /* grad_i W = dW/dr (x_i - x_j)/r, and x_i - x_j = -(dx,dy,dz) */
                 double gw = kern_dr(kernel, r, hi) / r;
@@ -690,6 +698,9 @@ void or_density(int64_t n, const double *x, const double *y, const double *z,
         rho[i] = s;
         divv[i] = dv / s;
         if (divv_mag) divv_mag[i] = dvm / s;
+        /* grad-h factor (Springel & Hernquist 2002) for h proportional to
+         * rho^(-1/3): Omega = 1 - (dh/drho) sum_j m_j dW/dh = 1 + h/(3 rho) sum */
+        if (omega) omega[i] = 1.0 + hi / (3.0 * s) * sh;
     }
 }
 
@@ -715,6 +726,7 @@ void or_eos(int64_t n, const double *rho, const double *u, double gamma, double 
 typedef struct {
     double gamma, alpha, beta, eta2, cfl;
     int kernel;
+    const double *omega;   /* grad-h factors, or NULL for the averaged-gradient form */
 } or_phys;
 
 /* the pair term of particle i from neighbour j: writes the acceleration
@@ -746,6 +758,21 @@ static void pair_force(const or_geom *g, int64_t i, int64_t j, const double *vx,
         Pi = (-ph->alpha * cb * mu + ph->beta * mu * mu) / rb;
         *mu_abs = fabs(mu);
     }
+    if (ph->omega) {
+        /* grad-h form: each pressure term with its own particle's gradient
+         * and grad-h factor, the viscosity with the averaged gradient */
+        double fi = p[i] / (ph->omega[i] * rho[i] * rho[i]);
+        double fj = p[j] / (ph->omega[j] * rho[j] * rho[j]);
+        double g = (fi * gwi + fj * gwj) + Pi * gbar;
+        *fx = -g * xij;
+        *fy = -g * yij;
+        *fz = -g * zij;
+        double e = fi * gwi + 0.5 * Pi * gbar;
+        *de = e * w;
+        if (de_abs)
+            *de_abs = fabs(e) * (fabs(vxij * xij) + fabs(vyij * yij) + fabs(vzij * zij));
+        return;
+    }
     double pi_term = p[i] / (rho[i] * rho[i]);
     double pj_term = p[j] / (rho[j] * rho[j]);
     double sfac = (pi_term + pj_term) + Pi;
@@ -765,11 +792,11 @@ void or_forces(int64_t n, const double *x, const double *y, const double *z,
                const int *periodic, const double *box_lo, const double *box_hi,
                const int64_t *off, const int32_t *idx, double alpha, double beta, double eta2,
                double cfl, double *ax, double *ay, double *az, double *du, double *dt_i,
-               double *amag, double *dumag, int kernel)
+               double *amag, double *dumag, int kernel, const double *omega)
 {
     or_geom g;
     geom_init(&g, x, y, z, periodic, box_lo, box_hi);
-    or_phys ph = {0.0, alpha, beta, eta2, cfl, kernel};
+    or_phys ph = {0.0, alpha, beta, eta2, cfl, kernel, omega};
 #pragma omp parallel for schedule(dynamic, 256)
     for (int64_t i = 0; i < n; ++i) {
         double sx = 0.0, sy = 0.0, sz = 0.0, se = 0.0, mumax = 0.0, mag = 0.0, emag = 0.0;
@@ -799,12 +826,12 @@ void or_pair_term(int64_t n, const double *x, const double *y, const double *z,
                   const double *h, const double *rho, const double *p, const double *c,
                   const int *periodic, const double *box_lo, const double *box_hi,
                   int64_t i, int64_t j, double alpha, double beta, double eta2, double *out4,
-                  int kernel)
+                  int kernel, const double *omega)
 {
     (void)n;
     or_geom g;
     geom_init(&g, x, y, z, periodic, box_lo, box_hi);
-    or_phys ph = {0.0, alpha, beta, eta2, 0.0, kernel};
+    or_phys ph = {0.0, alpha, beta, eta2, 0.0, kernel, omega};
     double fx, fy, fz, de, mua;
     pair_force(&g, i, j, vx, vy, vz, h, rho, p, c, &ph, &fx, &fy, &fz, &de, &mua, NULL);
     double mm = m[i] * m[j];
