@@ -67,14 +67,14 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def cpu_baseline(config: int, kernel: int = 0, integrator: int = 0):
+def cpu_baseline(config: int, kernel: int = 0, integrator: int = 0, grad_h: bool = False):
     """The oracle (as it stands) timed on this host for one kick-drift-kick
     step of the benchmark workload itself (the t = 0 evaluation that precedes
     it is not timed)."""
     import oracle as O
     from paper_1905_03344_amd import inputs
     ic = inputs.config_ic(config)
-    st = O.State(ic, O.Params(kernel=kernel, integrator=integrator))
+    st = O.State(ic, O.Params(kernel=kernel, integrator=integrator, grad_h=grad_h))
     st.evaluate(method=1)
     steps = 4 if ic.n <= 2_000_000 else 1
     t0 = time.perf_counter()
@@ -131,6 +131,8 @@ def main():
     ap.add_argument("--search-div", type=int, default=2)
     ap.add_argument("--integrator", default="kdk", choices=["kdk", "ab2"],
                     help="kick-drift-kick, or its positions with Adams-Bashforth energy")
+    ap.add_argument("--grad-h", action="store_true",
+                    help="grad-h correction terms in the momentum and energy sums (plain form)")
     ap.add_argument("--kernel", default="m4", choices=["m4", "wendland", "sinc5"],
                     help="smoothing kernel of the density and force sums")
     ap.add_argument("--walk-prefilter", default="matrix", choices=["matrix", "none"],
@@ -174,7 +176,7 @@ def main():
         ic_a = inputs.config_ic(args.config)
         tr = Simulation(ic_a, search_div=args.search_div, precision=precision,
                         extra_per_particle=extra_slots, walk_prefilter=prefilter, kernel=kernel,
-                        integrator=integrator)
+                        integrator=integrator, grad_h=args.grad_h)
         tr.evaluate()
         tr.sync()
         torch.cuda.synchronize()
@@ -202,7 +204,7 @@ def main():
     sim = Simulation(ic, search_div=args.search_div, precision=precision,
                      h_mode=ffi.SPH_H_LEARNED if learned else ffi.SPH_H_PLAIN,
                      extra_per_particle=extra_slots, walk_prefilter=prefilter, kernel=kernel,
-                     integrator=integrator)
+                     integrator=integrator, grad_h=args.grad_h)
     if learned:
         sim.set_mlp(w, norm)
     log(f"bench: n={n} max_level={sim.params.max_level} workspace={sim.ws_bytes/2**20:.1f} MiB")
@@ -283,7 +285,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": workload, "n": n, "form": args.form, "dt": "courant cfl 0.3",
                    "walk_prefilter": args.walk_prefilter, "kernel": args.kernel,
-                   "integrator": args.integrator},
+                   "integrator": args.integrator, "grad_h": bool(args.grad_h)},
         "roofline": roofline,
         "kernels": kernels,
         "stages_ms_per_step": {k: round(v, 4) for k, v in stage_ms.items()},
@@ -300,7 +302,7 @@ def main():
         out["learned"] = extra
     if not args.no_cpu_baseline:
         log("bench: cpu baseline (oracle)")
-        out["cpu_baseline"] = cpu_baseline(args.config, kernel, integrator)
+        out["cpu_baseline"] = cpu_baseline(args.config, kernel, integrator, args.grad_h)
     print(json.dumps(out), flush=True)
 
 

@@ -111,6 +111,7 @@ typedef struct sph_params {
     int32_t check_finite;   /* 1 = count non-finite fields (slower) */
     int32_t max_level;      /* finest Morton level of the cell table, 1..8 */
     int32_t search_div;     /* search cells are at least 2h/search_div wide (1..4, default 2) */
+    int32_t grad_h;         /* 1 = grad-h correction terms in A9 (SPH_FP64 only; default 0) */
 } sph_params;
 
 typedef struct sph_particles {
@@ -209,6 +210,14 @@ int sph_find_neighbors(sph_ctx *ctx, sph_particles *s, sph_nlist *nl);
  * with v the predicted velocity (pvx, pvy, pvz).  Writes rho[cur], divv[cur]. */
 int sph_density(sph_ctx *ctx, sph_particles *s, const sph_nlist *nl);
 
+/* With grad_h set, sph_density also forms the grad-h factor of each
+ * particle, for h taken as proportional to rho^(-1/3) (Springel & Hernquist
+ * 2002: a refinement of the kernel-derivative gradients that Table 1 lists
+ * for the mini-app, which the paper does not use itself):
+ *   Omega_i = 1 - (1/(3 rho_i)) sum_j m_j (3 W(r_ij,h_i) + r_ij dW/dr(r_ij,h_i)),
+ * the sum over L_i and i itself (equal to 1 + h_i/(3 rho_i) sum_j m_j dW/dh).
+ * It stays in the workspace; sph_get_omega copies it out. */
+
 /* A8: ideal gas, P = (gamma-1) rho u, c = sqrt(gamma (gamma-1) u), u = pu. */
 int sph_eos(sph_ctx *ctx, sph_particles *s);
 
@@ -219,6 +228,18 @@ int sph_eos(sph_ctx *ctx, sph_particles *s);
  * dt = cfl min_i h_i / (c_i + 1.2 (alpha c_i + beta max_j |mu_ij|)) written
  * to the device scalar *d_dt.  Writes ax, ay, az, du of buffer cur. */
 int sph_momentum_energy(sph_ctx *ctx, sph_particles *s, const sph_nlist *nl, double *d_dt);
+
+/* With grad_h set, A9 takes each pressure term with its own particle's
+ * gradient and grad-h factor, the viscosity with the averaged gradient:
+ *   a_i  = -sum_j m_j [P_i/(Omega_i rho_i^2) grad_i W(r,h_i)
+ *                      + P_j/(Omega_j rho_j^2) grad_i W(r,h_j) + Pi_ij grad W_bar]
+ *   du_i =  sum_j m_j [P_i/(Omega_i rho_i^2) v_ij . grad_i W(r,h_i)
+ *                      + (Pi_ij/2) v_ij . grad W_bar]
+ * (pairwise antisymmetric as before, so momentum and energy are conserved). */
+
+/* Copies Omega of the last sph_density (buffer cur order, n values) to
+ * d_omega (device).  Error if the context was created without grad_h. */
+int sph_get_omega(sph_ctx *ctx, const sph_particles *s, double *d_omega);
 
 /* A1-A9 at the stored state (pv = v, pu = u): the force evaluation that
  * starts a run.  *d_dt receives the Courant step. */

@@ -134,6 +134,8 @@ static const char *validate(const sph_params *p)
     if (p->search_div < 1 || p->search_div > 4) return "search_div must be in 1..4";
     if (p->integrator != SPH_INTEGRATOR_KDK && p->integrator != SPH_INTEGRATOR_AB2)
         return "integrator must be SPH_INTEGRATOR_KDK or SPH_INTEGRATOR_AB2";
+    if (p->grad_h != 0 && p->grad_h != 1) return "grad_h must be 0 or 1";
+    if (p->grad_h && p->precision != SPH_FP64) return "grad_h needs precision SPH_FP64";
     if (p->walk_prefilter != SPH_PREFILTER_NONE && p->walk_prefilter != SPH_PREFILTER_MATRIX)
         return "walk_prefilter must be SPH_PREFILTER_NONE or SPH_PREFILTER_MATRIX";
     if (!(p->gamma > 1.0)) return "gamma must exceed 1";
@@ -205,6 +207,7 @@ size_t sph_layout(const sph_params *p, void *base, Workspace *w)
     t.du_prev[0] = ab2 ? (double *)take(n * sizeof(double)) : nullptr;
     t.du_prev[1] = ab2 ? (double *)take(n * sizeof(double)) : nullptr;
     t.dt_prev = (double *)take(sizeof(double));
+    t.omega = p->grad_h ? (double *)take(n * sizeof(double)) : nullptr;
     t.nb_red = nb_red;
     t.nb_sort = nb_sort;
     t.scan_part_len = scan_part;
@@ -713,6 +716,18 @@ extern "C" int sph_get_features(sph_ctx *c, const sph_particles *s, const double
     if (r) return r;
     if (!d_dt || (s->n > 0 && !d_feat)) return set_err(c, SPH_EINVAL, "NULL pointer");
     TRY(launch_mlp_features(c, s, d_dt, d_feat), "features");
+    return SPH_OK;
+}
+
+extern "C" int sph_get_omega(sph_ctx *c, const sph_particles *s, double *d_omega)
+{
+    int r = check_particles(c, s);
+    if (r) return r;
+    if (!c->p.grad_h) return set_err(c, SPH_EINVAL, "context created without grad_h");
+    if (s->n > 0 && !d_omega) return set_err(c, SPH_EINVAL, "NULL pointer");
+    if (s->n > 0)
+        TRY(hipMemcpyAsync(d_omega, c->w.omega, s->n * sizeof(double), hipMemcpyDeviceToDevice,
+                           c->stream), "copy omega");
     return SPH_OK;
 }
 

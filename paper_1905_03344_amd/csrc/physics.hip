@@ -59,11 +59,13 @@ __global__ __launch_bounds__(SPH_BLOCK) void k_pack64(
     P.vzm[i] = make_double2(vz[i], m[i]);
 }
 
-template <int PM, bool EXTRA, int KER>
+// GH: also the grad-h factor Omega_i = 1 - (1/(3 rho_i)) sum_j m_j (3 W + r dW/dr)
+template <int PM, bool EXTRA, int KER, bool GH>
 __global__ __launch_bounds__(SPH_BLOCK) SPH_PAIR_WAVES_D void k_density(
     int64_t n, Pk64 P, const int32_t *__restrict__ nc, const int32_t *__restrict__ idx, int K, Geo g,
     double knorm,
-    double *__restrict__ rho, double *__restrict__ divv, int32_t *__restrict__ ecnt,
+    double *__restrict__ rho, double *__restrict__ divv, double *__restrict__ omega,
+    int32_t *__restrict__ ecnt,
     int32_t *__restrict__ eidx, int slots, int64_t *__restrict__ status)
 {
     const int lane = threadIdx.x & (SPH_GROUP - 1);
@@ -72,7 +74,7 @@ __global__ __launch_bounds__(SPH_BLOCK) SPH_PAIR_WAVES_D void k_density(
     int64_t appended = 0, dropped = 0;
     for (int r = 0; r < SPH_GROUP; ++r) {   // SPH_BLOCK / SPH_GROUP groups, SPH_GROUP rounds
         const int64_t i = base + (int64_t)r * (SPH_BLOCK / SPH_GROUP) + grp;
-        double s = 0.0, dv = 0.0, inv_h = 0.0, mi = 0.0;
+        double s = 0.0, dv = 0.0, t = 0.0, inv_h = 0.0, mi = 0.0;
         if (i < n) {
             const double2 pxy = P.xy[i], pzh = P.zh[i], pv = P.vxy[i], pvm = P.vzm[i];
             const double xi = pxy.x, yi = pxy.y, zi = pzh.x;
@@ -116,21 +118,29 @@ __global__ __launch_bounds__(SPH_BLOCK) SPH_PAIR_WAVES_D void k_density(
                     }
                     double rr = sqrt(r2);
                     double mj = mb[q];
-                    s += mj * kern_w<KER>(rr, inv_h, knorm);
+                    const double wk = kern_w<KER>(rr, inv_h, knorm);
+                    s += mj * wk;
                     if (rr > 0.0) {
-                        double gw = kern_dwdr<KER>(rr, inv_h, knorm) / rr;
+                        const double dw = kern_dwdr<KER>(rr, inv_h, knorm);
+                        double gw = dw / rr;
                         double vdot = (ub[q] - vxi) * (-dx) + (vb[q] - vyi) * (-dy) + (wb[q] - vzi) * (-dz);
                         dv += mj * vdot * gw;
+                        if (GH) t += mj * (3.0 * wk + rr * dw);
+                    } else if (GH) {
+                        t += mj * 3.0 * wk;
                     }
                 }
             }
         }
         s = group_sum(s);
         dv = group_sum(dv);
+        if (GH) t = group_sum(t);
         if (i < n && lane == 0) {
-            const double rh = mi * kern_w<KER>(0.0, inv_h, knorm) + s;
+            const double w0 = kern_w<KER>(0.0, inv_h, knorm);
+            const double rh = mi * w0 + s;
             rho[i] = rh;
             divv[i] = dv / rh;
+            if (GH) omega[i] = 1.0 - (3.0 * mi * w0 + t) / (3.0 * rh);
         }
     }
     if (EXTRA) {
@@ -232,21 +242,32 @@ hipError_t launch_density(sph_ctx *c, sph_particles *s, const sph_nlist *nl, boo
                        s->z[cur], s->h[cur], s->pvx, s->pvy, s->pvz, s->m[cur], P);
 #define SPH_DENSITY_ARGS                                                                        \
     dim3(nb), dim3(SPH_BLOCK), 0, c->stream, n, P, s->nc[cur], nl->idx, c->p.list_stride, g,     \
-        c->knorm, s->rho[cur], s->divv[cur], nl->ecnt, nl->eidx, c->p.extra_slots, c->w.status
-    if (build_extra) {
+        c->knorm, s->rho[cur], s->divv[cur], c->w.omega, nl->ecnt, nl->eidx, c->p.extra_slots,  \
+        c->w.status
+    if (c->p.grad_h) {
+        if (build_extra) {
+            SPH_DISPATCH_KER(c->p.kernel, SPH_DISPATCH_PM(periodic_mask(g),
+                hipLaunchKernelGGL((k_density<PM, true, KER, true>), SPH_DENSITY_ARGS)))
+        } else {
+            SPH_DISPATCH_KER(c->p.kernel, SPH_DISPATCH_PM(periodic_mask(g),
+                hipLaunchKernelGGL((k_density<PM, false, KER, true>), SPH_DENSITY_ARGS)))
+        }
+    } else if (build_extra) {
         SPH_DISPATCH_KER(c->p.kernel, SPH_DISPATCH_PM(periodic_mask(g),
-            hipLaunchKernelGGL((k_density<PM, true, KER>), SPH_DENSITY_ARGS)))
+            hipLaunchKernelGGL((k_density<PM, true, KER, false>), SPH_DENSITY_ARGS)))
     } else {
         SPH_DISPATCH_KER(c->p.kernel, SPH_DISPATCH_PM(periodic_mask(g),
-            hipLaunchKernelGGL((k_density<PM, false, KER>), SPH_DENSITY_ARGS)))
+            hipLaunchKernelGGL((k_density<PM, false, KER, false>), SPH_DENSITY_ARGS)))
     }
 #undef SPH_DENSITY_ARGS
     return hipGetLastError();
 }
 
-// ideal gas
+// ideal gas; the neighbour record carries P / (Omega rho^2) (Omega = 1
+// without grad-h terms, omega NULL)
 __global__ __launch_bounds__(SPH_BLOCK) void k_eos(int64_t n, const double *__restrict__ rho,
                                                    const double *__restrict__ u, double gamma,
+                                                   const double *__restrict__ omega,
                                                    double *__restrict__ p, double *__restrict__ c,
                                                    double2 *__restrict__ rp, int check,
                                                    int64_t *__restrict__ status)
@@ -259,7 +280,8 @@ __global__ __launch_bounds__(SPH_BLOCK) void k_eos(int64_t n, const double *__re
         double cv = sqrt(gamma * (gamma - 1.0) * u[i]);
         p[i] = pv;
         c[i] = cv;
-        rp[i] = make_double2(rh, pv / (rh * rh));   // P / rho^2 once per particle
+        const double den = omega ? omega[i] * (rh * rh) : rh * rh;
+        rp[i] = make_double2(rh, pv / den);   // P / (Omega rho^2) once per particle
         if (check && !(isfinite(pv) && isfinite(cv) && isfinite(rho[i]))) bad = 1;
     }
     if (check) block_add_i64(bad, status + ST_NONFINITE);
@@ -270,7 +292,8 @@ hipError_t launch_eos(sph_ctx *c, sph_particles *s)
     int64_t n = s->n;
     if (n == 0) return hipSuccess;
     hipLaunchKernelGGL(k_eos, dim3((unsigned)ceil_div(n, SPH_BLOCK)), dim3(SPH_BLOCK), 0,
-                       c->stream, n, s->rho[s->cur], s->pu, c->p.gamma, s->p, s->c, ctx_pk64(c).rp,
+                       c->stream, n, s->rho[s->cur], s->pu, c->p.gamma,
+                       c->p.grad_h ? c->w.omega : nullptr, s->p, s->c, ctx_pk64(c).rp,
                        c->p.check_finite, c->w.status);
     return hipGetLastError();
 }
@@ -284,7 +307,7 @@ struct ForceAcc {
 
 // neighbour fields of one pair, gathered ahead of the arithmetic
 struct NbrF {
-    double x, y, z, vx, vy, vz, m, h, rho, p, c;   // p holds P / rho^2
+    double x, y, z, vx, vy, vz, m, h, rho, p, c;   // p holds P / (Omega rho^2)
 };
 
 __device__ __forceinline__ NbrF load_nbr(int j, const Pk64 &P, const double *__restrict__ c)
@@ -297,7 +320,9 @@ __device__ __forceinline__ NbrF load_nbr(int j, const Pk64 &P, const double *__r
     return b;
 }
 
-template <int PM, int KER>
+// GH: pressure terms with each particle's own gradient (grad-h form), the
+// viscosity with the averaged one; otherwise everything with the average
+template <int PM, int KER, bool GH>
 __device__ __forceinline__ void force_pair(const NbrF &b, double xi, double yi, double zi,
                                            double vxi, double vyi, double vzi, double hi,
                                            double inv_hi, double rhoi, double ci, double pi_term,
@@ -329,8 +354,16 @@ __device__ __forceinline__ void force_pair(const NbrF &b, double xi, double yi, 
         A.mumax = fmax(A.mumax, fabs(mu));
     }
     double pj_term = b.p;
-    double sfac = (pi_term + pj_term) + Pi;
     double mj = b.m;
+    if (GH) {
+        double f = mj * ((pi_term * gwi + pj_term * gwj) + Pi * gbar);
+        A.ax -= f * xij;
+        A.ay -= f * yij;
+        A.az -= f * zij;
+        A.du += mj * (pi_term * gwi + 0.5 * Pi * gbar) * w;
+        return;
+    }
+    double sfac = (pi_term + pj_term) + Pi;
     double f = mj * sfac * gbar;
     A.ax -= f * xij;
     A.ay -= f * yij;
@@ -340,7 +373,7 @@ __device__ __forceinline__ void force_pair(const NbrF &b, double xi, double yi, 
 
 // S_i = L_i (row order) then E_i (ascending) in groups of SPH_GROUP lanes;
 // ELDS: E rows ranked in LDS here (capacity <= SPH_ELDS), else sorted already
-template <int PM, bool ELDS, int KER>
+template <int PM, bool ELDS, int KER, bool GH>
 __global__ __launch_bounds__(SPH_BLOCK) SPH_PAIR_WAVES_F void k_forces(
     int64_t n, Pk64 P, const double *__restrict__ c, const int32_t *__restrict__ nc, const int32_t *__restrict__ idx, int K,
     const int32_t *__restrict__ ecnt, const int32_t *__restrict__ eidx, int slots, Geo g,
@@ -388,7 +421,7 @@ __global__ __launch_bounds__(SPH_BLOCK) SPH_PAIR_WAVES_F void k_forces(
 #pragma unroll
                 for (int q = 0; q < SPH_FBATCH; ++q) {
                     if (k0 + q * SPH_GROUP >= tot) break;
-                    force_pair<PM, KER>(nb[q], xi, yi, zi, vxi, vyi, vzi, hi, inv_hi, rhoi, ci,
+                    force_pair<PM, KER, GH>(nb[q], xi, yi, zi, vxi, vyi, vzi, hi, inv_hi, rhoi, ci,
                                         pi_term, g, knorm, alpha, beta, eta2, A);
                 }
             }
@@ -445,14 +478,24 @@ hipError_t launch_forces(sph_ctx *c, sph_particles *s, const sph_nlist *nl, doub
     dim3((unsigned)nb), dim3(SPH_BLOCK), 0, c->stream, n, ctx_pk64(c), s->c, s->nc[cur],         \
         nl->idx, p.list_stride, nl->ecnt, nl->eidx, p.extra_slots, g, c->knorm, p.av_alpha,     \
         p.av_beta, p.av_eta2, p.cfl, s->ax[cur], s->ay[cur], s->az[cur], s->du[cur], part
-    if (p.extra_slots <= SPH_ELDS) {
-        SPH_DISPATCH_KER(p.kernel, SPH_DISPATCH_PM(periodic_mask(g),
-            hipLaunchKernelGGL((k_forces<PM, true, KER>), SPH_FORCE_ARGS)))
-    } else {
+    if (p.extra_slots > SPH_ELDS) {
         hipError_t e = launch_sort_extra(c, nl, n);
         if (e != hipSuccess) return e;
+    }
+    if (p.grad_h) {
+        if (p.extra_slots <= SPH_ELDS) {
+            SPH_DISPATCH_KER(p.kernel, SPH_DISPATCH_PM(periodic_mask(g),
+                hipLaunchKernelGGL((k_forces<PM, true, KER, true>), SPH_FORCE_ARGS)))
+        } else {
+            SPH_DISPATCH_KER(p.kernel, SPH_DISPATCH_PM(periodic_mask(g),
+                hipLaunchKernelGGL((k_forces<PM, false, KER, true>), SPH_FORCE_ARGS)))
+        }
+    } else if (p.extra_slots <= SPH_ELDS) {
         SPH_DISPATCH_KER(p.kernel, SPH_DISPATCH_PM(periodic_mask(g),
-            hipLaunchKernelGGL((k_forces<PM, false, KER>), SPH_FORCE_ARGS)))
+            hipLaunchKernelGGL((k_forces<PM, true, KER, false>), SPH_FORCE_ARGS)))
+    } else {
+        SPH_DISPATCH_KER(p.kernel, SPH_DISPATCH_PM(periodic_mask(g),
+            hipLaunchKernelGGL((k_forces<PM, false, KER, false>), SPH_FORCE_ARGS)))
     }
 #undef SPH_FORCE_ARGS
     return hipGetLastError();

@@ -101,6 +101,7 @@ struct Workspace {
     void *pk64;            // n_max * 80 bytes: FP64 neighbour records (Pk64, FP64 form)
     double *du_prev[2];    // AB2: du of the previous evaluation, ping-pong like the state
     double *dt_prev;       // AB2: the previous step's dt
+    double *omega;         // grad-h: Omega of the last density (n_max, FP64 form)
     int64_t nb_red;
     int64_t nb_sort;
     int64_t scan_part_len;

@@ -44,7 +44,8 @@ class sph_params(ctypes.Structure):
                 ("box_lo", _D * 3), ("box_hi", _D * 3), ("n_target", _I32), ("n_tol", _I32),
                 ("h_max_iter", _I32), ("precision", _I32), ("gamma", _D), ("av_alpha", _D),
                 ("av_beta", _D), ("av_eta2", _D), ("cfl", _D), ("h_mode", _I32),
-                ("check_finite", _I32), ("max_level", _I32), ("search_div", _I32)]
+                ("check_finite", _I32), ("max_level", _I32), ("search_div", _I32),
+                ("grad_h", _I32)]
 
 
 CARRIED_F64 = ("x", "y", "z", "vx", "vy", "vz", "m", "h", "u", "ax", "ay", "az", "du", "rho",
@@ -108,6 +109,7 @@ _SIGS = {
     "sph_mlp_get_weights": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_float), ctypes.POINTER(_D)]),
     "sph_mlp_fit_norm": (ctypes.c_int, [_P, _P, _I64]),
     "sph_get_features": (ctypes.c_int, [_P, ctypes.POINTER(sph_particles), _P, _P]),
+    "sph_get_omega": (ctypes.c_int, [_P, ctypes.POINTER(sph_particles), _P]),
     "sph_set_harvest": (ctypes.c_int, [_P, _P, _P, _I32]),
     "sph_mlp_forward": (ctypes.c_int, [_P, _P, _I64, _P, _P, _P]),
     "sph_mlp_backward": (ctypes.c_int, [_P, _P, _P, _P, _I64, _I64, _P]),
@@ -291,6 +293,10 @@ def sph_mlp_fit_norm(ctx, d_feat: int, n: int):
 
 def sph_get_features(ctx, s, d_dt: int, d_feat: int):
     check(lib().sph_get_features(ctx, ctypes.byref(s), d_dt, d_feat), ctx)
+
+
+def sph_get_omega(ctx, s, d_omega: int):
+    check(lib().sph_get_omega(ctx, ctypes.byref(s), d_omega), ctx)
 
 
 SPH_TARGET_SOLVED = 0

@@ -30,7 +30,7 @@ class Simulation:
     def __init__(self, ic, params: ffi.sph_params | None = None, device="cuda", n_max=None,
                  list_stride=128, extra_per_particle=48, max_level=None, search_div=2,
                  precision=ffi.SPH_FP64, check_finite=False, h_mode=ffi.SPH_H_PLAIN,
-                 walk_prefilter=None, kernel=None, integrator=None):
+                 walk_prefilter=None, kernel=None, integrator=None, grad_h=False):
         self.device = torch.device(device)
         n = ic.n
         self.n = n
@@ -56,6 +56,7 @@ class Simulation:
             p.kernel = int(kernel)
         if integrator is not None:
             p.integrator = int(integrator)
+        p.grad_h = int(bool(grad_h))
         p.precision = int(precision)
         p.check_finite = int(bool(check_finite))
         p.h_mode = int(h_mode)
@@ -133,6 +134,13 @@ class Simulation:
         if name == "key":
             a = a.view(np.uint32)
         return a
+
+    def omega(self):
+        """Grad-h factors of the last density evaluation (grad_h contexts)."""
+        out = torch.empty(self.n, dtype=torch.float64, device=self.device)
+        ffi.sph_get_omega(self.ctx, self.s, out.data_ptr())
+        self.sync()
+        return out.cpu().numpy()
 
     def set_field(self, name, values):
         self.field(name).copy_(torch.as_tensor(np.ascontiguousarray(values)).to(self.device))

@@ -67,6 +67,14 @@ def test_params_validation(lib):
     with pytest.raises(ffi.SphError) as e:
         ffi.sph_create(bad)
     assert "walk_prefilter" in str(e.value)
+    assert p.grad_h == 0
+    for gh, prec in ((2, ffi.SPH_FP64), (1, ffi.SPH_MIXED)):
+        bad = ffi.default_params()
+        bad.grad_h = gh
+        bad.precision = prec
+        with pytest.raises(ffi.SphError) as e:
+            ffi.sph_create(bad)
+        assert "grad_h" in str(e.value)
 
 
 def test_workspace_size_grows_with_n(lib):

@@ -282,6 +282,37 @@ def test_kernel_variants_parity(case, kernel):
     compare_fields(sim, st)
 
 
+@pytest.mark.parametrize("kernel", ["m4", "wendland"])
+@pytest.mark.parametrize("case", ["patch_23^3_ragged", "clumpy_12k"])
+def test_grad_h_parity(case, kernel):
+    """Grad-h correction terms: Omega, the forces and a step against the
+    oracle with the same terms."""
+    kid = {"m4": O.KERNEL_M4, "wendland": O.KERNEL_WENDLAND}[kernel]
+    ic = CASES[case]()
+    print(f"grad-h kernel {kernel} case {case} n={ic.n}", flush=True)
+    st = O.State(ic.copy(), O.Params(kernel=kid, grad_h=True))
+    st.keep_gather = True
+    st.evaluate(method=1)
+    sim = _sim(ic, extra_per_particle=96, kernel=kid, grad_h=True)
+    sim.evaluate()
+    sim.sync()
+    compare_cells(sim, st)
+    compare_neighbors(sim, st)
+    compare_fields(sim, st)
+    om = sim.omega()
+    assert np.max(np.abs(om - st.omega)) <= 10 * TOL
+    assert np.max(np.abs(st.omega - 1.0)) > 1e-3   # the correction is not trivial
+    _upload_oracle_state(sim, st)
+    dt = st.dt_next
+    st.step(dt, method=1)
+    sim.step(dt)
+    sim.sync()
+    compare_cells(sim, st)
+    compare_neighbors(sim, st)
+    compare_fields(sim, st)
+    assert np.max(np.abs(sim.omega() - st.omega)) <= 10 * TOL
+
+
 def test_lattice_nonconvergence_reported():
     from paper_1905_03344_amd import ffi
     ic = inputs.perfect_lattice(16)
