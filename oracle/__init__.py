@@ -20,8 +20,11 @@ h iteration -- band membership and the lattice non-convergence case;
 density/divergence -- lattice closed forms, two-particle closed form, rigid
 rotation; EOS -- closed form; forces -- antisymmetry and conservation laws,
 Galilean invariance, uniform-lattice equilibrium; integrator -- exactness
-for constant acceleration and second-order convergence; MLP -- finite
-differences.  None of these quantities is published in the paper, so no
+for constant acceleration and second-order convergence; grad-h terms --
+finite-difference derivatives of the thermal energy with h solved
+self-consistently; IAD matrices -- inverse of a brute-force moment sum and
+exact gradients of linear fields, IAD forces -- closed forms on a lattice
+under linear pressure and velocity fields; MLP -- finite differences.  None of these quantities is published in the paper, so no
 value is pinned to a printed number.
 """
 from __future__ import annotations
@@ -65,6 +68,7 @@ def lib():
         L.or_kernel_dwdh.restype = ctypes.c_double
         L.or_kernel_dwdh.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_double]
         L.or_hsolve.restype = ctypes.c_int64
+        L.or_iad.restype = ctypes.c_int64
         L.or_lists.restype = ctypes.c_int64
         L.or_mlp_loss_grad.restype = ctypes.c_double
         L.or_num_threads.restype = ctypes.c_int
@@ -124,6 +128,9 @@ KERNEL_M4, KERNEL_WENDLAND, KERNEL_SINC5 = 0, 1, 2
 # integrators: kick-drift-kick leapfrog; KDK positions and velocities with
 # the energy by second-order Adams-Bashforth
 INTEGRATOR_KDK, INTEGRATOR_AB2 = 0, 1
+# gradient estimators of the momentum and energy sums: kernel derivatives, or
+# the integral approach to derivatives (IAD)
+GRADIENTS_KERNEL, GRADIENTS_IAD = 0, 1
 
 
 def ab2_energy(u, du, du_prev, dt, dt_prev, hist):
@@ -257,7 +264,8 @@ def eos(rho, u, gamma=5.0 / 3.0):
 
 
 def forces(x, y, z, vx, vy, vz, m, h, rho, p, c, periodic, box_lo, box_hi, off, idx,
-           alpha=1.0, beta=2.0, eta2=0.01, cfl=0.3, with_mag=False, kernel=0, omega=None):
+           alpha=1.0, beta=2.0, eta2=0.01, cfl=0.3, with_mag=False, kernel=0, omega=None,
+           iad=None):
     """a, du, per-particle dt, sum_j m_j |f_ij| (and with_mag sum_j m_j |de_ij|)."""
     arr = [_f64(a) for a in (x, y, z, vx, vy, vz, m, h, rho, p, c)]
     n = len(arr[0])
@@ -268,7 +276,8 @@ def forces(x, y, z, vx, vy, vz, m, h, rho, p, c, periodic, box_lo, box_hi, off, 
                     _dbl3(*box_hi), _p(off, _i64), _p(idx, _i32), ctypes.c_double(alpha),
                     ctypes.c_double(beta), ctypes.c_double(eta2), ctypes.c_double(cfl),
                     *[_p(a) for a in out], ctypes.c_int(kernel),
-                    _p(_f64(omega)) if omega is not None else None)
+                    _p(_f64(omega)) if omega is not None else None,
+                    _p(_f64(iad)) if iad is not None else None)
     ax, ay, az, du, dt_i, amag, dumag = out
     if with_mag:
         return ax, ay, az, du, dt_i, amag, dumag
@@ -276,15 +285,30 @@ def forces(x, y, z, vx, vy, vz, m, h, rho, p, c, periodic, box_lo, box_hi, off, 
 
 
 def pair_term(x, y, z, vx, vy, vz, m, h, rho, p, c, periodic, box_lo, box_hi, i, j,
-              alpha=1.0, beta=2.0, eta2=0.01, kernel=0, omega=None):
+              alpha=1.0, beta=2.0, eta2=0.01, kernel=0, omega=None, iad=None):
     arr = [_f64(a) for a in (x, y, z, vx, vy, vz, m, h, rho, p, c)]
     out = np.zeros(4)
     lib().or_pair_term(ctypes.c_int64(len(arr[0])), *[_p(a) for a in arr], _int3(*periodic),
                        _dbl3(*box_lo), _dbl3(*box_hi), ctypes.c_int64(i), ctypes.c_int64(j),
                        ctypes.c_double(alpha), ctypes.c_double(beta), ctypes.c_double(eta2),
                        _p(out), ctypes.c_int(kernel),
-                       _p(_f64(omega)) if omega is not None else None)
+                       _p(_f64(omega)) if omega is not None else None,
+                       _p(_f64(iad)) if iad is not None else None)
     return out
+
+
+def iad_matrices(x, y, z, m, rho, h, periodic, box_lo, box_hi, off, idx, kernel=0):
+    """IAD inverse moment matrices c_i, (n, 6) as (xx, xy, xz, yy, yz, zz),
+    and the count of singular ones (left NaN)."""
+    arr = [_f64(a) for a in (x, y, z, m, rho, h)]
+    n = len(arr[0])
+    out = np.zeros((n, 6))
+    off = np.ascontiguousarray(off, dtype=np.int64)
+    idx = np.ascontiguousarray(idx, dtype=np.int32)
+    bad = lib().or_iad(ctypes.c_int64(n), *[_p(a) for a in arr], _int3(*periodic), _dbl3(*box_lo),
+                       _dbl3(*box_hi), _p(off, _i64), _p(idx, _i32), ctypes.c_int(kernel),
+                       _p(out))
+    return out, int(bad)
 
 
 def conservation(x, y, z, vx, vy, vz, m, u):
@@ -315,6 +339,7 @@ class Params:
     kernel: int = 0   # KERNEL_M4, KERNEL_WENDLAND or KERNEL_SINC5
     integrator: int = 0   # INTEGRATOR_KDK or INTEGRATOR_AB2
     grad_h: bool = False  # grad-h correction terms in the momentum and energy equations
+    gradients: int = 0    # GRADIENTS_KERNEL or GRADIENTS_IAD
 
 
 class State:
@@ -448,11 +473,18 @@ class State:
         self.divv_mag = dvmag
         P, c = eos(rho, u, self.p.gamma)
         self.P, self.c = P, c
+        self.iad = None
+        if self.p.gradients == GRADIENTS_IAD:
+            self.iad, bad = iad_matrices(f["x"], f["y"], f["z"], f["m"], rho, f["h"], *self.geom(),
+                                         self.off, self.idx, kernel=self.p.kernel)
+            if bad:
+                raise FloatingPointError(f"{bad} singular IAD matrices")
         ax, ay, az, du, dt_i, amag, dumag = forces(f["x"], f["y"], f["z"], *vel, f["m"], f["h"],
                                                    rho, P, c, *self.geom(), self.off, self.idx,
                                                    self.p.alpha, self.p.beta, self.p.eta2,
                                                    self.p.cfl, with_mag=True, kernel=self.p.kernel,
-                                                   omega=omega if self.p.grad_h else None)
+                                                   omega=omega if self.p.grad_h else None,
+                                                   iad=self.iad)
         f["ax"], f["ay"], f["az"], f["du"] = ax, ay, az, du
         self.amag, self.dumag, self.dt_i = amag, dumag, dt_i
         self.dt_next = float(dt_i.min()) if len(dt_i) else np.inf

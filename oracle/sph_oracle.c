@@ -723,10 +723,91 @@ void or_eos(int64_t n, const double *rho, const double *u, double gamma, double 
 /*   du_i =   sum_j m_j (P_i/rho_i^2 + Pi_ij/2) v_ij . gradWbar              */
 /*   dt_i = cfl h_i / (c_i + 1.2 (alpha c_i + beta max_j |mu_ij|))           */
 /* ------------------------------------------------------------------------ */
+/* ------------------------------------------------------------------------ */
+/* IAD: integral approach to derivatives (Garcia-Senz, Cabezon & Escartin     */
+/* 2012; Table 1 lists it for SPHYNX and, in development, the mini-app).      */
+/*   tau_i = sum_{j in L_i} (m_j/rho_j) d d^T W(r_ij, h_i),  d = x_j - x_i,  */
+/*   c_i = tau_i^{-1}, stored as (xx, xy, xz, yy, yz, zz).                    */
+/* The inverse by Gauss-Jordan elimination with partial pivoting.  Returns   */
+/* the number of particles whose tau is singular (their c is set to NaN).    */
+/* ------------------------------------------------------------------------ */
+static int invert3(double a[3][3], double out[3][3])
+{
+    double m[3][6];
+    for (int r = 0; r < 3; ++r)
+        for (int k = 0; k < 3; ++k) { m[r][k] = a[r][k]; m[r][k + 3] = (r == k); }
+    for (int col = 0; col < 3; ++col) {
+        int piv = col;
+        for (int r = col + 1; r < 3; ++r)
+            if (fabs(m[r][col]) > fabs(m[piv][col])) piv = r;
+        if (!(fabs(m[piv][col]) > 0.0)) return 1;
+        if (piv != col)
+            for (int k = 0; k < 6; ++k) { double t = m[col][k]; m[col][k] = m[piv][k]; m[piv][k] = t; }
+        double inv = 1.0 / m[col][col];
+        for (int k = 0; k < 6; ++k) m[col][k] *= inv;
+        for (int r = 0; r < 3; ++r) {
+            if (r == col) continue;
+            double f = m[r][col];
+            for (int k = 0; k < 6; ++k) m[r][k] -= f * m[col][k];
+        }
+    }
+    for (int r = 0; r < 3; ++r)
+        for (int k = 0; k < 3; ++k) out[r][k] = m[r][k + 3];
+    return 0;
+}
+
+int64_t or_iad(int64_t n, const double *x, const double *y, const double *z, const double *m,
+               const double *rho, const double *h, const int *periodic, const double *box_lo,
+               const double *box_hi, const int64_t *off, const int32_t *idx, int kernel,
+               double *c6)
+{
+    or_geom g;
+    geom_init(&g, x, y, z, periodic, box_lo, box_hi);
+    int64_t bad = 0;
+#pragma omp parallel for schedule(dynamic, 256) reduction(+ : bad)
+    for (int64_t i = 0; i < n; ++i) {
+        double r2max = 4.0 * h[i] * h[i];
+        double t[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+        for (int64_t k = off[i]; k < off[i + 1]; ++k) {
+            int64_t j = idx[k];
+            double d[3];
+            double r2 = pair_r2(&g, i, j, &d[0], &d[1], &d[2]);
+            if (!(r2 < r2max)) continue;
+            double vw = m[j] / rho[j] * kern(kernel, sqrt(r2), h[i]);
+            for (int a = 0; a < 3; ++a)
+                for (int b = 0; b < 3; ++b) t[a][b] += vw * d[a] * d[b];
+        }
+        double ci[3][3];
+        if (invert3(t, ci)) {
+            ++bad;
+            for (int k = 0; k < 6; ++k) c6[6 * i + k] = NAN;
+            continue;
+        }
+        /* tau is symmetric; its computed inverse is symmetric up to rounding:
+         * keep the mean of the two off-diagonal halves */
+        c6[6 * i + 0] = ci[0][0];
+        c6[6 * i + 1] = 0.5 * (ci[0][1] + ci[1][0]);
+        c6[6 * i + 2] = 0.5 * (ci[0][2] + ci[2][0]);
+        c6[6 * i + 3] = ci[1][1];
+        c6[6 * i + 4] = 0.5 * (ci[1][2] + ci[2][1]);
+        c6[6 * i + 5] = ci[2][2];
+    }
+    return bad;
+}
+
+/* c d for the symmetric c stored as (xx, xy, xz, yy, yz, zz) */
+static void sym_apply(const double *c, const double d[3], double out[3])
+{
+    out[0] = c[0] * d[0] + c[1] * d[1] + c[2] * d[2];
+    out[1] = c[1] * d[0] + c[3] * d[1] + c[4] * d[2];
+    out[2] = c[2] * d[0] + c[4] * d[1] + c[5] * d[2];
+}
+
 typedef struct {
     double gamma, alpha, beta, eta2, cfl;
     int kernel;
     const double *omega;   /* grad-h factors, or NULL for the averaged-gradient form */
+    const double *iad;     /* IAD matrices c (6 per particle), or NULL for kernel gradients */
 } or_phys;
 
 /* the pair term of particle i from neighbour j: writes the acceleration
@@ -757,6 +838,38 @@ static void pair_force(const or_geom *g, int64_t i, int64_t j, const double *vx,
         double mu = hb * w / (r2 + ph->eta2 * hb * hb);
         Pi = (-ph->alpha * cb * mu + ph->beta * mu * mu) / rb;
         *mu_abs = fabs(mu);
+    }
+    if (ph->iad) {
+        /* IAD: grad_i W(h_i) becomes A_i = c_i d W(r, h_i) and grad_i W(h_j)
+         * becomes A_j = c_j d W(r, h_j), d = x_j - x_i; pressure terms with
+         * their own particle's A, the viscosity with the mean of the two */
+        double d[3] = {dx, dy, dz}, Ai[3], Aj[3];
+        sym_apply(ph->iad + 6 * i, d, Ai);
+        sym_apply(ph->iad + 6 * j, d, Aj);
+        double wi = kern(ph->kernel, r, h[i]), wj = kern(ph->kernel, r, h[j]);
+        double fi = p[i] / ((ph->omega ? ph->omega[i] : 1.0) * rho[i] * rho[i]);
+        double fj = p[j] / ((ph->omega ? ph->omega[j] : 1.0) * rho[j] * rho[j]);
+        double G[3], Ab[3];
+        for (int a = 0; a < 3; ++a) {
+            Ai[a] *= wi;
+            Aj[a] *= wj;
+            Ab[a] = 0.5 * (Ai[a] + Aj[a]);
+            G[a] = (fi * Ai[a] + fj * Aj[a]) + Pi * Ab[a];
+        }
+        *fx = -G[0];
+        *fy = -G[1];
+        *fz = -G[2];
+        double v[3] = {vxij, vyij, vzij};
+        double e1 = 0.0, e2 = 0.0, a1 = 0.0, a2 = 0.0;
+        for (int a = 0; a < 3; ++a) {
+            e1 += v[a] * Ai[a];
+            e2 += v[a] * Ab[a];
+            a1 += fabs(v[a] * Ai[a]);
+            a2 += fabs(v[a] * Ab[a]);
+        }
+        *de = fi * e1 + 0.5 * Pi * e2;
+        if (de_abs) *de_abs = fabs(fi) * a1 + fabs(0.5 * Pi) * a2;
+        return;
     }
     if (ph->omega) {
         /* grad-h form: each pressure term with its own particle's gradient
@@ -792,11 +905,11 @@ void or_forces(int64_t n, const double *x, const double *y, const double *z,
                const int *periodic, const double *box_lo, const double *box_hi,
                const int64_t *off, const int32_t *idx, double alpha, double beta, double eta2,
                double cfl, double *ax, double *ay, double *az, double *du, double *dt_i,
-               double *amag, double *dumag, int kernel, const double *omega)
+               double *amag, double *dumag, int kernel, const double *omega, const double *iad)
 {
     or_geom g;
     geom_init(&g, x, y, z, periodic, box_lo, box_hi);
-    or_phys ph = {0.0, alpha, beta, eta2, cfl, kernel, omega};
+    or_phys ph = {0.0, alpha, beta, eta2, cfl, kernel, omega, iad};
 #pragma omp parallel for schedule(dynamic, 256)
     for (int64_t i = 0; i < n; ++i) {
         double sx = 0.0, sy = 0.0, sz = 0.0, se = 0.0, mumax = 0.0, mag = 0.0, emag = 0.0;
@@ -826,12 +939,12 @@ void or_pair_term(int64_t n, const double *x, const double *y, const double *z,
                   const double *h, const double *rho, const double *p, const double *c,
                   const int *periodic, const double *box_lo, const double *box_hi,
                   int64_t i, int64_t j, double alpha, double beta, double eta2, double *out4,
-                  int kernel, const double *omega)
+                  int kernel, const double *omega, const double *iad)
 {
     (void)n;
     or_geom g;
     geom_init(&g, x, y, z, periodic, box_lo, box_hi);
-    or_phys ph = {0.0, alpha, beta, eta2, 0.0, kernel, omega};
+    or_phys ph = {0.0, alpha, beta, eta2, 0.0, kernel, omega, iad};
     double fx, fy, fz, de, mua;
     pair_force(&g, i, j, vx, vy, vz, h, rho, p, c, &ph, &fx, &fy, &fz, &de, &mua, NULL);
     double mm = m[i] * m[j];
