@@ -67,14 +67,16 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def cpu_baseline(config: int, kernel: int = 0, integrator: int = 0, grad_h: bool = False):
+def cpu_baseline(config: int, kernel: int = 0, integrator: int = 0, grad_h: bool = False,
+                 gradients: int = 0):
     """The oracle (as it stands) timed on this host for one kick-drift-kick
     step of the benchmark workload itself (the t = 0 evaluation that precedes
     it is not timed)."""
     import oracle as O
     from paper_1905_03344_amd import inputs
     ic = inputs.config_ic(config)
-    st = O.State(ic, O.Params(kernel=kernel, integrator=integrator, grad_h=grad_h))
+    st = O.State(ic, O.Params(kernel=kernel, integrator=integrator, grad_h=grad_h,
+                              gradients=gradients))
     st.evaluate(method=1)
     steps = 4 if ic.n <= 2_000_000 else 1
     t0 = time.perf_counter()
@@ -131,6 +133,8 @@ def main():
     ap.add_argument("--search-div", type=int, default=2)
     ap.add_argument("--integrator", default="kdk", choices=["kdk", "ab2"],
                     help="kick-drift-kick, or its positions with Adams-Bashforth energy")
+    ap.add_argument("--gradients", default="kernel", choices=["kernel", "iad"],
+                    help="gradient estimator of the momentum and energy sums (iad: plain form)")
     ap.add_argument("--grad-h", action="store_true",
                     help="grad-h correction terms in the momentum and energy sums (plain form)")
     ap.add_argument("--kernel", default="m4", choices=["m4", "wendland", "sinc5"],
@@ -170,13 +174,14 @@ def main():
     kernel = {"m4": ffi.SPH_KERNEL_M4, "wendland": ffi.SPH_KERNEL_WENDLAND,
               "sinc5": ffi.SPH_KERNEL_SINC5}[args.kernel]
     integrator = (ffi.SPH_INTEGRATOR_AB2 if args.integrator == "ab2" else ffi.SPH_INTEGRATOR_KDK)
+    gradients = (ffi.SPH_GRADIENTS_IAD if args.gradients == "iad" else ffi.SPH_GRADIENTS_KERNEL)
     extra = {}
     if learned:
         from paper_1905_03344_amd import learned as L
         ic_a = inputs.config_ic(args.config)
         tr = Simulation(ic_a, search_div=args.search_div, precision=precision,
                         extra_per_particle=extra_slots, walk_prefilter=prefilter, kernel=kernel,
-                        integrator=integrator, grad_h=args.grad_h)
+                        integrator=integrator, grad_h=args.grad_h, gradients=gradients)
         tr.evaluate()
         tr.sync()
         torch.cuda.synchronize()
@@ -204,7 +209,7 @@ def main():
     sim = Simulation(ic, search_div=args.search_div, precision=precision,
                      h_mode=ffi.SPH_H_LEARNED if learned else ffi.SPH_H_PLAIN,
                      extra_per_particle=extra_slots, walk_prefilter=prefilter, kernel=kernel,
-                     integrator=integrator, grad_h=args.grad_h)
+                     integrator=integrator, grad_h=args.grad_h, gradients=gradients)
     if learned:
         sim.set_mlp(w, norm)
     log(f"bench: n={n} max_level={sim.params.max_level} workspace={sim.ws_bytes/2**20:.1f} MiB")
@@ -285,7 +290,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": workload, "n": n, "form": args.form, "dt": "courant cfl 0.3",
                    "walk_prefilter": args.walk_prefilter, "kernel": args.kernel,
-                   "integrator": args.integrator, "grad_h": bool(args.grad_h)},
+                   "integrator": args.integrator, "grad_h": bool(args.grad_h),
+                   "gradients": args.gradients},
         "roofline": roofline,
         "kernels": kernels,
         "stages_ms_per_step": {k: round(v, 4) for k, v in stage_ms.items()},
@@ -302,7 +308,8 @@ def main():
         out["learned"] = extra
     if not args.no_cpu_baseline:
         log("bench: cpu baseline (oracle)")
-        out["cpu_baseline"] = cpu_baseline(args.config, kernel, integrator, args.grad_h)
+        out["cpu_baseline"] = cpu_baseline(args.config, kernel, integrator, args.grad_h,
+                                           gradients)
     print(json.dumps(out), flush=True)
 
 

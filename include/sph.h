@@ -88,6 +88,17 @@ typedef struct sph_ctx sph_ctx;
 #define SPH_INTEGRATOR_KDK 0
 #define SPH_INTEGRATOR_AB2 1
 
+/* Gradient estimator of the momentum and energy sums (A9).  KERNEL: kernel
+ * derivatives (the mini-app's, Table 1).  IAD: the integral approach to
+ * derivatives that Table 1 lists for SPHYNX and, in development, for the
+ * mini-app (Garcia-Senz, Cabezon & Escartin 2012): per particle the moment
+ * matrix over its gather set,
+ *   tau_i = sum_{j in L_i} (m_j/rho_j) d_ij d_ij^T W(r_ij,h_i),  d_ij = x_j - x_i,
+ * its inverse c_i, and grad_i W(r,h_i) replaced by A_i = c_i d_ij W(r_ij,h_i),
+ * grad_i W(r,h_j) by A_j = c_j d_ij W(r_ij,h_j).  SPH_FP64 form only. */
+#define SPH_GRADIENTS_KERNEL 0
+#define SPH_GRADIENTS_IAD 1
+
 typedef struct sph_params {
     int64_t n_max;          /* largest particle count the workspace is sized for */
     int32_t list_stride;    /* K: capacity of each gather set L_i (default 128) */
@@ -112,6 +123,7 @@ typedef struct sph_params {
     int32_t max_level;      /* finest Morton level of the cell table, 1..8 */
     int32_t search_div;     /* search cells are at least 2h/search_div wide (1..4, default 2) */
     int32_t grad_h;         /* 1 = grad-h correction terms in A9 (SPH_FP64 only; default 0) */
+    int32_t gradients;      /* SPH_GRADIENTS_KERNEL (default) or SPH_GRADIENTS_IAD */
 } sph_params;
 
 typedef struct sph_particles {
@@ -170,6 +182,7 @@ typedef struct sph_stats {
     int64_t candidates;      /* candidate pairs tested by the h iteration */
     double dt;               /* Courant time step of the last evaluation */
     int64_t candidates_first;/* of those, tested by its first (all-particle) counting pass */
+    int64_t iad_singular;    /* IAD: particles whose moment matrix was not invertible */
 } sph_stats;
 
 /* Fill *p with the defaults above (n_max and capacities set to 0). */
@@ -236,6 +249,14 @@ int sph_momentum_energy(sph_ctx *ctx, sph_particles *s, const sph_nlist *nl, dou
  *   du_i =  sum_j m_j [P_i/(Omega_i rho_i^2) v_ij . grad_i W(r,h_i)
  *                      + (Pi_ij/2) v_ij . grad W_bar]
  * (pairwise antisymmetric as before, so momentum and energy are conserved). */
+
+/* With gradients = SPH_GRADIENTS_IAD, sph_momentum_energy first forms c_i
+ * for every particle (rho from the last sph_eos), then sums
+ *   a_i  = -sum_{j in S_i} m_j [f_i A_i + f_j A_j + Pi_ij (A_i + A_j)/2]
+ *   du_i =  sum_{j in S_i} m_j [f_i v_ij . A_i + (Pi_ij/2) v_ij . (A_i + A_j)/2]
+ * with f = P/rho^2 (P/(Omega rho^2) with grad_h).  A moment matrix whose
+ * determinant is not positive and finite counts in sph_stats.iad_singular
+ * and makes sph_sync return SPH_ENONFINITE. */
 
 /* Copies Omega of the last sph_density (buffer cur order, n values) to
  * d_omega (device).  Error if the context was created without grad_h. */

@@ -136,6 +136,10 @@ static const char *validate(const sph_params *p)
         return "integrator must be SPH_INTEGRATOR_KDK or SPH_INTEGRATOR_AB2";
     if (p->grad_h != 0 && p->grad_h != 1) return "grad_h must be 0 or 1";
     if (p->grad_h && p->precision != SPH_FP64) return "grad_h needs precision SPH_FP64";
+    if (p->gradients != SPH_GRADIENTS_KERNEL && p->gradients != SPH_GRADIENTS_IAD)
+        return "gradients must be SPH_GRADIENTS_KERNEL or SPH_GRADIENTS_IAD";
+    if (p->gradients == SPH_GRADIENTS_IAD && p->precision != SPH_FP64)
+        return "IAD gradients need precision SPH_FP64";
     if (p->walk_prefilter != SPH_PREFILTER_NONE && p->walk_prefilter != SPH_PREFILTER_MATRIX)
         return "walk_prefilter must be SPH_PREFILTER_NONE or SPH_PREFILTER_MATRIX";
     if (!(p->gamma > 1.0)) return "gamma must exceed 1";
@@ -208,6 +212,7 @@ size_t sph_layout(const sph_params *p, void *base, Workspace *w)
     t.du_prev[1] = ab2 ? (double *)take(n * sizeof(double)) : nullptr;
     t.dt_prev = (double *)take(sizeof(double));
     t.omega = p->grad_h ? (double *)take(n * sizeof(double)) : nullptr;
+    t.iad = p->gradients == SPH_GRADIENTS_IAD ? (double2 *)take(n * 3 * sizeof(double2)) : nullptr;
     t.nb_red = nb_red;
     t.nb_sort = nb_sort;
     t.scan_part_len = scan_part;
@@ -620,10 +625,12 @@ extern "C" int sph_sync(sph_ctx *c, sph_stats *st)
         st->candidates = h[ST_CANDIDATES];
         st->extra_total = h[ST_EXTRA_TOTAL];
         st->candidates_first = h[ST_CANDIDATES_FIRST];
+        st->iad_singular = h[ST_IAD_SINGULAR];
     }
     if (h[ST_LIST_OVERFLOW] || h[ST_EXTRA_OVERFLOW])
         return set_err(c, SPH_ECAPACITY, "a neighbour list exceeded its capacity");
     if (h[ST_NONFINITE]) return set_err(c, SPH_ENONFINITE, "non-finite field values");
+    if (h[ST_IAD_SINGULAR]) return set_err(c, SPH_ENONFINITE, "singular IAD moment matrix");
     if (h[ST_NONCONV]) return SPH_WNOCONV;
     return SPH_OK;
 }

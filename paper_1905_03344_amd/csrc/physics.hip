@@ -301,6 +301,11 @@ hipError_t launch_eos(sph_ctx *c, sph_particles *s)
 // ---------------------------------------------------------------------------
 // momentum, energy, artificial viscosity, Courant step
 // ---------------------------------------------------------------------------
+// gradient forms of the pair sums (template argument GR)
+#define SPH_GR_AVG 0   // averaged kernel gradient
+#define SPH_GR_OWN 1   // each pressure term with its own kernel gradient (grad-h)
+#define SPH_GR_IAD 2   // each pressure term with its own IAD gradient
+
 struct ForceAcc {
     double ax, ay, az, du, mumax;
 };
@@ -308,26 +313,128 @@ struct ForceAcc {
 // neighbour fields of one pair, gathered ahead of the arithmetic
 struct NbrF {
     double x, y, z, vx, vy, vz, m, h, rho, p, c;   // p holds P / (Omega rho^2)
+    double cm[6];                                  // IAD: c_j (xx, xy, xz, yy, yz, zz)
 };
 
-__device__ __forceinline__ NbrF load_nbr(int j, const Pk64 &P, const double *__restrict__ c)
+// the three IAD arrays of n_max double2 each
+struct IadC {
+    double2 *a, *b, *c;   // (xx, xy), (xz, yy), (yz, zz)
+};
+
+static IadC ctx_iad(sph_ctx *c)
+{
+    double2 *b = c->w.iad;
+    const int64_t n = c->p.n_max;
+    return IadC{b, b ? b + n : nullptr, b ? b + 2 * n : nullptr};
+}
+
+// IAD moment matrix over the gather set and its inverse, one group of
+// SPH_GROUP lanes per particle (as the density kernel): tau accumulates
+// (m_j/rho_j) W(r_ij,h_i) d d^T, d = x_j - x_i; c = adj(tau)/det(tau)
+template <int PM, int KER>
+__global__ __launch_bounds__(SPH_BLOCK) SPH_PAIR_WAVES_D void k_iad(
+    int64_t n, Pk64 P, const int32_t *__restrict__ nc, const int32_t *__restrict__ idx, int K,
+    Geo g, double knorm, IadC out, int64_t *__restrict__ status)
+{
+    const int lane = threadIdx.x & (SPH_GROUP - 1);
+    const int grp = threadIdx.x / SPH_GROUP;
+    const int64_t base = (int64_t)xcd_block(blockIdx.x, gridDim.x) * SPH_BLOCK;
+    int64_t bad = 0;
+    for (int r = 0; r < SPH_GROUP; ++r) {
+        const int64_t i = base + (int64_t)r * (SPH_BLOCK / SPH_GROUP) + grp;
+        double txx = 0.0, txy = 0.0, txz = 0.0, tyy = 0.0, tyz = 0.0, tzz = 0.0;
+        if (i < n) {
+            const double2 pxy = P.xy[i], pzh = P.zh[i];
+            const double xi = pxy.x, yi = pxy.y, zi = pzh.x;
+            const double inv_h = 1.0 / pzh.y;
+            const int cnt = min(nc[i], K);
+            const int32_t *row = idx + i * (int64_t)K;
+            for (int k0 = lane; k0 < cnt; k0 += SPH_BATCH * SPH_GROUP) {
+                int jb[SPH_BATCH];
+#pragma unroll
+                for (int q = 0; q < SPH_BATCH; ++q) {
+                    const int k = k0 + q * SPH_GROUP;
+                    jb[q] = k < cnt ? row[k] : (int)i;
+                }
+                double2 ab[SPH_BATCH], zb[SPH_BATCH], mb[SPH_BATCH], rb[SPH_BATCH];
+#pragma unroll
+                for (int q = 0; q < SPH_BATCH; ++q) {
+                    const int j = jb[q];
+                    ab[q] = P.xy[j]; zb[q] = P.zh[j]; mb[q] = P.vzm[j]; rb[q] = P.rp[j];
+                }
+#pragma unroll
+                for (int q = 0; q < SPH_BATCH; ++q) {
+                    if (k0 + q * SPH_GROUP >= cnt) break;
+                    const double dx = mimg<PM, 0>(xi, ab[q].x, g);
+                    const double dy = mimg<PM, 1>(yi, ab[q].y, g);
+                    const double dz = mimg<PM, 2>(zi, zb[q].x, g);
+                    const double rr = sqrt(exact_r2(dx, dy, dz));
+                    const double vw = mb[q].y / rb[q].x * kern_w<KER>(rr, inv_h, knorm);
+                    txx += vw * dx * dx; txy += vw * dx * dy; txz += vw * dx * dz;
+                    tyy += vw * dy * dy; tyz += vw * dy * dz; tzz += vw * dz * dz;
+                }
+            }
+        }
+        txx = group_sum(txx); txy = group_sum(txy); txz = group_sum(txz);
+        tyy = group_sum(tyy); tyz = group_sum(tyz); tzz = group_sum(tzz);
+        if (i < n && lane == 0) {
+            const double axx = tyy * tzz - tyz * tyz;
+            const double axy = txz * tyz - txy * tzz;
+            const double axz = txy * tyz - txz * tyy;
+            const double det = txx * axx + txy * axy + txz * axz;
+            if (!(det > 0.0) || !isfinite(det)) ++bad;
+            const double id = 1.0 / det;
+            const double ayy = txx * tzz - txz * txz;
+            const double ayz = txy * txz - txx * tyz;
+            const double azz = txx * tyy - txy * txy;
+            out.a[i] = make_double2(axx * id, axy * id);
+            out.b[i] = make_double2(axz * id, ayy * id);
+            out.c[i] = make_double2(ayz * id, azz * id);
+        }
+    }
+    block_add_i64(bad, status + ST_IAD_SINGULAR);
+}
+
+hipError_t launch_iad(sph_ctx *c, sph_particles *s, const sph_nlist *nl)
+{
+    const int64_t n = s->n;
+    if (n == 0) return hipSuccess;
+    Geo g = make_geo(c->p);
+    const IadC I = ctx_iad(c);
+    SPH_DISPATCH_KER(c->p.kernel, SPH_DISPATCH_PM(periodic_mask(g),
+        hipLaunchKernelGGL((k_iad<PM, KER>), dim3((unsigned)ceil_div(n, SPH_BLOCK)),
+                           dim3(SPH_BLOCK), 0, c->stream, n, ctx_pk64(c), s->nc[s->cur], nl->idx,
+                           c->p.list_stride, g, c->knorm, I, c->w.status)))
+    return hipGetLastError();
+}
+
+template <int GR>
+__device__ __forceinline__ NbrF load_nbr(int j, const Pk64 &P, const double *__restrict__ c,
+                                         const IadC &I)
 {
     NbrF b;
     const double2 a = P.xy[j], zh = P.zh[j], v = P.vxy[j], vm = P.vzm[j], rp = P.rp[j];
     b.x = a.x; b.y = a.y; b.z = zh.x; b.h = zh.y;
     b.vx = v.x; b.vy = v.y; b.vz = vm.x; b.m = vm.y;
     b.rho = rp.x; b.p = rp.y; b.c = c[j];
+    if (GR == SPH_GR_IAD) {
+        const double2 p0 = I.a[j], p1 = I.b[j], p2 = I.c[j];
+        b.cm[0] = p0.x; b.cm[1] = p0.y; b.cm[2] = p1.x;
+        b.cm[3] = p1.y; b.cm[4] = p2.x; b.cm[5] = p2.y;
+    }
     return b;
 }
 
-// GH: pressure terms with each particle's own gradient (grad-h form), the
-// viscosity with the averaged one; otherwise everything with the average
-template <int PM, int KER, bool GH>
+// GR: SPH_GR_AVG everything with the averaged kernel gradient; SPH_GR_OWN
+// pressure terms with each particle's own kernel gradient (grad-h form), the
+// viscosity with the average; SPH_GR_IAD pressure terms with each particle's
+// own IAD gradient A = c d W, the viscosity with their mean (ci: c_i)
+template <int PM, int KER, int GR>
 __device__ __forceinline__ void force_pair(const NbrF &b, double xi, double yi, double zi,
                                            double vxi, double vyi, double vzi, double hi,
                                            double inv_hi, double rhoi, double ci, double pi_term,
-                                           const Geo &g, double knorm, double alpha, double beta,
-                                           double eta2, ForceAcc &A)
+                                           const double *cmi, const Geo &g, double knorm,
+                                           double alpha, double beta, double eta2, ForceAcc &A)
 {
     double dx = mimg<PM, 0>(xi, b.x, g);
     double dy = mimg<PM, 1>(yi, b.y, g);
@@ -340,6 +447,34 @@ __device__ __forceinline__ void force_pair(const NbrF &b, double xi, double yi, 
     double xij = -dx, yij = -dy, zij = -dz;
     double vxij = vxi - b.vx, vyij = vyi - b.vy, vzij = vzi - b.vz;
     double w = vxij * xij + vyij * yij + vzij * zij;
+    if (GR == SPH_GR_IAD) {
+        double Pi = 0.0;
+        if (w < 0.0) {
+            double hb = 0.5 * (hi + b.h);
+            double cb = 0.5 * (ci + b.c);
+            double rb = 0.5 * (rhoi + b.rho);
+            double mu = hb * w / (r2 + eta2 * hb * hb);
+            Pi = (-alpha * cb * mu + beta * mu * mu) / rb;
+            A.mumax = fmax(A.mumax, fabs(mu));
+        }
+        const double wi = kern_w<KER>(r, inv_hi, knorm);
+        const double wj = kern_w<KER>(r, 1.0 / b.h, knorm);
+        // A = c d W with d = x_j - x_i = (dx, dy, dz)
+        const double aix = (cmi[0] * dx + cmi[1] * dy + cmi[2] * dz) * wi;
+        const double aiy = (cmi[1] * dx + cmi[3] * dy + cmi[4] * dz) * wi;
+        const double aiz = (cmi[2] * dx + cmi[4] * dy + cmi[5] * dz) * wi;
+        const double ajx = (b.cm[0] * dx + b.cm[1] * dy + b.cm[2] * dz) * wj;
+        const double ajy = (b.cm[1] * dx + b.cm[3] * dy + b.cm[4] * dz) * wj;
+        const double ajz = (b.cm[2] * dx + b.cm[4] * dy + b.cm[5] * dz) * wj;
+        const double abx = 0.5 * (aix + ajx), aby = 0.5 * (aiy + ajy), abz = 0.5 * (aiz + ajz);
+        const double mj = b.m, pj_term = b.p;
+        A.ax -= mj * ((pi_term * aix + pj_term * ajx) + Pi * abx);
+        A.ay -= mj * ((pi_term * aiy + pj_term * ajy) + Pi * aby);
+        A.az -= mj * ((pi_term * aiz + pj_term * ajz) + Pi * abz);
+        A.du += mj * (pi_term * (vxij * aix + vyij * aiy + vzij * aiz) +
+                      0.5 * Pi * (vxij * abx + vyij * aby + vzij * abz));
+        return;
+    }
     double gwi = kern_dwdr<KER>(r, inv_hi, knorm) * inv_r;
     double gwj = kern_dwdr<KER>(r, 1.0 / hj, knorm) * inv_r;
     double gbar = 0.5 * (gwi + gwj);
@@ -355,7 +490,7 @@ __device__ __forceinline__ void force_pair(const NbrF &b, double xi, double yi, 
     }
     double pj_term = b.p;
     double mj = b.m;
-    if (GH) {
+    if (GR == SPH_GR_OWN) {
         double f = mj * ((pi_term * gwi + pj_term * gwj) + Pi * gbar);
         A.ax -= f * xij;
         A.ay -= f * yij;
@@ -373,9 +508,9 @@ __device__ __forceinline__ void force_pair(const NbrF &b, double xi, double yi, 
 
 // S_i = L_i (row order) then E_i (ascending) in groups of SPH_GROUP lanes;
 // ELDS: E rows ranked in LDS here (capacity <= SPH_ELDS), else sorted already
-template <int PM, bool ELDS, int KER, bool GH>
+template <int PM, bool ELDS, int KER, int GR>
 __global__ __launch_bounds__(SPH_BLOCK) SPH_PAIR_WAVES_F void k_forces(
-    int64_t n, Pk64 P, const double *__restrict__ c, const int32_t *__restrict__ nc, const int32_t *__restrict__ idx, int K,
+    int64_t n, Pk64 P, IadC I, const double *__restrict__ c, const int32_t *__restrict__ nc, const int32_t *__restrict__ idx, int K,
     const int32_t *__restrict__ ecnt, const int32_t *__restrict__ eidx, int slots, Geo g,
     double knorm, double alpha, double beta, double eta2, double cfl, double *__restrict__ ax,
     double *__restrict__ ay, double *__restrict__ az, double *__restrict__ du,
@@ -393,7 +528,7 @@ __global__ __launch_bounds__(SPH_BLOCK) SPH_PAIR_WAVES_F void k_forces(
         ForceAcc A = {0.0, 0.0, 0.0, 0.0, 0.0};
         double hi = 0.0, ci = 0.0;
         if (i < n) {
-            const NbrF me = load_nbr((int)i, P, c);
+            const NbrF me = load_nbr<GR>((int)i, P, c, I);
             const double xi = me.x, yi = me.y, zi = me.z;
             const double vxi = me.vx, vyi = me.vy, vzi = me.vz;
             hi = me.h;
@@ -417,12 +552,12 @@ __global__ __launch_bounds__(SPH_BLOCK) SPH_PAIR_WAVES_F void k_forces(
                 NbrF nb[SPH_FBATCH];
 #pragma unroll
                 for (int q = 0; q < SPH_FBATCH; ++q)
-                    nb[q] = load_nbr(jb[q], P, c);
+                    nb[q] = load_nbr<GR>(jb[q], P, c, I);
 #pragma unroll
                 for (int q = 0; q < SPH_FBATCH; ++q) {
                     if (k0 + q * SPH_GROUP >= tot) break;
-                    force_pair<PM, KER, GH>(nb[q], xi, yi, zi, vxi, vyi, vzi, hi, inv_hi, rhoi, ci,
-                                        pi_term, g, knorm, alpha, beta, eta2, A);
+                    force_pair<PM, KER, GR>(nb[q], xi, yi, zi, vxi, vyi, vzi, hi, inv_hi, rhoi, ci,
+                                            pi_term, me.cm, g, knorm, alpha, beta, eta2, A);
                 }
             }
         }
@@ -475,28 +610,33 @@ hipError_t launch_forces(sph_ctx *c, sph_particles *s, const sph_nlist *nl, doub
     double *part = c->w.red_part;
     Geo g = make_geo(p);
 #define SPH_FORCE_ARGS                                                                          \
-    dim3((unsigned)nb), dim3(SPH_BLOCK), 0, c->stream, n, ctx_pk64(c), s->c, s->nc[cur],         \
+    dim3((unsigned)nb), dim3(SPH_BLOCK), 0, c->stream, n, ctx_pk64(c), I, s->c, s->nc[cur],      \
         nl->idx, p.list_stride, nl->ecnt, nl->eidx, p.extra_slots, g, c->knorm, p.av_alpha,     \
         p.av_beta, p.av_eta2, p.cfl, s->ax[cur], s->ay[cur], s->az[cur], s->du[cur], part
     if (p.extra_slots > SPH_ELDS) {
         hipError_t e = launch_sort_extra(c, nl, n);
         if (e != hipSuccess) return e;
     }
-    if (p.grad_h) {
-        if (p.extra_slots <= SPH_ELDS) {
-            SPH_DISPATCH_KER(p.kernel, SPH_DISPATCH_PM(periodic_mask(g),
-                hipLaunchKernelGGL((k_forces<PM, true, KER, true>), SPH_FORCE_ARGS)))
-        } else {
-            SPH_DISPATCH_KER(p.kernel, SPH_DISPATCH_PM(periodic_mask(g),
-                hipLaunchKernelGGL((k_forces<PM, false, KER, true>), SPH_FORCE_ARGS)))
-        }
-    } else if (p.extra_slots <= SPH_ELDS) {
-        SPH_DISPATCH_KER(p.kernel, SPH_DISPATCH_PM(periodic_mask(g),
-            hipLaunchKernelGGL((k_forces<PM, true, KER, false>), SPH_FORCE_ARGS)))
-    } else {
-        SPH_DISPATCH_KER(p.kernel, SPH_DISPATCH_PM(periodic_mask(g),
-            hipLaunchKernelGGL((k_forces<PM, false, KER, false>), SPH_FORCE_ARGS)))
+    const IadC I = ctx_iad(c);
+    const bool elds = p.extra_slots <= SPH_ELDS;
+#define SPH_FORCE_GR(GRV)                                                                       \
+    if (elds) {                                                                                 \
+        SPH_DISPATCH_KER(p.kernel, SPH_DISPATCH_PM(periodic_mask(g),                            \
+            hipLaunchKernelGGL((k_forces<PM, true, KER, GRV>), SPH_FORCE_ARGS)))                \
+    } else {                                                                                    \
+        SPH_DISPATCH_KER(p.kernel, SPH_DISPATCH_PM(periodic_mask(g),                            \
+            hipLaunchKernelGGL((k_forces<PM, false, KER, GRV>), SPH_FORCE_ARGS)))               \
     }
+    if (p.gradients == SPH_GRADIENTS_IAD) {
+        hipError_t e = launch_iad(c, s, nl);
+        if (e != hipSuccess) return e;
+        SPH_FORCE_GR(SPH_GR_IAD)
+    } else if (p.grad_h) {
+        SPH_FORCE_GR(SPH_GR_OWN)
+    } else {
+        SPH_FORCE_GR(SPH_GR_AVG)
+    }
+#undef SPH_FORCE_GR
 #undef SPH_FORCE_ARGS
     return hipGetLastError();
 }

@@ -46,6 +46,7 @@ enum {
     ST_CANDIDATES = 7,
     ST_EXTRA_TOTAL = 8,
     ST_CANDIDATES_FIRST = 9,   // candidates tested by round 0 of the h iteration
+    ST_IAD_SINGULAR = 10,      // IAD moment matrices that could not be inverted
     ST_COUNT = 16
 };
 
@@ -102,6 +103,7 @@ struct Workspace {
     double *du_prev[2];    // AB2: du of the previous evaluation, ping-pong like the state
     double *dt_prev;       // AB2: the previous step's dt
     double *omega;         // grad-h: Omega of the last density (n_max, FP64 form)
+    double2 *iad;          // IAD: c_i as 3 arrays of n_max double2 (xx,xy) (xz,yy) (yz,zz)
     int64_t nb_red;
     int64_t nb_sort;
     int64_t scan_part_len;

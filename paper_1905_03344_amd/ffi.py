@@ -20,6 +20,8 @@ SPH_WNOCONV = 1
 
 SPH_INTEGRATOR_KDK = 0
 SPH_INTEGRATOR_AB2 = 1
+SPH_GRADIENTS_KERNEL = 0
+SPH_GRADIENTS_IAD = 1
 SPH_KERNEL_M4 = 0
 SPH_KERNEL_WENDLAND = 1
 SPH_KERNEL_SINC5 = 2
@@ -45,7 +47,7 @@ class sph_params(ctypes.Structure):
                 ("h_max_iter", _I32), ("precision", _I32), ("gamma", _D), ("av_alpha", _D),
                 ("av_beta", _D), ("av_eta2", _D), ("cfl", _D), ("h_mode", _I32),
                 ("check_finite", _I32), ("max_level", _I32), ("search_div", _I32),
-                ("grad_h", _I32)]
+                ("grad_h", _I32), ("gradients", _I32)]
 
 
 CARRIED_F64 = ("x", "y", "z", "vx", "vy", "vz", "m", "h", "u", "ax", "ay", "az", "du", "rho",
@@ -70,7 +72,7 @@ class sph_stats(ctypes.Structure):
     _fields_ = [("nonconverged", _I64), ("list_overflow", _I64), ("extra_total", _I64),
                 ("extra_overflow", _I64), ("nonfinite", _I64), ("h_counts", _I64),
                 ("learned_accepted", _I64), ("learned_fallback", _I64), ("candidates", _I64),
-                ("dt", _D), ("candidates_first", _I64)]
+                ("dt", _D), ("candidates_first", _I64), ("iad_singular", _I64)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

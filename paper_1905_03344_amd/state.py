@@ -30,7 +30,8 @@ class Simulation:
     def __init__(self, ic, params: ffi.sph_params | None = None, device="cuda", n_max=None,
                  list_stride=128, extra_per_particle=48, max_level=None, search_div=2,
                  precision=ffi.SPH_FP64, check_finite=False, h_mode=ffi.SPH_H_PLAIN,
-                 walk_prefilter=None, kernel=None, integrator=None, grad_h=False):
+                 walk_prefilter=None, kernel=None, integrator=None, grad_h=False,
+                 gradients=None):
         self.device = torch.device(device)
         n = ic.n
         self.n = n
@@ -57,6 +58,8 @@ class Simulation:
         if integrator is not None:
             p.integrator = int(integrator)
         p.grad_h = int(bool(grad_h))
+        if gradients is not None:
+            p.gradients = int(gradients)
         p.precision = int(precision)
         p.check_finite = int(bool(check_finite))
         p.h_mode = int(h_mode)

@@ -75,6 +75,14 @@ def test_params_validation(lib):
         with pytest.raises(ffi.SphError) as e:
             ffi.sph_create(bad)
         assert "grad_h" in str(e.value)
+    assert p.gradients == ffi.SPH_GRADIENTS_KERNEL
+    for gr, prec in ((2, ffi.SPH_FP64), (ffi.SPH_GRADIENTS_IAD, ffi.SPH_MIXED)):
+        bad = ffi.default_params()
+        bad.gradients = gr
+        bad.precision = prec
+        with pytest.raises(ffi.SphError) as e:
+            ffi.sph_create(bad)
+        assert "gradients" in str(e.value) or "IAD" in str(e.value)
 
 
 def test_workspace_size_grows_with_n(lib):

@@ -313,6 +313,59 @@ def test_grad_h_parity(case, kernel):
     assert np.max(np.abs(sim.omega() - st.omega)) <= 10 * TOL
 
 
+@pytest.mark.parametrize("variant", ["iad", "iad+grad_h", "iad_wendland"])
+@pytest.mark.parametrize("case", ["patch_23^3_ragged", "clumpy_12k"])
+def test_iad_parity(case, variant):
+    """IAD gradients: the forces and a step against the oracle with the same
+    estimator (and grad-h factors, or the Wendland kernel)."""
+    from paper_1905_03344_amd import ffi
+    kid = O.KERNEL_WENDLAND if variant == "iad_wendland" else O.KERNEL_M4
+    gh = variant == "iad+grad_h"
+    ic = CASES[case]()
+    print(f"IAD variant {variant} case {case} n={ic.n}", flush=True)
+    st = O.State(ic.copy(), O.Params(kernel=kid, grad_h=gh, gradients=O.GRADIENTS_IAD))
+    st.keep_gather = True
+    st.evaluate(method=1)
+    sim = _sim(ic, extra_per_particle=96, kernel=kid, grad_h=gh,
+               gradients=ffi.SPH_GRADIENTS_IAD)
+    sim.evaluate()
+    code, stats = sim.sync()
+    assert stats.iad_singular == 0
+    compare_cells(sim, st)
+    compare_neighbors(sim, st)
+    compare_fields(sim, st)
+    _upload_oracle_state(sim, st)
+    dt = st.dt_next
+    st.step(dt, method=1)
+    sim.step(dt)
+    sim.sync()
+    compare_cells(sim, st)
+    compare_neighbors(sim, st)
+    compare_fields(sim, st)
+
+
+def test_iad_singular_matrices_reported():
+    """Two flat layers far apart (a three-dimensional box, but every
+    neighbourhood lies in one plane): every IAD moment matrix is singular,
+    which sph_sync reports as an error."""
+    from paper_1905_03344_amd import ffi
+    g = (np.arange(12) + 0.5) / 12
+    x, y = (a.ravel() for a in np.meshgrid(g, g, indexing="ij"))
+    x = np.concatenate([x, x])
+    y = np.concatenate([y, y])
+    z = np.concatenate([np.zeros(144), np.full(144, 10.0)])
+    n = len(x)
+    zeros = np.zeros(n)
+    ic = inputs.ParticleSet(x, y, z, zeros.copy(), zeros.copy(), zeros.copy(), np.full(n, 1.0 / n),
+                            np.full(n, 0.2), np.ones(n), name="two_layers")
+    print(f"IAD singular layers n={ic.n}", flush=True)
+    sim = _sim(ic, extra_per_particle=96, gradients=ffi.SPH_GRADIENTS_IAD)
+    sim.evaluate()
+    with pytest.raises(ffi.SphError) as e:
+        sim.sync()
+    assert e.value.code == ffi.SPH_ENONFINITE and "IAD" in str(e.value)
+
+
 def test_lattice_nonconvergence_reported():
     from paper_1905_03344_amd import ffi
     ic = inputs.perfect_lattice(16)
