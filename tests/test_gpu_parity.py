@@ -406,6 +406,31 @@ def test_tiny_inputs():
     sim0.sync()
 
 
+@pytest.mark.parametrize("variant", ["grad_h", "iad"])
+def test_tiny_inputs_variants(variant):
+    from paper_1905_03344_amd import ffi
+    kw = {"grad_h": True} if variant == "grad_h" else {"gradients": ffi.SPH_GRADIENTS_IAD}
+    print(f"tiny inputs {variant}", flush=True)
+    ic0 = inputs.square_patch(4, 1).subset(np.array([], dtype=np.int64))
+    sim0 = _sim(ic0, **kw)
+    sim0.evaluate()
+    sim0.sync()
+    # one particle: no neighbours; Omega = 0 (its own term is the whole sum),
+    # and its IAD moment matrix is zero, hence singular
+    ic = inputs.square_patch(4, 1).subset(np.array([5]))
+    sim = _sim(ic, **kw)
+    sim.evaluate()
+    if variant == "grad_h":
+        code, stats = sim.sync()
+        assert stats.nonconverged == 1
+        assert abs(sim.omega()[0]) < 1e-15
+        assert sim.numpy("ax")[0] == 0.0 and sim.numpy("du")[0] == 0.0
+    else:
+        with pytest.raises(ffi.SphError) as e:
+            sim.sync()
+        assert e.value.code == ffi.SPH_ENONFINITE
+
+
 @pytest.mark.slow
 def test_config2_full_size_parity():
     # 100^3 square patch, the launch configuration bench.py times
