@@ -122,7 +122,7 @@ typedef struct sph_params {
     int32_t check_finite;   /* 1 = count non-finite fields (slower) */
     int32_t max_level;      /* finest Morton level of the cell table, 1..8 */
     int32_t search_div;     /* search cells are at least 2h/search_div wide (1..4, default 2) */
-    int32_t grad_h;         /* 1 = grad-h correction terms in A9 (SPH_FP64 only; default 0) */
+    int32_t grad_h;         /* 1 = grad-h correction terms in A9 (default 0) */
     int32_t gradients;      /* SPH_GRADIENTS_KERNEL (default) or SPH_GRADIENTS_IAD */
 } sph_params;
 

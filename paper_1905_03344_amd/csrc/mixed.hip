@@ -196,12 +196,14 @@ __device__ __forceinline__ MixGeo mix_geo(const double *__restrict__ bbox, const
     return G;
 }
 
-template <int PM, bool EXTRA, int KER>
+// GH: also the grad-h factor Omega_i = 1 - (1/(3 rho_i)) sum_j m_j (3 W + r dW/dr)
+template <int PM, bool EXTRA, int KER, bool GH>
 __global__ __launch_bounds__(SPH_BLOCK) SPH_PAIR_WAVES_D void k_density_mixed(
     int64_t n, MixQ Q, const int32_t *__restrict__ nc, const int32_t *__restrict__ idx, int K,
     const double *__restrict__ bbox, Geo g, float knorm, const double *__restrict__ x,
     const double *__restrict__ y, const double *__restrict__ z, const double *__restrict__ h,
-    double *__restrict__ rho, double *__restrict__ divv, int32_t *__restrict__ ecnt,
+    double *__restrict__ rho, double *__restrict__ divv, double *__restrict__ omega,
+    int32_t *__restrict__ ecnt,
     int32_t *__restrict__ eidx, int slots, int64_t *__restrict__ status)
 {
     const int lane = threadIdx.x & (SPH_MGROUP - 1);
@@ -211,7 +213,7 @@ __global__ __launch_bounds__(SPH_BLOCK) SPH_PAIR_WAVES_D void k_density_mixed(
     const MixGeo G = mix_geo(bbox, g);
     for (int rr = 0; rr < SPH_MGROUP; ++rr) {   // SPH_BLOCK / SPH_MGROUP groups, SPH_MGROUP rounds
         const int64_t i = base + (int64_t)rr * (SPH_BLOCK / SPH_MGROUP) + grp;
-        NeuF s = {0.0f, 0.0f}, dv = {0.0f, 0.0f};
+        NeuF s = {0.0f, 0.0f}, dv = {0.0f, 0.0f}, t = {0.0f, 0.0f};
         float4 ai = make_float4(0.f, 0.f, 0.f, 0.f), bi = ai;
         float inv_h = 0.0f;
         if (i < n) {
@@ -272,25 +274,33 @@ __global__ __launch_bounds__(SPH_BLOCK) SPH_PAIR_WAVES_D void k_density_mixed(
                     }
                     float r = sqrtf(r2);
                     const float mj = bj.w;
-                    neu_add(s, mj * kern_w_f<KER>(r, inv_h, knorm));
+                    const float wk = kern_w_f<KER>(r, inv_h, knorm);
+                    neu_add(s, mj * wk);
                     if (r > 0.0f) {
-                        float gw = kern_dwdr_f<KER>(r, inv_h, knorm) / r;
+                        const float dw = kern_dwdr_f<KER>(r, inv_h, knorm);
+                        float gw = dw / r;
                         float vdot = (bj.x - bi.x) * (-dx) + (bj.y - bi.y) * (-dy) +
                                      (bj.z - bi.z) * (-dz);
                         neu_add(dv, mj * vdot * gw);
+                        if (GH) neu_add(t, mj * (3.0f * wk + r * dw));
+                    } else if (GH) {
+                        neu_add(t, mj * 3.0f * wk);
                     }
                 }
             }
         }
         s = mgroup_neu(s);
         dv = mgroup_neu(dv);
+        if (GH) t = mgroup_neu(t);
         if (i < n && lane == 0) {
-            NeuF tot = {bi.w * kern_w_f<KER>(0.0f, inv_h, knorm), 0.0f};
+            const float w0 = kern_w_f<KER>(0.0f, inv_h, knorm);
+            NeuF tot = {bi.w * w0, 0.0f};
             neu_add(tot, s.s);
             tot.c += s.c;
             const double sd = neu_val(tot);
             rho[i] = sd;
             divv[i] = neu_val(dv) / sd;
+            if (GH) omega[i] = 1.0 - (3.0 * (double)(bi.w * w0) + neu_val(t)) / (3.0 * sd);
         }
     }
     if (EXTRA) {
@@ -302,6 +312,7 @@ __global__ __launch_bounds__(SPH_BLOCK) SPH_PAIR_WAVES_D void k_density_mixed(
 // EOS in FP64 (as the plain form) and the FP32 force fields of the record
 __global__ __launch_bounds__(SPH_BLOCK) void k_eos_mixed(int64_t n, const double *__restrict__ rho,
                                                          const double *__restrict__ u, double gamma,
+                                                         const double *__restrict__ omega,
                                                          double *__restrict__ p,
                                                          double *__restrict__ c,
                                                          MixQ Q, int check,
@@ -317,7 +328,7 @@ __global__ __launch_bounds__(SPH_BLOCK) void k_eos_mixed(int64_t n, const double
         c[i] = cv;
         Q.C[i].y = (float)cv;
         Q.C[i].z = (float)rh;
-        Q.C[i].w = (float)(pv / (rh * rh));
+        Q.C[i].w = (float)(pv / (omega ? omega[i] * (rh * rh) : rh * rh));   // P / (Omega rho^2)
         if (check && !(isfinite(pv) && isfinite(cv) && isfinite(rh))) bad = 1;
     }
     if (check) block_add_i64(bad, status + ST_NONFINITE);
@@ -336,7 +347,8 @@ struct QuadF {
     float4 a, b, c;
 };
 
-template <int PM, int KER>
+// GH: pressure terms with each particle's own gradient (grad-h form)
+template <int PM, int KER, bool GH>
 __device__ __forceinline__ void force_pair_f(const QuadF &ri, float inv_hi, uint32_t gi,
                                              const QuadF &rj, const MixGeo &G, float knorm,
                                              float alpha, float beta, float eta2, ForceAccF &A)
@@ -364,8 +376,16 @@ __device__ __forceinline__ void force_pair_f(const QuadF &ri, float inv_hi, uint
         Pi = (-alpha * cb * mu + beta * mu * mu) / rb;
         A.mumax = fmaxf(A.mumax, fabsf(mu));
     }
-    float sfac = (ri.c.w + rj.c.w) + Pi;
     float mj = rj.b.w;
+    if (GH) {
+        float f = mj * ((ri.c.w * gwi + rj.c.w * gwj) + Pi * gbar);
+        neu_add(A.ax, -f * xij);
+        neu_add(A.ay, -f * yij);
+        neu_add(A.az, -f * zij);
+        neu_add(A.du, mj * (ri.c.w * gwi + 0.5f * Pi * gbar) * w);
+        return;
+    }
+    float sfac = (ri.c.w + rj.c.w) + Pi;
     float f = mj * sfac * gbar;
     neu_add(A.ax, -f * xij);
     neu_add(A.ay, -f * yij);
@@ -375,7 +395,7 @@ __device__ __forceinline__ void force_pair_f(const QuadF &ri, float inv_hi, uint
 
 // S_i = L_i (row order) then E_i (ascending), SPH_MGROUP lanes per particle;
 // ELDS: E rows ranked in LDS here (capacity <= SPH_ELDS), else sorted already
-template <int PM, bool ELDS, int KER>
+template <int PM, bool ELDS, int KER, bool GH>
 __global__ __launch_bounds__(SPH_BLOCK) SPH_PAIR_WAVES_F void k_forces_mixed(
     int64_t n, MixQ Q, const int32_t *__restrict__ nc, const int32_t *__restrict__ idx, int K,
     const int32_t *__restrict__ ecnt, const int32_t *__restrict__ eidx, int slots,
@@ -423,7 +443,7 @@ __global__ __launch_bounds__(SPH_BLOCK) SPH_PAIR_WAVES_F void k_forces_mixed(
 #pragma unroll
                 for (int q = 0; q < SPH_MFBATCH; ++q) {
                     if (k0 + q * SPH_MGROUP >= tot) break;
-                    force_pair_f<PM, KER>(ri, inv_hi, gi, rb[q], G, knorm, alpha, beta, eta2, A);
+                    force_pair_f<PM, KER, GH>(ri, inv_hi, gi, rb[q], G, knorm, alpha, beta, eta2, A);
                 }
             }
         }
@@ -489,14 +509,21 @@ hipError_t launch_density_mixed(sph_ctx *c, sph_particles *s, const sph_nlist *n
 #define SPH_DENSITY_ARGS                                                                      \
     dim3(nb), dim3(SPH_BLOCK), 0, c->stream, n, Q, s->nc[cur], nl->idx, c->p.list_stride,      \
         c->w.bbox, g, (float)c->knorm, s->x[cur], s->y[cur], s->z[cur], s->h[cur], s->rho[cur], \
-        s->divv[cur], nl->ecnt, nl->eidx, c->p.extra_slots, c->w.status
-    if (build_extra) {
-        SPH_DISPATCH_KER(c->p.kernel, SPH_DISPATCH_PM(periodic_mask(g),
-            hipLaunchKernelGGL((k_density_mixed<PM, true, KER>), SPH_DENSITY_ARGS)))
-    } else {
-        SPH_DISPATCH_KER(c->p.kernel, SPH_DISPATCH_PM(periodic_mask(g),
-            hipLaunchKernelGGL((k_density_mixed<PM, false, KER>), SPH_DENSITY_ARGS)))
+        s->divv[cur], c->w.omega, nl->ecnt, nl->eidx, c->p.extra_slots, c->w.status
+#define SPH_DENSITY_GH(GHV)                                                                   \
+    if (build_extra) {                                                                        \
+        SPH_DISPATCH_KER(c->p.kernel, SPH_DISPATCH_PM(periodic_mask(g),                       \
+            hipLaunchKernelGGL((k_density_mixed<PM, true, KER, GHV>), SPH_DENSITY_ARGS)))     \
+    } else {                                                                                  \
+        SPH_DISPATCH_KER(c->p.kernel, SPH_DISPATCH_PM(periodic_mask(g),                       \
+            hipLaunchKernelGGL((k_density_mixed<PM, false, KER, GHV>), SPH_DENSITY_ARGS)))    \
     }
+    if (c->p.grad_h) {
+        SPH_DENSITY_GH(true)
+    } else {
+        SPH_DENSITY_GH(false)
+    }
+#undef SPH_DENSITY_GH
 #undef SPH_DENSITY_ARGS
     return hipGetLastError();
 }
@@ -506,8 +533,9 @@ hipError_t launch_eos_mixed(sph_ctx *c, sph_particles *s)
     int64_t n = s->n;
     if (n == 0) return hipSuccess;
     hipLaunchKernelGGL(k_eos_mixed, dim3((unsigned)ceil_div(n, SPH_BLOCK)), dim3(SPH_BLOCK), 0,
-                       c->stream, n, s->rho[s->cur], s->pu, c->p.gamma, s->p, s->c,
-                       ctx_quads(c), c->p.check_finite, c->w.status);
+                       c->stream, n, s->rho[s->cur], s->pu, c->p.gamma,
+                       c->p.grad_h ? c->w.omega : nullptr, s->p, s->c, ctx_quads(c),
+                       c->p.check_finite, c->w.status);
     return hipGetLastError();
 }
 
@@ -523,15 +551,25 @@ hipError_t launch_forces_mixed(sph_ctx *c, sph_particles *s, const sph_nlist *nl
         p.list_stride, nl->ecnt, nl->eidx, p.extra_slots, c->w.bbox, g, (float)c->knorm,       \
         (float)p.av_alpha, (float)p.av_beta, (float)p.av_eta2, p.av_alpha, p.av_beta, p.cfl,   \
         s->h[cur], s->c, s->ax[cur], s->ay[cur], s->az[cur], s->du[cur], c->w.red_part
-    if (p.extra_slots <= SPH_ELDS) {
-        SPH_DISPATCH_KER(p.kernel, SPH_DISPATCH_PM(periodic_mask(g),
-            hipLaunchKernelGGL((k_forces_mixed<PM, true, KER>), SPH_FORCE_ARGS)))
-    } else {
+    if (p.extra_slots > SPH_ELDS) {
         hipError_t e = launch_sort_extra(c, nl, n);
         if (e != hipSuccess) return e;
-        SPH_DISPATCH_KER(p.kernel, SPH_DISPATCH_PM(periodic_mask(g),
-            hipLaunchKernelGGL((k_forces_mixed<PM, false, KER>), SPH_FORCE_ARGS)))
     }
+    const bool elds = p.extra_slots <= SPH_ELDS;
+#define SPH_FORCE_GH(GHV)                                                                     \
+    if (elds) {                                                                               \
+        SPH_DISPATCH_KER(p.kernel, SPH_DISPATCH_PM(periodic_mask(g),                          \
+            hipLaunchKernelGGL((k_forces_mixed<PM, true, KER, GHV>), SPH_FORCE_ARGS)))        \
+    } else {                                                                                  \
+        SPH_DISPATCH_KER(p.kernel, SPH_DISPATCH_PM(periodic_mask(g),                          \
+            hipLaunchKernelGGL((k_forces_mixed<PM, false, KER, GHV>), SPH_FORCE_ARGS)))       \
+    }
+    if (p.grad_h) {
+        SPH_FORCE_GH(true)
+    } else {
+        SPH_FORCE_GH(false)
+    }
+#undef SPH_FORCE_GH
 #undef SPH_FORCE_ARGS
     return hipGetLastError();
 }

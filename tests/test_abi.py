@@ -68,7 +68,7 @@ def test_params_validation(lib):
         ffi.sph_create(bad)
     assert "walk_prefilter" in str(e.value)
     assert p.grad_h == 0
-    for gh, prec in ((2, ffi.SPH_FP64), (1, ffi.SPH_MIXED)):
+    for gh, prec in ((2, ffi.SPH_FP64), (-1, ffi.SPH_MIXED)):
         bad = ffi.default_params()
         bad.grad_h = gh
         bad.precision = prec

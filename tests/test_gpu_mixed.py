@@ -79,6 +79,33 @@ def test_mixed_kernel_variants(kernel):
     check_mixed_fields(sim, st)
 
 
+@pytest.mark.parametrize("case", ["patch_23^3_ragged", "clumpy_12k"])
+def test_mixed_grad_h(case):
+    """Grad-h terms in the mixed form: Omega (its sum of about two in units
+    of 3 rho, so 5e-5 absolute), the fields, and a step."""
+    from test_gpu_parity import _upload_oracle_state, compare_cells, compare_neighbors
+    ic = CASES[case]()
+    print(f"mixed grad-h case {case} n={ic.n}", flush=True)
+    st = O.State(ic.copy(), O.Params(grad_h=True))
+    st.keep_gather = True
+    st.evaluate(method=1)
+    sim = _sim(ic, extra_per_particle=96, grad_h=True)
+    sim.evaluate()
+    sim.sync()
+    compare_cells(sim, st)
+    compare_neighbors(sim, st)
+    check_mixed_fields(sim, st)
+    assert np.max(np.abs(sim.omega() - st.omega)) <= 5 * TOL
+    _upload_oracle_state(sim, st)
+    dt = st.dt_next
+    st.step(dt, method=1)
+    sim.step(dt)
+    sim.sync()
+    compare_cells(sim, st)
+    compare_neighbors(sim, st)
+    check_mixed_fields(sim, st)
+
+
 def test_mixed_step_parity():
     from test_gpu_parity import _upload_oracle_state, compare_cells, compare_neighbors
     ic = inputs.square_patch(20, inputs.CONFIG_SEEDS[1])
