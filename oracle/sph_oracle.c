@@ -27,7 +27,10 @@
  *     1983, same section), energy equation and a Courant time step;
  *   - kick-drift-kick leapfrog update and conservation sums (Neumaier);
  *     the paper's own energy update (second-order Adams-Bashforth) as the
- *     alternative integrator, positions and velocities as in KDK.
+ *     alternative integrator, positions and velocities as in KDK;
+ *   - accuracy variants of the momentum and energy sums: grad-h factors
+ *     (Springel & Hernquist 2002) and IAD gradients (Table 1; Garcia-Senz,
+ *     Cabezon & Escartin 2012).
  *   - the learned smoothing-length MLP (6-64-64-1, tanh, bf16 operands)
  *     forward, analytic backward and Adam, in FP64 on bf16-rounded operands.
  *

@@ -2,7 +2,8 @@
 configuration bench.py times.
 
 * 1,000,000-particle patch: the whole state against the oracle, at t = 0 and
-  after one step at the Courant dt (plain FP64), and the mixed form at t = 0.
+  after one step at the Courant dt (plain FP64), the mixed form at t = 0, and
+  the IAD gradients with grad-h factors at t = 0.
 * 8,000,000 (mixed form) and 64,000,000 (plain FP64 and mixed): sampled
   outputs.  The oracle evaluates a cube of the patch at the GPU's own
   smoothing lengths and compares the particles at least 4 h_max inside it
@@ -55,6 +56,26 @@ def test_patch_1M_evaluate_and_step():
     compare_cells(sim, st)
     compare_neighbors(sim, st)
     compare_fields(sim, st)
+
+
+def test_patch_1M_grad_h_iad_evaluate():
+    """The accuracy variants at the benchmark size: IAD gradients with the
+    grad-h factors (FP64), the whole state at t = 0 against the oracle."""
+    from paper_1905_03344_amd import ffi
+    from test_gpu_parity import compare_cells, compare_fields, compare_neighbors
+    ic = inputs.config_ic(2)
+    print("1M IAD + grad-h: oracle evaluate", flush=True)
+    st = O.State(ic.copy(), O.Params(grad_h=True, gradients=O.GRADIENTS_IAD))
+    st.keep_gather = True
+    st.evaluate(method=1)
+    print("1M IAD + grad-h: gpu evaluate", flush=True)
+    sim = _sim(ic, grad_h=True, gradients=ffi.SPH_GRADIENTS_IAD)
+    sim.evaluate()
+    sim.sync()
+    compare_cells(sim, st)
+    compare_neighbors(sim, st)
+    compare_fields(sim, st)
+    assert np.max(np.abs(sim.omega() - st.omega)) <= 10 * TOL
 
 
 def test_patch_1M_mixed_evaluate():
