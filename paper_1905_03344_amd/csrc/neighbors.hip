@@ -458,9 +458,11 @@ struct Shell {
 
 // Sub-groups of at most this many particles are counted one particle at a
 // time with the candidates spread over the lanes (transposed mode); larger
-// ones stream their union box through LDS tiles that every member tests.
+// ones stream their union box through LDS tiles that every member tests
+// (4 with SPH_SPLIT_H 3: measured best of 4, 6, 8, 16 on the jittered
+// lattice; 16 suits the clumpy mixture alone)
 #ifndef SPH_SMALL_GROUP
-#define SPH_SMALL_GROUP 8
+#define SPH_SMALL_GROUP 4
 #endif
 // a group is split by Morton prefix while its positions spread over more than
 // this many search diameters (3: measured best of 1.5, 2, 3, 5)
@@ -468,9 +470,10 @@ struct Shell {
 #define SPH_SPLIT_SPREAD 3.0
 #endif
 // lanes whose search radius exceeds this multiple of the group's smallest
-// form a later group (2: measured best of 1.5, 2, 3 and no split)
+// form a later group (3: measured best of 1.5, 2, 3, 4, 6 with the matrix-core
+// candidate test; the clumpy mixture gains 7%, the lattice is indifferent)
 #ifndef SPH_SPLIT_H
-#define SPH_SPLIT_H 2.0
+#define SPH_SPLIT_H 3.0
 #endif
 
 // exact r^2 between a lane's particle and candidate coordinates (the same
