@@ -344,6 +344,36 @@ def test_iad_parity(case, variant):
     compare_fields(sim, st)
 
 
+def test_all_options_two_steps():
+    """Every option at once -- Wendland kernel, IAD gradients, grad-h
+    factors, the Adams-Bashforth energy update, no walk prefilter -- for two
+    steps with different dt, each from the oracle's state."""
+    from paper_1905_03344_amd import ffi
+    ic = CASES["clumpy_12k"]()
+    print(f"all options n={ic.n}", flush=True)
+    st = O.State(ic.copy(), O.Params(kernel=O.KERNEL_WENDLAND, grad_h=True,
+                                     gradients=O.GRADIENTS_IAD, integrator=O.INTEGRATOR_AB2))
+    st.keep_gather = True
+    st.evaluate(method=1)
+    sim = _sim(ic, extra_per_particle=96, kernel=ffi.SPH_KERNEL_WENDLAND, grad_h=True,
+               gradients=ffi.SPH_GRADIENTS_IAD, integrator=ffi.SPH_INTEGRATOR_AB2,
+               walk_prefilter=ffi.SPH_PREFILTER_NONE)
+    sim.evaluate()
+    sim.sync()
+    compare_fields(sim, st)
+    for k, dt in enumerate((0.5 * st.dt_next, 0.8 * st.dt_next)):
+        _upload_oracle_state(sim, st)
+        st.step(dt, method=1)
+        sim.step(dt)
+        sim.sync()
+        compare_cells(sim, st)
+        compare_neighbors(sim, st)
+        compare_fields(sim, st)
+        for f in ("vx", "vy", "vz", "u"):
+            scale = np.max(np.abs(st.f[f]))
+            assert np.max(np.abs(sim.numpy(f) - st.f[f])) <= TOL * scale, (k, f)
+
+
 def test_iad_singular_matrices_reported():
     """Two flat layers far apart (a three-dimensional box, but every
     neighbourhood lies in one plane): every IAD moment matrix is singular,
