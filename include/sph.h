@@ -95,7 +95,8 @@ typedef struct sph_ctx sph_ctx;
  * matrix over its gather set,
  *   tau_i = sum_{j in L_i} (m_j/rho_j) d_ij d_ij^T W(r_ij,h_i),  d_ij = x_j - x_i,
  * its inverse c_i, and grad_i W(r,h_i) replaced by A_i = c_i d_ij W(r_ij,h_i),
- * grad_i W(r,h_j) by A_j = c_j d_ij W(r_ij,h_j).  SPH_FP64 form only. */
+ * grad_i W(r,h_j) by A_j = c_j d_ij W(r_ij,h_j).  In the mixed form tau is a
+ * compensated FP32 sum, inverted in FP64 and used in FP32. */
 #define SPH_GRADIENTS_KERNEL 0
 #define SPH_GRADIENTS_IAD 1
 

@@ -137,8 +137,6 @@ static const char *validate(const sph_params *p)
     if (p->grad_h != 0 && p->grad_h != 1) return "grad_h must be 0 or 1";
     if (p->gradients != SPH_GRADIENTS_KERNEL && p->gradients != SPH_GRADIENTS_IAD)
         return "gradients must be SPH_GRADIENTS_KERNEL or SPH_GRADIENTS_IAD";
-    if (p->gradients == SPH_GRADIENTS_IAD && p->precision != SPH_FP64)
-        return "IAD gradients need precision SPH_FP64";
     if (p->walk_prefilter != SPH_PREFILTER_NONE && p->walk_prefilter != SPH_PREFILTER_MATRIX)
         return "walk_prefilter must be SPH_PREFILTER_NONE or SPH_PREFILTER_MATRIX";
     if (!(p->gamma > 1.0)) return "gamma must exceed 1";

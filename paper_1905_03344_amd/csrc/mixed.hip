@@ -14,7 +14,7 @@
 // with x = lo + g * w + delta, w = L/1024 the key-cell width.  1/h of a
 // neighbour is formed in the pair (hardware reciprocal, 1 ulp).
 struct MixQ {
-    float4 *A, *B, *C, *D;   // D: unused fourth quad of the 64-byte record
+    float4 *A, *B, *C, *D;   // D: IAD (c_xx, c_xy, c_xz, c_yy), else unused
 };
 __host__ __device__ static inline MixQ mix_quads(void *base, int64_t n_max)
 {
@@ -342,13 +342,17 @@ struct ForceAccF {
     float mumax;
 };
 
-// own fields of particle i (a, b, c) and the gathered fields of j
+// own fields of particle i (a, b, c) and the gathered fields of j; d, e:
+// the IAD matrix when gradients are IAD
 struct QuadF {
-    float4 a, b, c;
+    float4 a, b, c, d;
+    float2 e;
 };
 
-// GH: pressure terms with each particle's own gradient (grad-h form)
-template <int PM, int KER, bool GH>
+// GR: 0 averaged kernel gradient; 1 pressure terms with each particle's own
+// kernel gradient (grad-h form); 2 pressure terms with each particle's own
+// IAD gradient A = c d W, the viscosity with their mean
+template <int PM, int KER, int GR>
 __device__ __forceinline__ void force_pair_f(const QuadF &ri, float inv_hi, uint32_t gi,
                                              const QuadF &rj, const MixGeo &G, float knorm,
                                              float alpha, float beta, float eta2, ForceAccF &A)
@@ -364,6 +368,34 @@ __device__ __forceinline__ void force_pair_f(const QuadF &ri, float inv_hi, uint
     float xij = -dx, yij = -dy, zij = -dz;
     float vxij = ri.b.x - rj.b.x, vyij = ri.b.y - rj.b.y, vzij = ri.b.z - rj.b.z;
     float w = vxij * xij + vyij * yij + vzij * zij;
+    if (GR == 2) {
+        float Pi = 0.0f;
+        if (w < 0.0f) {
+            float hb = 0.5f * (ri.c.x + rj.c.x);
+            float cb = 0.5f * (ri.c.y + rj.c.y);
+            float rb = 0.5f * (ri.c.z + rj.c.z);
+            float mu = hb * w / (r2 + eta2 * hb * hb);
+            Pi = (-alpha * cb * mu + beta * mu * mu) / rb;
+            A.mumax = fmaxf(A.mumax, fabsf(mu));
+        }
+        const float wi = kern_w_f<KER>(r, inv_hi, knorm);
+        const float wj = kern_w_f<KER>(r, __builtin_amdgcn_rcpf(rj.c.x), knorm);
+        // A = c d W with d = x_j - x_i = (dx, dy, dz); c = (d.x d.y d.z d.w e.x e.y)
+        const float aix = (ri.d.x * dx + ri.d.y * dy + ri.d.z * dz) * wi;
+        const float aiy = (ri.d.y * dx + ri.d.w * dy + ri.e.x * dz) * wi;
+        const float aiz = (ri.d.z * dx + ri.e.x * dy + ri.e.y * dz) * wi;
+        const float ajx = (rj.d.x * dx + rj.d.y * dy + rj.d.z * dz) * wj;
+        const float ajy = (rj.d.y * dx + rj.d.w * dy + rj.e.x * dz) * wj;
+        const float ajz = (rj.d.z * dx + rj.e.x * dy + rj.e.y * dz) * wj;
+        const float abx = 0.5f * (aix + ajx), aby = 0.5f * (aiy + ajy), abz = 0.5f * (aiz + ajz);
+        const float mj = rj.b.w, pi_t = ri.c.w, pj_t = rj.c.w;
+        neu_add(A.ax, -mj * ((pi_t * aix + pj_t * ajx) + Pi * abx));
+        neu_add(A.ay, -mj * ((pi_t * aiy + pj_t * ajy) + Pi * aby));
+        neu_add(A.az, -mj * ((pi_t * aiz + pj_t * ajz) + Pi * abz));
+        neu_add(A.du, mj * (pi_t * (vxij * aix + vyij * aiy + vzij * aiz) +
+                            0.5f * Pi * (vxij * abx + vyij * aby + vzij * abz)));
+        return;
+    }
     float gwi = kern_dwdr_f<KER>(r, inv_hi, knorm) * inv_r;
     float gwj = kern_dwdr_f<KER>(r, __builtin_amdgcn_rcpf(rj.c.x), knorm) * inv_r;
     float gbar = 0.5f * (gwi + gwj);
@@ -377,7 +409,7 @@ __device__ __forceinline__ void force_pair_f(const QuadF &ri, float inv_hi, uint
         A.mumax = fmaxf(A.mumax, fabsf(mu));
     }
     float mj = rj.b.w;
-    if (GH) {
+    if (GR == 1) {
         float f = mj * ((ri.c.w * gwi + rj.c.w * gwj) + Pi * gbar);
         neu_add(A.ax, -f * xij);
         neu_add(A.ay, -f * yij);
@@ -395,9 +427,9 @@ __device__ __forceinline__ void force_pair_f(const QuadF &ri, float inv_hi, uint
 
 // S_i = L_i (row order) then E_i (ascending), SPH_MGROUP lanes per particle;
 // ELDS: E rows ranked in LDS here (capacity <= SPH_ELDS), else sorted already
-template <int PM, bool ELDS, int KER, bool GH>
+template <int PM, bool ELDS, int KER, int GR>
 __global__ __launch_bounds__(SPH_BLOCK) SPH_PAIR_WAVES_F void k_forces_mixed(
-    int64_t n, MixQ Q, const int32_t *__restrict__ nc, const int32_t *__restrict__ idx, int K,
+    int64_t n, MixQ Q, const float2 *__restrict__ qe, const int32_t *__restrict__ nc, const int32_t *__restrict__ idx, int K,
     const int32_t *__restrict__ ecnt, const int32_t *__restrict__ eidx, int slots,
     const double *__restrict__ bbox, Geo g, float knorm, float alpha, float beta, float eta2,
     double alpha_d,
@@ -419,6 +451,7 @@ __global__ __launch_bounds__(SPH_BLOCK) SPH_PAIR_WAVES_F void k_forces_mixed(
         if (i < n) {
             QuadF ri;
             ri.a = Q.A[i]; ri.b = Q.B[i]; ri.c = Q.C[i];
+            if (GR == 2) { ri.d = Q.D[i]; ri.e = qe[i]; }
             const float inv_hi = (float)(1.0 / h[i]);
             const uint32_t gi = cell_of(ri.a);
             const int cnt = min(nc[i], K);
@@ -439,11 +472,12 @@ __global__ __launch_bounds__(SPH_BLOCK) SPH_PAIR_WAVES_F void k_forces_mixed(
 #pragma unroll
                 for (int q = 0; q < SPH_MFBATCH; ++q) {
                     rb[q].a = Q.A[jb[q]]; rb[q].b = Q.B[jb[q]]; rb[q].c = Q.C[jb[q]];
+                    if (GR == 2) { rb[q].d = Q.D[jb[q]]; rb[q].e = qe[jb[q]]; }
                 }
 #pragma unroll
                 for (int q = 0; q < SPH_MFBATCH; ++q) {
                     if (k0 + q * SPH_MGROUP >= tot) break;
-                    force_pair_f<PM, KER, GH>(ri, inv_hi, gi, rb[q], G, knorm, alpha, beta, eta2, A);
+                    force_pair_f<PM, KER, GR>(ri, inv_hi, gi, rb[q], G, knorm, alpha, beta, eta2, A);
                 }
             }
         }
@@ -539,6 +573,94 @@ hipError_t launch_eos_mixed(sph_ctx *c, sph_particles *s)
     return hipGetLastError();
 }
 
+// IAD moment matrix in FP32 with compensated sums (SPH_MGROUP lanes per
+// particle over its gather set), inverted in FP64 by adjugate over
+// determinant, stored as floats: (xx, xy, xz, yy) in the D quad, (yz, zz) in qe
+template <int PM, int KER>
+__global__ __launch_bounds__(SPH_BLOCK) SPH_PAIR_WAVES_D void k_iad_mixed(
+    int64_t n, MixQ Q, float2 *__restrict__ qe, const int32_t *__restrict__ nc,
+    const int32_t *__restrict__ idx, int K, const double *__restrict__ bbox, Geo g, float knorm,
+    const double *__restrict__ h, int64_t *__restrict__ status)
+{
+    const int lane = threadIdx.x & (SPH_MGROUP - 1);
+    const int grp = threadIdx.x / SPH_MGROUP;
+    const int64_t base = (int64_t)xcd_block(blockIdx.x, gridDim.x) * SPH_BLOCK;
+    const MixGeo G = mix_geo(bbox, g);
+    int64_t bad = 0;
+    for (int rr = 0; rr < SPH_MGROUP; ++rr) {
+        const int64_t i = base + (int64_t)rr * (SPH_BLOCK / SPH_MGROUP) + grp;
+        NeuF t[6] = {{0.f, 0.f}, {0.f, 0.f}, {0.f, 0.f}, {0.f, 0.f}, {0.f, 0.f}, {0.f, 0.f}};
+        if (i < n) {
+            const float4 ai = Q.A[i];
+            const float inv_h = (float)(1.0 / h[i]);
+            const uint32_t gi = cell_of(ai);
+            const int cnt = min(nc[i], K);
+            const int32_t *row = idx + i * (int64_t)K;
+            for (int k0 = lane; k0 < cnt; k0 += SPH_MBATCH * SPH_MGROUP) {
+                int jb[SPH_MBATCH];
+#pragma unroll
+                for (int q = 0; q < SPH_MBATCH; ++q) {
+                    const int k = k0 + q * SPH_MGROUP;
+                    jb[q] = k < cnt ? row[k] : (int)i;
+                }
+                float4 ab[SPH_MBATCH];
+                float mb[SPH_MBATCH], rb[SPH_MBATCH];
+#pragma unroll
+                for (int q = 0; q < SPH_MBATCH; ++q) {
+                    ab[q] = Q.A[jb[q]];
+                    mb[q] = Q.B[jb[q]].w;
+                    rb[q] = Q.C[jb[q]].z;
+                }
+#pragma unroll
+                for (int q = 0; q < SPH_MBATCH; ++q) {
+                    if (k0 + q * SPH_MGROUP >= cnt) break;
+                    const uint32_t gj = cell_of(ab[q]);
+                    const float dx = split_diff<PM, 0>(gi, gj, ai.x, ab[q].x, G);
+                    const float dy = split_diff<PM, 1>(gi, gj, ai.y, ab[q].y, G);
+                    const float dz = split_diff<PM, 2>(gi, gj, ai.z, ab[q].z, G);
+                    const float r = sqrtf(dx * dx + dy * dy + dz * dz);
+                    const float vw = mb[q] / rb[q] * kern_w_f<KER>(r, inv_h, knorm);
+                    neu_add(t[0], vw * dx * dx); neu_add(t[1], vw * dx * dy);
+                    neu_add(t[2], vw * dx * dz); neu_add(t[3], vw * dy * dy);
+                    neu_add(t[4], vw * dy * dz); neu_add(t[5], vw * dz * dz);
+                }
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < 6; ++k) t[k] = mgroup_neu(t[k]);
+        if (i < n && lane == 0) {
+            const double txx = neu_val(t[0]), txy = neu_val(t[1]), txz = neu_val(t[2]);
+            const double tyy = neu_val(t[3]), tyz = neu_val(t[4]), tzz = neu_val(t[5]);
+            const double axx = tyy * tzz - tyz * tyz;
+            const double axy = txz * tyz - txy * tzz;
+            const double axz = txy * tyz - txz * tyy;
+            const double det = txx * axx + txy * axy + txz * axz;
+            if (!(det > 0.0) || !isfinite(det)) ++bad;
+            const double id = 1.0 / det;
+            const double ayy = txx * tzz - txz * txz;
+            const double ayz = txy * txz - txx * tyz;
+            const double azz = txx * tyy - txy * txy;
+            Q.D[i] = make_float4((float)(axx * id), (float)(axy * id), (float)(axz * id),
+                                 (float)(ayy * id));
+            qe[i] = make_float2((float)(ayz * id), (float)(azz * id));
+        }
+    }
+    block_add_i64(bad, status + ST_IAD_SINGULAR);
+}
+
+static hipError_t launch_iad_mixed(sph_ctx *c, sph_particles *s, const sph_nlist *nl)
+{
+    const int64_t n = s->n;
+    if (n == 0) return hipSuccess;
+    Geo g = make_geo(c->p);
+    SPH_DISPATCH_KER(c->p.kernel, SPH_DISPATCH_PM(periodic_mask(g),
+        hipLaunchKernelGGL((k_iad_mixed<PM, KER>), dim3((unsigned)ceil_div(n, SPH_BLOCK)),
+                           dim3(SPH_BLOCK), 0, c->stream, n, ctx_quads(c), (float2 *)c->w.iad,
+                           s->nc[s->cur], nl->idx, c->p.list_stride, c->w.bbox, g,
+                           (float)c->knorm, s->h[s->cur], c->w.status)))
+    return hipGetLastError();
+}
+
 hipError_t launch_forces_mixed(sph_ctx *c, sph_particles *s, const sph_nlist *nl)
 {
     int64_t n = s->n;
@@ -547,7 +669,8 @@ hipError_t launch_forces_mixed(sph_ctx *c, sph_particles *s, const sph_nlist *nl
     int64_t nb = ceil_div(n > 0 ? n : 1, SPH_BLOCK);
     Geo g = make_geo(p);
 #define SPH_FORCE_ARGS                                                                        \
-    dim3((unsigned)nb), dim3(SPH_BLOCK), 0, c->stream, n, ctx_quads(c), s->nc[cur], nl->idx,   \
+    dim3((unsigned)nb), dim3(SPH_BLOCK), 0, c->stream, n, ctx_quads(c), (const float2 *)c->w.iad, \
+        s->nc[cur], nl->idx,                                                                   \
         p.list_stride, nl->ecnt, nl->eidx, p.extra_slots, c->w.bbox, g, (float)c->knorm,       \
         (float)p.av_alpha, (float)p.av_beta, (float)p.av_eta2, p.av_alpha, p.av_beta, p.cfl,   \
         s->h[cur], s->c, s->ax[cur], s->ay[cur], s->az[cur], s->du[cur], c->w.red_part
@@ -556,20 +679,24 @@ hipError_t launch_forces_mixed(sph_ctx *c, sph_particles *s, const sph_nlist *nl
         if (e != hipSuccess) return e;
     }
     const bool elds = p.extra_slots <= SPH_ELDS;
-#define SPH_FORCE_GH(GHV)                                                                     \
+#define SPH_FORCE_GR(GRV)                                                                     \
     if (elds) {                                                                               \
         SPH_DISPATCH_KER(p.kernel, SPH_DISPATCH_PM(periodic_mask(g),                          \
-            hipLaunchKernelGGL((k_forces_mixed<PM, true, KER, GHV>), SPH_FORCE_ARGS)))        \
+            hipLaunchKernelGGL((k_forces_mixed<PM, true, KER, GRV>), SPH_FORCE_ARGS)))        \
     } else {                                                                                  \
         SPH_DISPATCH_KER(p.kernel, SPH_DISPATCH_PM(periodic_mask(g),                          \
-            hipLaunchKernelGGL((k_forces_mixed<PM, false, KER, GHV>), SPH_FORCE_ARGS)))       \
+            hipLaunchKernelGGL((k_forces_mixed<PM, false, KER, GRV>), SPH_FORCE_ARGS)))       \
     }
-    if (p.grad_h) {
-        SPH_FORCE_GH(true)
+    if (p.gradients == SPH_GRADIENTS_IAD) {
+        hipError_t e = launch_iad_mixed(c, s, nl);
+        if (e != hipSuccess) return e;
+        SPH_FORCE_GR(2)
+    } else if (p.grad_h) {
+        SPH_FORCE_GR(1)
     } else {
-        SPH_FORCE_GH(false)
+        SPH_FORCE_GR(0)
     }
-#undef SPH_FORCE_GH
+#undef SPH_FORCE_GR
 #undef SPH_FORCE_ARGS
     return hipGetLastError();
 }

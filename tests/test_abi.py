@@ -76,7 +76,7 @@ def test_params_validation(lib):
             ffi.sph_create(bad)
         assert "grad_h" in str(e.value)
     assert p.gradients == ffi.SPH_GRADIENTS_KERNEL
-    for gr, prec in ((2, ffi.SPH_FP64), (ffi.SPH_GRADIENTS_IAD, ffi.SPH_MIXED)):
+    for gr, prec in ((2, ffi.SPH_FP64), (-1, ffi.SPH_MIXED)):
         bad = ffi.default_params()
         bad.gradients = gr
         bad.precision = prec

@@ -106,6 +106,36 @@ def test_mixed_grad_h(case):
     check_mixed_fields(sim, st)
 
 
+@pytest.mark.parametrize("variant", ["iad", "iad+grad_h"])
+@pytest.mark.parametrize("case", ["patch_23^3_ragged", "clumpy_12k"])
+def test_mixed_iad(case, variant):
+    """IAD gradients in the mixed form (FP32 moment sums, FP64 inverse, FP32
+    pair terms): the fields and a step against the oracle."""
+    from paper_1905_03344_amd import ffi
+    from test_gpu_parity import _upload_oracle_state, compare_cells, compare_neighbors
+    gh = variant == "iad+grad_h"
+    ic = CASES[case]()
+    print(f"mixed {variant} case {case} n={ic.n}", flush=True)
+    st = O.State(ic.copy(), O.Params(grad_h=gh, gradients=O.GRADIENTS_IAD))
+    st.keep_gather = True
+    st.evaluate(method=1)
+    sim = _sim(ic, extra_per_particle=96, grad_h=gh, gradients=ffi.SPH_GRADIENTS_IAD)
+    sim.evaluate()
+    code, stats = sim.sync()
+    assert stats.iad_singular == 0
+    compare_cells(sim, st)
+    compare_neighbors(sim, st)
+    check_mixed_fields(sim, st)
+    _upload_oracle_state(sim, st)
+    dt = st.dt_next
+    st.step(dt, method=1)
+    sim.step(dt)
+    sim.sync()
+    compare_cells(sim, st)
+    compare_neighbors(sim, st)
+    check_mixed_fields(sim, st)
+
+
 def test_mixed_step_parity():
     from test_gpu_parity import _upload_oracle_state, compare_cells, compare_neighbors
     ic = inputs.square_patch(20, inputs.CONFIG_SEEDS[1])
