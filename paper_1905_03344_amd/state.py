@@ -32,6 +32,16 @@ class Simulation:
                  precision=ffi.SPH_FP64, check_finite=False, h_mode=ffi.SPH_H_PLAIN,
                  walk_prefilter=None, kernel=None, integrator=None, grad_h=False,
                  gradients=None):
+        """Allocate the state and the workspace for ic and bind a context.
+
+        precision: ffi.SPH_FP64 or ffi.SPH_MIXED; h_mode: ffi.SPH_H_PLAIN or
+        ffi.SPH_H_LEARNED (weights via set_mlp); kernel: ffi.SPH_KERNEL_*;
+        integrator: ffi.SPH_INTEGRATOR_KDK or _AB2; grad_h: grad-h correction
+        terms; gradients: ffi.SPH_GRADIENTS_KERNEL or _IAD; walk_prefilter:
+        ffi.SPH_PREFILTER_MATRIX or _NONE.  None keeps the library default.
+        list_stride and extra_per_particle are the capacities of the gather
+        and complement rows; max_level None picks the cell level from the
+        extent and the smallest h."""
         self.device = torch.device(device)
         n = ic.n
         self.n = n
