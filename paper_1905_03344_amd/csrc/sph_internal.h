@@ -268,7 +268,9 @@ __device__ __forceinline__ void wave_lds_sync()
 // depend on the order atomics filled the row).  Rows of up to SPH_ELDS
 // entries are ranked in LDS by the particle's lane group inside the force
 // kernel; with more slots the rows are sorted in memory beforehand.
+#ifndef SPH_ELDS
 #define SPH_ELDS 128
+#endif
 template <int G>
 __device__ __forceinline__ void erow_sort_lds(const int32_t *__restrict__ erow, int ne, int lane,
                                               int32_t *raw, int32_t *srt)
