@@ -105,3 +105,20 @@ def test_unbound_context_rejects_calls(lib):
     assert rc == ffi.SPH_ENOMEM
     assert b"workspace" in lib.sph_last_error(ctx)
     ffi.sph_destroy(ctx)
+
+
+def test_missing_library_fails_loudly():
+    """Without the built library the binding raises; there is no CPU path."""
+    import subprocess
+    import sys
+    code = ("from paper_1905_03344_amd import ffi\n"
+            "ffi.LIB_PATH = '/nonexistent/libsph.so'\n"
+            "ffi._lib = None\n"
+            "try:\n"
+            "    ffi.lib()\n"
+            "except ImportError as e:\n"
+            "    print('raised', e)\n")
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    out = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, cwd=root,
+                         timeout=120)
+    assert out.returncode == 0 and out.stdout.startswith("raised"), out.stdout + out.stderr
