@@ -135,6 +135,9 @@ def main():
                     help="kick-drift-kick, or its positions with Adams-Bashforth energy")
     ap.add_argument("--gradients", default="kernel", choices=["kernel", "iad"],
                     help="gradient estimator of the momentum and energy sums (iad: plain form)")
+    ap.add_argument("--walk-defer-group", type=int, default=None,
+                    help="first-round walk sub-groups up to this size go to the per-particle "
+                         "tail (default: 16 on the clumpy mixture, else the library's 4)")
     ap.add_argument("--grad-h", action="store_true",
                     help="grad-h correction terms in the momentum and energy sums (plain form)")
     ap.add_argument("--kernel", default="m4", choices=["m4", "wendland", "sinc5"],
@@ -164,6 +167,9 @@ def main():
     learned = args.form == "learned"
     # complement rows: the clumpy mixture's density contrast needs more slots
     extra_slots = 96 if args.config == 4 else 48
+    defer = args.walk_defer_group
+    if defer is None:
+        defer = 16 if args.config == 4 else 0
     # the learned form is timed on seed B of the workload after training on
     # 20 plain steps of seed A (the same distribution)
     ic = inputs.config_ic(args.config, seed_offset=100 if learned else 0)
@@ -181,7 +187,8 @@ def main():
         ic_a = inputs.config_ic(args.config)
         tr = Simulation(ic_a, search_div=args.search_div, precision=precision,
                         extra_per_particle=extra_slots, walk_prefilter=prefilter, kernel=kernel,
-                        integrator=integrator, grad_h=args.grad_h, gradients=gradients)
+                        integrator=integrator, grad_h=args.grad_h, gradients=gradients,
+                        walk_defer_group=defer)
         tr.evaluate()
         tr.sync()
         torch.cuda.synchronize()
@@ -209,7 +216,8 @@ def main():
     sim = Simulation(ic, search_div=args.search_div, precision=precision,
                      h_mode=ffi.SPH_H_LEARNED if learned else ffi.SPH_H_PLAIN,
                      extra_per_particle=extra_slots, walk_prefilter=prefilter, kernel=kernel,
-                     integrator=integrator, grad_h=args.grad_h, gradients=gradients)
+                     integrator=integrator, grad_h=args.grad_h, gradients=gradients,
+                     walk_defer_group=defer)
     if learned:
         sim.set_mlp(w, norm)
     log(f"bench: n={n} max_level={sim.params.max_level} workspace={sim.ws_bytes/2**20:.1f} MiB")
@@ -289,7 +297,8 @@ def main():
         "dtype": "f64" if args.form == "plain" else "f32/f64",
         "data": "synthetic",
         "config": {"workload": workload, "n": n, "form": args.form, "dt": "courant cfl 0.3",
-                   "walk_prefilter": args.walk_prefilter, "kernel": args.kernel,
+                   "walk_prefilter": args.walk_prefilter, "walk_defer_group": defer or 4,
+                   "kernel": args.kernel,
                    "integrator": args.integrator, "grad_h": bool(args.grad_h),
                    "gradients": args.gradients},
         "roofline": roofline,

@@ -125,6 +125,11 @@ typedef struct sph_params {
     int32_t search_div;     /* search cells are at least 2h/search_div wide (1..4, default 2) */
     int32_t grad_h;         /* 1 = grad-h correction terms in A9 (default 0) */
     int32_t gradients;      /* SPH_GRADIENTS_KERNEL (default) or SPH_GRADIENTS_IAD */
+    int32_t walk_defer_group; /* first h-iteration round: particles in walk sub-groups of at
+                               * most this many (0 = default 4; 1..64) are counted one per
+                               * wave afterwards; larger suits strongly clustered inputs.
+                               * Sets, h and counts do not depend on it; a gather row may
+                               * come in another order (sums then differ by rounding). */
 } sph_params;
 
 typedef struct sph_particles {

@@ -135,6 +135,8 @@ static const char *validate(const sph_params *p)
     if (p->integrator != SPH_INTEGRATOR_KDK && p->integrator != SPH_INTEGRATOR_AB2)
         return "integrator must be SPH_INTEGRATOR_KDK or SPH_INTEGRATOR_AB2";
     if (p->grad_h != 0 && p->grad_h != 1) return "grad_h must be 0 or 1";
+    if (p->walk_defer_group < 0 || p->walk_defer_group > 64)
+        return "walk_defer_group must be in 0..64";
     if (p->gradients != SPH_GRADIENTS_KERNEL && p->gradients != SPH_GRADIENTS_IAD)
         return "gradients must be SPH_GRADIENTS_KERNEL or SPH_GRADIENTS_IAD";
     if (p->walk_prefilter != SPH_PREFILTER_NONE && p->walk_prefilter != SPH_PREFILTER_MATRIX)

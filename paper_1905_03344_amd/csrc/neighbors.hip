@@ -11,19 +11,21 @@ struct Search {
     int lmax;
     int div;
     int prefilter;   // SPH_PREFILTER_*
+    int defer;       // first round: sub-groups of at most this many go to the tail
     double lo[3], L[3];
     double margin;
     Geo g;
 };
 
 __device__ __forceinline__ Search make_search(const int32_t *cs, int lmax, int div, int prefilter,
-                                              const double *bbox, Geo g)
+                                              int defer, const double *bbox, Geo g)
 {
     Search S;
     S.cs = cs;
     S.lmax = lmax;
     S.div = div;
     S.prefilter = prefilter;
+    S.defer = defer;
     double mx = 0.0;
     for (int d = 0; d < 3; ++d) {
         S.lo[d] = bbox[d];
@@ -463,6 +465,13 @@ struct Shell {
 // lattice; 16 suits the clumpy mixture alone)
 #ifndef SPH_SMALL_GROUP
 #define SPH_SMALL_GROUP 4
+#endif
+// in the all-particle first round, sub-groups of at most this many particles
+// are left to the per-particle tail (one wave per particle) instead; the
+// default of sph_params.walk_defer_group (4: best on the jittered lattice,
+// 16 on the clumpy mixture, whose sparse regions leave many small groups)
+#ifndef SPH_DEFER_GROUP
+#define SPH_DEFER_GROUP 4
 #endif
 // a group is split by Morton prefix while its positions spread over more than
 // this many search diameters (3: measured best of 1.5, 2, 3, 5)
@@ -907,7 +916,7 @@ __device__ int wave_count(WaveLds &L, bool act, int64_t i, double xi, double yi,
             members &= __ballot(((ki ^ lk) >> hb) == 0u);
         }
         pending &= ~members;
-        if (DEFER && __popcll(members) <= SPH_SMALL_GROUP) {
+        if (DEFER && __popcll(members) <= S.defer) {
             if ((members >> lane) & 1ull) *deferred = true;
         } else if (!DEFER && __popcll(members) <= SPH_SMALL_GROUP) {
             uint64_t rest = members;
@@ -1030,7 +1039,7 @@ struct HArgs {
     const double *bbox;
     const double *hk;
     Geo g;
-    int lmax, div, prefilter, target, tol, maxit;
+    int lmax, div, prefilter, defer, target, tol, maxit;
     HIter H;
     Shell SH;
     int64_t *status;
@@ -1123,7 +1132,7 @@ __attribute__((amdgpu_waves_per_eu(SPH_ROUND_WAVES, SPH_ROUND_WAVES))) void k_hs
     // rounds (a learned try that is left behind does not count); one that
     // has used them waits, still listed, for the per-particle tail
     const bool valid = listed && (!wl || (A.H.bits[i] >> 8) < SPH_WAVE_ROUNDS + 1);
-    const Search S = make_search(A.cs, A.lmax, A.div, A.prefilter, A.bbox, A.g);
+    const Search S = make_search(A.cs, A.lmax, A.div, A.prefilter, A.defer, A.bbox, A.g);
 
     // only what the walk needs is live across it; the iteration state is
     // set up (round 0) or loaded (later rounds) afterwards
@@ -1250,7 +1259,7 @@ __global__ __launch_bounds__(SPH_BLOCK) __attribute__((amdgpu_waves_per_eu(2, 2)
     const int64_t gw = (int64_t)blockIdx.x * WAVES_PER_BLOCK + w;
     const int64_t nw = (int64_t)gridDim.x * WAVES_PER_BLOCK;
     const int64_t total = *wcount;
-    const Search S = make_search(A.cs, A.lmax, A.div, A.prefilter, A.bbox, A.g);
+    const Search S = make_search(A.cs, A.lmax, A.div, A.prefilter, A.defer, A.bbox, A.g);
     int64_t counts = 0, tested = 0, nonconv = 0, overflow = 0, acc = 0, fallback = 0;
     for (int64_t t = gw; t < total; t += nw) {
         const int64_t i = wl[t];
@@ -1318,7 +1327,7 @@ __global__ __launch_bounds__(SPH_BLOCK) void k_refill(HArgs A, int64_t n)
     int64_t overflow = 0, tested = 0;
     const bool act = i < n && A.refill[i];
     if (__ballot(act)) {
-        const Search S = make_search(A.cs, A.lmax, A.div, A.prefilter, A.bbox, A.g);
+        const Search S = make_search(A.cs, A.lmax, A.div, A.prefilter, A.defer, A.bbox, A.g);
         double xi = 0.0, yi = 0.0, zi = 0.0, hi = 0.0;
         uint32_t ki = 0;
         if (i < n) {
@@ -1366,6 +1375,7 @@ hipError_t launch_hsolve(sph_ctx *c, sph_particles *s, sph_nlist *nl, const doub
     A.lmax = p.max_level;
     A.div = p.search_div;
     A.prefilter = p.walk_prefilter;
+    A.defer = p.walk_defer_group > 0 ? p.walk_defer_group : SPH_DEFER_GROUP;
     A.target = p.n_target;
     A.tol = p.n_tol;
     A.maxit = p.h_max_iter;

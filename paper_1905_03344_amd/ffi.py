@@ -47,7 +47,7 @@ class sph_params(ctypes.Structure):
                 ("h_max_iter", _I32), ("precision", _I32), ("gamma", _D), ("av_alpha", _D),
                 ("av_beta", _D), ("av_eta2", _D), ("cfl", _D), ("h_mode", _I32),
                 ("check_finite", _I32), ("max_level", _I32), ("search_div", _I32),
-                ("grad_h", _I32), ("gradients", _I32)]
+                ("grad_h", _I32), ("gradients", _I32), ("walk_defer_group", _I32)]
 
 
 CARRIED_F64 = ("x", "y", "z", "vx", "vy", "vz", "m", "h", "u", "ax", "ay", "az", "du", "rho",

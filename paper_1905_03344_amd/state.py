@@ -31,14 +31,16 @@ class Simulation:
                  list_stride=128, extra_per_particle=48, max_level=None, search_div=2,
                  precision=ffi.SPH_FP64, check_finite=False, h_mode=ffi.SPH_H_PLAIN,
                  walk_prefilter=None, kernel=None, integrator=None, grad_h=False,
-                 gradients=None):
+                 gradients=None, walk_defer_group=None):
         """Allocate the state and the workspace for ic and bind a context.
 
         precision: ffi.SPH_FP64 or ffi.SPH_MIXED; h_mode: ffi.SPH_H_PLAIN or
         ffi.SPH_H_LEARNED (weights via set_mlp); kernel: ffi.SPH_KERNEL_*;
         integrator: ffi.SPH_INTEGRATOR_KDK or _AB2; grad_h: grad-h correction
         terms; gradients: ffi.SPH_GRADIENTS_KERNEL or _IAD; walk_prefilter:
-        ffi.SPH_PREFILTER_MATRIX or _NONE.  None keeps the library default.
+        ffi.SPH_PREFILTER_MATRIX or _NONE; walk_defer_group: first-round
+        sub-groups up to this size go to the per-particle tail (speed only).
+        None keeps the library default.
         list_stride and extra_per_particle are the capacities of the gather
         and complement rows; max_level None picks the cell level from the
         extent and the smallest h."""
@@ -70,6 +72,8 @@ class Simulation:
         p.grad_h = int(bool(grad_h))
         if gradients is not None:
             p.gradients = int(gradients)
+        if walk_defer_group is not None:
+            p.walk_defer_group = int(walk_defer_group)
         p.precision = int(precision)
         p.check_finite = int(bool(check_finite))
         p.h_mode = int(h_mode)

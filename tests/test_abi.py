@@ -76,6 +76,12 @@ def test_params_validation(lib):
             ffi.sph_create(bad)
         assert "grad_h" in str(e.value)
     assert p.gradients == ffi.SPH_GRADIENTS_KERNEL
+    assert p.walk_defer_group == 0
+    bad = ffi.default_params()
+    bad.walk_defer_group = 65
+    with pytest.raises(ffi.SphError) as e:
+        ffi.sph_create(bad)
+    assert "walk_defer_group" in str(e.value)
     for gr, prec in ((2, ffi.SPH_FP64), (-1, ffi.SPH_MIXED)):
         bad = ffi.default_params()
         bad.gradients = gr

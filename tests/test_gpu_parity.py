@@ -233,6 +233,7 @@ def test_walk_prefilter_paths(case):
     ic = CASES[case]()
     outs = []
     for pf in (ffi.SPH_PREFILTER_NONE, ffi.SPH_PREFILTER_MATRIX):
+        print(f"walk paths {case} prefilter {pf}", flush=True)
         sim = _sim(ic, extra_per_particle=96, walk_prefilter=pf)
         sim.evaluate()
         sim.step(0.0)
@@ -244,6 +245,33 @@ def test_walk_prefilter_paths(case):
         outs.append(out)
     for f in outs[0]:
         np.testing.assert_array_equal(outs[0][f], outs[1][f], err_msg=f)
+
+
+@pytest.mark.parametrize("defer", [16, 64])
+@pytest.mark.parametrize("case", ["patch_23^3_ragged", "clumpy_12k"])
+def test_walk_defer_group_parity(case, defer):
+    """More of the first round left to the per-particle tail: the same cells,
+    sets, h and counts as the oracle, fields to the usual tolerance (a gather
+    row may come in another order), after an evaluation and a step."""
+    ic = CASES[case]()
+    print(f"walk defer {defer} case {case} n={ic.n}", flush=True)
+    st = O.State(ic.copy())
+    st.keep_gather = True
+    st.evaluate(method=1)
+    sim = _sim(ic, extra_per_particle=96, walk_defer_group=defer)
+    sim.evaluate()
+    sim.sync()
+    compare_cells(sim, st)
+    compare_neighbors(sim, st)
+    compare_fields(sim, st)
+    _upload_oracle_state(sim, st)
+    dt = st.dt_next
+    st.step(dt, method=1)
+    sim.step(dt)
+    sim.sync()
+    compare_cells(sim, st)
+    compare_neighbors(sim, st)
+    compare_fields(sim, st)
 
 
 KERNEL_VARIANTS = ["wendland", "sinc5"]
