@@ -153,7 +153,7 @@ def main():
         return
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the multi-GPU "
-              "decomposition is a design, not part of this build", file=sys.stderr)
+              "decomposition is designed but not implemented", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
