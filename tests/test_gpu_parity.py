@@ -464,11 +464,13 @@ def test_tiny_inputs():
     sim0.sync()
 
 
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
 @pytest.mark.parametrize("variant", ["grad_h", "iad"])
-def test_tiny_inputs_variants(variant):
+def test_tiny_inputs_variants(variant, precision):
     from paper_1905_03344_amd import ffi
     kw = {"grad_h": True} if variant == "grad_h" else {"gradients": ffi.SPH_GRADIENTS_IAD}
-    print(f"tiny inputs {variant}", flush=True)
+    kw["precision"] = ffi.SPH_FP64 if precision == "fp64" else ffi.SPH_MIXED
+    print(f"tiny inputs {variant} {precision}", flush=True)
     ic0 = inputs.square_patch(4, 1).subset(np.array([], dtype=np.int64))
     sim0 = _sim(ic0, **kw)
     sim0.evaluate()
