@@ -187,3 +187,68 @@ def test_state_grad_h_switch_changes_only_forces():
     np.testing.assert_array_equal(s0.f["rho"], s1.f["rho"])
     assert np.all(s1.omega > 0.5) and np.all(s1.omega < 1.5)
     assert not np.array_equal(s0.f["ax"], s1.f["ax"])
+
+
+def test_plain_energy_rate_is_adiabatic_with_unequal_pressures():
+    """The plain (kernel-averaged) energy equation at one common, fixed h:
+    there grad W_bar = grad_i W(r, h), so du_i must equal
+    (P_i / rho_i^2) d rho_i / dt, the first law of an adiabatic gas, with
+    d rho_i / dt a central difference of the brute-force density sum along
+    the velocity field.  Each particle has its own u, so pressures differ
+    pair by pair: taking P_j / rho_j^2 (or a mean) in place of P_i / rho_i^2
+    fails this check."""
+    pos, m = _cloud(seed=11)
+    n = len(m)
+    h = np.full(n, 1.25)
+    rng = np.random.default_rng(17)
+    vel = rng.standard_normal(pos.shape)
+    u = 0.3 + 2.0 * rng.random(n)
+    off, idx = _all_pairs(n)
+    rho, divv = O.density(*pos.T, *vel.T, m, h, (0, 0, 0), (0, 0, 0), (0, 0, 0), off, idx)
+    np.testing.assert_allclose(rho, _rho_of(pos, m, h), rtol=1e-13)
+    P, c = O.eos(rho, u)
+    ratio = P / rho ** 2
+    assert np.max(ratio) > 3.0 * np.min(ratio)
+    ax, ay, az, du, dt_i, amag = O.forces(*pos.T, *vel.T, m, h, rho, P, c, (0, 0, 0), (0, 0, 0),
+                                          (0, 0, 0), off, idx, alpha=0.0, beta=0.0)
+    eps = 1e-6
+    drho = (_rho_of(pos + eps * vel, m, h) - _rho_of(pos - eps * vel, m, h)) / (2 * eps)
+    expect = ratio * drho
+    np.testing.assert_allclose(du, expect, rtol=0, atol=1e-7 * np.max(np.abs(expect)))
+    assert np.max(np.abs(expect)) > 1e-2
+
+
+def test_plain_force_is_energy_gradient_at_fixed_h():
+    """At one common, fixed h the plain momentum equation is the exact
+    gradient of the thermal energy of an adiabatic gas, m_i a_i = -dE/dx_i
+    with E = sum_k m_k K rho_k^(gamma-1) / (gamma-1); densities (hence
+    pressures) differ across the cloud, so both pressure terms are checked
+    pair by pair."""
+    pos, m = _cloud(seed=4)
+    n = len(m)
+    h = np.full(n, 1.25)
+    vel = np.zeros_like(pos)
+    off, idx = _all_pairs(n)
+    rho, _ = O.density(*pos.T, *vel.T, m, h, (0, 0, 0), (0, 0, 0), (0, 0, 0), off, idx)
+    P = K_ADIA * rho ** GAMMA
+    c = np.sqrt(GAMMA * P / rho)
+    assert np.max(P) > 3.0 * np.min(P)
+    ax, ay, az, *_ = O.forces(*pos.T, *vel.T, m, h, rho, P, c, (0, 0, 0), (0, 0, 0), (0, 0, 0),
+                              off, idx, alpha=0.0, beta=0.0)
+    a = np.stack([ax, ay, az], 1)
+
+    def energy(p):
+        r = _rho_of(p, m, h)
+        return np.sum(m * K_ADIA * r ** (GAMMA - 1) / (GAMMA - 1))
+
+    eps = 1e-6
+    rng = np.random.default_rng(2)
+    worst = 0.0
+    for i in rng.choice(n, 16, replace=False):
+        for d in range(3):
+            pp, pm = pos.copy(), pos.copy()
+            pp[i, d] += eps
+            pm[i, d] -= eps
+            g = -(energy(pp) - energy(pm)) / (2 * eps) / m[i]
+            worst = max(worst, abs(a[i, d] - g))
+    assert worst < 1e-6 * np.max(np.abs(a))
