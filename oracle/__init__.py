@@ -153,6 +153,11 @@ def num_threads():
     return lib().or_num_threads()
 
 
+def set_num_threads(n: int):
+    """Thread count of the oracle's later parallel loops (for timing)."""
+    lib().or_set_num_threads(ctypes.c_int(int(n)))
+
+
 # ---------------------------------------------------------------------------
 # geometry: bounding box, keys, sort, cell tables
 # ---------------------------------------------------------------------------

@@ -1069,6 +1069,17 @@ int or_num_threads(void)
 #endif
 }
 
+/* Thread count of the later parallel loops (timing the oracle on one core
+ * and on all of them); n < 1 is ignored. */
+void or_set_num_threads(int n)
+{
+#ifdef _OPENMP
+    if (n >= 1) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
+
 /* ------------------------------------------------------------------------ */
 /* Learned smoothing length: MLP 6 -> 64 -> 64 -> 1, tanh hidden layers.      */
 /* Weights are row-major [out][in].  Operands entering each layer (inputs,   */

@@ -93,17 +93,21 @@ def test_patch_1M_mixed_evaluate():
     check_mixed_fields(sim, st)
 
 
-def _sampled_check(sim, tol, half=0.05):
-    """Oracle on the cube |x|,|y|,|z| < half at the GPU's h, with the
-    velocity and energy the evaluation used; compare the particles 4 h_max
-    inside it.  Selection happens on the device."""
+def _sampled_check(sim, tol, half=0.05, centre=(0.0, 0.0, 0.0)):
+    """Oracle on the cube |x - centre| < half (each coordinate) at the GPU's
+    h, with the velocity and energy the evaluation used; compare the
+    particles 4 h_max inside it.  Selection happens on the device."""
     import torch
-    x, y, z = sim.field("x"), sim.field("y"), sim.field("z")
+    cx, cy, cz = (float(v) for v in centre)
+    x, y, z = sim.field("x") - cx, sim.field("y") - cy, sim.field("z") - cz
     sel = (x.abs() < half) & (y.abs() < half) & (z.abs() < half)
     names = {"x": "x", "y": "y", "z": "z", "vx": "pvx", "vy": "pvy", "vz": "pvz", "m": "m",
              "h": "h", "u": "pu", "rho": "rho", "divv": "divv", "ax": "ax", "ay": "ay",
              "az": "az", "du": "du", "nc": "nc"}
     f = {k: sim.field(v)[sel].cpu().numpy() for k, v in names.items()}
+    f["x"] -= cx
+    f["y"] -= cy
+    f["z"] -= cz
     hmax = float(f["h"].max())
     inner = half - 4.0 * hmax * 1.01
     assert inner > 0, (half, hmax)
@@ -163,18 +167,80 @@ def _properties(sim, momentum_tol):
             assert int(i) in sj
 
 
-@pytest.mark.parametrize("precision", ["mixed"])
+def _h_prev_by_id(sim):
+    """h of the current state indexed by particle id (on the device): the
+    h_prev every particle starts the next step's iteration from."""
+    import torch
+    ids = sim.field("id").long()
+    out = torch.empty(sim.n, dtype=torch.float64, device=sim.device)
+    out[ids] = sim.field("h")
+    return out
+
+
+def _cells_and_h_sampled(sim, h_prev_by_id, half, rng_seed=11):
+    """Cell keys, sort order and smoothing lengths after a step at any size.
+    * bounding box: the exact min/max of x and y, the box in periodic z;
+    * keys of 200,000 sampled particles: the oracle's keys of their
+      positions in that box, bit for bit;
+    * the sort: keys non-decreasing, a permutation, ties in the previous
+      step's storage order (stable);
+    * h: the oracle's iteration from the same h_prev over a cube of the
+      patch, bit for bit (with the counts and the convergence flags) for the
+      particles 4 h_max inside it, whose trial counts see only particles in
+      the cube."""
+    import torch
+    from paper_1905_03344_amd import ffi
+    x, y, z = sim.field("x"), sim.field("y"), sim.field("z")
+    bb = sim.bbox()
+    assert bb[0] == float(x.min()) and bb[3] == float(x.max())
+    assert bb[1] == float(y.min()) and bb[4] == float(y.max())
+    assert bb[2] == sim.params.box_lo[2] and bb[5] == sim.params.box_hi[2]
+    rng = np.random.default_rng(rng_seed)
+    ii = torch.as_tensor(rng.choice(sim.n, min(sim.n, 200_000), replace=False),
+                         device=sim.device)
+    key_ref = O.cell_keys(x[ii].cpu().numpy(), y[ii].cpu().numpy(), z[ii].cpu().numpy(),
+                          bb[:3], bb[3:])
+    key = sim.field("key")[ii].cpu().numpy().view(np.uint32)
+    np.testing.assert_array_equal(key, key_ref)
+    k64 = sim.field("key").long() & 0xFFFFFFFF
+    perm = sim.field("perm").long()
+    assert bool((k64[1:] >= k64[:-1]).all())
+    assert bool((torch.bincount(perm, minlength=sim.n) == 1).all())
+    tie = k64[1:] == k64[:-1]
+    assert bool((perm[1:][tie] > perm[:-1][tie]).all())
+    # h from the same h_prev, on a cube of the patch
+    hprev = h_prev_by_id[sim.field("id").long()]
+    sel = (x.abs() < half) & (y.abs() < half) & (z.abs() < half)
+    f = {k: sim.field(k)[sel].cpu().numpy() for k in ("x", "y", "z", "h", "nc")}
+    f["flags"] = sim.field("flags")[sel].cpu().numpy()
+    hp = hprev[sel].cpu().numpy()
+    per, lo, hi = (0, 0, 0), (-half,) * 3, (half,) * 3
+    h, nc, flag, _, _ = O.hsolve(f["x"], f["y"], f["z"], hp, per, lo, hi)
+    hmax = max(float(f["h"].max()), float(h.max()))
+    inner = half - 4.0 * hmax * 1.01
+    deep = (np.abs(f["x"]) < inner) & (np.abs(f["y"]) < inner) & (np.abs(f["z"]) < inner)
+    assert deep.sum() > 100
+    np.testing.assert_array_equal(f["h"][deep], h[deep])
+    np.testing.assert_array_equal(f["nc"][deep], nc[deep])
+    np.testing.assert_array_equal(f["flags"][deep] & ffi.SPH_FLAG_NOCONV, flag[deep])
+    return int(deep.sum())
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
 def test_patch_8M_sampled(precision):
     from paper_1905_03344_amd import ffi
     ic = inputs.config_ic(3)
-    sim = _sim(ic, precision=ffi.SPH_MIXED)
-    print("8M: gpu evaluate + step", flush=True)
+    prec = ffi.SPH_FP64 if precision == "fp64" else ffi.SPH_MIXED
+    sim = _sim(ic, precision=prec)
+    print(f"8M {precision}: gpu evaluate + step", flush=True)
     sim.evaluate()
+    hp = _h_prev_by_id(sim)
     sim.step(0.0)
     sim.sync()
-    n = _sampled_check(sim, TOL_MIXED)
-    print(f"8M: {n} sampled particles agree", flush=True)
-    _properties(sim, 1e-5)
+    nh = _cells_and_h_sampled(sim, hp, half=0.04)
+    n = _sampled_check(sim, TOL if precision == "fp64" else TOL_MIXED)
+    print(f"8M {precision}: {nh} sampled h and {n} sampled fields agree", flush=True)
+    _properties(sim, 1e-9 if precision == "fp64" else 1e-5)
 
 
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
@@ -186,8 +252,11 @@ def test_patch_64M_sampled(precision):
     del ic
     print(f"64M {precision}: gpu evaluate + step", flush=True)
     sim.evaluate()
+    hp = _h_prev_by_id(sim)
     sim.step(0.0)
     sim.sync()
+    nh = _cells_and_h_sampled(sim, hp, half=0.025)
+    del hp
     n = _sampled_check(sim, TOL if precision == "fp64" else TOL_MIXED, half=0.03)
-    print(f"64M {precision}: {n} sampled particles agree", flush=True)
+    print(f"64M {precision}: {nh} sampled h and {n} sampled fields agree", flush=True)
     _properties(sim, 1e-9 if precision == "fp64" else 1e-5)

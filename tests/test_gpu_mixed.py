@@ -4,10 +4,15 @@ coordinates, compensated FP32 sums) against the FP64 oracle.
 The neighbour search is shared with the FP64 path, so cells, h, counts and
 both neighbour sets must still match bit for bit.  Fields: density within
 1e-5 relative; acceleration, du and divergence within 1e-5 of the oracle's
-sum of term magnitudes per particle (the condition number of each sum).
-The normwise error of the acceleration (max |da| / max |a|) is bounded at
-1e-4: on the rotating patch the net force is a ~100x cancellation of its
-terms, so FP32 rounding of a few ulp per term shows up at ~1e-5 of it."""
+sum of term magnitudes per particle (the condition number of each sum); and
+the acceleration normwise, max_i |a_i - a_i^ref| / max_i |a_i^ref| over the
+vectors, within 1e-5 (measured 2.0e-7 to 2.3e-7 on the patch 20^3, the
+ragged 23^3 patch, the clumpy 12k set and the 1M patch).  A per-component
+normwise bound would not be a measure of the form's accuracy: on the patch,
+periodic in z and uniform at t = 0, a_z is the jitter's residue of terms
+~10^4 times larger, so max |a_z| is tiny and the same FP32 term errors give
+max |da_z| / max |a_z| ~ 1.5e-5 while x and y (where the free surface sets
+the scale) give 2e-7."""
 import numpy as np
 import pytest
 
@@ -17,7 +22,6 @@ from paper_1905_03344_amd import inputs
 pytestmark = pytest.mark.gpu
 
 TOL = 1e-5
-TOL_NORMWISE = 1e-4
 
 
 def _sim(ic, **kw):
@@ -34,7 +38,10 @@ def check_mixed_fields(sim, st):
     for k in ("ax", "ay", "az"):
         d = np.abs(sim.numpy(k) - st.f[k])
         assert np.all(d <= TOL * st.amag), (k, np.max(d / st.amag))
-        assert np.max(d) <= TOL_NORMWISE * np.max(np.abs(st.f[k]))
+    a = np.stack([sim.numpy(k) for k in ("ax", "ay", "az")], 1)
+    ref = np.stack([st.f[k] for k in ("ax", "ay", "az")], 1)
+    normwise = np.max(np.linalg.norm(a - ref, axis=1)) / np.max(np.linalg.norm(ref, axis=1))
+    assert normwise <= TOL, normwise
     d = np.abs(sim.numpy("du") - st.f["du"])
     assert np.all(d <= TOL * st.dumag + 1e-300), np.max(d / (st.dumag + 1e-300))
     assert abs(sim.dt() - st.dt_next) <= TOL * st.dt_next

@@ -178,16 +178,28 @@ def test_ab2_step_parity():
             assert np.max(np.abs(sim.numpy(f) - st.f[f])) <= TOL * scale, (k, f)
 
 
-def test_conservation_parity():
-    ic = inputs.square_patch(21, 9)
+@pytest.mark.parametrize("case", ["patch_21^3", "clumpy_12k"])
+def test_conservation_parity(case):
+    """All seven sums: E relative, P normalised by sum m|v| and every
+    component of L by sum m|x||v| (the patch's P, L_x and L_y vanish
+    analytically; the clumpy set's noisy velocities make all seven
+    non-trivial)."""
+    ic = (inputs.square_patch(21, 9) if case == "patch_21^3"
+          else inputs.clumpy(n_clumps=4, per_clump=2500, n_background=2000, seed=5))
     st = O.State(ic.copy())
-    sim = _sim(ic)
+    sim = _sim(ic, extra_per_particle=96)
     out = sim.conservation()
     ref = st.conservation()
     assert abs(out[6] - ref[6]) <= TOL * abs(ref[6])
-    assert abs(out[5] - ref[5]) <= TOL * abs(ref[5])
-    pscale = np.sum(ic.m * np.sqrt(ic.vx ** 2 + ic.vy ** 2 + ic.vz ** 2))
-    assert np.all(np.abs(out[:3] - ref[:3]) <= TOL * pscale)
+    vmag = np.sqrt(ic.vx ** 2 + ic.vy ** 2 + ic.vz ** 2)
+    pscale = np.sum(ic.m * vmag)
+    lscale = np.sum(ic.m * np.sqrt(ic.x ** 2 + ic.y ** 2 + ic.z ** 2) * vmag)
+    assert np.all(np.abs(out[:3] - ref[:3]) <= TOL * pscale), (out[:3], ref[:3])
+    assert np.all(np.abs(out[3:6] - ref[3:6]) <= TOL * lscale), (out[3:6], ref[3:6])
+    if case == "patch_21^3":
+        assert abs(out[5] - ref[5]) <= TOL * abs(ref[5])
+    else:
+        assert np.all(np.abs(ref[3:6]) > 1e-6 * lscale)
 
 
 def test_deterministic_runs():
