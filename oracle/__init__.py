@@ -131,6 +131,9 @@ INTEGRATOR_KDK, INTEGRATOR_AB2 = 0, 1
 # gradient estimators of the momentum and energy sums: kernel derivatives, or
 # the integral approach to derivatives (IAD)
 GRADIENTS_KERNEL, GRADIENTS_IAD = 0, 1
+# volume elements of the density sum (Table 1): standard (X = m) or generalized,
+# X_i = (m_i / rho_i)^p from the previous evaluation's density
+VOLUMES_STANDARD, VOLUMES_GENERALIZED = 0, 1
 
 
 def ab2_energy(u, du, du_prev, dt, dt_prev, hist):
@@ -241,23 +244,29 @@ def lists(x, y, z, h, periodic, box_lo, box_hi, method=1, symmetric=True):
 # ---------------------------------------------------------------------------
 
 def density(x, y, z, vx, vy, vz, m, h, periodic, box_lo, box_hi, off, idx, with_mag=False,
-            kernel=0, with_omega=False):
+            kernel=0, with_omega=False, X=None, with_ysum=False):
     """rho, divv (and, with_mag, (1/rho) sum |m_j (v_j - v_i).grad W|, the scale
     of the divergence sum used for conditioning-aware comparisons; with_omega
-    also the grad-h factors Omega, appended last)."""
+    also the grad-h factors Omega; with_ysum the weighted sum Y, appended in
+    that order).  X: the weights of generalized volume elements (None: the
+    standard density, X = m)."""
     arr = [_f64(a) for a in (x, y, z, vx, vy, vz, m, h)]
     n = len(arr[0])
     rho = np.zeros(n)
     divv = np.zeros(n)
     mag = np.zeros(n)
     om = np.zeros(n)
+    ys = np.zeros(n)
     off = np.ascontiguousarray(off, dtype=np.int64)
     idx = np.ascontiguousarray(idx, dtype=np.int32)
+    Xa = _f64(X) if X is not None else None
     lib().or_density(ctypes.c_int64(n), *[_p(a) for a in arr], _int3(*periodic), _dbl3(*box_lo),
                      _dbl3(*box_hi), _p(off, _i64), _p(idx, _i32), _p(rho), _p(divv), _p(mag),
-                     ctypes.c_int(kernel), _p(om))
+                     ctypes.c_int(kernel), _p(om), _p(Xa) if Xa is not None else None, _p(ys))
     out = (rho, divv, mag) if with_mag else (rho, divv)
-    return out + (om,) if with_omega else out
+    if with_omega:
+        out = out + (om,)
+    return out + (ys,) if with_ysum else out
 
 
 def eos(rho, u, gamma=5.0 / 3.0):
@@ -270,8 +279,9 @@ def eos(rho, u, gamma=5.0 / 3.0):
 
 def forces(x, y, z, vx, vy, vz, m, h, rho, p, c, periodic, box_lo, box_hi, off, idx,
            alpha=1.0, beta=2.0, eta2=0.01, cfl=0.3, with_mag=False, kernel=0, omega=None,
-           iad=None):
-    """a, du, per-particle dt, sum_j m_j |f_ij| (and with_mag sum_j m_j |de_ij|)."""
+           iad=None, gve=None):
+    """a, du, per-particle dt, sum_j m_j |f_ij| (and with_mag sum_j m_j |de_ij|).
+    gve: (X/m, P/Y^2) per particle for generalized volume elements."""
     arr = [_f64(a) for a in (x, y, z, vx, vy, vz, m, h, rho, p, c)]
     n = len(arr[0])
     out = [np.zeros(n) for _ in range(7)]
@@ -282,15 +292,27 @@ def forces(x, y, z, vx, vy, vz, m, h, rho, p, c, periodic, box_lo, box_hi, off, 
                     ctypes.c_double(beta), ctypes.c_double(eta2), ctypes.c_double(cfl),
                     *[_p(a) for a in out], ctypes.c_int(kernel),
                     _p(_f64(omega)) if omega is not None else None,
-                    _p(_f64(iad)) if iad is not None else None)
+                    _p(_f64(iad)) if iad is not None else None,
+                    *_gve_ptrs(gve))
     ax, ay, az, du, dt_i, amag, dumag = out
     if with_mag:
         return ax, ay, az, du, dt_i, amag, dumag
     return ax, ay, az, du, dt_i, amag
 
 
+_gve_keep = []
+
+
+def _gve_ptrs(gve):
+    if gve is None:
+        return None, None
+    r, g = _f64(gve[0]), _f64(gve[1])
+    _gve_keep[:] = [r, g]   # alive for the duration of the call
+    return _p(r), _p(g)
+
+
 def pair_term(x, y, z, vx, vy, vz, m, h, rho, p, c, periodic, box_lo, box_hi, i, j,
-              alpha=1.0, beta=2.0, eta2=0.01, kernel=0, omega=None, iad=None):
+              alpha=1.0, beta=2.0, eta2=0.01, kernel=0, omega=None, iad=None, gve=None):
     arr = [_f64(a) for a in (x, y, z, vx, vy, vz, m, h, rho, p, c)]
     out = np.zeros(4)
     lib().or_pair_term(ctypes.c_int64(len(arr[0])), *[_p(a) for a in arr], _int3(*periodic),
@@ -298,7 +320,8 @@ def pair_term(x, y, z, vx, vy, vz, m, h, rho, p, c, periodic, box_lo, box_hi, i,
                        ctypes.c_double(alpha), ctypes.c_double(beta), ctypes.c_double(eta2),
                        _p(out), ctypes.c_int(kernel),
                        _p(_f64(omega)) if omega is not None else None,
-                       _p(_f64(iad)) if iad is not None else None)
+                       _p(_f64(iad)) if iad is not None else None,
+                       *_gve_ptrs(gve))
     return out
 
 
@@ -345,6 +368,8 @@ class Params:
     integrator: int = 0   # INTEGRATOR_KDK or INTEGRATOR_AB2
     grad_h: bool = False  # grad-h correction terms in the momentum and energy equations
     gradients: int = 0    # GRADIENTS_KERNEL or GRADIENTS_IAD
+    volumes: int = 0      # VOLUMES_STANDARD or VOLUMES_GENERALIZED
+    gve_exponent: float = 0.7   # p of the generalized weights X = (m / rho)^p
 
 
 class State:
@@ -422,7 +447,7 @@ class State:
         f.pop("du_prev", None)   # an evaluation starts the integrator afresh
         self.dt_prev = None
         self.build_cells()
-        self._evaluate_sorted((f["vx"], f["vy"], f["vz"]), f["u"], method)
+        self._evaluate_sorted((f["vx"], f["vy"], f["vz"]), f["u"], method, fresh=True)
         return self.dt_next
 
     def step(self, dt=None, method=1):
@@ -466,18 +491,34 @@ class State:
             self.dt_prev = dt
         return dt
 
-    def _evaluate_sorted(self, vel, u, method):
+    def gve_weights(self, rho_prev):
+        """X_i = (m_i / rho_i)^p of generalized volume elements."""
+        return np.power(self.f["m"] / rho_prev, self.p.gve_exponent)
+
+    def _evaluate_sorted(self, vel, u, method, fresh=False):
         f = self.f
         self.pv = (vel, u)
         self.find_neighbors(method)
-        rho, divv, dvmag, omega = density(f["x"], f["y"], f["z"], *vel, f["m"], f["h"],
-                                          *self.geom(), self.off, self.idx, with_mag=True,
-                                          kernel=self.p.kernel, with_omega=True)
+        X = None
+        if self.p.volumes == VOLUMES_GENERALIZED:
+            # the weights come from the previous evaluation's density; an
+            # evaluation that starts a run takes the standard density first
+            rho_prev = f["rho"]
+            if fresh:
+                rho_prev, _ = density(f["x"], f["y"], f["z"], *vel, f["m"], f["h"], *self.geom(),
+                                      self.off, self.idx, kernel=self.p.kernel)
+            X = self.gve_weights(rho_prev)
+        rho, divv, dvmag, omega, ysum = density(f["x"], f["y"], f["z"], *vel, f["m"], f["h"],
+                                                *self.geom(), self.off, self.idx, with_mag=True,
+                                                kernel=self.p.kernel, with_omega=True, X=X,
+                                                with_ysum=True)
         self.omega = omega
+        self.X, self.ysum = X, ysum
         f["rho"], f["divv"] = rho, divv
         self.divv_mag = dvmag
         P, c = eos(rho, u, self.p.gamma)
         self.P, self.c = P, c
+        gve = (X / f["m"], P / (ysum * ysum)) if X is not None else None
         self.iad = None
         if self.p.gradients == GRADIENTS_IAD:
             self.iad, bad = iad_matrices(f["x"], f["y"], f["z"], f["m"], rho, f["h"], *self.geom(),
@@ -489,7 +530,7 @@ class State:
                                                    self.p.alpha, self.p.beta, self.p.eta2,
                                                    self.p.cfl, with_mag=True, kernel=self.p.kernel,
                                                    omega=omega if self.p.grad_h else None,
-                                                   iad=self.iad)
+                                                   iad=self.iad, gve=gve)
         f["ax"], f["ay"], f["az"], f["du"] = ax, ay, az, du
         self.amag, self.dumag, self.dt_i = amag, dumag, dt_i
         self.dt_next = float(dt_i.min()) if len(dt_i) else np.inf

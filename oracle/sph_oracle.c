@@ -662,21 +662,29 @@ void or_free(void *p) { free(p); }
 /*   rho_i  = m_i W(0,h_i) + sum_{j in L_i} m_j W(r_ij, h_i)                  */
 /*   divv_i = (1/rho_i) sum_{j in L_i} m_j (v_j - v_i) . grad_i W(r_ij, h_i)  */
 /* entries of S_i outside L_i are skipped (their kernel value is zero).       */
+/* Generalized volume elements (X non-NULL; Table 1 lists them for SPHYNX,   */
+/* and as in development for the mini-app; read as Hopkins 2013 and          */
+/* Cabezon et al. 2017): the weighted sum                                    */
+/*   Y_i = X_i W(0,h_i) + sum_{j in L_i} X_j W(r_ij, h_i)                    */
+/* gives the volume V_i = X_i / Y_i and the density rho_i = m_i Y_i / X_i    */
+/* (X = m is the standard sum); Y_i is returned in ysum when non-NULL.       */
 /* ------------------------------------------------------------------------ */
 void or_density(int64_t n, const double *x, const double *y, const double *z,
                 const double *vx, const double *vy, const double *vz, const double *m,
                 const double *h, const int *periodic, const double *box_lo,
                 const double *box_hi, const int64_t *off, const int32_t *idx,
-                double *rho, double *divv, double *divv_mag, int kernel, double *omega)
+                double *rho, double *divv, double *divv_mag, int kernel, double *omega,
+                const double *X, double *ysum)
 {
     or_geom g;
     geom_init(&g, x, y, z, periodic, box_lo, box_hi);
+    const double *wgt = X ? X : m;
 #pragma omp parallel for schedule(dynamic, 256)
     for (int64_t i = 0; i < n; ++i) {
         double hi = h[i];
         double twoh = 2.0 * hi;
         double r2max = twoh * twoh;
-        double s = m[i] * kern(kernel, 0.0, hi);
+        double s = wgt[i] * kern(kernel, 0.0, hi);
         double sh = m[i] * or_kernel_dwdh(kernel, 0.0, hi);   /* sum of m_j dW/dh */
         double dv = 0.0, dvm = 0.0;
         for (int64_t k = off[i]; k < off[i + 1]; ++k) {
@@ -685,7 +693,7 @@ void or_density(int64_t n, const double *x, const double *y, const double *z,
             double r2 = pair_r2(&g, i, j, &dx, &dy, &dz);
             if (!(r2 < r2max)) continue;
             double r = sqrt(r2);
-            s += m[j] * kern(kernel, r, hi);
+            s += wgt[j] * kern(kernel, r, hi);
             sh += m[j] * or_kernel_dwdh(kernel, r, hi);
             if (r > 0.0) {
                 /* grad_i W = dW/dr (x_i - x_j)/r, and x_i - x_j = -(dx,dy,dz) */
@@ -698,12 +706,14 @@ void or_density(int64_t n, const double *x, const double *y, const double *z,
                 dvm += fabs(m[j] * gw) * vabs;
             }
         }
-        rho[i] = s;
-        divv[i] = dv / s;
-        if (divv_mag) divv_mag[i] = dvm / s;
+        double rh = X ? m[i] * s / X[i] : s;
+        rho[i] = rh;
+        if (ysum) ysum[i] = s;
+        divv[i] = dv / rh;
+        if (divv_mag) divv_mag[i] = dvm / rh;
         /* grad-h factor (Springel & Hernquist 2002) for h proportional to
          * rho^(-1/3): Omega = 1 - (dh/drho) sum_j m_j dW/dh = 1 + h/(3 rho) sum */
-        if (omega) omega[i] = 1.0 + hi / (3.0 * s) * sh;
+        if (omega) omega[i] = 1.0 + hi / (3.0 * rh) * sh;
     }
 }
 
@@ -811,6 +821,8 @@ typedef struct {
     int kernel;
     const double *omega;   /* grad-h factors, or NULL for the averaged-gradient form */
     const double *iad;     /* IAD matrices c (6 per particle), or NULL for kernel gradients */
+    const double *gve_r;   /* generalized volume elements: X_i / m_i, or NULL */
+    const double *gve_g;   /* and P_i / Y_i^2 */
 } or_phys;
 
 /* the pair term of particle i from neighbour j: writes the acceleration
@@ -874,6 +886,25 @@ static void pair_force(const or_geom *g, int64_t i, int64_t j, const double *vx,
         if (de_abs) *de_abs = fabs(fi) * a1 + fabs(0.5 * Pi) * a2;
         return;
     }
+    if (ph->gve_r) {
+        /* generalized volume elements: from the Lagrangian with V_i = X_i/Y_i
+         * (X held fixed), m_i a_i = -sum_j X_i X_j [P_i/Y_i^2 grad_i W(h_i)
+         * + P_j/Y_j^2 grad_i W(h_j)] and du_i = (X_i P_i/(m_i Y_i^2)) sum_j
+         * X_j v_ij . grad_i W(h_i); per unit m_j with r = X/m, g = P/Y^2:
+         * r_i r_j (g_i grad_i W(h_i) + g_j grad_i W(h_j)); the viscosity
+         * keeps the averaged gradient */
+        double rr = ph->gve_r[i] * ph->gve_r[j];
+        double fi = rr * ph->gve_g[i], fj = rr * ph->gve_g[j];
+        double gg = (fi * gwi + fj * gwj) + Pi * gbar;
+        *fx = -gg * xij;
+        *fy = -gg * yij;
+        *fz = -gg * zij;
+        double e = fi * gwi + 0.5 * Pi * gbar;
+        *de = e * w;
+        if (de_abs)
+            *de_abs = fabs(e) * (fabs(vxij * xij) + fabs(vyij * yij) + fabs(vzij * zij));
+        return;
+    }
     if (ph->omega) {
         /* grad-h form: each pressure term with its own particle's gradient
          * and grad-h factor, the viscosity with the averaged gradient */
@@ -908,11 +939,12 @@ void or_forces(int64_t n, const double *x, const double *y, const double *z,
                const int *periodic, const double *box_lo, const double *box_hi,
                const int64_t *off, const int32_t *idx, double alpha, double beta, double eta2,
                double cfl, double *ax, double *ay, double *az, double *du, double *dt_i,
-               double *amag, double *dumag, int kernel, const double *omega, const double *iad)
+               double *amag, double *dumag, int kernel, const double *omega, const double *iad,
+               const double *gve_r, const double *gve_g)
 {
     or_geom g;
     geom_init(&g, x, y, z, periodic, box_lo, box_hi);
-    or_phys ph = {0.0, alpha, beta, eta2, cfl, kernel, omega, iad};
+    or_phys ph = {0.0, alpha, beta, eta2, cfl, kernel, omega, iad, gve_r, gve_g};
 #pragma omp parallel for schedule(dynamic, 256)
     for (int64_t i = 0; i < n; ++i) {
         double sx = 0.0, sy = 0.0, sz = 0.0, se = 0.0, mumax = 0.0, mag = 0.0, emag = 0.0;
@@ -942,12 +974,13 @@ void or_pair_term(int64_t n, const double *x, const double *y, const double *z,
                   const double *h, const double *rho, const double *p, const double *c,
                   const int *periodic, const double *box_lo, const double *box_hi,
                   int64_t i, int64_t j, double alpha, double beta, double eta2, double *out4,
-                  int kernel, const double *omega, const double *iad)
+                  int kernel, const double *omega, const double *iad, const double *gve_r,
+                  const double *gve_g)
 {
     (void)n;
     or_geom g;
     geom_init(&g, x, y, z, periodic, box_lo, box_hi);
-    or_phys ph = {0.0, alpha, beta, eta2, 0.0, kernel, omega, iad};
+    or_phys ph = {0.0, alpha, beta, eta2, 0.0, kernel, omega, iad, gve_r, gve_g};
     double fx, fy, fz, de, mua;
     pair_force(&g, i, j, vx, vy, vz, h, rho, p, c, &ph, &fx, &fy, &fz, &de, &mua, NULL);
     double mm = m[i] * m[j];
