@@ -16,7 +16,9 @@
  *   - Every array argument is a DEVICE pointer owned by the caller; the
  *     library never allocates device memory.  Scratch memory is one
  *     caller-allocated workspace of sph_workspace_size() bytes, bound with
- *     sph_bind() together with the HIP stream every call launches on.
+ *     sph_bind() together with the HIP stream every call launches on (the
+ *     one exception, sph_conservation_noalloc, uses a 64 KiB array the
+ *     library's code object holds per GPU).
  *   - Calls are asynchronous on the bound stream and return an int status.
  *     Argument errors are reported at once; conditions found by kernels
  *     (list overflow, non-convergence, non-finite values) are reported by
@@ -284,6 +286,22 @@ int sph_step(sph_ctx *ctx, sph_particles *s, sph_nlist *nl, double dt, double *d
  * d_out7 = [P_x, P_y, P_z, L_x, L_y, L_z, E], P = sum m v,
  * L = sum m x cross v, E = sum m (v.v/2 + u), over buffer cur. */
 int sph_conservation(sph_ctx *ctx, const sph_particles *s, double *d_out7);
+
+/* For callers that cannot allocate device memory or bind a workspace (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * allocation): the conservation sums of sph_conservation without a context.
+ * The same kernels, block count and reduction order, hence the same bits;
+ * the block partials go to a 64 KiB array the library holds per GPU
+ * (1024 blocks x 8 doubles, the most the launch uses for any n, so no n is
+ * too large), looked up on the first call on each device.  Launches on
+ * `stream` (hipStream_t cast to void*; NULL = the null stream), which must
+ * belong to the current device.  Allocates nothing and does not wait.
+ * Every call on one GPU uses that GPU's one array: calls that overlap on a
+ * GPU (other streams, other threads) race and must be serialised by the
+ * caller.  s needs x, y, z, vx, vy, vz, m, u of buffer s->cur; d_out7 is a
+ * device array of 7 doubles.  Returns SPH_EINVAL for a NULL or inconsistent
+ * argument, SPH_EHIP for a runtime error. */
+int sph_conservation_noalloc(const sph_particles *s, double *d_out7, void *stream);
 
 /* Wait for the bound stream; fill *st (may be NULL) from the device status
  * words and reset them.  Returns SPH_ECAPACITY on list overflow,

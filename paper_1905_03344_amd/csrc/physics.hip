@@ -1,5 +1,7 @@
 // Density and divergence, equation of state, momentum / energy / viscosity
 // with the Courant step, kick-drift-kick integrator and conservation sums.
+#include <mutex>
+
 #include "sph_internal.h"
 
 // rho_i = m_i W(0,h_i) + sum_{L_i} m_j W(r_ij,h_i);
@@ -865,4 +867,65 @@ hipError_t launch_conservation(sph_ctx *c, const sph_particles *s, double *out7)
     hipLaunchKernelGGL(k_cons_final, dim3(1), dim3(SPH_BLOCK), 0, c->stream, c->w.red_part, nb,
                        out7);
     return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Allocation-free conservation sums.  The block partials live in `scratch`,
+// a file-scope device array (each GPU the library runs on holds its own copy
+// until the process ends) instead of the bound workspace; the same kernels
+// and the same block count as sph_conservation, so the same bits.  Host code
+// must not pass `scratch` itself to a kernel (in host code the name stands
+// for a host-side symbol): its device address is looked up once per device
+// with hipGetSymbolAddress and kept in g_scratch_dev.
+// ---------------------------------------------------------------------------
+#define SPH_CONS_MAX_BLOCKS 1024
+#define SPH_NOALLOC_MAX_DEVICES 64
+static __device__ __align__(256) double scratch[SPH_CONS_MAX_BLOCKS * 8];
+
+static std::mutex g_scratch_mu;
+static double *g_scratch_dev[SPH_NOALLOC_MAX_DEVICES];
+
+// device address of this GPU's scratch (the current device's), looked up on
+// the first call on that device
+static hipError_t scratch_on_current_device(double **out)
+{
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= SPH_NOALLOC_MAX_DEVICES) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_dev[dev]) {
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        if (!p) return hipErrorInvalidSymbol;
+        g_scratch_dev[dev] = (double *)p;
+    }
+    *out = g_scratch_dev[dev];
+    return hipSuccess;
+}
+
+extern "C" int sph_conservation_noalloc(const sph_particles *s, double *d_out7, void *stream)
+{
+    if (!s || !d_out7) return SPH_EINVAL;
+    if (s->n < 0 || (s->cur != 0 && s->cur != 1)) return SPH_EINVAL;
+    const int k = s->cur;
+    const int64_t n = s->n;
+    if (n > 0) {
+        const void *f[] = {s->x[k], s->y[k], s->z[k], s->vx[k], s->vy[k], s->vz[k], s->m[k],
+                           s->u[k]};
+        for (const void *q : f)
+            if (!q) return SPH_EINVAL;
+    }
+    double *part = nullptr;
+    if (scratch_on_current_device(&part) != hipSuccess) return SPH_EHIP;
+    // at most SPH_CONS_MAX_BLOCKS blocks stride over any n, so the partials
+    // always fit; the block count is sph_conservation's
+    int64_t nb = ceil_div(n > 0 ? n : 1, SPH_BLOCK);
+    if (nb > SPH_CONS_MAX_BLOCKS) nb = SPH_CONS_MAX_BLOCKS;
+    hipStream_t st = (hipStream_t)stream;
+    hipLaunchKernelGGL(k_cons_partial, dim3((unsigned)nb), dim3(SPH_BLOCK), 0, st, n, s->x[k],
+                       s->y[k], s->z[k], s->vx[k], s->vy[k], s->vz[k], s->m[k], s->u[k], part);
+    hipLaunchKernelGGL(k_cons_final, dim3(1), dim3(SPH_BLOCK), 0, st, part, nb, d_out7);
+    return hipGetLastError() == hipSuccess ? SPH_OK : SPH_EHIP;
 }

@@ -102,6 +102,7 @@ _SIGS = {
     "sph_evaluate": (ctypes.c_int, [_P, ctypes.POINTER(sph_particles), ctypes.POINTER(sph_nlist), _P]),
     "sph_step": (ctypes.c_int, [_P, ctypes.POINTER(sph_particles), ctypes.POINTER(sph_nlist), _D, _P]),
     "sph_conservation": (ctypes.c_int, [_P, ctypes.POINTER(sph_particles), _P]),
+    "sph_conservation_noalloc": (ctypes.c_int, [ctypes.POINTER(sph_particles), _P, _P]),
     "sph_sync": (ctypes.c_int, [_P, ctypes.POINTER(sph_stats)]),
     "sph_last_error": (ctypes.c_char_p, [_P]),
     "sph_copy_internal": (ctypes.c_int, [_P, ctypes.c_int, _P, ctypes.c_size_t, ctypes.POINTER(ctypes.c_size_t)]),
@@ -230,6 +231,14 @@ def sph_step(ctx, s, nl, dt: float, d_dt: int):
 
 def sph_conservation(ctx, s, d_out7: int):
     check(lib().sph_conservation(ctx, ctypes.byref(s), d_out7), ctx)
+
+
+def sph_conservation_noalloc(s, d_out7: int, stream: int):
+    """The allocation-free variant (no context; stream is a hipStream_t)."""
+    code = lib().sph_conservation_noalloc(ctypes.byref(s), d_out7, stream)
+    if code != SPH_OK:
+        raise SphError(code, "sph_conservation_noalloc: " +
+                       ("invalid argument" if code == SPH_EINVAL else "HIP runtime error"))
 
 
 def sph_sync(ctx, allow=(SPH_OK, SPH_WNOCONV)):
