@@ -102,6 +102,23 @@ typedef struct sph_ctx sph_ctx;
 #define SPH_GRADIENTS_KERNEL 0
 #define SPH_GRADIENTS_IAD 1
 
+/* Volume elements of the density sum (A7).  STANDARD: V_i = m_i / rho_i,
+ * rho_i = sum_j m_j W(r_ij, h_i) (the mini-app's, Table 1).  GENERALIZED:
+ * the generalized volume elements Table 1 lists for SPHYNX and, in
+ * development, for the mini-app (Hopkins 2013; Cabezon, Garcia-Senz &
+ * Figueira 2017): weights X_i = (m_i / rho_i)^p from the density of the
+ * previous evaluation (p = gve_exponent; sph_evaluate takes the standard
+ * density at its h first), Y_i = sum_j X_j W(r_ij, h_i) over L_i and i
+ * itself, V_i = X_i / Y_i and rho_i = m_i Y_i / X_i.  The momentum and energy
+ * equations are those of the Lagrangian with these volumes (X and h held
+ * fixed), with r = X/m and g = P/Y^2:
+ *   a_i  = -sum_j m_j [r_i r_j (g_i grad_i W(h_i) + g_j grad_i W(h_j)) + Pi_ij grad W_bar]
+ *   du_i =  sum_j m_j [r_i r_j g_i v_ij . grad_i W(h_i) + (Pi_ij/2) v_ij . grad W_bar]
+ * (pairwise antisymmetric: momentum and energy are conserved).  Not combined
+ * with grad_h or IAD gradients. */
+#define SPH_VOLUMES_STANDARD 0
+#define SPH_VOLUMES_GENERALIZED 1
+
 typedef struct sph_params {
     int64_t n_max;          /* largest particle count the workspace is sized for */
     int32_t list_stride;    /* K: capacity of each gather set L_i (default 128) */
@@ -130,8 +147,11 @@ typedef struct sph_params {
     int32_t walk_defer_group; /* first h-iteration round: particles in walk sub-groups of at
                                * most this many (0 = default 4; 1..64) are counted one per
                                * wave afterwards; larger suits strongly clustered inputs.
-                               * Sets, h and counts do not depend on it; a gather row may
-                               * come in another order (sums then differ by rounding). */
+                               * Speed only: sets, rows, h, counts and fields do not
+                               * depend on it. */
+    int32_t volumes;        /* SPH_VOLUMES_STANDARD (default) or SPH_VOLUMES_GENERALIZED */
+    int32_t pad1;
+    double gve_exponent;    /* p of the generalized weights X = (m/rho)^p, in [0, 1] (0.7) */
 } sph_params;
 
 typedef struct sph_particles {
@@ -164,13 +184,11 @@ typedef struct sph_particles {
  * so that j in S_i <=> i in S_j.  Both parts are stored particle-major: row
  * i of L is idx[i * list_stride + k], k < nc[i] (nc in sph_particles), and
  * row i of E is eidx[i * extra_slots + k], k < ecnt[i].  L_i comes in
- * ascending index order, except that a set completed from the shell of an
- * earlier count (see sph_find_neighbors) lists the members closer than the
- * shell's inner radius first, each part ascending; the order depends only on
- * the particle's positions and h, not on how particles were grouped.  E_i is
- * in no particular order (the force kernel visits each E_i in ascending
- * index order, so results do not depend on it).  All indices refer to the
- * current (sorted) particle order. */
+ * ascending index order however it was counted (the same row, bit for bit,
+ * whatever the walk grouping).  E_i is in no particular order (the force
+ * kernel visits each E_i in ascending index order, so results do not depend
+ * on it).  All indices refer to the current (sorted) particle order.
+ * sph_interaction_csr exports S_i as compressed rows. */
 typedef struct sph_nlist {
     int32_t *idx;           /* stride * list_stride entries */
     int64_t stride;         /* rows allocated, >= n (a multiple of 64) */
@@ -191,6 +209,7 @@ typedef struct sph_stats {
     double dt;               /* Courant time step of the last evaluation */
     int64_t candidates_first;/* of those, tested by its first (all-particle) counting pass */
     int64_t iad_singular;    /* IAD: particles whose moment matrix was not invertible */
+    int64_t csr_overflow;    /* sph_interaction_csr: entries beyond the caller's capacity */
 } sph_stats;
 
 /* Fill *p with the defaults above (n_max and capacities set to 0). */
@@ -230,6 +249,20 @@ int sph_find_neighbors(sph_ctx *ctx, sph_particles *s, sph_nlist *nl);
  * divv_i = (1/rho_i) sum_{j in L_i} m_j (v_j - v_i) . grad_i W(r_ij,h_i),
  * with v the predicted velocity (pvx, pvy, pvz).  Writes rho[cur], divv[cur]. */
 int sph_density(sph_ctx *ctx, sph_particles *s, const sph_nlist *nl);
+
+/* The interaction sets S_i = L_i U E_i as compressed rows, for callers that
+ * take neighbour lists in that form (the per-step neighbour discovery of the
+ * mini-app's loop, section "Co-Design of the Mini-App"): d_off[n + 1]
+ * (int64, device) receives the row offsets, d_off[n] = sum |S_i|, and
+ * d_idx[d_off[i] ..] (int32, device) row i in ascending index order (the
+ * current, sorted particle order).  Call after sph_find_neighbors (or a
+ * step), before the next sph_build_cells.  Entries at positions >= capacity
+ * are not written; they are counted in sph_stats.csr_overflow and make the
+ * next sph_sync return SPH_ECAPACITY (d_off is always complete, so a caller
+ * can size d_idx from d_off[n] and call again).  Uses the workspace's
+ * per-particle scratch; the padded rows of sph_nlist stay as they are. */
+int sph_interaction_csr(sph_ctx *ctx, const sph_particles *s, const sph_nlist *nl,
+                        int64_t *d_off, int32_t *d_idx, int64_t capacity);
 
 /* With grad_h set, sph_density also forms the grad-h factor of each
  * particle, for h taken as proportional to rho^(-1/3) (Springel & Hernquist

@@ -114,6 +114,8 @@ extern "C" void sph_default_params(sph_params *p)
     p->search_div = 2;
     p->walk_prefilter = SPH_PREFILTER_MATRIX;
     p->integrator = SPH_INTEGRATOR_KDK;
+    p->volumes = SPH_VOLUMES_STANDARD;
+    p->gve_exponent = 0.7;
 }
 
 extern "C" const char *sph_params_error(void) { return g_params_error; }
@@ -141,6 +143,14 @@ static const char *validate(const sph_params *p)
         return "gradients must be SPH_GRADIENTS_KERNEL or SPH_GRADIENTS_IAD";
     if (p->walk_prefilter != SPH_PREFILTER_NONE && p->walk_prefilter != SPH_PREFILTER_MATRIX)
         return "walk_prefilter must be SPH_PREFILTER_NONE or SPH_PREFILTER_MATRIX";
+    if (p->volumes != SPH_VOLUMES_STANDARD && p->volumes != SPH_VOLUMES_GENERALIZED)
+        return "volumes must be SPH_VOLUMES_STANDARD or SPH_VOLUMES_GENERALIZED";
+    if (p->volumes == SPH_VOLUMES_GENERALIZED) {
+        if (p->grad_h || p->gradients != SPH_GRADIENTS_KERNEL)
+            return "generalized volume elements are not combined with grad_h or IAD gradients";
+        if (!(p->gve_exponent >= 0.0 && p->gve_exponent <= 1.0))
+            return "gve_exponent must be in [0, 1]";
+    }
     if (!(p->gamma > 1.0)) return "gamma must exceed 1";
     if (!(p->cfl > 0.0)) return "cfl must be positive";
     if (!(p->av_eta2 > 0.0)) return "av_eta2 must be positive";
@@ -212,6 +222,9 @@ size_t sph_layout(const sph_params *p, void *base, Workspace *w)
     t.dt_prev = (double *)take(sizeof(double));
     t.omega = p->grad_h ? (double *)take(n * sizeof(double)) : nullptr;
     t.iad = p->gradients == SPH_GRADIENTS_IAD ? (double2 *)take(n * 3 * sizeof(double2)) : nullptr;
+    const bool gve = p->volumes == SPH_VOLUMES_GENERALIZED;
+    t.gve_x = gve ? (double *)take(n * sizeof(double)) : nullptr;
+    t.gve_y = gve ? (double *)take(n * sizeof(double)) : nullptr;
     t.nb_red = nb_red;
     t.nb_sort = nb_sort;
     t.scan_part_len = scan_part;
@@ -550,7 +563,10 @@ extern "C" int sph_evaluate(sph_ctx *c, sph_particles *s, sph_nlist *nl, double 
     if (r) return r;
     TRY(launch_copy_pred(c, s), "copy prediction");
     c->ab2_hist = 0;   // the integrator starts afresh from this state
-    return evaluate_sorted(c, s, nl, d_dt, nullptr);
+    c->gve_fresh = 1;  // generalized weights from the standard density at this h
+    r = evaluate_sorted(c, s, nl, d_dt, nullptr);
+    c->gve_fresh = 0;
+    return r;
 }
 
 extern "C" int sph_step(sph_ctx *c, sph_particles *s, sph_nlist *nl, double dt, double *d_dt)
@@ -603,6 +619,20 @@ extern "C" int sph_conservation(sph_ctx *c, const sph_particles *s, double *d_ou
     return SPH_OK;
 }
 
+extern "C" int sph_interaction_csr(sph_ctx *c, const sph_particles *s, const sph_nlist *nl,
+                                   int64_t *d_off, int32_t *d_idx, int64_t capacity)
+{
+    int r = check_particles(c, s);
+    if (r) return r;
+    r = check_nlist(c, s, nl);
+    if (r) return r;
+    if (!d_off) return set_err(c, SPH_EINVAL, "d_off is NULL");
+    if (capacity < 0) return set_err(c, SPH_EINVAL, "capacity < 0");
+    if (capacity > 0 && !d_idx) return set_err(c, SPH_EINVAL, "d_idx is NULL");
+    TRY(launch_interaction_csr(c, s, nl, d_off, d_idx, capacity), "interaction csr");
+    return SPH_OK;
+}
+
 extern "C" int sph_sync(sph_ctx *c, sph_stats *st)
 {
     if (!c) return SPH_EINVAL;
@@ -625,8 +655,9 @@ extern "C" int sph_sync(sph_ctx *c, sph_stats *st)
         st->extra_total = h[ST_EXTRA_TOTAL];
         st->candidates_first = h[ST_CANDIDATES_FIRST];
         st->iad_singular = h[ST_IAD_SINGULAR];
+        st->csr_overflow = h[ST_CSR_OVERFLOW];
     }
-    if (h[ST_LIST_OVERFLOW] || h[ST_EXTRA_OVERFLOW])
+    if (h[ST_LIST_OVERFLOW] || h[ST_EXTRA_OVERFLOW] || h[ST_CSR_OVERFLOW])
         return set_err(c, SPH_ECAPACITY, "a neighbour list exceeded its capacity");
     if (h[ST_NONFINITE]) return set_err(c, SPH_ENONFINITE, "non-finite field values");
     if (h[ST_IAD_SINGULAR]) return set_err(c, SPH_ENONFINITE, "singular IAD moment matrix");

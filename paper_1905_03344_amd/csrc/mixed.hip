@@ -14,7 +14,8 @@
 // with x = lo + g * w + delta, w = L/1024 the key-cell width.  1/h of a
 // neighbour is formed in the pair (hardware reciprocal, 1 ulp).
 struct MixQ {
-    float4 *A, *B, *C, *D;   // D: IAD (c_xx, c_xy, c_xz, c_yy), else unused
+    float4 *A, *B, *C, *D;   // D: IAD (c_xx, c_xy, c_xz, c_yy); generalized volumes
+                             // (X, X/m, 0, 0); else unused
 };
 __host__ __device__ static inline MixQ mix_quads(void *base, int64_t n_max)
 {
@@ -196,15 +197,19 @@ __device__ __forceinline__ MixGeo mix_geo(const double *__restrict__ bbox, const
     return G;
 }
 
-// GH: also the grad-h factor Omega_i = 1 - (1/(3 rho_i)) sum_j m_j (3 W + r dW/dr)
-template <int PM, bool EXTRA, int KER, bool GH>
+// GH: also the grad-h factor Omega_i = 1 - (1/(3 rho_i)) sum_j m_j (3 W + r dW/dr).
+// GV: generalized volume elements, Y_i = X_i W(0,h_i) + sum_{L_i} X_j W(r_ij,h_i)
+// with X from the D quads (compensated FP32 sum, stored in FP64 in ysum) and
+// rho_i = m_i Y_i / X_i in FP64 (X and m from the FP64 arrays)
+template <int PM, bool EXTRA, int KER, bool GH, bool GV>
 __global__ __launch_bounds__(SPH_BLOCK) SPH_PAIR_WAVES_D void k_density_mixed(
     int64_t n, MixQ Q, const int32_t *__restrict__ nc, const int32_t *__restrict__ idx, int K,
     const double *__restrict__ bbox, Geo g, float knorm, const double *__restrict__ x,
     const double *__restrict__ y, const double *__restrict__ z, const double *__restrict__ h,
     double *__restrict__ rho, double *__restrict__ divv, double *__restrict__ omega,
     int32_t *__restrict__ ecnt,
-    int32_t *__restrict__ eidx, int slots, int64_t *__restrict__ status)
+    int32_t *__restrict__ eidx, int slots, int64_t *__restrict__ status,
+    const double *__restrict__ X, const double *__restrict__ m, double *__restrict__ ysum)
 {
     const int lane = threadIdx.x & (SPH_MGROUP - 1);
     const int grp = threadIdx.x / SPH_MGROUP;
@@ -233,12 +238,13 @@ __global__ __launch_bounds__(SPH_BLOCK) SPH_PAIR_WAVES_D void k_density_mixed(
                     jb[q] = k < cnt ? row[k] : (int)i;
                 }
                 float4 ab[SPH_MBATCH], bb[SPH_MBATCH];
-                float hb[SPH_MBATCH];
+                float hb[SPH_MBATCH], xb[SPH_MBATCH];
 #pragma unroll
                 for (int q = 0; q < SPH_MBATCH; ++q) {
                     ab[q] = Q.A[jb[q]];
                     bb[q] = Q.B[jb[q]];
                     if (EXTRA) hb[q] = Q.C[jb[q]].x;
+                    xb[q] = GV ? Q.D[jb[q]].x : 0.0f;
                 }
 #pragma unroll
                 for (int q = 0; q < SPH_MBATCH; ++q) {
@@ -275,7 +281,7 @@ __global__ __launch_bounds__(SPH_BLOCK) SPH_PAIR_WAVES_D void k_density_mixed(
                     float r = sqrtf(r2);
                     const float mj = bj.w;
                     const float wk = kern_w_f<KER>(r, inv_h, knorm);
-                    neu_add(s, mj * wk);
+                    neu_add(s, (GV ? xb[q] : mj) * wk);
                     if (r > 0.0f) {
                         const float dw = kern_dwdr_f<KER>(r, inv_h, knorm);
                         float gw = dw / r;
@@ -294,10 +300,14 @@ __global__ __launch_bounds__(SPH_BLOCK) SPH_PAIR_WAVES_D void k_density_mixed(
         if (GH) t = mgroup_neu(t);
         if (i < n && lane == 0) {
             const float w0 = kern_w_f<KER>(0.0f, inv_h, knorm);
-            NeuF tot = {bi.w * w0, 0.0f};
+            NeuF tot = {(GV ? Q.D[i].x : bi.w) * w0, 0.0f};
             neu_add(tot, s.s);
             tot.c += s.c;
-            const double sd = neu_val(tot);
+            double sd = neu_val(tot);
+            if (GV) {
+                ysum[i] = sd;
+                sd = m[i] * sd / X[i];
+            }
             rho[i] = sd;
             divv[i] = neu_val(dv) / sd;
             if (GH) omega[i] = 1.0 - (3.0 * (double)(bi.w * w0) + neu_val(t)) / (3.0 * sd);
@@ -310,13 +320,17 @@ __global__ __launch_bounds__(SPH_BLOCK) SPH_PAIR_WAVES_D void k_density_mixed(
 }
 
 // EOS in FP64 (as the plain form) and the FP32 force fields of the record
+// (generalized volumes, X non-NULL: the record carries q = (X/m) P / Y^2)
 __global__ __launch_bounds__(SPH_BLOCK) void k_eos_mixed(int64_t n, const double *__restrict__ rho,
                                                          const double *__restrict__ u, double gamma,
                                                          const double *__restrict__ omega,
                                                          double *__restrict__ p,
                                                          double *__restrict__ c,
                                                          MixQ Q, int check,
-                                                         int64_t *__restrict__ status)
+                                                         int64_t *__restrict__ status,
+                                                         const double *__restrict__ X,
+                                                         const double *__restrict__ m,
+                                                         const double *__restrict__ ysum)
 {
     int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     int64_t bad = 0;
@@ -328,7 +342,12 @@ __global__ __launch_bounds__(SPH_BLOCK) void k_eos_mixed(int64_t n, const double
         c[i] = cv;
         Q.C[i].y = (float)cv;
         Q.C[i].z = (float)rh;
-        Q.C[i].w = (float)(pv / (omega ? omega[i] * (rh * rh) : rh * rh));   // P / (Omega rho^2)
+        if (X) {
+            const double yv = ysum[i];
+            Q.C[i].w = (float)(X[i] / m[i] * pv / (yv * yv));
+        } else {
+            Q.C[i].w = (float)(pv / (omega ? omega[i] * (rh * rh) : rh * rh));   // P / (Omega rho^2)
+        }
         if (check && !(isfinite(pv) && isfinite(cv) && isfinite(rh))) bad = 1;
     }
     if (check) block_add_i64(bad, status + ST_NONFINITE);
@@ -351,7 +370,9 @@ struct QuadF {
 
 // GR: 0 averaged kernel gradient; 1 pressure terms with each particle's own
 // kernel gradient (grad-h form); 2 pressure terms with each particle's own
-// IAD gradient A = c d W, the viscosity with their mean
+// IAD gradient A = c d W, the viscosity with their mean; 3 generalized
+// volume elements (c.w = q = r g, d.x = X, d.y = r = X/m), the viscosity with
+// the averaged gradient
 template <int PM, int KER, int GR>
 __device__ __forceinline__ void force_pair_f(const QuadF &ri, float inv_hi, uint32_t gi,
                                              const QuadF &rj, const MixGeo &G, float knorm,
@@ -409,6 +430,16 @@ __device__ __forceinline__ void force_pair_f(const QuadF &ri, float inv_hi, uint
         A.mumax = fmaxf(A.mumax, fabsf(mu));
     }
     float mj = rj.b.w;
+    if (GR == 3) {
+        // m_j r_i r_j g_i = X_j q_i and m_j r_i r_j g_j = r_i m_j q_j
+        const float ti = rj.d.x * ri.c.w * gwi;
+        float f = (ti + ri.d.y * mj * rj.c.w * gwj) + mj * Pi * gbar;
+        neu_add(A.ax, -f * xij);
+        neu_add(A.ay, -f * yij);
+        neu_add(A.az, -f * zij);
+        neu_add(A.du, (ti + 0.5f * mj * Pi * gbar) * w);
+        return;
+    }
     if (GR == 1) {
         float f = mj * ((ri.c.w * gwi + rj.c.w * gwj) + Pi * gbar);
         neu_add(A.ax, -f * xij);
@@ -452,6 +483,7 @@ __global__ __launch_bounds__(SPH_BLOCK) SPH_PAIR_WAVES_F void k_forces_mixed(
             QuadF ri;
             ri.a = Q.A[i]; ri.b = Q.B[i]; ri.c = Q.C[i];
             if (GR == 2) { ri.d = Q.D[i]; ri.e = qe[i]; }
+            if (GR == 3) ri.d = Q.D[i];
             const float inv_hi = (float)(1.0 / h[i]);
             const uint32_t gi = cell_of(ri.a);
             const int cnt = min(nc[i], K);
@@ -473,6 +505,7 @@ __global__ __launch_bounds__(SPH_BLOCK) SPH_PAIR_WAVES_F void k_forces_mixed(
                 for (int q = 0; q < SPH_MFBATCH; ++q) {
                     rb[q].a = Q.A[jb[q]]; rb[q].b = Q.B[jb[q]]; rb[q].c = Q.C[jb[q]];
                     if (GR == 2) { rb[q].d = Q.D[jb[q]]; rb[q].e = qe[jb[q]]; }
+                    if (GR == 3) rb[q].d = Q.D[jb[q]];
                 }
 #pragma unroll
                 for (int q = 0; q < SPH_MFBATCH; ++q) {
@@ -525,6 +558,21 @@ hipError_t launch_pack_mixed(sph_ctx *c, sph_particles *s)
     return hipGetLastError();
 }
 
+// generalized volume elements: X_i = (m_i / rho_i)^p from the density held
+// (FP64), with X and X/m in FP32 in the D quad for the pair loops
+__global__ __launch_bounds__(SPH_BLOCK) void k_gve_weights_mixed(int64_t n,
+                                                                 const double *__restrict__ m,
+                                                                 const double *__restrict__ rho,
+                                                                 double p, double *__restrict__ X,
+                                                                 MixQ Q)
+{
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const double xv = pow(m[i] / rho[i], p);
+    X[i] = xv;
+    Q.D[i] = make_float4((float)xv, (float)(xv / m[i]), 0.0f, 0.0f);
+}
+
 hipError_t launch_density_mixed(sph_ctx *c, sph_particles *s, const sph_nlist *nl,
                                 bool build_extra)
 {
@@ -543,21 +591,33 @@ hipError_t launch_density_mixed(sph_ctx *c, sph_particles *s, const sph_nlist *n
 #define SPH_DENSITY_ARGS                                                                      \
     dim3(nb), dim3(SPH_BLOCK), 0, c->stream, n, Q, s->nc[cur], nl->idx, c->p.list_stride,      \
         c->w.bbox, g, (float)c->knorm, s->x[cur], s->y[cur], s->z[cur], s->h[cur], s->rho[cur], \
-        s->divv[cur], c->w.omega, nl->ecnt, nl->eidx, c->p.extra_slots, c->w.status
-#define SPH_DENSITY_GH(GHV)                                                                   \
-    if (build_extra) {                                                                        \
-        SPH_DISPATCH_KER(c->p.kernel, SPH_DISPATCH_PM(periodic_mask(g),                       \
-            hipLaunchKernelGGL((k_density_mixed<PM, true, KER, GHV>), SPH_DENSITY_ARGS)))     \
-    } else {                                                                                  \
-        SPH_DISPATCH_KER(c->p.kernel, SPH_DISPATCH_PM(periodic_mask(g),                       \
-            hipLaunchKernelGGL((k_density_mixed<PM, false, KER, GHV>), SPH_DENSITY_ARGS)))    \
-    }
-    if (c->p.grad_h) {
-        SPH_DENSITY_GH(true)
+        s->divv[cur], c->w.omega, nl->ecnt, nl->eidx, c->p.extra_slots, c->w.status,           \
+        c->w.gve_x, s->m[cur], c->w.gve_y
+#define SPH_DENSITY(EX, GHV, GVV)                                                             \
+    SPH_DISPATCH_KER(c->p.kernel, SPH_DISPATCH_PM(periodic_mask(g),                           \
+        hipLaunchKernelGGL((k_density_mixed<PM, EX, KER, GHV, GVV>), SPH_DENSITY_ARGS)))
+    if (c->p.volumes == SPH_VOLUMES_GENERALIZED) {
+        // weights from the previous evaluation's density (the standard one
+        // first when an evaluation starts a run), in FP64 and in the D quads
+        bool extra = build_extra;
+        if (c->gve_fresh) {
+            if (extra) { SPH_DENSITY(true, false, false) }
+            else { SPH_DENSITY(false, false, false) }
+            extra = false;
+        }
+        hipLaunchKernelGGL(k_gve_weights_mixed, dim3(nb), dim3(SPH_BLOCK), 0, c->stream, n,
+                           s->m[cur], s->rho[cur], c->p.gve_exponent, c->w.gve_x, Q);
+        if (extra) { SPH_DENSITY(true, false, true) }
+        else { SPH_DENSITY(false, false, true) }
+    } else if (c->p.grad_h) {
+        if (build_extra) { SPH_DENSITY(true, true, false) }
+        else { SPH_DENSITY(false, true, false) }
+    } else if (build_extra) {
+        SPH_DENSITY(true, false, false)
     } else {
-        SPH_DENSITY_GH(false)
+        SPH_DENSITY(false, false, false)
     }
-#undef SPH_DENSITY_GH
+#undef SPH_DENSITY
 #undef SPH_DENSITY_ARGS
     return hipGetLastError();
 }
@@ -569,7 +629,7 @@ hipError_t launch_eos_mixed(sph_ctx *c, sph_particles *s)
     hipLaunchKernelGGL(k_eos_mixed, dim3((unsigned)ceil_div(n, SPH_BLOCK)), dim3(SPH_BLOCK), 0,
                        c->stream, n, s->rho[s->cur], s->pu, c->p.gamma,
                        c->p.grad_h ? c->w.omega : nullptr, s->p, s->c, ctx_quads(c),
-                       c->p.check_finite, c->w.status);
+                       c->p.check_finite, c->w.status, c->w.gve_x, s->m[s->cur], c->w.gve_y);
     return hipGetLastError();
 }
 
@@ -693,6 +753,8 @@ hipError_t launch_forces_mixed(sph_ctx *c, sph_particles *s, const sph_nlist *nl
         SPH_FORCE_GR(2)
     } else if (p.grad_h) {
         SPH_FORCE_GR(1)
+    } else if (p.volumes == SPH_VOLUMES_GENERALIZED) {
+        SPH_FORCE_GR(3)
     } else {
         SPH_FORCE_GR(0)
     }

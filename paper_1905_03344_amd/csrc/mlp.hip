@@ -90,6 +90,27 @@ __device__ __forceinline__ void mlp_load_regs(const MlpDev &M, MlpRegs &R)
     R.b3 = M.master[MLP_B3];
 }
 
+// tanh in FP32, written from the function itself: for |x| < 0.625 the odd
+// polynomial x (1 + s P(s)), s = x^2, P of degree 4 fitted to (tanh(x)/x - 1)/s
+// on that interval (relative error below 2e-7 in FP32 arithmetic); above it
+// 1 - 2 / (1 + e^{2|x|}) with the hardware exp2 and reciprocal (absolute error
+// below 2e-7 where tanh > 0.55), sign restored; e^{2|x|} = inf gives 1.
+// Activations are rounded to bfloat16 (relative half-ulp 2^-9) afterwards.
+__device__ __forceinline__ float tanh_f(float x)
+{
+    const float ax = fabsf(x);
+    const float s = x * x;
+    float p = -0.005710217636078596f;
+    p = p * s + 0.02064412832260132f;
+    p = p * s - 0.05374139919877052f;
+    p = p * s + 0.13331463932991028f;
+    p = p * s - 0.3333328366279602f;
+    const float small = x + x * (s * p);
+    const float e = __builtin_amdgcn_exp2f(ax * 2.8853900817779268f);   // e^{2|x|}
+    const float big = 1.0f - 2.0f * __builtin_amdgcn_rcpf(1.0f + e);
+    return ax < 0.625f ? small : copysignf(big, x);
+}
+
 // forward of one tile of 16 particles; x = this lane's B operand of layer 1
 // (features 4(l/16)+v of particle l%16, bf16 bits, zero beyond 6).
 // Returns y of particle l%16 in every lane; a1/a2 (FP32 activations) and
@@ -102,7 +123,7 @@ __device__ __forceinline__ float mlp_tile_forward(const MlpRegs &R, s4_t x, floa
         f4_t d = {0.f, 0.f, 0.f, 0.f};
         d = mfma(R.w1[t], x, d);
         for (int v = 0; v < 4; ++v) {
-            float a = tanhf(d[v] + R.b1[t][v]);
+            float a = tanh_f(d[v] + R.b1[t][v]);
             a1[t][v] = a;
             h1[t][v] = (short)bf16_bits_f(a);
         }
@@ -111,7 +132,7 @@ __device__ __forceinline__ float mlp_tile_forward(const MlpRegs &R, s4_t x, floa
         f4_t d = {0.f, 0.f, 0.f, 0.f};
         for (int kt = 0; kt < 4; ++kt) d = mfma(R.w2[mt][kt], h1[kt], d);
         for (int v = 0; v < 4; ++v) {
-            float a = tanhf(d[v] + R.b2[mt][v]);
+            float a = tanh_f(d[v] + R.b2[mt][v]);
             a2[mt][v] = a;
             h2[mt][v] = (short)bf16_bits_f(a);
         }
@@ -161,7 +182,10 @@ __device__ __forceinline__ void raw_features(int64_t i, const double *__restrict
 }
 
 // ---------------------------------------------------------------------------
-// step use: features -> MLP -> predicted h, 16 particles per tile
+// step use: features -> MLP -> predicted h.  A wave takes 64 particles at a
+// time: each lane forms one particle's standardised bf16 features (FP64
+// logs, roots and divisions once per particle) into LDS, then the four
+// tiles of 16 particles go through the network.
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(SPH_BLOCK) void k_mlp_predict(
     int64_t n, MlpDev M, const double *__restrict__ h, const int32_t *__restrict__ nc,
@@ -170,30 +194,44 @@ __global__ __launch_bounds__(SPH_BLOCK) void k_mlp_predict(
     const double *__restrict__ u, double gamma, const double *__restrict__ dtp,
     double *__restrict__ h_try, float *__restrict__ y_out)
 {
-    const int l = threadIdx.x & 63;
+    __shared__ uint16_t xs[MLP_WAVES_PER_BLOCK][64][8];
+    const int l = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int g = l >> 4;
     const int64_t wave = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6;
     const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
     MlpRegs R;
     mlp_load_regs(M, R);
     const double dt = *dtp;
-    const int64_t ntiles = (n + 15) / 16;
-    for (int64_t t = wave; t < ntiles; t += nwaves) {
-        const int64_t p = t * 16 + (l & 15);
+    const int64_t nchunks = (n + 63) / 64;
+    for (int64_t ch = wave; ch < nchunks; ch += nwaves) {
+        const int64_t p = ch * 64 + l;
         const bool valid = p < n;
         double f[6] = {0, 0, 0, 0, 0, 0};
         if (valid) {
             raw_features(p, h, nc, rho, divv, m, vx, vy, vz, u, gamma, dt, f);
             for (int k = 0; k < 6; ++k) f[k] = (double)(float)f[k];
         }
-        s4_t x = feature_operand(f, M.norm, valid);
-        float a1[4][4], a2[4][4];
-        s4_t h1[4], h2[4];
-        float y = mlp_tile_forward(R, x, a1, h1, a2, h2);
-        if (valid && l < 16) {
-            double yc = fmin(fmax((double)y, -0.5), 0.5);
-            h_try[p] = h[p] * exp(yc);
-            if (y_out) y_out[p] = y;
+        for (int k = 0; k < 6; ++k)
+            xs[w][l][k] = valid ? bf16_bits_d((f[k] - M.norm[k]) / M.norm[6 + k]) : (uint16_t)0;
+        xs[w][l][6] = 0;
+        xs[w][l][7] = 0;
+        wave_lds_sync();
+        for (int t = 0; t < 4; ++t) {
+            const int q = 16 * t + (l & 15);
+            s4_t x;
+            for (int v = 0; v < 4; ++v) x[v] = (short)xs[w][q][(4 * g + v) & 7];
+            if (g >= 2) x = s4_t{0, 0, 0, 0};
+            float a1[4][4], a2[4][4];
+            s4_t h1[4], h2[4];
+            const float y = mlp_tile_forward(R, x, a1, h1, a2, h2);
+            const int64_t pt = ch * 64 + q;
+            if (l < 16 && pt < n) {
+                const double yc = fmin(fmax((double)y, -0.5), 0.5);
+                h_try[pt] = h[pt] * exp(yc);
+                if (y_out) y_out[pt] = y;
+            }
         }
+        wave_lds_sync();
     }
 }
 
@@ -581,12 +619,20 @@ static unsigned mlp_blocks(int64_t n)
     return (unsigned)ceil_div(waves, MLP_WAVES_PER_BLOCK);
 }
 
+// k_mlp_predict: one wave per 64 particles, at most 8192 waves
+static unsigned mlp_predict_blocks(int64_t n)
+{
+    int64_t chunks = (n + 63) / 64;
+    int64_t waves = chunks < 8192 ? chunks : 8192;
+    return (unsigned)ceil_div(waves, MLP_WAVES_PER_BLOCK);
+}
+
 hipError_t launch_mlp_predict(sph_ctx *c, sph_particles *s, double *h_try)
 {
     int64_t n = s->n;
     if (n == 0) return hipSuccess;
     int k = s->cur;
-    hipLaunchKernelGGL(k_mlp_predict, dim3(mlp_blocks(n)), dim3(SPH_BLOCK), 0, c->stream, n,
+    hipLaunchKernelGGL(k_mlp_predict, dim3(mlp_predict_blocks(n)), dim3(SPH_BLOCK), 0, c->stream, n,
                        mlp_dev(c), s->h[k], s->nc[k], s->rho[k], s->divv[k], s->m[k], s->pvx,
                        s->pvy, s->pvz, s->pu, c->p.gamma, c->w.dt_cur, h_try, (float *)nullptr);
     return hipGetLastError();

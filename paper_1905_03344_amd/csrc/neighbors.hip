@@ -137,18 +137,17 @@ __device__ __forceinline__ int count_fill(const Search &S, const double *__restr
 // next h stays inside it.  Particles that need another full count, and
 // those of small (scattered) groups, which round 0 leaves alone, go to the
 // tail: one wave per particle, full counts until the iteration ends.
-// With h_try (learned mode) round 0 counts at h_try[i] and accepts it when
-// in the band.  A miss whose plain start h[i] lies inside the try's shell
-// goes on with the plain iteration from h[i] on that shell, as the plain
-// solve's round 0 would; any other miss (also one whose count is unknown
-// because the try's shell overflowed) starts the plain iteration from h[i]
-// in one worklist round before the tail.  Groups in round 0 are formed from
-// positions and h[i] alone, and every particle gets the same budget of walks
-// before the tail, so a miss follows the plain solve's path; cells are
-// walked in Morton order, so its gather set does not depend on which wave
-// counts it.
-// The gather set of the last counted h is written (row i of idx); particles
-// whose kept h is not the last counted one are rewritten by k_refill.
+// With h_try (learned mode) round 0 counts at h_try[i], without a shell,
+// and accepts it when in the band.  A miss starts the plain iteration from
+// h[i] in the tail, whose first count of such a particle is the plain
+// solve's round-0 count (with the shell and the iteration on it); a miss
+// whose try equals h[i] exactly goes on with the plain iteration at once.
+// Every count is exact, so a miss follows the plain solve's path and ends
+// on its h; cells are walked in Morton order, so gather sets do not depend
+// on which wave counts them.
+// The gather set of the last counted h is written (row i of idx), ascending
+// (a set completed from a shell is merged in place); particles whose kept h
+// is not the last counted one are rewritten by k_refill.
 //
 // Counting is wave-cooperative: a wave owns 64 particles (consecutive in
 // Morton order, or consecutive entries of a worklist), split into groups of
@@ -452,6 +451,14 @@ __device__ __forceinline__ double tile_r2(const WaveLds &L, int t, double xi, do
 #ifndef SPH_SHELL_D
 #define SPH_SHELL_D 24.0
 #endif
+// shell of the learned try: 0, none (every miss restarts in the tail).  A
+// narrow one (|r - 2h| < 2h/96) would let misses whose h_prev is in band
+// converge without a new walk, but recording it costs more than the tail
+// saves: 64M patch 143 ms per step without, 163 ms with; 1M clumpy mixture
+// 4.75 against 4.88 ms
+#ifndef SPH_TRY_SHELL_D
+#define SPH_TRY_SHELL_D 0.0
+#endif
 struct Shell {
     int32_t *j;     // SPH_SHELL_SLOTS * sstride
     double *r2;     // SPH_SHELL_SLOTS * sstride
@@ -501,9 +508,12 @@ __device__ __forceinline__ double pair_r2(double xi, double yi, double zi, doubl
 // member lane tests every candidate (LDS tiles).  Transposed mode
 // (tm >= 0, one member, lane tm): lane t tests candidate t of each chunk of
 // 64 against the member, and the member's counters are kept wave-uniform.
+// Candidates with r^2 < T (A <= T <= B, the counted radius squared) are
+// written to the row in candidate order, those with A <= r^2 < B to the
+// shell; N counts the row's members.
 template <int PM, bool TRANSPOSED>
 __device__ void walk_group(WaveLds &L, uint64_t members, int tm, int64_t i, double xi, double yi,
-                           double zi, double A2, double B2, const double *__restrict__ x,
+                           double zi, double A2, double B2, double T2, const double *__restrict__ x,
                            const double *__restrict__ y, const double *__restrict__ z,
                            int32_t *__restrict__ idx, int64_t stride, int K, const Shell &SH,
                            const Search &S, const Geo &g, int &N, int &nsh, int32_t *&wp,
@@ -632,6 +642,7 @@ __device__ void walk_group(WaveLds &L, uint64_t members, int tm, int64_t i, doub
     const double zm = TRANSPOSED ? __shfl(zi, tm, 64) : 0.0;
     const double A2m = TRANSPOSED ? __shfl(A2, tm, 64) : 0.0;
     const double B2m = TRANSPOSED ? __shfl(B2, tm, 64) : 0.0;
+    const double T2m = TRANSPOSED ? __shfl(T2, tm, 64) : 0.0;
     const int64_t im = TRANSPOSED ? (int64_t)__shfl((int)i, tm, 64) : 0;
     int Nm = 0, nshm = 0;
     const uint64_t below = (1ull << lane) - 1ull;
@@ -685,7 +696,7 @@ __device__ void walk_group(WaveLds &L, uint64_t members, int tm, int64_t i, doub
                 if (j >= 0) {
                     r2 = wraps ? pair_r2<PM>(xm, ym, zm, x[j], y[j], z[j], g)
                                : pair_r2<0>(xm, ym, zm, x[j], y[j], z[j], g);
-                    hin = r2 < A2m && j != (int)im;
+                    hin = r2 < T2m && j != (int)im;
                     hsh = !(r2 < A2m) && r2 < B2m;
                 }
                 const uint64_t bin = __ballot(hin);
@@ -745,6 +756,7 @@ __device__ void walk_group(WaveLds &L, uint64_t members, int tm, int64_t i, doub
                             if (r2 < A2) {
                                 hin |= 1ull << t;
                             } else if (r2 < B2) {
+                                if (r2 < T2) hin |= 1ull << t;
                                 if (nsh >= 0 && nsh < SPH_SHELL_SLOTS) {
                                     SH.j[(int64_t)nsh * SH.sstride + i] = L.c[t].j;
                                     SH.r2[(int64_t)nsh * SH.sstride + i] = r2;
@@ -761,7 +773,23 @@ __device__ void walk_group(WaveLds &L, uint64_t members, int tm, int64_t i, doub
                         if (wraps) tile_hits<PM, false>(L, m, xi, yi, zi, A2, B2, g, &hin, &hsh);
                         else tile_hits<0, false>(L, m, xi, yi, zi, A2, B2, g, &hin, &hsh);
                     }
-                    // inner members in candidate order, skipping self
+                    // shell members with their exact r^2; those below T join
+                    // the row
+                    while (hsh) {
+                        int t = __ffsll((unsigned long long)hsh) - 1;
+                        hsh &= hsh - 1;
+                        const double r2 = wraps ? tile_r2<PM>(L, t, xi, yi, zi, g)
+                                                : tile_r2<0>(L, t, xi, yi, zi, g);
+                        if (r2 < T2) hin |= 1ull << t;
+                        if (nsh >= 0 && nsh < SPH_SHELL_SLOTS) {
+                            SH.j[(int64_t)nsh * SH.sstride + i] = L.c[t].j;
+                            SH.r2[(int64_t)nsh * SH.sstride + i] = r2;
+                            ++nsh;
+                        } else {
+                            nsh = -1;
+                        }
+                    }
+                    // the row's members in candidate order, skipping self
                     while (hin) {
                         int t = __ffsll((unsigned long long)hin) - 1;
                         hin &= hin - 1;
@@ -769,20 +797,6 @@ __device__ void walk_group(WaveLds &L, uint64_t members, int tm, int64_t i, doub
                         if (jj != (int)i) {
                             if (N < K) wp[N] = jj;
                             ++N;
-                        }
-                    }
-                    // shell members with their exact r^2
-                    while (hsh) {
-                        int t = __ffsll((unsigned long long)hsh) - 1;
-                        hsh &= hsh - 1;
-                        if (nsh >= 0 && nsh < SPH_SHELL_SLOTS) {
-                            double r2 = wraps ? tile_r2<PM>(L, t, xi, yi, zi, g)
-                                              : tile_r2<0>(L, t, xi, yi, zi, g);
-                            SH.j[(int64_t)nsh * SH.sstride + i] = L.c[t].j;
-                            SH.r2[(int64_t)nsh * SH.sstride + i] = r2;
-                            ++nsh;
-                        } else {
-                            nsh = -1;
                         }
                     }
                 }
@@ -858,11 +872,11 @@ __device__ void walk_group(WaveLds &L, uint64_t members, int tm, int64_t i, doub
 }
 
 // One wave-cooperative count for every lane with act set at its own hc:
-// members with r^2 < A are written to row i of idx (at most K), shell
-// members (A <= r^2 < B) to the shell arrays (at most SPH_SHELL_SLOTS;
-// *nsh = -1 when more).  Returns the number of inner members (self
-// excluded); self is never a shell member.  With A = B there is no shell and
-// the whole gather set at sqrt(A)/2 is written.  The output does not depend
+// the gather set at hc (members with r^2 < T = (2 hc)^2) is written to row i
+// of idx (at most K, ascending), shell members (A <= r^2 < B) to the shell
+// arrays (at most SPH_SHELL_SLOTS; *nsh = -1 when more).  Returns the number
+// of the row's members (self excluded); self is never a shell member.  With
+// A = B = T there is no shell.  The output does not depend
 // on which lanes are counted together.  Lanes are grouped by position and by
 // hsplit (their h for that purpose); with DEFER, lanes that end up in
 // a small group are not counted and get *deferred = true (their particles
@@ -870,7 +884,7 @@ __device__ void walk_group(WaveLds &L, uint64_t members, int tm, int64_t i, doub
 template <int PM, bool DEFER>
 __device__ int wave_count(WaveLds &L, bool act, int64_t i, double xi, double yi, double zi,
                           uint32_t ki, double hsplit, bool *deferred,
-                          double A2, double B2, const double *__restrict__ x,
+                          double A2, double B2, double T2, const double *__restrict__ x,
                           const double *__restrict__ y, const double *__restrict__ z,
                           int32_t *__restrict__ idx, int64_t stride, int K, const Shell &SH,
                           int *nsh_out, const Search &S, const Geo &g, int64_t &tested)
@@ -923,11 +937,11 @@ __device__ int wave_count(WaveLds &L, bool act, int64_t i, double xi, double yi,
             while (rest) {
                 const int m = __ffsll((unsigned long long)rest) - 1;
                 rest &= rest - 1;
-                walk_group<PM, true>(L, 1ull << m, m, i, xi, yi, zi, A2, B2, x, y, z, idx, stride,
+                walk_group<PM, true>(L, 1ull << m, m, i, xi, yi, zi, A2, B2, T2, x, y, z, idx, stride,
                                      K, SH, S, g, N, nsh, wp, tested);
             }
         } else {
-            walk_group<PM, false>(L, members, -1, i, xi, yi, zi, A2, B2, x, y, z, idx, stride, K,
+            walk_group<PM, false>(L, members, -1, i, xi, yi, zi, A2, B2, T2, x, y, z, idx, stride, K,
                                   SH, S, g, N, nsh, wp, tested);
         }
     }
@@ -964,7 +978,12 @@ __device__ __forceinline__ void hs_store(const HIter &H, int64_t i, const HState
 }
 
 #define HS_WALK 256        // one full walk in the bits field
-#define SPH_WAVE_ROUNDS 0  // worklist rounds after round 0 (one more after a try pass)
+#ifndef SPH_FIRST_SHELL
+#define SPH_FIRST_SHELL 1  // round 0 of the plain solve records the shell of its count
+#endif
+#ifndef SPH_WAVE_ROUNDS
+#define SPH_WAVE_ROUNDS 0  // worklist rounds after round 0
+#endif
 
 // one step of the iteration after a count N at hc.
 // returns 0 = count again at s.next, 1 = converged, 2 = stopped unconverged
@@ -1045,16 +1064,18 @@ struct HArgs {
     int64_t *status;
 };
 
-// After a walk at hc that wrote the nin members closer than sqrt(A)/2 to
-// row i and the nsh shell members (A <= r^2 < B; -1 when they overflowed)
-// to the shell arrays: one iteration step at hc, then more while the next h
-// stays inside the shell, all counted exactly from the shell.  Returns the
-// h_update result; 0 leaves st.next for the next full count (hc itself after
-// an overflow).  When the iteration ends, the kept h's gather set is
-// completed in the row (writer) if it lies in this shell, else
-// st.last_h = -1 marks the row for rewriting.
+// After a walk at hc that wrote the gather set at hc (nrow members, r^2 <
+// T = (2 hc)^2) to row i and the nsh shell members (A <= r^2 < B; -1 when
+// they overflowed) to the shell arrays: one iteration step at hc, then more
+// while the next h stays inside the shell, all counted exactly from the
+// shell.  Returns the h_update result; 0 leaves st.next for the next full
+// count (hc itself after an overflow).  When the iteration ends on an h
+// inside this shell other than hc, the writer adjusts the row to that h's
+// gather set (shell members merged in or taken out, the row stays
+// ascending); a kept h outside the shell sets st.last_h = -1, marking the
+// row for rewriting.
 __device__ int shell_iterate(const HArgs &A, int64_t i, HState &st, double hc, double hprev,
-                             int nin, int nsh, double A2, double B2, bool writer, uint8_t &fl,
+                             int nrow, int nsh, double A2, double B2, bool writer, uint8_t &fl,
                              int64_t &counts, int64_t &acc, int64_t &fallback)
 {
 #pragma clang fp contract(off)
@@ -1062,16 +1083,24 @@ __device__ int shell_iterate(const HArgs &A, int64_t i, HState &st, double hc, d
         st.next = hc;   // shell overflow: the exact count needs a full walk
         return 0;
     }
+    const int64_t ss = A.SH.sstride;
+    const double t0 = 2.0 * hc;
+    const double T2 = t0 * t0;
+    // members closer than the shell's inner radius (read from the shell only
+    // when the iteration goes on past hc)
+    int nin = -1;
     auto shell_count = [&](double r2m) {
+        if (nin < 0) {
+            nin = nrow;
+            for (int k = 0; k < nsh; ++k) nin -= A.SH.r2[(int64_t)k * ss + i] < T2 ? 1 : 0;
+        }
         int c = nin;
-        for (int k = 0; k < nsh; ++k) c += A.SH.r2[(int64_t)k * A.SH.sstride + i] < r2m ? 1 : 0;
+        for (int k = 0; k < nsh; ++k) c += A.SH.r2[(int64_t)k * ss + i] < r2m ? 1 : 0;
         return c;
     };
     auto in_shell = [&](double r2m) { return r2m >= A2 && r2m <= B2; };
-    const double t0 = 2.0 * hc;
     ++counts;
-    int res = h_update(st, hc, shell_count(t0 * t0), hprev, A.target, A.tol, A.maxit, A.hk, fl,
-                       acc, fallback);
+    int res = h_update(st, hc, nrow, hprev, A.target, A.tol, A.maxit, A.hk, fl, acc, fallback);
     while (res == 0) {
         const double tn = 2.0 * st.next;
         const double r2n = tn * tn;
@@ -1082,21 +1111,60 @@ __device__ int shell_iterate(const HArgs &A, int64_t i, HState &st, double hc, d
                        fallback);
     }
     if (res != 0) {
-        // the gather set of the kept h: inner members are in place when the
-        // kept h lies in this shell; append its shell members
         const double tk = 2.0 * st.best_h;
         const double r2k = tk * tk;
-        if (in_shell(r2k) && st.best_n == shell_count(r2k)) {
-            if (writer) {
-                int pos = nin;
-                for (int k = 0; k < nsh; ++k) {
-                    if (A.SH.r2[(int64_t)k * A.SH.sstride + i] < r2k) {
-                        if (pos < A.K) A.idx[i * (int64_t)A.K + pos] = A.SH.j[(int64_t)k * A.SH.sstride + i];
-                        ++pos;
+        if (in_shell(r2k) && (r2k == T2 ? st.best_n == nrow : st.best_n == shell_count(r2k))) {
+            st.last_h = st.best_h;
+            if (r2k != T2 && (nrow > A.K || st.best_n > A.K)) {
+                // the row does not hold the gather set at hc whole: rewrite it
+                if (st.best_n <= A.K) st.last_h = -1.0;
+            } else if (writer && r2k > T2) {
+                // shell members with T <= r^2 < (2h)^2 join the row: merge
+                // from the back, in place (both runs ascending and disjoint)
+                int32_t *row = A.idx + i * (int64_t)A.K;
+                auto prev_in = [&](int k) {
+                    while (k >= 0) {
+                        const double r2 = A.SH.r2[(int64_t)k * ss + i];
+                        if (!(r2 < T2) && r2 < r2k) break;
+                        --k;
+                    }
+                    return k;
+                };
+                int k = prev_in(nsh - 1);
+                int p = nrow - 1;
+                for (int o = st.best_n - 1; k >= 0; --o) {
+                    const int32_t sj = A.SH.j[(int64_t)k * ss + i];
+                    const int32_t ij = p >= 0 ? row[p] : 0;
+                    if (p >= 0 && ij > sj) {
+                        row[o] = ij;
+                        --p;
+                    } else {
+                        row[o] = sj;
+                        k = prev_in(k - 1);
                     }
                 }
+            } else if (writer && r2k < T2) {
+                // shell members with (2h)^2 <= r^2 < T leave the row
+                int32_t *row = A.idx + i * (int64_t)A.K;
+                auto next_out = [&](int k) {
+                    while (k < nsh) {
+                        const double r2 = A.SH.r2[(int64_t)k * ss + i];
+                        if (!(r2 < r2k) && r2 < T2) break;
+                        ++k;
+                    }
+                    return k;
+                };
+                int k = next_out(0);
+                int o = 0;
+                for (int q = 0; q < nrow; ++q) {
+                    const int32_t v = row[q];
+                    if (k < nsh && v == A.SH.j[(int64_t)k * ss + i]) {
+                        k = next_out(k + 1);
+                        continue;
+                    }
+                    row[o++] = v;
+                }
             }
-            st.last_h = st.best_h;
         } else {
             st.last_h = -1.0;   // the kept h lies outside this shell: rewrite its set
         }
@@ -1147,8 +1215,17 @@ __attribute__((amdgpu_waves_per_eu(SPH_ROUND_WAVES, SPH_ROUND_WAVES))) void k_hs
         }
     }
     int64_t tested = 0, counts = 0, acc = 0, fallback = 0, nonconv = 0, overflow = 0;
-    const double ta = 2.0 * hc * (1.0 - 1.0 / SPH_SHELL_D), tb = 2.0 * hc * (1.0 + 1.0 / SPH_SHELL_D);
-    const double A2 = ta * ta, B2 = tb * tb;
+    // The learned try, accepted almost always, is counted without a shell
+    // (SPH_TRY_SHELL_D): a miss restarts the plain iteration from h_prev,
+    // with its shell, in the tail.  Plain counts record the shell, on which
+    // most misses of h_prev converge.
+    const bool try_walk = FIRST && A.h_try != nullptr;
+    const double sd = try_walk ? SPH_TRY_SHELL_D
+                               : ((FIRST && !SPH_FIRST_SHELL) ? 0.0 : SPH_SHELL_D);
+    const double ta = sd > 0.0 ? 2.0 * hc * (1.0 - 1.0 / sd) : 2.0 * hc;
+    const double tb = sd > 0.0 ? 2.0 * hc * (1.0 + 1.0 / sd) : 2.0 * hc;
+    const double tt = 2.0 * hc;
+    const double A2 = ta * ta, B2 = tb * tb, T2 = tt * tt;
     int nin = 0, nsh = 0;
     bool deferred = false;
     // a wave whose slots are all past the end has nothing to do.  Round 0
@@ -1162,7 +1239,7 @@ __attribute__((amdgpu_waves_per_eu(SPH_ROUND_WAVES, SPH_ROUND_WAVES))) void k_hs
             ki = A.key[i];
         }
         nin = wave_count<PM, FIRST>(lds[w], valid, i, xi, yi, zi, ki, hsplit, &deferred, A2, B2,
-                                    A.x, A.y, A.z, A.idx, A.stride, A.K, A.SH, &nsh, S, A.g,
+                                    T2, A.x, A.y, A.z, A.idx, A.stride, A.K, A.SH, &nsh, S, A.g,
                                     tested);
     }
     double hprev = 0.0;
@@ -1280,10 +1357,11 @@ __global__ __launch_bounds__(SPH_BLOCK) __attribute__((amdgpu_waves_per_eu(2, 2)
             if (shell_walk) {
                 shell_walk = false;
                 const double ta = 2.0 * hc * (1.0 - 1.0 / SPH_SHELL_D), tb = 2.0 * hc * (1.0 + 1.0 / SPH_SHELL_D);
-                const double A2 = ta * ta, B2 = tb * tb;
+                const double tt = 2.0 * hc;
+                const double A2 = ta * ta, B2 = tb * tb, T2 = tt * tt;
                 int nin = wave_count<PM, false>(lds[w], lane == 0, i, xi, yi, zi, ki, hc, &dfr, A2,
-                                                B2, A.x, A.y, A.z, A.idx, A.stride, A.K, A.SH, &nsh,
-                                                S, A.g, tested);
+                                                B2, T2, A.x, A.y, A.z, A.idx, A.stride, A.K, A.SH,
+                                                &nsh, S, A.g, tested);
                 nin = __shfl(nin, 0, 64);
                 nsh = __shfl(nsh, 0, 64);
                 // the shell arrays were written by other lanes: make them visible
@@ -1295,7 +1373,7 @@ __global__ __launch_bounds__(SPH_BLOCK) __attribute__((amdgpu_waves_per_eu(2, 2)
             const double t2 = 2.0 * hc;
             const double r2m = t2 * t2;
             int N = wave_count<PM, false>(lds[w], lane == 0, i, xi, yi, zi, ki, hc, &dfr, r2m, r2m,
-                                   A.x, A.y, A.z, A.idx, A.stride, A.K, A.SH, &nsh, S, A.g,
+                                   r2m, A.x, A.y, A.z, A.idx, A.stride, A.K, A.SH, &nsh, S, A.g,
                                    tested);
             N = __shfl(N, 0, 64);
             ++counts;
@@ -1339,8 +1417,8 @@ __global__ __launch_bounds__(SPH_BLOCK) void k_refill(HArgs A, int64_t n)
         const double r2m = t2 * t2;
         int nsh = 0;
         bool dfr;
-        int N = wave_count<PM, false>(lds[w], act, i, xi, yi, zi, ki, hi, &dfr, r2m, r2m, A.x, A.y,
-                               A.z, A.idx, A.stride, A.K, A.SH, &nsh, S, A.g, tested);
+        int N = wave_count<PM, false>(lds[w], act, i, xi, yi, zi, ki, hi, &dfr, r2m, r2m, r2m, A.x,
+                               A.y, A.z, A.idx, A.stride, A.K, A.SH, &nsh, S, A.g, tested);
         if (act && N > A.K) ++overflow;
     }
     block_add_i64(overflow, A.status + ST_LIST_OVERFLOW);
@@ -1470,5 +1548,76 @@ hipError_t launch_extra(sph_ctx *c, sph_particles *s, sph_nlist *nl)
         hipLaunchKernelGGL(k_extra<PM>, dim3(nb), dim3(SPH_BLOCK), 0, c->stream, n, s->x[cur],
                            s->y[cur], s->z[cur], s->h[cur], s->nc[cur], nl->idx, nl->stride,
                            p.list_stride, g, nl->ecnt, nl->eidx, p.extra_slots, c->w.status))
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// The interaction sets as CSR, S_i = L_i U E_i with ascending rows, exported
+// from the padded rows: row sizes, their exclusive scan, then every row
+// merged by ranking.  L_i is ascending and E_i unordered; the two are
+// disjoint, so an entry's place in S_i is the number of entries of both
+// below it (a binary search in L_i, a count over the short E_i).
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(SPH_BLOCK) void k_csr_sizes(int64_t n, const int32_t *__restrict__ nc,
+                                                         int K, const int32_t *__restrict__ ecnt,
+                                                         int slots, int32_t *__restrict__ sz)
+{
+    const int64_t i = global_index();
+    if (i < n) sz[i] = min(nc[i], K) + min(ecnt[i], slots);
+}
+
+__global__ __launch_bounds__(SPH_BLOCK) void k_csr_fill(
+    int64_t n, const int32_t *__restrict__ nc, const int32_t *__restrict__ idx, int K,
+    const int32_t *__restrict__ ecnt, const int32_t *__restrict__ eidx, int slots,
+    const int64_t *__restrict__ off, int32_t *__restrict__ out, int64_t cap,
+    int64_t *__restrict__ status)
+{
+    const int64_t i = global_index();
+    int64_t dropped = 0;
+    if (i < n) {
+        const int nl = min(nc[i], K), ne = min(ecnt[i], slots);
+        const int32_t *L = idx + i * (int64_t)K;
+        const int32_t *E = eidx + i * (int64_t)slots;
+        const int64_t o = off[i];
+        for (int k = 0; k < nl; ++k) {
+            const int32_t v = L[k];
+            int r = k;
+            for (int e = 0; e < ne; ++e) r += E[e] < v ? 1 : 0;
+            if (o + r < cap) out[o + r] = v;
+            else ++dropped;
+        }
+        for (int e = 0; e < ne; ++e) {
+            const int32_t v = E[e];
+            int r = 0;
+            for (int f = 0; f < ne; ++f) r += E[f] < v ? 1 : 0;
+            int a = 0, b = nl;   // entries of L below v: the first index with L[a] > v
+            while (a < b) {
+                const int mid = (a + b) >> 1;
+                if (L[mid] < v) a = mid + 1;
+                else b = mid;
+            }
+            r += a;
+            if (o + r < cap) out[o + r] = v;
+            else ++dropped;
+        }
+    }
+    block_add_i64(dropped, status + ST_CSR_OVERFLOW);
+}
+
+hipError_t launch_interaction_csr(sph_ctx *c, const sph_particles *s, const sph_nlist *nl,
+                                  int64_t *off, int32_t *out, int64_t cap)
+{
+    const int64_t n = s->n;
+    const sph_params &p = c->p;
+    const int cur = s->cur;
+    const unsigned nb = (unsigned)ceil_div(n > 0 ? n : 1, SPH_BLOCK);
+    if (n > 0)
+        hipLaunchKernelGGL(k_csr_sizes, dim3(nb), dim3(SPH_BLOCK), 0, c->stream, n, s->nc[cur],
+                           p.list_stride, nl->ecnt, p.extra_slots, c->w.work);
+    hipError_t e = launch_scan_i32_to_i64(c, c->w.work, off, n);
+    if (e != hipSuccess || n == 0) return e;
+    hipLaunchKernelGGL(k_csr_fill, dim3(nb), dim3(SPH_BLOCK), 0, c->stream, n, s->nc[cur],
+                       nl->idx, p.list_stride, nl->ecnt, nl->eidx, p.extra_slots, off, out, cap,
+                       c->w.status);
     return hipGetLastError();
 }

@@ -61,14 +61,17 @@ __global__ __launch_bounds__(SPH_BLOCK) void k_pack64(
     P.vzm[i] = make_double2(vz[i], m[i]);
 }
 
-// GH: also the grad-h factor Omega_i = 1 - (1/(3 rho_i)) sum_j m_j (3 W + r dW/dr)
-template <int PM, bool EXTRA, int KER, bool GH>
+// GH: also the grad-h factor Omega_i = 1 - (1/(3 rho_i)) sum_j m_j (3 W + r dW/dr).
+// GV: generalized volume elements, Y_i = X_i W(0,h_i) + sum_{L_i} X_j W(r_ij,h_i)
+// (stored in ysum) and rho_i = m_i Y_i / X_i; the divergence keeps m_j.
+template <int PM, bool EXTRA, int KER, bool GH, bool GV>
 __global__ __launch_bounds__(SPH_BLOCK) SPH_PAIR_WAVES_D void k_density(
     int64_t n, Pk64 P, const int32_t *__restrict__ nc, const int32_t *__restrict__ idx, int K, Geo g,
     double knorm,
     double *__restrict__ rho, double *__restrict__ divv, double *__restrict__ omega,
     int32_t *__restrict__ ecnt,
-    int32_t *__restrict__ eidx, int slots, int64_t *__restrict__ status)
+    int32_t *__restrict__ eidx, int slots, int64_t *__restrict__ status,
+    const double *__restrict__ X, double *__restrict__ ysum)
 {
     const int lane = threadIdx.x & (SPH_GROUP - 1);
     const int grp = threadIdx.x / SPH_GROUP;
@@ -96,13 +99,14 @@ __global__ __launch_bounds__(SPH_BLOCK) SPH_PAIR_WAVES_D void k_density(
                     jb[q] = k < cnt ? row[k] : (int)i;
                 }
                 double xb[SPH_BATCH], yb[SPH_BATCH], zb[SPH_BATCH], hb[SPH_BATCH], mb[SPH_BATCH];
-                double ub[SPH_BATCH], vb[SPH_BATCH], wb[SPH_BATCH];
+                double ub[SPH_BATCH], vb[SPH_BATCH], wb[SPH_BATCH], qb[SPH_BATCH];
 #pragma unroll
                 for (int q = 0; q < SPH_BATCH; ++q) {
                     const int j = jb[q];
                     const double2 a = P.xy[j], b = P.zh[j], cv = P.vxy[j], d = P.vzm[j];
                     xb[q] = a.x; yb[q] = a.y; zb[q] = b.x; hb[q] = b.y;
                     ub[q] = cv.x; vb[q] = cv.y; wb[q] = d.x; mb[q] = d.y;
+                    qb[q] = GV ? X[j] : 0.0;
                 }
 #pragma unroll
                 for (int q = 0; q < SPH_BATCH; ++q) {
@@ -121,7 +125,7 @@ __global__ __launch_bounds__(SPH_BLOCK) SPH_PAIR_WAVES_D void k_density(
                     double rr = sqrt(r2);
                     double mj = mb[q];
                     const double wk = kern_w<KER>(rr, inv_h, knorm);
-                    s += mj * wk;
+                    s += (GV ? qb[q] : mj) * wk;
                     if (rr > 0.0) {
                         const double dw = kern_dwdr<KER>(rr, inv_h, knorm);
                         double gw = dw / rr;
@@ -139,7 +143,15 @@ __global__ __launch_bounds__(SPH_BLOCK) SPH_PAIR_WAVES_D void k_density(
         if (GH) t = group_sum(t);
         if (i < n && lane == 0) {
             const double w0 = kern_w<KER>(0.0, inv_h, knorm);
-            const double rh = mi * w0 + s;
+            double rh;
+            if (GV) {
+                const double xi_w = X[i];
+                const double yv = xi_w * w0 + s;
+                rh = mi * yv / xi_w;
+                ysum[i] = yv;
+            } else {
+                rh = mi * w0 + s;
+            }
             rho[i] = rh;
             divv[i] = dv / rh;
             if (GH) omega[i] = 1.0 - (3.0 * mi * w0 + t) / (3.0 * rh);
@@ -228,6 +240,15 @@ hipError_t launch_sort_extra(sph_ctx *c, const sph_nlist *nl, int64_t n)
     return hipGetLastError();
 }
 
+// generalized volume elements: X_i = (m_i / rho_i)^p from the density held
+__global__ __launch_bounds__(SPH_BLOCK) void k_gve_weights(int64_t n, const double *__restrict__ m,
+                                                           const double *__restrict__ rho,
+                                                           double p, double *__restrict__ X)
+{
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i < n) X[i] = pow(m[i] / rho[i], p);
+}
+
 hipError_t launch_density(sph_ctx *c, sph_particles *s, const sph_nlist *nl, bool build_extra)
 {
     int64_t n = s->n;
@@ -245,34 +266,48 @@ hipError_t launch_density(sph_ctx *c, sph_particles *s, const sph_nlist *nl, boo
 #define SPH_DENSITY_ARGS                                                                        \
     dim3(nb), dim3(SPH_BLOCK), 0, c->stream, n, P, s->nc[cur], nl->idx, c->p.list_stride, g,     \
         c->knorm, s->rho[cur], s->divv[cur], c->w.omega, nl->ecnt, nl->eidx, c->p.extra_slots,  \
-        c->w.status
-    if (c->p.grad_h) {
-        if (build_extra) {
-            SPH_DISPATCH_KER(c->p.kernel, SPH_DISPATCH_PM(periodic_mask(g),
-                hipLaunchKernelGGL((k_density<PM, true, KER, true>), SPH_DENSITY_ARGS)))
-        } else {
-            SPH_DISPATCH_KER(c->p.kernel, SPH_DISPATCH_PM(periodic_mask(g),
-                hipLaunchKernelGGL((k_density<PM, false, KER, true>), SPH_DENSITY_ARGS)))
+        c->w.status, c->w.gve_x, c->w.gve_y
+#define SPH_DENSITY(EX, GHV, GVV)                                                               \
+    SPH_DISPATCH_KER(c->p.kernel, SPH_DISPATCH_PM(periodic_mask(g),                             \
+        hipLaunchKernelGGL((k_density<PM, EX, KER, GHV, GVV>), SPH_DENSITY_ARGS)))
+    if (c->p.volumes == SPH_VOLUMES_GENERALIZED) {
+        // the weights come from the density of the previous evaluation; an
+        // evaluation that starts a run forms the standard density first
+        bool extra = build_extra;
+        if (c->gve_fresh) {
+            if (extra) { SPH_DENSITY(true, false, false) }
+            else { SPH_DENSITY(false, false, false) }
+            extra = false;
         }
+        hipLaunchKernelGGL(k_gve_weights, dim3(nb), dim3(SPH_BLOCK), 0, c->stream, n, s->m[cur],
+                           s->rho[cur], c->p.gve_exponent, c->w.gve_x);
+        if (extra) { SPH_DENSITY(true, false, true) }
+        else { SPH_DENSITY(false, false, true) }
+    } else if (c->p.grad_h) {
+        if (build_extra) { SPH_DENSITY(true, true, false) }
+        else { SPH_DENSITY(false, true, false) }
     } else if (build_extra) {
-        SPH_DISPATCH_KER(c->p.kernel, SPH_DISPATCH_PM(periodic_mask(g),
-            hipLaunchKernelGGL((k_density<PM, true, KER, false>), SPH_DENSITY_ARGS)))
+        SPH_DENSITY(true, false, false)
     } else {
-        SPH_DISPATCH_KER(c->p.kernel, SPH_DISPATCH_PM(periodic_mask(g),
-            hipLaunchKernelGGL((k_density<PM, false, KER, false>), SPH_DENSITY_ARGS)))
+        SPH_DENSITY(false, false, false)
     }
+#undef SPH_DENSITY
 #undef SPH_DENSITY_ARGS
     return hipGetLastError();
 }
 
 // ideal gas; the neighbour record carries P / (Omega rho^2) (Omega = 1
-// without grad-h terms, omega NULL)
+// without grad-h terms, omega NULL), or with generalized volume elements
+// (X non-NULL) q = (X/m) P / Y^2
 __global__ __launch_bounds__(SPH_BLOCK) void k_eos(int64_t n, const double *__restrict__ rho,
                                                    const double *__restrict__ u, double gamma,
                                                    const double *__restrict__ omega,
                                                    double *__restrict__ p, double *__restrict__ c,
                                                    double2 *__restrict__ rp, int check,
-                                                   int64_t *__restrict__ status)
+                                                   int64_t *__restrict__ status,
+                                                   const double *__restrict__ X,
+                                                   const double *__restrict__ m,
+                                                   const double *__restrict__ ysum)
 {
     int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     int64_t bad = 0;
@@ -282,8 +317,13 @@ __global__ __launch_bounds__(SPH_BLOCK) void k_eos(int64_t n, const double *__re
         double cv = sqrt(gamma * (gamma - 1.0) * u[i]);
         p[i] = pv;
         c[i] = cv;
-        const double den = omega ? omega[i] * (rh * rh) : rh * rh;
-        rp[i] = make_double2(rh, pv / den);   // P / (Omega rho^2) once per particle
+        if (X) {
+            const double yv = ysum[i];
+            rp[i] = make_double2(rh, X[i] / m[i] * pv / (yv * yv));
+        } else {
+            const double den = omega ? omega[i] * (rh * rh) : rh * rh;
+            rp[i] = make_double2(rh, pv / den);   // P / (Omega rho^2) once per particle
+        }
         if (check && !(isfinite(pv) && isfinite(cv) && isfinite(rho[i]))) bad = 1;
     }
     if (check) block_add_i64(bad, status + ST_NONFINITE);
@@ -296,7 +336,7 @@ hipError_t launch_eos(sph_ctx *c, sph_particles *s)
     hipLaunchKernelGGL(k_eos, dim3((unsigned)ceil_div(n, SPH_BLOCK)), dim3(SPH_BLOCK), 0,
                        c->stream, n, s->rho[s->cur], s->pu, c->p.gamma,
                        c->p.grad_h ? c->w.omega : nullptr, s->p, s->c, ctx_pk64(c).rp,
-                       c->p.check_finite, c->w.status);
+                       c->p.check_finite, c->w.status, c->w.gve_x, s->m[s->cur], c->w.gve_y);
     return hipGetLastError();
 }
 
@@ -307,6 +347,7 @@ hipError_t launch_eos(sph_ctx *c, sph_particles *s)
 #define SPH_GR_AVG 0   // averaged kernel gradient
 #define SPH_GR_OWN 1   // each pressure term with its own kernel gradient (grad-h)
 #define SPH_GR_IAD 2   // each pressure term with its own IAD gradient
+#define SPH_GR_GVE 3   // generalized volume elements: r_i r_j (g_i grad W(h_i) + g_j grad W(h_j))
 
 struct ForceAcc {
     double ax, ay, az, du, mumax;
@@ -314,7 +355,8 @@ struct ForceAcc {
 
 // neighbour fields of one pair, gathered ahead of the arithmetic
 struct NbrF {
-    double x, y, z, vx, vy, vz, m, h, rho, p, c;   // p holds P / (Omega rho^2)
+    double x, y, z, vx, vy, vz, m, h, rho, p, c;   // p holds P / (Omega rho^2), or q = r g
+    double xw;                                     // generalized volumes: X_j
     double cm[6];                                  // IAD: c_j (xx, xy, xz, yy, yz, zz)
 };
 
@@ -412,13 +454,14 @@ hipError_t launch_iad(sph_ctx *c, sph_particles *s, const sph_nlist *nl)
 
 template <int GR>
 __device__ __forceinline__ NbrF load_nbr(int j, const Pk64 &P, const double *__restrict__ c,
-                                         const IadC &I)
+                                         const IadC &I, const double *__restrict__ Xw)
 {
     NbrF b;
     const double2 a = P.xy[j], zh = P.zh[j], v = P.vxy[j], vm = P.vzm[j], rp = P.rp[j];
     b.x = a.x; b.y = a.y; b.z = zh.x; b.h = zh.y;
     b.vx = v.x; b.vy = v.y; b.vz = vm.x; b.m = vm.y;
     b.rho = rp.x; b.p = rp.y; b.c = c[j];
+    b.xw = GR == SPH_GR_GVE ? Xw[j] : 0.0;
     if (GR == SPH_GR_IAD) {
         const double2 p0 = I.a[j], p1 = I.b[j], p2 = I.c[j];
         b.cm[0] = p0.x; b.cm[1] = p0.y; b.cm[2] = p1.x;
@@ -430,13 +473,16 @@ __device__ __forceinline__ NbrF load_nbr(int j, const Pk64 &P, const double *__r
 // GR: SPH_GR_AVG everything with the averaged kernel gradient; SPH_GR_OWN
 // pressure terms with each particle's own kernel gradient (grad-h form), the
 // viscosity with the average; SPH_GR_IAD pressure terms with each particle's
-// own IAD gradient A = c d W, the viscosity with their mean (ci: c_i)
+// own IAD gradient A = c d W, the viscosity with their mean (ci: c_i);
+// SPH_GR_GVE the generalized-volume pressure terms (pi_term = q_i = r_i g_i,
+// b.p = q_j, ri = X_i / m_i, b.xw = X_j), the viscosity with the average
 template <int PM, int KER, int GR>
 __device__ __forceinline__ void force_pair(const NbrF &b, double xi, double yi, double zi,
                                            double vxi, double vyi, double vzi, double hi,
                                            double inv_hi, double rhoi, double ci, double pi_term,
-                                           const double *cmi, const Geo &g, double knorm,
-                                           double alpha, double beta, double eta2, ForceAcc &A)
+                                           const double *cmi, double ri, const Geo &g,
+                                           double knorm, double alpha, double beta, double eta2,
+                                           ForceAcc &A)
 {
     double dx = mimg<PM, 0>(xi, b.x, g);
     double dy = mimg<PM, 1>(yi, b.y, g);
@@ -492,6 +538,16 @@ __device__ __forceinline__ void force_pair(const NbrF &b, double xi, double yi, 
     }
     double pj_term = b.p;
     double mj = b.m;
+    if (GR == SPH_GR_GVE) {
+        // m_j r_i r_j g_i = X_j q_i and m_j r_i r_j g_j = r_i m_j q_j
+        const double ti = b.xw * pi_term * gwi;
+        double f = (ti + ri * mj * pj_term * gwj) + mj * Pi * gbar;
+        A.ax -= f * xij;
+        A.ay -= f * yij;
+        A.az -= f * zij;
+        A.du += (ti + 0.5 * mj * Pi * gbar) * w;
+        return;
+    }
     if (GR == SPH_GR_OWN) {
         double f = mj * ((pi_term * gwi + pj_term * gwj) + Pi * gbar);
         A.ax -= f * xij;
@@ -512,7 +568,8 @@ __device__ __forceinline__ void force_pair(const NbrF &b, double xi, double yi, 
 // ELDS: E rows ranked in LDS here (capacity <= SPH_ELDS), else sorted already
 template <int PM, bool ELDS, int KER, int GR>
 __global__ __launch_bounds__(SPH_BLOCK) SPH_PAIR_WAVES_F void k_forces(
-    int64_t n, Pk64 P, IadC I, const double *__restrict__ c, const int32_t *__restrict__ nc, const int32_t *__restrict__ idx, int K,
+    int64_t n, Pk64 P, IadC I, const double *__restrict__ Xw, const double *__restrict__ c,
+    const int32_t *__restrict__ nc, const int32_t *__restrict__ idx, int K,
     const int32_t *__restrict__ ecnt, const int32_t *__restrict__ eidx, int slots, Geo g,
     double knorm, double alpha, double beta, double eta2, double cfl, double *__restrict__ ax,
     double *__restrict__ ay, double *__restrict__ az, double *__restrict__ du,
@@ -530,13 +587,14 @@ __global__ __launch_bounds__(SPH_BLOCK) SPH_PAIR_WAVES_F void k_forces(
         ForceAcc A = {0.0, 0.0, 0.0, 0.0, 0.0};
         double hi = 0.0, ci = 0.0;
         if (i < n) {
-            const NbrF me = load_nbr<GR>((int)i, P, c, I);
+            const NbrF me = load_nbr<GR>((int)i, P, c, I, Xw);
             const double xi = me.x, yi = me.y, zi = me.z;
             const double vxi = me.vx, vyi = me.vy, vzi = me.vz;
             hi = me.h;
             const double inv_hi = 1.0 / hi, rhoi = me.rho;
             ci = me.c;
             const double pi_term = me.p;
+            const double ri = GR == SPH_GR_GVE ? me.xw / me.m : 0.0;
             const int cnt = min(nc[i], K);
             const int ne = min(ecnt[i], slots);
             const int32_t *lrow = idx + i * (int64_t)K;
@@ -554,12 +612,12 @@ __global__ __launch_bounds__(SPH_BLOCK) SPH_PAIR_WAVES_F void k_forces(
                 NbrF nb[SPH_FBATCH];
 #pragma unroll
                 for (int q = 0; q < SPH_FBATCH; ++q)
-                    nb[q] = load_nbr<GR>(jb[q], P, c, I);
+                    nb[q] = load_nbr<GR>(jb[q], P, c, I, Xw);
 #pragma unroll
                 for (int q = 0; q < SPH_FBATCH; ++q) {
                     if (k0 + q * SPH_GROUP >= tot) break;
                     force_pair<PM, KER, GR>(nb[q], xi, yi, zi, vxi, vyi, vzi, hi, inv_hi, rhoi, ci,
-                                            pi_term, me.cm, g, knorm, alpha, beta, eta2, A);
+                                            pi_term, me.cm, ri, g, knorm, alpha, beta, eta2, A);
                 }
             }
         }
@@ -612,7 +670,8 @@ hipError_t launch_forces(sph_ctx *c, sph_particles *s, const sph_nlist *nl, doub
     double *part = c->w.red_part;
     Geo g = make_geo(p);
 #define SPH_FORCE_ARGS                                                                          \
-    dim3((unsigned)nb), dim3(SPH_BLOCK), 0, c->stream, n, ctx_pk64(c), I, s->c, s->nc[cur],      \
+    dim3((unsigned)nb), dim3(SPH_BLOCK), 0, c->stream, n, ctx_pk64(c), I, c->w.gve_x, s->c,      \
+        s->nc[cur],                                                                             \
         nl->idx, p.list_stride, nl->ecnt, nl->eidx, p.extra_slots, g, c->knorm, p.av_alpha,     \
         p.av_beta, p.av_eta2, p.cfl, s->ax[cur], s->ay[cur], s->az[cur], s->du[cur], part
     if (p.extra_slots > SPH_ELDS) {
@@ -635,6 +694,8 @@ hipError_t launch_forces(sph_ctx *c, sph_particles *s, const sph_nlist *nl, doub
         SPH_FORCE_GR(SPH_GR_IAD)
     } else if (p.grad_h) {
         SPH_FORCE_GR(SPH_GR_OWN)
+    } else if (p.volumes == SPH_VOLUMES_GENERALIZED) {
+        SPH_FORCE_GR(SPH_GR_GVE)
     } else {
         SPH_FORCE_GR(SPH_GR_AVG)
     }

@@ -47,6 +47,7 @@ enum {
     ST_EXTRA_TOTAL = 8,
     ST_CANDIDATES_FIRST = 9,   // candidates tested by round 0 of the h iteration
     ST_IAD_SINGULAR = 10,      // IAD moment matrices that could not be inverted
+    ST_CSR_OVERFLOW = 11,      // interaction-set CSR entries beyond the caller's capacity
     ST_COUNT = 16
 };
 
@@ -104,6 +105,8 @@ struct Workspace {
     double *dt_prev;       // AB2: the previous step's dt
     double *omega;         // grad-h: Omega of the last density (n_max, FP64 form)
     double2 *iad;          // IAD: c_i as 3 arrays of n_max double2 (xx,xy) (xz,yy) (yz,zz)
+    double *gve_x;         // generalized volumes: weights X (n_max)
+    double *gve_y;         // and the sums Y = sum_j X_j W(h_i) of the last density (n_max)
     int64_t nb_red;
     int64_t nb_sort;
     int64_t scan_part_len;
@@ -127,6 +130,7 @@ struct sph_ctx {
     int harvest_mode;      // SPH_TARGET_*
     double knorm;          // B_5 of the sinc kernel (sph_create)
     int ab2_hist;          // AB2: a step since the last bind / evaluation
+    int gve_fresh;         // generalized volumes: no previous density (sph_evaluate)
     char err[512];
 };
 
@@ -177,6 +181,8 @@ hipError_t launch_kick(sph_ctx *c, sph_particles *s);
 hipError_t launch_set_dt(sph_ctx *c, double dt, const double *d_dt);
 hipError_t launch_copy_pred(sph_ctx *c, sph_particles *s);
 hipError_t launch_conservation(sph_ctx *c, const sph_particles *s, double *out7);
+hipError_t launch_interaction_csr(sph_ctx *c, const sph_particles *s, const sph_nlist *nl,
+                                  int64_t *off, int32_t *out, int64_t cap);
 
 static inline Geo make_geo(const sph_params &p)
 {

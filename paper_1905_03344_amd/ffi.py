@@ -22,6 +22,8 @@ SPH_INTEGRATOR_KDK = 0
 SPH_INTEGRATOR_AB2 = 1
 SPH_GRADIENTS_KERNEL = 0
 SPH_GRADIENTS_IAD = 1
+SPH_VOLUMES_STANDARD = 0
+SPH_VOLUMES_GENERALIZED = 1
 SPH_KERNEL_M4 = 0
 SPH_KERNEL_WENDLAND = 1
 SPH_KERNEL_SINC5 = 2
@@ -47,7 +49,8 @@ class sph_params(ctypes.Structure):
                 ("h_max_iter", _I32), ("precision", _I32), ("gamma", _D), ("av_alpha", _D),
                 ("av_beta", _D), ("av_eta2", _D), ("cfl", _D), ("h_mode", _I32),
                 ("check_finite", _I32), ("max_level", _I32), ("search_div", _I32),
-                ("grad_h", _I32), ("gradients", _I32), ("walk_defer_group", _I32)]
+                ("grad_h", _I32), ("gradients", _I32), ("walk_defer_group", _I32),
+                ("volumes", _I32), ("pad1", _I32), ("gve_exponent", _D)]
 
 
 CARRIED_F64 = ("x", "y", "z", "vx", "vy", "vz", "m", "h", "u", "ax", "ay", "az", "du", "rho",
@@ -72,7 +75,8 @@ class sph_stats(ctypes.Structure):
     _fields_ = [("nonconverged", _I64), ("list_overflow", _I64), ("extra_total", _I64),
                 ("extra_overflow", _I64), ("nonfinite", _I64), ("h_counts", _I64),
                 ("learned_accepted", _I64), ("learned_fallback", _I64), ("candidates", _I64),
-                ("dt", _D), ("candidates_first", _I64), ("iad_singular", _I64)]
+                ("dt", _D), ("candidates_first", _I64), ("iad_singular", _I64),
+                ("csr_overflow", _I64)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -102,6 +106,7 @@ _SIGS = {
     "sph_evaluate": (ctypes.c_int, [_P, ctypes.POINTER(sph_particles), ctypes.POINTER(sph_nlist), _P]),
     "sph_step": (ctypes.c_int, [_P, ctypes.POINTER(sph_particles), ctypes.POINTER(sph_nlist), _D, _P]),
     "sph_conservation": (ctypes.c_int, [_P, ctypes.POINTER(sph_particles), _P]),
+    "sph_interaction_csr": (ctypes.c_int, [_P, ctypes.POINTER(sph_particles), ctypes.POINTER(sph_nlist), _P, _P, _I64]),
     "sph_conservation_noalloc": (ctypes.c_int, [ctypes.POINTER(sph_particles), _P, _P]),
     "sph_sync": (ctypes.c_int, [_P, ctypes.POINTER(sph_stats)]),
     "sph_last_error": (ctypes.c_char_p, [_P]),
@@ -227,6 +232,11 @@ def sph_evaluate(ctx, s, nl, d_dt: int):
 
 def sph_step(ctx, s, nl, dt: float, d_dt: int):
     check(lib().sph_step(ctx, ctypes.byref(s), ctypes.byref(nl), float(dt), d_dt), ctx)
+
+
+def sph_interaction_csr(ctx, s, nl, d_off: int, d_idx: int, capacity: int):
+    check(lib().sph_interaction_csr(ctx, ctypes.byref(s), ctypes.byref(nl), d_off, d_idx,
+                                    int(capacity)), ctx)
 
 
 def sph_conservation(ctx, s, d_out7: int):

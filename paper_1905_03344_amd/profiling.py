@@ -5,6 +5,9 @@
         --kernel "void k_hsolve_round<4, true>" --source neighbors.hip \\
         --workload square_patch_100^3_1M_fp64 --last 2 --out profiles/X_traffic.json
     python -m paper_1905_03344_amd.profiling stats --csv run_kernel_stats.csv --top 12
+    python -m paper_1905_03344_amd.profiling counters --csv A.csv B.csv \\
+        --kernel "void k_hsolve_round<4, true>" --source neighbors.hip \\
+        --workload "square_patch_400^3_64M" [--traffic T.json --duration-us D] --out C.json
 
 `traffic` turns two counter runs (FETCH_SIZE, then WRITE_SIZE, KiB per
 dispatch) into HBM bytes per launch of one kernel, each counter scaled by
@@ -76,6 +79,85 @@ def traffic(a):
     print(json.dumps(rec))
 
 
+# MI355X: 256 compute units of 4 SIMDs each
+CU_NUM = 256
+SIMD_NUM = 4 * CU_NUM
+
+
+def counters(a):
+    """Busy fractions of one kernel from counter passes (per dispatch, the
+    median of the last `last` dispatches; every pass run on the same
+    command):
+      valu_busy = SQ_ACTIVE_INST_VALU * 4 / SIMD_NUM / GRBM_GUI_ACTIVE
+      valu_lanes = SQ_THREAD_CYCLES_VALU / (64 SQ_ACTIVE_INST_VALU)
+      mfma_busy = SQ_VALU_MFMA_BUSY_CYCLES / (4 CU_NUM GRBM_GUI_ACTIVE)
+      ta_busy = TA_TA_BUSY (summed over units) / (CU_NUM GRBM_GUI_ACTIVE)
+      lds_busy = SQ_ACTIVE_INST_LDS * 4 / SIMD_NUM / GRBM_GUI_ACTIVE
+    and, with --traffic, the measured HBM fraction: the traffic record's
+    bytes per launch over the kernel's average duration (--duration-us)
+    against 8 TB/s.  `bound` names the busiest of VALU, TA and HBM."""
+    vals = {}
+    for path in a.csv:
+        seen = {}
+        for r in _rows(path):
+            if not r["Kernel_Name"].startswith(a.kernel):
+                continue
+            d = int(r["Dispatch_Id"])
+            key = (r["Counter_Name"], d)
+            seen[key] = seen.get(key, 0.0) + float(r["Counter_Value"])
+        names = {k[0] for k in seen}
+        for nm in names:
+            ds = sorted(d for (c, d) in seen if c == nm)[-a.last:]
+            vals[nm] = statistics.median(seen[(nm, d)] for d in ds)
+    g = vals.get("GRBM_GUI_ACTIVE")
+    rec = {"kernel": a.kernel, "workload": a.workload, "raw_per_dispatch": vals}
+    if g:
+        if "SQ_ACTIVE_INST_VALU" in vals:
+            rec["valu_busy"] = round(vals["SQ_ACTIVE_INST_VALU"] * 4 / SIMD_NUM / g, 4)
+            if "SQ_THREAD_CYCLES_VALU" in vals and vals["SQ_ACTIVE_INST_VALU"] > 0:
+                rec["valu_lanes"] = round(vals["SQ_THREAD_CYCLES_VALU"] /
+                                          (64.0 * vals["SQ_ACTIVE_INST_VALU"]), 4)
+        if "SQ_VALU_MFMA_BUSY_CYCLES" in vals:
+            rec["mfma_busy"] = round(vals["SQ_VALU_MFMA_BUSY_CYCLES"] / (4.0 * CU_NUM * g), 4)
+        if "TA_TA_BUSY" in vals:
+            rec["ta_busy"] = round(vals["TA_TA_BUSY"] / (CU_NUM * g), 4)
+        if "SQ_ACTIVE_INST_LDS" in vals:
+            rec["lds_busy"] = round(vals["SQ_ACTIVE_INST_LDS"] * 4 / SIMD_NUM / g, 4)
+    if a.traffic and a.duration_us:
+        with open(a.traffic) as f:
+            t = json.load(f)
+        rec["hbm_frac_measured"] = round(t["bytes_per_launch"] / (a.duration_us * 1e-6) / 8e12, 4)
+    cand = {k: rec[k] for k in ("valu_busy", "ta_busy", "hbm_frac_measured") if k in rec}
+    if cand:
+        top = max(cand, key=cand.get)
+        rec["bound"] = {"valu_busy": "alu", "ta_busy": "alu", "hbm_frac_measured": "hbm"}[top]
+        rec["busiest"] = top
+    rec["source"] = a.source
+    rec["source_sha256_16"] = source_digest(os.path.join(HERE, "csrc", a.source))
+    rec["commands"] = a.commands
+    with open(a.out, "w") as f:
+        json.dump(rec, f, indent=1)
+        f.write("\n")
+    print(json.dumps(rec))
+
+
+def dispatches(a):
+    """Average duration of the last `last` dispatches of each kernel whose
+    name starts with one of the prefixes, from a rocprofv3 kernel trace (the
+    timed steps of a run, after its t = 0 evaluation and warmup steps)."""
+    rows = _rows(a.trace)
+    print("| kernel | dispatches | avg us (last %d) |" % a.last)
+    print("|---|---|---|")
+    for pre in a.kernel:
+        ds = [r for r in rows if r["Kernel_Name"].startswith(pre)]
+        ds.sort(key=lambda r: int(r["Start_Timestamp"]))
+        tail = ds[-a.last:]
+        if not tail:
+            continue
+        us = [(int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3 for r in tail]
+        print(f"| `{pre}` | {len(ds)} | {sum(us) / len(us):.1f} |")
+
+
 def stats(a):
     rows = _rows(a.csv)
     rows.sort(key=lambda r: -float(r["TotalDurationNs"]))
@@ -99,8 +181,20 @@ def main(argv=None):
     s = sub.add_parser("stats")
     s.add_argument("--csv", required=True)
     s.add_argument("--top", type=int, default=12)
+    d = sub.add_parser("dispatches")
+    d.add_argument("--trace", required=True)
+    d.add_argument("--kernel", nargs="+", required=True)
+    d.add_argument("--last", type=int, default=3)
+    c = sub.add_parser("counters")
+    c.add_argument("--csv", nargs="+", required=True)
+    for k in ("kernel", "source", "workload", "out"):
+        c.add_argument("--" + k, required=True)
+    c.add_argument("--traffic")
+    c.add_argument("--duration-us", type=float)
+    c.add_argument("--last", type=int, default=1)
+    c.add_argument("--commands", nargs="*", default=[])
     a = ap.parse_args(argv)
-    traffic(a) if a.cmd == "traffic" else stats(a)
+    {"traffic": traffic, "stats": stats, "counters": counters, "dispatches": dispatches}[a.cmd](a)
 
 
 if __name__ == "__main__":

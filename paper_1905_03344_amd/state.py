@@ -31,13 +31,14 @@ class Simulation:
                  list_stride=128, extra_per_particle=48, max_level=None, search_div=2,
                  precision=ffi.SPH_FP64, check_finite=False, h_mode=ffi.SPH_H_PLAIN,
                  walk_prefilter=None, kernel=None, integrator=None, grad_h=False,
-                 gradients=None, walk_defer_group=None):
+                 gradients=None, walk_defer_group=None, volumes=None, gve_exponent=None):
         """Allocate the state and the workspace for ic and bind a context.
 
         precision: ffi.SPH_FP64 or ffi.SPH_MIXED; h_mode: ffi.SPH_H_PLAIN or
         ffi.SPH_H_LEARNED (weights via set_mlp); kernel: ffi.SPH_KERNEL_*;
         integrator: ffi.SPH_INTEGRATOR_KDK or _AB2; grad_h: grad-h correction
-        terms; gradients: ffi.SPH_GRADIENTS_KERNEL or _IAD; walk_prefilter:
+        terms; gradients: ffi.SPH_GRADIENTS_KERNEL or _IAD; volumes:
+        ffi.SPH_VOLUMES_STANDARD or _GENERALIZED (weights (m/rho)^gve_exponent); walk_prefilter:
         ffi.SPH_PREFILTER_MATRIX or _NONE; walk_defer_group: first-round
         sub-groups up to this size go to the per-particle tail (speed only).
         None keeps the library default.
@@ -74,6 +75,10 @@ class Simulation:
             p.gradients = int(gradients)
         if walk_defer_group is not None:
             p.walk_defer_group = int(walk_defer_group)
+        if volumes is not None:
+            p.volumes = int(volumes)
+        if gve_exponent is not None:
+            p.gve_exponent = float(gve_exponent)
         p.precision = int(precision)
         p.check_finite = int(bool(check_finite))
         p.h_mode = int(h_mode)
@@ -267,6 +272,18 @@ class Simulation:
         code = np.sort(ii.astype(np.int64) * max(n, 1) + e[kk, ii].astype(np.int64))
         eoff = np.concatenate([[0], np.cumsum(np.bincount(ii, minlength=n))]).astype(np.int64)
         return eoff, (code % max(n, 1)).astype(np.int32)
+
+    def interaction_csr_device(self):
+        """S_i = L_i U E_i as CSR with ascending rows, built by the library
+        (sph_interaction_csr): (off int64[n+1], idx int32[total]) tensors."""
+        off = torch.zeros(self.n + 1, dtype=torch.int64, device=self.device)
+        ffi.sph_interaction_csr(self.ctx, self.s, self.nl, off.data_ptr(), 0, 0)
+        self.sync(allow=(ffi.SPH_OK, ffi.SPH_WNOCONV, ffi.SPH_ECAPACITY))
+        total = int(off[-1].item())
+        idx = torch.zeros(max(total, 1), dtype=torch.int32, device=self.device)
+        ffi.sph_interaction_csr(self.ctx, self.s, self.nl, off.data_ptr(), idx.data_ptr(), total)
+        self.sync()
+        return off, idx[:total]
 
     def interaction_csr(self):
         """S_i = L_i U E_i as CSR with ascending rows (for comparisons)."""

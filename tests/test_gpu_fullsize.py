@@ -216,7 +216,11 @@ def _cells_and_h_sampled(sim, h_prev_by_id, half, rng_seed=11):
     hp = hprev[sel].cpu().numpy()
     per, lo, hi = (0, 0, 0), (-half,) * 3, (half,) * 3
     h, nc, flag, _, _ = O.hsolve(f["x"], f["y"], f["z"], hp, per, lo, hi)
-    hmax = max(float(f["h"].max()), float(h.max()))
+    # a trial h of the iteration stays within a factor 2 of h_prev (the
+    # largest Hernquist-Katz factor), so a particle 4 max(h_prev, h) inside
+    # the cube sees all it counts; particles near the cube's faces (where
+    # the oracle's counts are truncated and its h grows) are not compared
+    hmax = max(float(f["h"].max()), float(hp.max()))
     inner = half - 4.0 * hmax * 1.01
     deep = (np.abs(f["x"]) < inner) & (np.abs(f["y"]) < inner) & (np.abs(f["z"]) < inner)
     assert deep.sum() > 100
@@ -237,7 +241,7 @@ def test_patch_8M_sampled(precision):
     hp = _h_prev_by_id(sim)
     sim.step(0.0)
     sim.sync()
-    nh = _cells_and_h_sampled(sim, hp, half=0.04)
+    nh = _cells_and_h_sampled(sim, hp, half=0.06)
     n = _sampled_check(sim, TOL if precision == "fp64" else TOL_MIXED)
     print(f"8M {precision}: {nh} sampled h and {n} sampled fields agree", flush=True)
     _properties(sim, 1e-9 if precision == "fp64" else 1e-5)

@@ -286,6 +286,81 @@ def test_walk_defer_group_parity(case, defer):
     compare_fields(sim, st)
 
 
+def _gather_rows_flat(sim):
+    """The gather rows concatenated in particle order, each in stored order."""
+    nc, idx = sim.gather_dense()
+    K = idx.shape[0]
+    mask = np.arange(K)[:, None] < np.minimum(nc, K)[None, :]
+    return idx.T[mask.T]
+
+
+@pytest.mark.parametrize("case", ["patch_23^3_ragged", "clumpy_12k"])
+def test_gather_rows_canonical_and_csr(case):
+    """Every gather row L_i is stored in ascending index order, so it equals
+    the oracle's row element by element (not only as a set), whether the
+    walk counted it in a group, completed it from a shell, or left it to the
+    per-particle tail: with walk_defer_group 4, 16 and 64 the rows and every
+    field are bit-identical after an evaluation and a step.  The CSR export
+    of S_i = L_i U E_i equals the oracle's interaction sets exactly."""
+    ic = CASES[case]()
+    st = O.State(ic.copy())
+    st.keep_gather = True
+    st.evaluate(method=1)
+    st0 = {k: v.copy() for k, v in st.f.items()}
+    dt = st.dt_next
+    ref_rows_t0 = st.lidx.copy()
+    st.step(dt, method=1)
+    outs = []
+    for defer in (0, 16, 64):
+        print(f"canonical rows {case} defer {defer}", flush=True)
+        sim = _sim(ic, extra_per_particle=96, walk_defer_group=defer)
+        sim.evaluate()
+        sim.sync()
+        np.testing.assert_array_equal(_gather_rows_flat(sim), ref_rows_t0)
+        for f in ("x", "y", "z", "vx", "vy", "vz", "m", "h", "u", "ax", "ay", "az", "du", "rho",
+                  "divv"):
+            sim.set_field(f, st0[f])
+        sim.set_field("nc", st0["nc"].astype(np.int32))
+        sim.set_field("id", st0["id"].astype(np.int32))
+        sim.step(dt)
+        sim.sync()
+        compare_cells(sim, st)
+        np.testing.assert_array_equal(sim.numpy("h"), st.f["h"])
+        np.testing.assert_array_equal(sim.numpy("nc"), st.f["nc"])
+        np.testing.assert_array_equal(_gather_rows_flat(sim), st.lidx)
+        off, idx = sim.interaction_csr_device()
+        np.testing.assert_array_equal(off.cpu().numpy(), st.off)
+        np.testing.assert_array_equal(idx.cpu().numpy(), st.idx)
+        outs.append({f: sim.numpy(f).copy() for f in ("rho", "divv", "ax", "ay", "az", "du")})
+    for o in outs[1:]:
+        for f in o:
+            np.testing.assert_array_equal(outs[0][f], o[f], err_msg=f)
+
+
+def test_interaction_csr_capacity():
+    """Too small an index array: d_off complete, nothing written past the
+    capacity, SPH_ECAPACITY from the next sync."""
+    import torch
+    from paper_1905_03344_amd import ffi
+    ic = inputs.square_patch(12, 4)
+    sim = _sim(ic)
+    sim.evaluate()
+    sim.sync()
+    off, idx = sim.interaction_csr_device()
+    total = int(off[-1])
+    off2 = torch.zeros_like(off)
+    buf = torch.full((total,), -7, dtype=torch.int32, device=sim.device)
+    cap = total // 2
+    ffi.sph_interaction_csr(sim.ctx, sim.s, sim.nl, off2.data_ptr(), buf.data_ptr(), cap)
+    with pytest.raises(ffi.SphError) as e:
+        sim.sync()
+    assert e.value.code == ffi.SPH_ECAPACITY
+    np.testing.assert_array_equal(off2.cpu().numpy(), off.cpu().numpy())
+    b = buf.cpu().numpy()
+    np.testing.assert_array_equal(b[:cap], idx.cpu().numpy()[:cap])
+    assert np.all(b[cap:] == -7)
+
+
 KERNEL_VARIANTS = ["wendland", "sinc5"]
 
 
@@ -351,6 +426,53 @@ def test_grad_h_parity(case, kernel):
     compare_neighbors(sim, st)
     compare_fields(sim, st)
     assert np.max(np.abs(sim.omega() - st.omega)) <= 10 * TOL
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+@pytest.mark.parametrize("kernel", ["m4", "wendland"])
+@pytest.mark.parametrize("case", ["patch_23^3_ragged", "clumpy_12k"])
+def test_generalized_volumes_parity(case, kernel, precision):
+    """Generalized volume elements (weights (m/rho)^0.7 of the previous
+    density; the standard density first at t = 0): density, forces and a
+    step from the oracle's state against the oracle with the same volumes,
+    FP64 to 1e-12, the mixed form to its tolerance."""
+    from paper_1905_03344_amd import ffi
+    from test_gpu_mixed import check_mixed_fields
+    kid = {"m4": O.KERNEL_M4, "wendland": O.KERNEL_WENDLAND}[kernel]
+    ic = CASES[case]()
+    print(f"volumes {precision} kernel {kernel} case {case} n={ic.n}", flush=True)
+    st = O.State(ic.copy(), O.Params(kernel=kid, volumes=O.VOLUMES_GENERALIZED,
+                                     gve_exponent=0.7))
+    st.keep_gather = True
+    st.evaluate(method=1)
+    prec = ffi.SPH_FP64 if precision == "fp64" else ffi.SPH_MIXED
+    sim = _sim(ic, extra_per_particle=96, kernel=kid, precision=prec,
+               volumes=ffi.SPH_VOLUMES_GENERALIZED, gve_exponent=0.7)
+    check = compare_fields if precision == "fp64" else check_mixed_fields
+    sim.evaluate()
+    sim.sync()
+    compare_cells(sim, st)
+    compare_neighbors(sim, st)
+    check(sim, st)
+    # a non-trivial change of the density against the standard volumes
+    std = O.State(ic.copy(), O.Params(kernel=kid))
+    std.evaluate(method=1)
+    assert np.max(np.abs(st.f["rho"] / std.f["rho"] - 1.0)) > 1e-4
+    _upload_oracle_state(sim, st)
+    dt = st.dt_next
+    st.step(dt, method=1)
+    sim.step(dt)
+    sim.sync()
+    compare_cells(sim, st)
+    compare_neighbors(sim, st)
+    check(sim, st)
+
+
+def test_generalized_volumes_rejects_other_variants():
+    from paper_1905_03344_amd import ffi
+    for kw in ({"grad_h": True}, {"gradients": ffi.SPH_GRADIENTS_IAD}, {"gve_exponent": 1.5}):
+        with pytest.raises(ffi.SphError):
+            _sim(inputs.square_patch(6, 1), volumes=ffi.SPH_VOLUMES_GENERALIZED, **kw)
 
 
 @pytest.mark.parametrize("variant", ["iad", "iad+grad_h", "iad_wendland"])
