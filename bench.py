@@ -197,7 +197,8 @@ def run_form(args, config, form, ic, precision_mixed, learned_weights=None, defe
                      h_mode=ffi.SPH_H_LEARNED if learned else ffi.SPH_H_PLAIN,
                      extra_per_particle=extra_slots, walk_prefilter=args.prefilter,
                      kernel=args.kernel_id, integrator=args.integrator_id, grad_h=args.grad_h,
-                     gradients=args.gradients_id, walk_defer_group=defer)
+                     gradients=args.gradients_id, walk_defer_group=defer,
+                     walk_strategy=args.strategy_id)
     if learned:
         sim.set_mlp(*learned_weights)
     n = sim.n
@@ -264,7 +265,8 @@ def train_learned(args, config, ic_train, defer, extra_slots):
     tr = Simulation(ic_train, search_div=args.search_div, precision=ffi.SPH_MIXED,
                     extra_per_particle=extra_slots, walk_prefilter=args.prefilter,
                     kernel=args.kernel_id, integrator=args.integrator_id, grad_h=args.grad_h,
-                    gradients=args.gradients_id, walk_defer_group=defer)
+                    gradients=args.gradients_id, walk_defer_group=defer,
+                    walk_strategy=args.strategy_id)
     tr.evaluate()
     tr.sync()
     torch.cuda.synchronize()
@@ -493,6 +495,9 @@ def main():
     ap.add_argument("--walk-prefilter", default="matrix", choices=["matrix", "none"],
                     help="candidate test of the h-iteration walk: bf16 Gram prefilter on the "
                          "matrix cores with an exact FP64 band, or FP64 for every candidate")
+    ap.add_argument("--walk-strategy", default="auto", choices=["auto", "shell", "worklist"],
+                    help="after the first count: the shell of that count (small runs) or a "
+                         "worklist round (large runs); auto picks by size")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a 1 GiB device copy (PMC byte-counter calibration)")
     args = ap.parse_args()
@@ -518,6 +523,8 @@ def main():
                           else ffi.SPH_INTEGRATOR_KDK)
     args.gradients_id = (ffi.SPH_GRADIENTS_IAD if args.gradients == "iad"
                          else ffi.SPH_GRADIENTS_KERNEL)
+    args.strategy_id = {"auto": ffi.SPH_WALK_AUTO, "shell": ffi.SPH_WALK_SHELL_FIRST,
+                        "worklist": ffi.SPH_WALK_WORKLIST}[args.walk_strategy]
     config = args.config
     # complement rows: the clumpy mixture's density contrast needs more slots
     extra_slots = 96 if config == 4 else 48
@@ -581,6 +588,7 @@ def main():
                    "seed": inputs.CONFIG_SEEDS[config] + (100 if seed_b else 0),
                    "form": main_form, "dt": "courant cfl 0.3",
                    "walk_prefilter": args.walk_prefilter, "walk_defer_group": defer or 4,
+                   "walk_strategy": args.walk_strategy,
                    "kernel": args.kernel, "integrator": args.integrator,
                    "grad_h": bool(args.grad_h), "gradients": args.gradients},
         "roofline": _roofline(kernels, workload) if main_form == "plain" else None,

@@ -79,6 +79,17 @@ typedef struct sph_ctx sph_ctx;
 #define SPH_PREFILTER_NONE 0
 #define SPH_PREFILTER_MATRIX 1
 
+/* How the h iteration continues after its first count (speed only: h, counts,
+ * sets and rows are the same).  SHELL_FIRST: the first count records the shell
+ * |r - 2h| < 2h/24, on which most particles that miss the band converge
+ * without another walk; the rest are counted one particle per wave.
+ * WORKLIST: the first count records no shell; the particles that miss get one
+ * more wave-cooperative count (with the shell) before the per-particle tail.
+ * AUTO: WORKLIST from 4,000,000 particles on, else SHELL_FIRST. */
+#define SPH_WALK_AUTO 0
+#define SPH_WALK_SHELL_FIRST 1
+#define SPH_WALK_WORKLIST 2
+
 /* Time integrators of sph_step.  KDK: kick-drift-kick leapfrog (positions,
  * velocities and energy).  AB2: the same positions and velocities, the
  * energy by second-order Adams-Bashforth with a variable step (the paper's
@@ -150,7 +161,7 @@ typedef struct sph_params {
                                * Speed only: sets, rows, h, counts and fields do not
                                * depend on it. */
     int32_t volumes;        /* SPH_VOLUMES_STANDARD (default) or SPH_VOLUMES_GENERALIZED */
-    int32_t pad1;
+    int32_t walk_strategy;  /* SPH_WALK_AUTO (default), _SHELL_FIRST or _WORKLIST (speed only)*/
     double gve_exponent;    /* p of the generalized weights X = (m/rho)^p, in [0, 1] (0.7) */
 } sph_params;
 

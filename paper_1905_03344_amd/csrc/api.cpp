@@ -143,6 +143,8 @@ static const char *validate(const sph_params *p)
         return "gradients must be SPH_GRADIENTS_KERNEL or SPH_GRADIENTS_IAD";
     if (p->walk_prefilter != SPH_PREFILTER_NONE && p->walk_prefilter != SPH_PREFILTER_MATRIX)
         return "walk_prefilter must be SPH_PREFILTER_NONE or SPH_PREFILTER_MATRIX";
+    if (p->walk_strategy < SPH_WALK_AUTO || p->walk_strategy > SPH_WALK_WORKLIST)
+        return "walk_strategy must be SPH_WALK_AUTO, SPH_WALK_SHELL_FIRST or SPH_WALK_WORKLIST";
     if (p->volumes != SPH_VOLUMES_STANDARD && p->volumes != SPH_VOLUMES_GENERALIZED)
         return "volumes must be SPH_VOLUMES_STANDARD or SPH_VOLUMES_GENERALIZED";
     if (p->volumes == SPH_VOLUMES_GENERALIZED) {
@@ -204,8 +206,7 @@ size_t sph_layout(const sph_params *p, void *base, Workspace *w)
     t.hs_itk = (int32_t *)take(n * sizeof(int32_t));
     t.hs_bits = (int32_t *)take(n * sizeof(int32_t));
     t.shell_stride = ceil_div(n, 64) * 64;
-    t.shell_j = (int32_t *)take(SPH_SHELL_SLOTS * t.shell_stride * sizeof(int32_t));
-    t.shell_r2 = (double *)take(SPH_SHELL_SLOTS * t.shell_stride * sizeof(double));
+    t.shell_e = (int2 *)take(SPH_SHELL_SLOTS * t.shell_stride * sizeof(int2));
     t.mixrec = p->precision == SPH_MIXED ? take(n * 64) : nullptr;
     t.mlp_master = (float *)take(SPH_MLP_ROW * sizeof(float));
     t.mlp_m = (float *)take(SPH_MLP_ROW * sizeof(float));

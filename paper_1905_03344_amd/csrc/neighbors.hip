@@ -133,10 +133,12 @@ __device__ __forceinline__ int count_fill(const Search &S, const double *__restr
 //   above it lower the upper bracket; bisect once both are set, else
 //   h *= T[min(N, 1023)]; at most maxit counts.
 // Structure: round 0 counts every particle once with wave-cooperative
-// walks (below) and keeps iterating on the shell of that count while the
-// next h stays inside it.  Particles that need another full count, and
-// those of small (scattered) groups, which round 0 leaves alone, go to the
-// tail: one wave per particle, full counts until the iteration ends.
+// walks (below) and, in runs below SPH_BIG_N particles, keeps iterating on
+// the shell of that count while the next h stays inside it.  Particles that
+// need another full count go to one wave-cooperative worklist round (large
+// runs: with the shell there), and what remains, with the particles of small
+// (scattered) groups that round 0 leaves alone, to the tail: one wave per
+// particle, full counts until the iteration ends.
 // With h_try (learned mode) round 0 counts at h_try[i], without a shell,
 // and accepts it when in the band.  A miss starts the plain iteration from
 // h[i] in the tail, whose first count of such a particle is the plain
@@ -459,11 +461,19 @@ __device__ __forceinline__ double tile_r2(const WaveLds &L, int t, double xi, do
 #ifndef SPH_TRY_SHELL_D
 #define SPH_TRY_SHELL_D 0.0
 #endif
+// A shell member is one 8-byte entry: its index and its r^2 rounded to FP32
+// (one store per member).  Counts from the shell stay exact: the FP32 value
+// decides a comparison with a threshold T when it lies outside a relative
+// band of 2^-22 around T (its rounding error is at most 2^-24 relative),
+// and inside the band the FP64 r^2 is formed again from the positions.
 struct Shell {
-    int32_t *j;     // SPH_SHELL_SLOTS * sstride
-    double *r2;     // SPH_SHELL_SLOTS * sstride
+    int2 *e;        // SPH_SHELL_SLOTS * sstride: (j, float bits of r^2)
     int64_t sstride;
 };
+__device__ __forceinline__ int2 shell_entry(int32_t j, double r2)
+{
+    return make_int2(j, __float_as_int((float)r2));
+}
 
 // Sub-groups of at most this many particles are counted one particle at a
 // time with the candidates spread over the lanes (transposed mode); larger
@@ -679,23 +689,22 @@ __device__ void walk_group(WaveLds &L, uint64_t members, int tm, int64_t i, doub
             rw += __popcll(starts) + (__ballot(len > 0 && k == 64) != 0 ? 1 : 0);
             return j;
         };
-        // union mode keeps the next tile's candidate in flight while the
-        // current tile is tested
-        int jn = -1;
+        // the next tile's (union) or chunk's (transposed) candidate stays in
+        // flight while the current one is tested
+        int jn = window(0);
         double xn = 0.0, yn = 0.0, zn = 0.0;
-        if (!TRANSPOSED) {
-            jn = window(0);
-            if (jn >= 0) { xn = x[jn]; yn = y[jn]; zn = z[jn]; }
-        }
+        if (jn >= 0) { xn = x[jn]; yn = y[jn]; zn = z[jn]; }
         for (int base = 0; base < total; base += 64) {
-            int j = -1;
-            if (TRANSPOSED) j = window(base);
             if (TRANSPOSED) {
+                const int j = jn;
+                const double xc = xn, yc = yn, zc = zn;
+                jn = window(base + 64);
+                if (jn >= 0) { xn = x[jn]; yn = y[jn]; zn = z[jn]; }
                 bool hin = false, hsh = false;
                 double r2 = 0.0;
                 if (j >= 0) {
-                    r2 = wraps ? pair_r2<PM>(xm, ym, zm, x[j], y[j], z[j], g)
-                               : pair_r2<0>(xm, ym, zm, x[j], y[j], z[j], g);
+                    r2 = wraps ? pair_r2<PM>(xm, ym, zm, xc, yc, zc, g)
+                               : pair_r2<0>(xm, ym, zm, xc, yc, zc, g);
                     hin = r2 < T2m && j != (int)im;
                     hsh = !(r2 < A2m) && r2 < B2m;
                 }
@@ -709,8 +718,7 @@ __device__ void walk_group(WaveLds &L, uint64_t members, int tm, int64_t i, doub
                     if (nshm + c <= SPH_SHELL_SLOTS) {
                         const int ps = nshm + __popcll(bsh & below);
                         if (hsh) {
-                            SH.j[(int64_t)ps * SH.sstride + im] = j;
-                            SH.r2[(int64_t)ps * SH.sstride + im] = r2;
+                            SH.e[(int64_t)ps * SH.sstride + im] = shell_entry(j, r2);
                         }
                         nshm += c;
                     } else {
@@ -758,8 +766,7 @@ __device__ void walk_group(WaveLds &L, uint64_t members, int tm, int64_t i, doub
                             } else if (r2 < B2) {
                                 if (r2 < T2) hin |= 1ull << t;
                                 if (nsh >= 0 && nsh < SPH_SHELL_SLOTS) {
-                                    SH.j[(int64_t)nsh * SH.sstride + i] = L.c[t].j;
-                                    SH.r2[(int64_t)nsh * SH.sstride + i] = r2;
+                                    SH.e[(int64_t)nsh * SH.sstride + i] = shell_entry(L.c[t].j, r2);
                                     ++nsh;
                                 } else {
                                     nsh = -1;
@@ -782,8 +789,7 @@ __device__ void walk_group(WaveLds &L, uint64_t members, int tm, int64_t i, doub
                                                 : tile_r2<0>(L, t, xi, yi, zi, g);
                         if (r2 < T2) hin |= 1ull << t;
                         if (nsh >= 0 && nsh < SPH_SHELL_SLOTS) {
-                            SH.j[(int64_t)nsh * SH.sstride + i] = L.c[t].j;
-                            SH.r2[(int64_t)nsh * SH.sstride + i] = r2;
+                            SH.e[(int64_t)nsh * SH.sstride + i] = shell_entry(L.c[t].j, r2);
                             ++nsh;
                         } else {
                             nsh = -1;
@@ -978,11 +984,17 @@ __device__ __forceinline__ void hs_store(const HIter &H, int64_t i, const HState
 }
 
 #define HS_WALK 256        // one full walk in the bits field
-#ifndef SPH_FIRST_SHELL
-#define SPH_FIRST_SHELL 1  // round 0 of the plain solve records the shell of its count
-#endif
-#ifndef SPH_WAVE_ROUNDS
-#define SPH_WAVE_ROUNDS 0  // worklist rounds after round 0
+// Large runs (n >= SPH_BIG_N) count round 0 without a shell and give the
+// particles that need another count one wave-cooperative worklist round,
+// with the shell, before the per-particle tail: recording a shell for every
+// particle costs more than the worklist round for the few percent that
+// iterate (64M patch, plain: 170 against 194 ms per step).  Smaller runs
+// record the shell in round 0 and send only the rest to the tail: their
+// worklist would be too short to fill the GPU (1M patch 3.95 against 4.52
+// ms, 1M clumpy mixture 6.29 against 7.21 ms).  sph_params.walk_strategy
+// can force either.
+#ifndef SPH_BIG_N
+#define SPH_BIG_N 4000000
 #endif
 
 // one step of the iteration after a count N at hc.
@@ -1059,6 +1071,8 @@ struct HArgs {
     const double *hk;
     Geo g;
     int lmax, div, prefilter, defer, target, tol, maxit;
+    int first_shell;   // round 0 records the shell of its count (plain counts)
+    int rounds;        // wave-cooperative worklist rounds after round 0
     HIter H;
     Shell SH;
     int64_t *status;
@@ -1086,16 +1100,32 @@ __device__ int shell_iterate(const HArgs &A, int64_t i, HState &st, double hc, d
     const int64_t ss = A.SH.sstride;
     const double t0 = 2.0 * hc;
     const double T2 = t0 * t0;
+    // r^2 of shell member k below T (exact: see Shell)
+    auto below = [&](int k, double T) {
+        const int2 e = A.SH.e[(int64_t)k * ss + i];
+        const double f = (double)__int_as_float(e.y);
+        if (f < T * (1.0 - 0x1p-22)) return true;
+        if (f > T * (1.0 + 0x1p-22)) return false;
+        const int64_t j = e.x;
+        double d[3] = {A.x[j] - A.x[i], A.y[j] - A.y[i], A.z[j] - A.z[i]};
+        for (int a = 0; a < 3; ++a) {
+            if (A.g.per[a]) {
+                const double up = d[a] - A.g.L[a], dn = d[a] + A.g.L[a];
+                d[a] = (d[a] > A.g.halfL[a]) ? up : ((d[a] < -A.g.halfL[a]) ? dn : d[a]);
+            }
+        }
+        return exact_r2(d[0], d[1], d[2]) < T;
+    };
     // members closer than the shell's inner radius (read from the shell only
     // when the iteration goes on past hc)
     int nin = -1;
     auto shell_count = [&](double r2m) {
         if (nin < 0) {
             nin = nrow;
-            for (int k = 0; k < nsh; ++k) nin -= A.SH.r2[(int64_t)k * ss + i] < T2 ? 1 : 0;
+            for (int k = 0; k < nsh; ++k) nin -= below(k, T2) ? 1 : 0;
         }
         int c = nin;
-        for (int k = 0; k < nsh; ++k) c += A.SH.r2[(int64_t)k * ss + i] < r2m ? 1 : 0;
+        for (int k = 0; k < nsh; ++k) c += below(k, r2m) ? 1 : 0;
         return c;
     };
     auto in_shell = [&](double r2m) { return r2m >= A2 && r2m <= B2; };
@@ -1124,8 +1154,7 @@ __device__ int shell_iterate(const HArgs &A, int64_t i, HState &st, double hc, d
                 int32_t *row = A.idx + i * (int64_t)A.K;
                 auto prev_in = [&](int k) {
                     while (k >= 0) {
-                        const double r2 = A.SH.r2[(int64_t)k * ss + i];
-                        if (!(r2 < T2) && r2 < r2k) break;
+                        if (!below(k, T2) && below(k, r2k)) break;
                         --k;
                     }
                     return k;
@@ -1133,7 +1162,7 @@ __device__ int shell_iterate(const HArgs &A, int64_t i, HState &st, double hc, d
                 int k = prev_in(nsh - 1);
                 int p = nrow - 1;
                 for (int o = st.best_n - 1; k >= 0; --o) {
-                    const int32_t sj = A.SH.j[(int64_t)k * ss + i];
+                    const int32_t sj = A.SH.e[(int64_t)k * ss + i].x;
                     const int32_t ij = p >= 0 ? row[p] : 0;
                     if (p >= 0 && ij > sj) {
                         row[o] = ij;
@@ -1148,8 +1177,7 @@ __device__ int shell_iterate(const HArgs &A, int64_t i, HState &st, double hc, d
                 int32_t *row = A.idx + i * (int64_t)A.K;
                 auto next_out = [&](int k) {
                     while (k < nsh) {
-                        const double r2 = A.SH.r2[(int64_t)k * ss + i];
-                        if (!(r2 < r2k) && r2 < T2) break;
+                        if (!below(k, r2k) && below(k, T2)) break;
                         ++k;
                     }
                     return k;
@@ -1158,7 +1186,7 @@ __device__ int shell_iterate(const HArgs &A, int64_t i, HState &st, double hc, d
                 int o = 0;
                 for (int q = 0; q < nrow; ++q) {
                     const int32_t v = row[q];
-                    if (k < nsh && v == A.SH.j[(int64_t)k * ss + i]) {
+                    if (k < nsh && v == A.SH.e[(int64_t)k * ss + i].x) {
                         k = next_out(k + 1);
                         continue;
                     }
@@ -1196,10 +1224,10 @@ __attribute__((amdgpu_waves_per_eu(SPH_ROUND_WAVES, SPH_ROUND_WAVES))) void k_hs
     const int64_t total = wl ? *wcount : n;
     const bool listed = slot < total;
     const int64_t i = listed ? (wl ? (int64_t)wl[slot] : slot) : 0;
-    // each particle takes at most SPH_WAVE_ROUNDS + 1 full walks in these
+    // each particle takes at most A.rounds + 1 full walks in these
     // rounds (a learned try that is left behind does not count); one that
     // has used them waits, still listed, for the per-particle tail
-    const bool valid = listed && (!wl || (A.H.bits[i] >> 8) < SPH_WAVE_ROUNDS + 1);
+    const bool valid = listed && (!wl || (A.H.bits[i] >> 8) < A.rounds + 1);
     const Search S = make_search(A.cs, A.lmax, A.div, A.prefilter, A.defer, A.bbox, A.g);
 
     // only what the walk needs is live across it; the iteration state is
@@ -1217,11 +1245,12 @@ __attribute__((amdgpu_waves_per_eu(SPH_ROUND_WAVES, SPH_ROUND_WAVES))) void k_hs
     int64_t tested = 0, counts = 0, acc = 0, fallback = 0, nonconv = 0, overflow = 0;
     // The learned try, accepted almost always, is counted without a shell
     // (SPH_TRY_SHELL_D): a miss restarts the plain iteration from h_prev,
-    // with its shell, in the tail.  Plain counts record the shell, on which
-    // most misses of h_prev converge.
+    // with its shell, in the worklist round (large runs) or the tail.  Plain
+    // counts of small runs record the shell, on which most misses of h_prev
+    // converge (SPH_BIG_N).
     const bool try_walk = FIRST && A.h_try != nullptr;
     const double sd = try_walk ? SPH_TRY_SHELL_D
-                               : ((FIRST && !SPH_FIRST_SHELL) ? 0.0 : SPH_SHELL_D);
+                               : ((FIRST && !A.first_shell) ? 0.0 : SPH_SHELL_D);
     const double ta = sd > 0.0 ? 2.0 * hc * (1.0 - 1.0 / sd) : 2.0 * hc;
     const double tb = sd > 0.0 ? 2.0 * hc * (1.0 + 1.0 / sd) : 2.0 * hc;
     const double tt = 2.0 * hc;
@@ -1260,7 +1289,7 @@ __attribute__((amdgpu_waves_per_eu(SPH_ROUND_WAVES, SPH_ROUND_WAVES))) void k_hs
     if (valid && deferred) {
         // no walk taken: untouched state, walk budget spent so that only
         // the tail takes it up (with full counts)
-        st.bits |= (SPH_WAVE_ROUNDS + 1) * HS_WALK;
+        st.bits |= (A.rounds + 1) * HS_WALK;
         hs_store(A.H, i, st);
         A.work[i] = 1;
     } else if (valid) {
@@ -1327,7 +1356,13 @@ __global__ __launch_bounds__(SPH_BLOCK) void k_compact(int64_t n, const int32_t 
 // iterating to the end with full wave-cooperative counts (the whole gather
 // set written at every count, no shell).
 template <int PM>
-__global__ __launch_bounds__(SPH_BLOCK) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_hsolve_tail(HArgs A, const int32_t *__restrict__ wl,
+// waves per SIMD the tail kernel is compiled for (4 against 2: 64M patch,
+// learned form, 152 against 156 ms per step; the plain form is indifferent)
+#ifndef SPH_TAIL_WAVES
+#define SPH_TAIL_WAVES 4
+#endif
+__global__ __launch_bounds__(SPH_BLOCK)
+__attribute__((amdgpu_waves_per_eu(SPH_TAIL_WAVES, SPH_TAIL_WAVES))) void k_hsolve_tail(HArgs A, const int32_t *__restrict__ wl,
                                                            const int64_t *__restrict__ wcount)
 {
 #pragma clang fp contract(off)
@@ -1454,12 +1489,16 @@ hipError_t launch_hsolve(sph_ctx *c, sph_particles *s, sph_nlist *nl, const doub
     A.div = p.search_div;
     A.prefilter = p.walk_prefilter;
     A.defer = p.walk_defer_group > 0 ? p.walk_defer_group : SPH_DEFER_GROUP;
+    const bool worklist = p.walk_strategy == SPH_WALK_WORKLIST ||
+                          (p.walk_strategy == SPH_WALK_AUTO && n >= SPH_BIG_N);
+    A.first_shell = worklist ? 0 : 1;
+    A.rounds = worklist ? 1 : 0;
     A.target = p.n_target;
     A.tol = p.n_tol;
     A.maxit = p.h_max_iter;
     A.H = {c->w.hs_next, c->w.hs_lo, c->w.hs_hi, c->w.hs_best_h, c->w.hs_last_h,
            c->w.hs_best_n, c->w.hs_itk, c->w.hs_bits};
-    A.SH = {c->w.shell_j, c->w.shell_r2, c->w.shell_stride};
+    A.SH = {c->w.shell_e, c->w.shell_stride};
     A.status = c->w.status;
     const int pm = periodic_mask(g);
     if (phase == 0) {
@@ -1468,7 +1507,7 @@ hipError_t launch_hsolve(sph_ctx *c, sph_particles *s, sph_nlist *nl, const doub
                                n, (const int32_t *)nullptr, (const int64_t *)nullptr))
         return hipGetLastError();
     }
-    const int rounds = SPH_WAVE_ROUNDS;
+    const int rounds = A.rounds;
     for (int r = 0; r <= rounds; ++r) {
         hipError_t e = launch_scan_i32_to_i64(c, c->w.work, c->w.woff, n);
         if (e != hipSuccess) return e;

@@ -88,8 +88,8 @@ struct Workspace {
     int32_t *wl;           // n_max: the worklist
     double *hs_next, *hs_lo, *hs_hi, *hs_best_h, *hs_last_h;  // h iteration state, n_max each
     int32_t *hs_best_n, *hs_itk, *hs_bits;
-    int32_t *shell_j;      // SPH_SHELL_SLOTS per particle, slot-major with shell_stride
-    double *shell_r2;
+    int2 *shell_e;         // SPH_SHELL_SLOTS per particle, slot-major with shell_stride:
+                           // (j, FP32 bits of r^2)
     int64_t shell_stride;
     void *mixrec;          // n_max records of 64 bytes (mixed form)
     // learned smoothing length

@@ -31,7 +31,8 @@ class Simulation:
                  list_stride=128, extra_per_particle=48, max_level=None, search_div=2,
                  precision=ffi.SPH_FP64, check_finite=False, h_mode=ffi.SPH_H_PLAIN,
                  walk_prefilter=None, kernel=None, integrator=None, grad_h=False,
-                 gradients=None, walk_defer_group=None, volumes=None, gve_exponent=None):
+                 gradients=None, walk_defer_group=None, volumes=None, gve_exponent=None,
+                 walk_strategy=None):
         """Allocate the state and the workspace for ic and bind a context.
 
         precision: ffi.SPH_FP64 or ffi.SPH_MIXED; h_mode: ffi.SPH_H_PLAIN or
@@ -39,7 +40,7 @@ class Simulation:
         integrator: ffi.SPH_INTEGRATOR_KDK or _AB2; grad_h: grad-h correction
         terms; gradients: ffi.SPH_GRADIENTS_KERNEL or _IAD; volumes:
         ffi.SPH_VOLUMES_STANDARD or _GENERALIZED (weights (m/rho)^gve_exponent); walk_prefilter:
-        ffi.SPH_PREFILTER_MATRIX or _NONE; walk_defer_group: first-round
+        ffi.SPH_PREFILTER_MATRIX or _NONE; walk_strategy: ffi.SPH_WALK_*; walk_defer_group: first-round
         sub-groups up to this size go to the per-particle tail (speed only).
         None keeps the library default.
         list_stride and extra_per_particle are the capacities of the gather
@@ -77,6 +78,8 @@ class Simulation:
             p.walk_defer_group = int(walk_defer_group)
         if volumes is not None:
             p.volumes = int(volumes)
+        if walk_strategy is not None:
+            p.walk_strategy = int(walk_strategy)
         if gve_exponent is not None:
             p.gve_exponent = float(gve_exponent)
         p.precision = int(precision)

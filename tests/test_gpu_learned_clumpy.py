@@ -149,9 +149,12 @@ def trained_125k():
     return w, norm
 
 
-def test_learned_step_clumpy_vs_oracle(trained_125k):
+@pytest.mark.parametrize("strategy", ["auto", "worklist"])
+def test_learned_step_clumpy_vs_oracle(trained_125k, strategy):
     """One learned step of the mixed form on a 125,000-particle clumpy set
-    (seed B) from the oracle's state, with the clumpy workload's settings."""
+    (seed B) from the oracle's state, with the clumpy workload's settings;
+    misses restart in the per-particle tail (auto at this size) or in a
+    worklist round first."""
     from paper_1905_03344_amd import ffi
     from paper_1905_03344_amd.state import Simulation
     from test_gpu_mixed import check_mixed_fields
@@ -162,7 +165,9 @@ def test_learned_step_clumpy_vs_oracle(trained_125k):
     st.keep_gather = True
     st.evaluate(method=1)
     sim = Simulation(ic, h_mode=ffi.SPH_H_LEARNED, precision=ffi.SPH_MIXED,
-                     extra_per_particle=EXTRA, walk_defer_group=DEFER)
+                     extra_per_particle=EXTRA, walk_defer_group=DEFER,
+                     walk_strategy=(ffi.SPH_WALK_WORKLIST if strategy == "worklist"
+                                    else ffi.SPH_WALK_AUTO))
     sim.set_mlp(w, norm)
     _upload_oracle_state(sim, st)
     dt = st.dt_next

@@ -299,9 +299,12 @@ def test_gather_rows_canonical_and_csr(case):
     """Every gather row L_i is stored in ascending index order, so it equals
     the oracle's row element by element (not only as a set), whether the
     walk counted it in a group, completed it from a shell, or left it to the
-    per-particle tail: with walk_defer_group 4, 16 and 64 the rows and every
-    field are bit-identical after an evaluation and a step.  The CSR export
-    of S_i = L_i U E_i equals the oracle's interaction sets exactly."""
+    per-particle tail: with walk_defer_group 4, 16 and 64, and with the
+    first count recording its shell or leaving the misses to a worklist
+    round, the rows and every field are bit-identical after an evaluation
+    and a step.  The CSR export of S_i = L_i U E_i equals the oracle's
+    interaction sets exactly."""
+    from paper_1905_03344_amd import ffi
     ic = CASES[case]()
     st = O.State(ic.copy())
     st.keep_gather = True
@@ -311,9 +314,11 @@ def test_gather_rows_canonical_and_csr(case):
     ref_rows_t0 = st.lidx.copy()
     st.step(dt, method=1)
     outs = []
-    for defer in (0, 16, 64):
-        print(f"canonical rows {case} defer {defer}", flush=True)
-        sim = _sim(ic, extra_per_particle=96, walk_defer_group=defer)
+    for defer, strategy in ((0, ffi.SPH_WALK_AUTO), (16, ffi.SPH_WALK_SHELL_FIRST),
+                            (64, ffi.SPH_WALK_SHELL_FIRST), (0, ffi.SPH_WALK_WORKLIST),
+                            (16, ffi.SPH_WALK_WORKLIST)):
+        print(f"canonical rows {case} defer {defer} strategy {strategy}", flush=True)
+        sim = _sim(ic, extra_per_particle=96, walk_defer_group=defer, walk_strategy=strategy)
         sim.evaluate()
         sim.sync()
         np.testing.assert_array_equal(_gather_rows_flat(sim), ref_rows_t0)
