@@ -276,18 +276,23 @@ def train_learned(args, config, ic_train, defer, extra_slots):
     # in whole shells: train towards the solved h
     mode = ffi.SPH_TARGET_CENTRED if config == 4 else ffi.SPH_TARGET_SOLVED
     n = tr.n
-    # 20 harvested plain steps; at 64M rows of 2 steps (128M rows, 4.6 GB)
-    harvest_steps = 20 if n <= 8_000_000 else 2
+    # 20 harvested plain steps; above 8M particles rows of 4 steps after 2
+    # unharvested ones (the timed steps come after 2 warmup steps), 2 epochs
+    big = n > 8_000_000
+    skip, harvest_steps, epochs = (2, 4, 2) if big else (0, 20, 4)
+    for _ in range(skip):
+        tr.step(0.0)
     feat, target = L.harvest(tr, steps=harvest_steps, target_mode=mode)
     tr.sync()
     t1 = time.perf_counter()
-    w, norm, losses = L.train(tr, feat, target, seed=inputs.CONFIG_SEEDS[config])
+    w, norm, losses = L.train(tr, feat, target, seed=inputs.CONFIG_SEEDS[config], epochs=epochs)
     torch.cuda.synchronize()
     t2 = time.perf_counter()
-    rec = {"harvest_steps": harvest_steps, "rows": int(feat.shape[0]),
+    rec = {"steps_before_harvest": skip, "harvest_steps": harvest_steps,
+           "rows": int(feat.shape[0]),
            "target": "centred" if mode == ffi.SPH_TARGET_CENTRED else "solved",
            "harvest_s": round(t1 - t0, 3), "train_s": round(t2 - t1, 3),
-           "epochs": 4, "batch": 8192,
+           "epochs": epochs, "batch": 8192,
            "loss_first": float(losses[0]), "loss_last": float(losses[-1]),
            "target_mse_zero_model": float((target.double() ** 2).mean())}
     del feat, target, tr

@@ -79,15 +79,18 @@ def traffic(a):
     print(json.dumps(rec))
 
 
-# MI355X: 256 compute units of 4 SIMDs each
+# MI355X: 256 compute units of 4 SIMDs each in 8 XCDs; rocprofv3 reports
+# GRBM_GUI_ACTIVE summed over the XCDs (a dispatch reads 8x its duration in
+# cycles), so the busy fractions divide by the per-XCD value
 CU_NUM = 256
 SIMD_NUM = 4 * CU_NUM
+XCD_NUM = 8
 
 
 def counters(a):
     """Busy fractions of one kernel from counter passes (per dispatch, the
     median of the last `last` dispatches; every pass run on the same
-    command):
+    command; g = GRBM_GUI_ACTIVE / XCD_NUM, the kernel's cycles):
       valu_busy = SQ_ACTIVE_INST_VALU * 4 / SIMD_NUM / GRBM_GUI_ACTIVE
       valu_lanes = SQ_THREAD_CYCLES_VALU / (64 SQ_ACTIVE_INST_VALU)
       mfma_busy = SQ_VALU_MFMA_BUSY_CYCLES / (4 CU_NUM GRBM_GUI_ACTIVE)
@@ -110,6 +113,7 @@ def counters(a):
             ds = sorted(d for (c, d) in seen if c == nm)[-a.last:]
             vals[nm] = statistics.median(seen[(nm, d)] for d in ds)
     g = vals.get("GRBM_GUI_ACTIVE")
+    g = g / XCD_NUM if g else g
     rec = {"kernel": a.kernel, "workload": a.workload, "raw_per_dispatch": vals}
     if g:
         if "SQ_ACTIVE_INST_VALU" in vals:
