@@ -29,6 +29,14 @@ __host__ __device__ static inline MixQ mix_quads(void *base, int64_t n_max)
 #ifndef SPH_MGROUP
 #define SPH_MGROUP 8
 #endif
+// rounds per block of the mixed force kernel: a block takes
+// SPH_MROUNDS_F * SPH_BLOCK / SPH_MGROUP consecutive particles (64M patch,
+// ms per launch: 8 rounds 29.3, 4 rounds 29.6, 2 rounds 30.3; the FP64
+// kernel, whose records are larger, prefers 2)
+#ifndef SPH_MROUNDS_F
+#define SPH_MROUNDS_F 8
+#endif
+#define SPH_MPTILE_F (SPH_MROUNDS_F * (SPH_BLOCK / SPH_MGROUP))
 #ifndef SPH_MBATCH
 #define SPH_MBATCH 4
 #endif
@@ -278,13 +286,14 @@ __global__ __launch_bounds__(SPH_BLOCK) SPH_PAIR_WAVES_D void k_density_mixed(
                         }
                         if (outside) extra_append(j, (int)i, ecnt, eidx, slots, appended, dropped);
                     }
-                    float r = sqrtf(r2);
+                    const float rinv = r2 > 0.0f ? rsqrtf(r2) : 0.0f;
+                    const float r = r2 * rinv;
                     const float mj = bj.w;
                     const float wk = kern_w_f<KER>(r, inv_h, knorm);
                     neu_add(s, (GV ? xb[q] : mj) * wk);
                     if (r > 0.0f) {
                         const float dw = kern_dwdr_f<KER>(r, inv_h, knorm);
-                        float gw = dw / r;
+                        float gw = dw * rinv;
                         float vdot = (bj.x - bi.x) * (-dx) + (bj.y - bi.y) * (-dy) +
                                      (bj.z - bi.z) * (-dz);
                         neu_add(dv, mj * vdot * gw);
@@ -395,8 +404,10 @@ __device__ __forceinline__ void force_pair_f(const QuadF &ri, float inv_hi, uint
             float hb = 0.5f * (ri.c.x + rj.c.x);
             float cb = 0.5f * (ri.c.y + rj.c.y);
             float rb = 0.5f * (ri.c.z + rj.c.z);
-            float mu = hb * w / (r2 + eta2 * hb * hb);
-            Pi = (-alpha * cb * mu + beta * mu * mu) / rb;
+            const float den = r2 + eta2 * hb * hb;
+            const float rq = __builtin_amdgcn_rcpf(den * rb);
+            const float mu = hb * w * (rb * rq);
+            Pi = (-alpha * cb * mu + beta * mu * mu) * (den * rq);
             A.mumax = fmaxf(A.mumax, fabsf(mu));
         }
         const float wi = kern_w_f<KER>(r, inv_hi, knorm);
@@ -425,8 +436,11 @@ __device__ __forceinline__ void force_pair_f(const QuadF &ri, float inv_hi, uint
         float hb = 0.5f * (ri.c.x + rj.c.x);
         float cb = 0.5f * (ri.c.y + rj.c.y);
         float rb = 0.5f * (ri.c.z + rj.c.z);
-        float mu = hb * w / (r2 + eta2 * hb * hb);
-        Pi = (-alpha * cb * mu + beta * mu * mu) / rb;
+        // mu = hb w / den and Pi = (..) / rb from one reciprocal of den rb
+        const float den = r2 + eta2 * hb * hb;
+        const float rq = __builtin_amdgcn_rcpf(den * rb);
+        const float mu = hb * w * (rb * rq);
+        Pi = (-alpha * cb * mu + beta * mu * mu) * (den * rq);
         A.mumax = fmaxf(A.mumax, fabsf(mu));
     }
     float mj = rj.b.w;
@@ -471,12 +485,12 @@ __global__ __launch_bounds__(SPH_BLOCK) SPH_PAIR_WAVES_F void k_forces_mixed(
     const int lane = threadIdx.x & (SPH_MGROUP - 1);
     const int grp = threadIdx.x / SPH_MGROUP;
     const int64_t blk = xcd_block(blockIdx.x, gridDim.x);
-    const int64_t base = blk * SPH_BLOCK;
+    const int64_t base = blk * SPH_MPTILE_F;
     double dti = INFINITY;
     const MixGeo G = mix_geo(bbox, g);
     __shared__ int32_t e_raw[ELDS ? SPH_BLOCK / SPH_MGROUP : 1][ELDS ? SPH_ELDS : 1];
     __shared__ int32_t e_srt[ELDS ? SPH_BLOCK / SPH_MGROUP : 1][ELDS ? SPH_ELDS : 1];
-    for (int rr = 0; rr < SPH_MGROUP; ++rr) {   // SPH_BLOCK / SPH_MGROUP groups, SPH_MGROUP rounds
+    for (int rr = 0; rr < SPH_MROUNDS_F; ++rr) {   // SPH_BLOCK / SPH_MGROUP groups per round
         const int64_t i = base + (int64_t)rr * (SPH_BLOCK / SPH_MGROUP) + grp;
         ForceAccF A = {{0.f, 0.f}, {0.f, 0.f}, {0.f, 0.f}, {0.f, 0.f}, 0.f};
         if (i < n) {
@@ -726,7 +740,8 @@ hipError_t launch_forces_mixed(sph_ctx *c, sph_particles *s, const sph_nlist *nl
     int64_t n = s->n;
     int cur = s->cur;
     const sph_params &p = c->p;
-    int64_t nb = ceil_div(n > 0 ? n : 1, SPH_BLOCK);
+    int64_t nb = ceil_div(n > 0 ? n : 1, SPH_MPTILE_F);
+    c->dt_parts = nb;
     Geo g = make_geo(p);
 #define SPH_FORCE_ARGS                                                                        \
     dim3((unsigned)nb), dim3(SPH_BLOCK), 0, c->stream, n, ctx_quads(c), (const float2 *)c->w.iad, \

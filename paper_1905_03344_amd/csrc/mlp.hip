@@ -508,17 +508,31 @@ __global__ __launch_bounds__(SPH_BLOCK) void k_mlp_train(int64_t n, MlpDev M,
     }
 }
 
-// fixed-order sum of the partial rows: grad[k] = sum_w part[w][k]
+// fixed-order sum of the partial rows: grad[k] = sum_w part[w][k].  A block
+// takes 32 columns; its 8 slices of 32 threads sum the rows w = q, q + 8, ...
+// of their slice q in order, and the 8 slice sums are added as a fixed tree.
+#define MLP_RED_COLS 32
+#define MLP_RED_SLICES (SPH_BLOCK / MLP_RED_COLS)
 __global__ __launch_bounds__(SPH_BLOCK) void k_mlp_reduce(const float *__restrict__ part, int nrows,
                                                           float *__restrict__ grad,
                                                           float *__restrict__ loss_out)
 {
-    int k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k > MLP_NP) return;
+    __shared__ float sh[MLP_RED_SLICES][MLP_RED_COLS];
+    const int c = threadIdx.x % MLP_RED_COLS, q = threadIdx.x / MLP_RED_COLS;
+    const int k = blockIdx.x * MLP_RED_COLS + c;
     float s = 0.f;
-    for (int w = 0; w < nrows; ++w) s += part[(int64_t)w * MLP_ROW + k];
-    grad[k] = s;   // grad[MLP_NP] = loss
-    if (k == MLP_NP && loss_out) *loss_out = s;
+    if (k <= MLP_NP)
+        for (int w = q; w < nrows; w += MLP_RED_SLICES) s += part[(int64_t)w * MLP_ROW + k];
+    sh[q][c] = s;
+    __syncthreads();
+    for (int h = MLP_RED_SLICES / 2; h > 0; h >>= 1) {
+        if (q < h) sh[q][c] += sh[q + h][c];
+        __syncthreads();
+    }
+    if (q == 0 && k <= MLP_NP) {
+        grad[k] = sh[0][c];   // grad[MLP_NP] = loss
+        if (k == MLP_NP && loss_out) *loss_out = sh[0][c];
+    }
 }
 
 // Feature standardisation: FP64 mean and population standard deviation of
@@ -678,7 +692,7 @@ hipError_t launch_mlp_grad(sph_ctx *c, const float *feat, const float *target,
     unsigned nb = MLP_TRAIN_WAVES / MLP_WAVES_PER_BLOCK;
     hipLaunchKernelGGL(k_mlp_train, dim3(nb), dim3(SPH_BLOCK), 0, c->stream, n, mlp_dev(c), feat,
                        target, rows, row0, c->w.mlp_part);
-    hipLaunchKernelGGL(k_mlp_reduce, dim3((unsigned)ceil_div(MLP_NP + 1, SPH_BLOCK)),
+    hipLaunchKernelGGL(k_mlp_reduce, dim3((unsigned)ceil_div(MLP_NP + 1, MLP_RED_COLS)),
                        dim3(SPH_BLOCK), 0, c->stream, c->w.mlp_part, MLP_TRAIN_WAVES, grad,
                        loss_out);
     return hipGetLastError();

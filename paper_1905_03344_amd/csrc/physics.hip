@@ -13,9 +13,10 @@
 // and each load touches a few cache lines instead of one per lane.  Each
 // lane sums its share of the pairs (k = lane, lane + SPH_GROUP, ...) and the
 // group adds the partial sums in a fixed butterfly order, so results are
-// reproducible.  Block b treats particles [SPH_BLOCK b, SPH_BLOCK (b+1)):
-// in round r its G = SPH_BLOCK / SPH_GROUP groups take particles
-// SPH_BLOCK b + G r + group.  Eight lanes per particle (eight particles per
+// reproducible.  Block b treats the T = SPH_PTILE_D (density) or
+// SPH_PTILE_F (forces) particles [T b, T (b+1)): in round r its
+// G = SPH_BLOCK / SPH_GROUP groups take particles T b + G r + group.
+// Eight lanes per particle (eight particles per
 // wave) measured best of 4, 8, 16, 32 and 64: a wave load then spans the
 // short row segments of eight consecutive particles, whose neighbours
 // overlap, and rows of ~100 entries keep the lanes busy.
@@ -28,6 +29,24 @@
 #ifndef SPH_FBATCH
 #define SPH_FBATCH 2
 #endif
+// rounds per block of the density (D) and force (F) kernels: a block takes
+// SPH_PTILE_* = SPH_PROUNDS_* * SPH_BLOCK / SPH_GROUP consecutive particles.
+// Measured (8M / 64M patch, ms per launch): forces 8 rounds 6.02 / 47.2,
+// 4 rounds 5.77 / 45.2, 2 rounds 5.69 / 44.5 (a narrower window of
+// particles in flight per XCD); density 8 rounds 4.86 / 37.1, 4 rounds
+// 4.90 / 37.6, 2 rounds 5.07 / 39.1.  Non-temporal row loads (keeping the
+// rows out of L2) made the forces slower (47.2 -> 51.4 ms), and so did a
+// direct-mapped LDS cache of neighbour records in the density kernel
+// (37 -> 53 ms with 512 slots, 71 with 1024: its fill phases serialise on
+// load latency at two blocks per CU).
+#ifndef SPH_PROUNDS_D
+#define SPH_PROUNDS_D 8
+#endif
+#ifndef SPH_PROUNDS_F
+#define SPH_PROUNDS_F 2
+#endif
+#define SPH_PTILE_D (SPH_PROUNDS_D * (SPH_BLOCK / SPH_GROUP))
+#define SPH_PTILE_F (SPH_PROUNDS_F * (SPH_BLOCK / SPH_GROUP))
 
 __device__ __forceinline__ double group_sum(double v)
 {
@@ -75,9 +94,9 @@ __global__ __launch_bounds__(SPH_BLOCK) SPH_PAIR_WAVES_D void k_density(
 {
     const int lane = threadIdx.x & (SPH_GROUP - 1);
     const int grp = threadIdx.x / SPH_GROUP;
-    const int64_t base = (int64_t)xcd_block(blockIdx.x, gridDim.x) * SPH_BLOCK;
+    const int64_t base = (int64_t)xcd_block(blockIdx.x, gridDim.x) * SPH_PTILE_D;
     int64_t appended = 0, dropped = 0;
-    for (int r = 0; r < SPH_GROUP; ++r) {   // SPH_BLOCK / SPH_GROUP groups, SPH_GROUP rounds
+    for (int r = 0; r < SPH_PROUNDS_D; ++r) {   // SPH_BLOCK / SPH_GROUP groups per round
         const int64_t i = base + (int64_t)r * (SPH_BLOCK / SPH_GROUP) + grp;
         double s = 0.0, dv = 0.0, t = 0.0, inv_h = 0.0, mi = 0.0;
         if (i < n) {
@@ -122,13 +141,14 @@ __global__ __launch_bounds__(SPH_BLOCK) SPH_PAIR_WAVES_D void k_density(
                         if (!(r2 < twoh * twoh))
                             extra_append(j, (int)i, ecnt, eidx, slots, appended, dropped);
                     }
-                    double rr = sqrt(r2);
+                    const double rinv = r2 > 0.0 ? rsqrt_nr(r2) : 0.0;
+                    double rr = r2 * rinv;
                     double mj = mb[q];
                     const double wk = kern_w<KER>(rr, inv_h, knorm);
                     s += (GV ? qb[q] : mj) * wk;
                     if (rr > 0.0) {
                         const double dw = kern_dwdr<KER>(rr, inv_h, knorm);
-                        double gw = dw / rr;
+                        double gw = dw * rinv;
                         double vdot = (ub[q] - vxi) * (-dx) + (vb[q] - vyi) * (-dy) + (wb[q] - vzi) * (-dz);
                         dv += mj * vdot * gw;
                         if (GH) t += mj * (3.0 * wk + rr * dw);
@@ -260,11 +280,12 @@ hipError_t launch_density(sph_ctx *c, sph_particles *s, const sph_nlist *nl, boo
     int cur = s->cur;
     Geo g = make_geo(c->p);
     unsigned nb = (unsigned)ceil_div(n, SPH_BLOCK);
+    const unsigned nbt = (unsigned)ceil_div(n, SPH_PTILE_D);
     const Pk64 P = ctx_pk64(c);
     hipLaunchKernelGGL(k_pack64, dim3(nb), dim3(SPH_BLOCK), 0, c->stream, n, s->x[cur], s->y[cur],
                        s->z[cur], s->h[cur], s->pvx, s->pvy, s->pvz, s->m[cur], P);
 #define SPH_DENSITY_ARGS                                                                        \
-    dim3(nb), dim3(SPH_BLOCK), 0, c->stream, n, P, s->nc[cur], nl->idx, c->p.list_stride, g,     \
+    dim3(nbt), dim3(SPH_BLOCK), 0, c->stream, n, P, s->nc[cur], nl->idx, c->p.list_stride, g,     \
         c->knorm, s->rho[cur], s->divv[cur], c->w.omega, nl->ecnt, nl->eidx, c->p.extra_slots,  \
         c->w.status, c->w.gve_x, c->w.gve_y
 #define SPH_DENSITY(EX, GHV, GVV)                                                               \
@@ -412,7 +433,8 @@ __global__ __launch_bounds__(SPH_BLOCK) SPH_PAIR_WAVES_D void k_iad(
                     const double dx = mimg<PM, 0>(xi, ab[q].x, g);
                     const double dy = mimg<PM, 1>(yi, ab[q].y, g);
                     const double dz = mimg<PM, 2>(zi, zb[q].x, g);
-                    const double rr = sqrt(exact_r2(dx, dy, dz));
+                    const double r2 = exact_r2(dx, dy, dz);
+                    const double rr = r2 > 0.0 ? r2 * rsqrt_nr(r2) : 0.0;
                     const double vw = mb[q].y / rb[q].x * kern_w<KER>(rr, inv_h, knorm);
                     txx += vw * dx * dx; txy += vw * dx * dy; txz += vw * dx * dz;
                     tyy += vw * dy * dy; tyz += vw * dy * dz; tzz += vw * dz * dz;
@@ -489,8 +511,8 @@ __device__ __forceinline__ void force_pair(const NbrF &b, double xi, double yi, 
     double dz = mimg<PM, 2>(zi, b.z, g);
     double r2 = dx * dx + dy * dy + dz * dz;
     if (!(r2 > 0.0)) return;
-    double r = sqrt(r2);
-    double inv_r = 1.0 / r;
+    const double inv_r = rsqrt_nr(r2);
+    const double r = r2 * inv_r;
     double hj = b.h;
     double xij = -dx, yij = -dy, zij = -dz;
     double vxij = vxi - b.vx, vyij = vyi - b.vy, vzij = vzi - b.vz;
@@ -501,12 +523,15 @@ __device__ __forceinline__ void force_pair(const NbrF &b, double xi, double yi, 
             double hb = 0.5 * (hi + b.h);
             double cb = 0.5 * (ci + b.c);
             double rb = 0.5 * (rhoi + b.rho);
-            double mu = hb * w / (r2 + eta2 * hb * hb);
-            Pi = (-alpha * cb * mu + beta * mu * mu) / rb;
+            // mu = hb w / den and Pi = (..) / rb from one reciprocal of den rb
+            const double den = r2 + eta2 * hb * hb;
+            const double rq = rcp_nr(den * rb);
+            const double mu = hb * w * (rb * rq);
+            Pi = (-alpha * cb * mu + beta * mu * mu) * (den * rq);
             A.mumax = fmax(A.mumax, fabs(mu));
         }
         const double wi = kern_w<KER>(r, inv_hi, knorm);
-        const double wj = kern_w<KER>(r, 1.0 / b.h, knorm);
+        const double wj = kern_w<KER>(r, rcp_nr(b.h), knorm);
         // A = c d W with d = x_j - x_i = (dx, dy, dz)
         const double aix = (cmi[0] * dx + cmi[1] * dy + cmi[2] * dz) * wi;
         const double aiy = (cmi[1] * dx + cmi[3] * dy + cmi[4] * dz) * wi;
@@ -524,7 +549,7 @@ __device__ __forceinline__ void force_pair(const NbrF &b, double xi, double yi, 
         return;
     }
     double gwi = kern_dwdr<KER>(r, inv_hi, knorm) * inv_r;
-    double gwj = kern_dwdr<KER>(r, 1.0 / hj, knorm) * inv_r;
+    double gwj = kern_dwdr<KER>(r, rcp_nr(hj), knorm) * inv_r;
     double gbar = 0.5 * (gwi + gwj);
     double rhoj = b.rho;
     double Pi = 0.0;
@@ -532,8 +557,10 @@ __device__ __forceinline__ void force_pair(const NbrF &b, double xi, double yi, 
         double hb = 0.5 * (hi + hj);
         double cb = 0.5 * (ci + b.c);
         double rb = 0.5 * (rhoi + rhoj);
-        double mu = hb * w / (r2 + eta2 * hb * hb);
-        Pi = (-alpha * cb * mu + beta * mu * mu) / rb;
+        const double den = r2 + eta2 * hb * hb;
+        const double rq = rcp_nr(den * rb);
+        const double mu = hb * w * (rb * rq);
+        Pi = (-alpha * cb * mu + beta * mu * mu) * (den * rq);
         A.mumax = fmax(A.mumax, fabs(mu));
     }
     double pj_term = b.p;
@@ -578,11 +605,11 @@ __global__ __launch_bounds__(SPH_BLOCK) SPH_PAIR_WAVES_F void k_forces(
     const int lane = threadIdx.x & (SPH_GROUP - 1);
     const int grp = threadIdx.x / SPH_GROUP;
     const int64_t blk = xcd_block(blockIdx.x, gridDim.x);
-    const int64_t base = blk * SPH_BLOCK;
+    const int64_t base = blk * SPH_PTILE_F;
     __shared__ int32_t e_raw[ELDS ? SPH_BLOCK / SPH_GROUP : 1][ELDS ? SPH_ELDS : 1];
     __shared__ int32_t e_srt[ELDS ? SPH_BLOCK / SPH_GROUP : 1][ELDS ? SPH_ELDS : 1];
     double dti = INFINITY;
-    for (int r = 0; r < SPH_GROUP; ++r) {   // SPH_BLOCK / SPH_GROUP groups, SPH_GROUP rounds
+    for (int r = 0; r < SPH_PROUNDS_F; ++r) {   // SPH_BLOCK / SPH_GROUP groups per round
         const int64_t i = base + (int64_t)r * (SPH_BLOCK / SPH_GROUP) + grp;
         ForceAcc A = {0.0, 0.0, 0.0, 0.0, 0.0};
         double hi = 0.0, ci = 0.0;
@@ -665,9 +692,10 @@ hipError_t launch_forces(sph_ctx *c, sph_particles *s, const sph_nlist *nl, doub
     int64_t n = s->n;
     int cur = s->cur;
     const sph_params &p = c->p;
-    int64_t nb = ceil_div(n > 0 ? n : 1, SPH_BLOCK);
-    // dt partials live in the reduction area sized for n_max / SPH_BLOCK blocks
+    int64_t nb = ceil_div(n > 0 ? n : 1, SPH_PTILE_F);
+    // dt partials live in the reduction area (sized for n_max / 32 blocks)
     double *part = c->w.red_part;
+    c->dt_parts = nb;
     Geo g = make_geo(p);
 #define SPH_FORCE_ARGS                                                                          \
     dim3((unsigned)nb), dim3(SPH_BLOCK), 0, c->stream, n, ctx_pk64(c), I, c->w.gve_x, s->c,      \
@@ -706,10 +734,10 @@ hipError_t launch_forces(sph_ctx *c, sph_particles *s, const sph_nlist *nl, doub
 
 hipError_t launch_dt_min(sph_ctx *c, int64_t n, double *d_dt)
 {
-    int64_t nb = ceil_div(n > 0 ? n : 1, SPH_BLOCK);
+    (void)n;
     if (d_dt)
-        hipLaunchKernelGGL(k_min_final, dim3(1), dim3(SPH_BLOCK), 0, c->stream, c->w.red_part, nb,
-                           d_dt);
+        hipLaunchKernelGGL(k_min_final, dim3(1), dim3(SPH_BLOCK), 0, c->stream, c->w.red_part,
+                           c->dt_parts, d_dt);
     return hipGetLastError();
 }
 

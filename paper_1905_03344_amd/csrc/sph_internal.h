@@ -81,7 +81,7 @@ struct Workspace {
     double *hk;            // 1024 Hernquist-Katz factors
     int64_t *status;       // ST_COUNT
     double *dt_cur;        // 1: dt used by the current step
-    double *red_part;      // nb_red * 8 reduction partials
+    double *red_part;      // reduction partials: nb_red * 8, or one per force block
     uint8_t *refill;       // n_max
     int32_t *work;         // n_max: particles needing the per-particle iteration
     int64_t *woff;         // n_max + 1: their worklist positions
@@ -131,6 +131,7 @@ struct sph_ctx {
     double knorm;          // B_5 of the sinc kernel (sph_create)
     int ab2_hist;          // AB2: a step since the last bind / evaluation
     int gve_fresh;         // generalized volumes: no previous density (sph_evaluate)
+    int64_t dt_parts;      // dt partials the last force launch wrote to red_part
     char err[512];
 };
 
@@ -319,6 +320,30 @@ __device__ __forceinline__ double exact_r2(double dx, double dy, double dz)
     double c = dz * dz;
     double ab = a + b;
     return ab + c;
+}
+
+// Reciprocal and inverse square root for the pair sums (x positive and
+// normal): the hardware estimate refined by two Newton-Raphson steps,
+// y <- y + y (1 - x y) and y <- y + (y / 2)(1 - x y^2).  Each step squares
+// the relative error, so the result is within a couple of ulps of the
+// correctly rounded value -- far inside the pair sums' rounding -- for a
+// third of the instructions of an IEEE division or square root.  The
+// neighbour search never uses these: its decisions take exact r^2.
+__device__ __forceinline__ double rcp_nr(double x)
+{
+    double y = __builtin_amdgcn_rcp(x);
+    double e = fma(-x, y, 1.0);
+    y = fma(y, e, y);
+    e = fma(-x, y, 1.0);
+    return fma(y, e, y);
+}
+__device__ __forceinline__ double rsqrt_nr(double x)
+{
+    double y = __builtin_amdgcn_rsq(x);
+    double e = fma(-(x * y), y, 1.0);
+    y = fma(0.5 * y, e, y);
+    e = fma(-(x * y), y, 1.0);
+    return fma(0.5 * y, e, y);
 }
 
 // integer cell index in [0, 1023] of v within [lo, lo + L]

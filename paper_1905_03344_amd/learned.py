@@ -68,7 +68,10 @@ def train(sim, feat: torch.Tensor, target: torch.Tensor, seed: int, epochs: int 
     ffi.sph_mlp_fit_norm(sim.ctx, feat.data_ptr(), n)
     flat0, norm = sim.get_mlp()
     sim.set_mlp(flat0, norm)   # clears the Adam state
-    order = torch.from_numpy(inputs.shuffle_order(seed, n)).to(sim.device)
+    # row order: a seeded permutation drawn on the device (hundreds of
+    # millions of rows at the full workloads)
+    gen = torch.Generator(device=sim.device).manual_seed(seed)
+    order = torch.randperm(n, generator=gen, device=sim.device, dtype=torch.int32)
     nb = (n + batch - 1) // batch
     loss = torch.zeros(max(epochs * nb, 1), dtype=torch.float32, device=sim.device)
     ffi.sph_mlp_train(sim.ctx, feat.data_ptr(), target.data_ptr(), order.data_ptr(), n, batch,
