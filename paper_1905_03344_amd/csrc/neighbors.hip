@@ -466,6 +466,10 @@ __device__ __forceinline__ double tile_r2(const WaveLds &L, int t, double xi, do
 // decides a comparison with a threshold T when it lies outside a relative
 // band of 2^-22 around T (its rounding error is at most 2^-24 relative),
 // and inside the band the FP64 r^2 is formed again from the positions.
+#ifndef SPH_SHELL_BATCH
+#define SPH_SHELL_BATCH 2
+#endif
+static_assert(SPH_SHELL_SLOTS + SPH_SHELL_BATCH <= 64, "shell member masks are 64-bit");
 struct Shell {
     int2 *e;        // SPH_SHELL_SLOTS * sstride: (j, float bits of r^2)
     int64_t sstride;
@@ -1098,11 +1102,11 @@ __device__ int shell_iterate(const HArgs &A, int64_t i, HState &st, double hc, d
         return 0;
     }
     const int64_t ss = A.SH.sstride;
+    const int2 *se = A.SH.e + i;   // shell member k at se[k * ss]
     const double t0 = 2.0 * hc;
     const double T2 = t0 * t0;
-    // r^2 of shell member k below T (exact: see Shell)
-    auto below = [&](int k, double T) {
-        const int2 e = A.SH.e[(int64_t)k * ss + i];
+    // r^2 of shell member e below T (exact: see Shell)
+    auto below = [&](int2 e, double T) {
         const double f = (double)__int_as_float(e.y);
         if (f < T * (1.0 - 0x1p-22)) return true;
         if (f > T * (1.0 + 0x1p-22)) return false;
@@ -1116,17 +1120,32 @@ __device__ int shell_iterate(const HArgs &A, int64_t i, HState &st, double hc, d
         }
         return exact_r2(d[0], d[1], d[2]) < T;
     };
-    // members closer than the shell's inner radius (read from the shell only
-    // when the iteration goes on past hc)
-    int nin = -1;
-    auto shell_count = [&](double r2m) {
-        if (nin < 0) {
-            nin = nrow;
-            for (int k = 0; k < nsh; ++k) nin -= below(k, T2) ? 1 : 0;
+    // bit k: shell member k has r^2 < T; members read SPH_SHELL_BATCH at a
+    // time so that their loads are in flight together (padding reads as
+    // r^2 = +inf)
+    auto mask_below = [&](double T) {
+        uint64_t m = 0;
+        for (int k0 = 0; k0 < nsh; k0 += SPH_SHELL_BATCH) {
+            int2 e[SPH_SHELL_BATCH];
+#pragma unroll
+            for (int u = 0; u < SPH_SHELL_BATCH; ++u)
+                e[u] = k0 + u < nsh ? se[(int64_t)(k0 + u) * ss] : make_int2(0, 0x7f800000);
+#pragma unroll
+            for (int u = 0; u < SPH_SHELL_BATCH; ++u)
+                m |= (uint64_t)(below(e[u], T) ? 1 : 0) << (k0 + u);
         }
-        int c = nin;
-        for (int k = 0; k < nsh; ++k) c += below(k, r2m) ? 1 : 0;
-        return c;
+        return m;
+    };
+    // members below T (in the row), read from the shell only when the
+    // iteration goes on past hc
+    uint64_t mT = 0;
+    bool have_mT = false;
+    auto shell_count = [&](double r2m) {
+        if (!have_mT) {
+            mT = mask_below(T2);
+            have_mT = true;
+        }
+        return nrow - __popcll(mT) + __popcll(mask_below(r2m));
     };
     auto in_shell = [&](double r2m) { return r2m >= A2 && r2m <= B2; };
     ++counts;
@@ -1148,49 +1167,72 @@ __device__ int shell_iterate(const HArgs &A, int64_t i, HState &st, double hc, d
             if (r2k != T2 && (nrow > A.K || st.best_n > A.K)) {
                 // the row does not hold the gather set at hc whole: rewrite it
                 if (st.best_n <= A.K) st.last_h = -1.0;
-            } else if (writer && r2k > T2) {
-                // shell members with T <= r^2 < (2h)^2 join the row: merge
-                // from the back, in place (both runs ascending and disjoint)
+            } else if (writer && r2k != T2) {
+                // the row reads four entries ahead of its cursor q (in
+                // flight together); every write lands at or behind q
                 int32_t *row = A.idx + i * (int64_t)A.K;
-                auto prev_in = [&](int k) {
-                    while (k >= 0) {
-                        if (!below(k, T2) && below(k, r2k)) break;
-                        --k;
-                    }
-                    return k;
+                const int dq = r2k > T2 ? -1 : 1;
+                int q = r2k > T2 ? nrow - 1 : 0;
+                auto rd = [&](int p) { return (p >= 0 && p < nrow) ? row[p] : 0; };
+                int32_t w0 = rd(q), w1 = rd(q + dq), w2 = rd(q + 2 * dq), w3 = rd(q + 3 * dq);
+                auto advance = [&]() {
+                    q += dq;
+                    w0 = w1;
+                    w1 = w2;
+                    w2 = w3;
+                    w3 = rd(q + 3 * dq);
                 };
-                int k = prev_in(nsh - 1);
-                int p = nrow - 1;
-                for (int o = st.best_n - 1; k >= 0; --o) {
-                    const int32_t sj = A.SH.e[(int64_t)k * ss + i].x;
-                    const int32_t ij = p >= 0 ? row[p] : 0;
-                    if (p >= 0 && ij > sj) {
-                        row[o] = ij;
-                        --p;
-                    } else {
-                        row[o] = sj;
-                        k = prev_in(k - 1);
+                if (r2k > T2) {
+                    // shell members with T <= r^2 < (2h)^2 join the row: merge
+                    // from the back, in place (both runs ascending, disjoint);
+                    // joins in descending k, i.e. descending index
+                    uint64_t rest = mask_below(r2k) & ~mT;
+                    int t = __popcll(rest);
+                    int32_t sj = 0, sn = 0;
+                    if (t > 0) {
+                        const int k = 63 - __clzll(rest);
+                        rest &= ~(1ull << k);
+                        sj = se[(int64_t)k * ss].x;
+                        if (rest) sn = se[(int64_t)(63 - __clzll(rest)) * ss].x;
                     }
-                }
-            } else if (writer && r2k < T2) {
-                // shell members with (2h)^2 <= r^2 < T leave the row
-                int32_t *row = A.idx + i * (int64_t)A.K;
-                auto next_out = [&](int k) {
-                    while (k < nsh) {
-                        if (!below(k, r2k) && below(k, T2)) break;
-                        ++k;
+                    while (t > 0) {
+                        if (q >= 0 && w0 > sj) {
+                            row[q + t] = w0;
+                            advance();
+                        } else {
+                            row[q + t] = sj;
+                            if (--t > 0) {
+                                rest &= ~(1ull << (63 - __clzll(rest)));
+                                sj = sn;
+                                if (rest) sn = se[(int64_t)(63 - __clzll(rest)) * ss].x;
+                            }
+                        }
                     }
-                    return k;
-                };
-                int k = next_out(0);
-                int o = 0;
-                for (int q = 0; q < nrow; ++q) {
-                    const int32_t v = row[q];
-                    if (k < nsh && v == A.SH.e[(int64_t)k * ss + i].x) {
-                        k = next_out(k + 1);
-                        continue;
+                } else {
+                    // shell members with (2h)^2 <= r^2 < T leave the row
+                    uint64_t rest = mT & ~mask_below(r2k);
+                    int32_t sj = -1, sn = -1;
+                    if (rest) {
+                        const int k = __ffsll((unsigned long long)rest) - 1;
+                        rest &= rest - 1;
+                        sj = se[(int64_t)k * ss].x;
+                        if (rest) sn = se[(int64_t)(__ffsll((unsigned long long)rest) - 1) * ss].x;
                     }
-                    row[o++] = v;
+                    int o = 0;
+                    while (q < nrow) {
+                        const int32_t v = w0;
+                        advance();
+                        if (v == sj) {
+                            sj = sn;
+                            if (rest) {
+                                rest &= rest - 1;
+                                sn = rest ? se[(int64_t)(__ffsll((unsigned long long)rest) - 1) * ss].x
+                                          : -1;
+                            }
+                            continue;
+                        }
+                        row[o++] = v;
+                    }
                 }
             }
         } else {
