@@ -179,8 +179,8 @@ size_t sph_layout(const sph_params *p, void *base, Workspace *w)
     int64_t scan_part = ceil_div(scan_n, SPH_SCAN_TILE) + 2;
     int64_t ncell = ((int64_t)1 << (3 * p->max_level)) + 1;
     // reduction partials: 8 per block of the reductions, one per block of
-    // the force kernels (at least 32 particles each)
-    const int64_t nb_pair = ceil_div(n, 32);
+    // the force kernels (at least 32 particles each) and 256 slice minima
+    const int64_t nb_pair = ceil_div(n, 32) + 256;
     int64_t red_len = nb_pair > 2048 * 8 ? nb_pair : 2048 * 8;
     Workspace t;
     t.bbox = (double *)take(6 * sizeof(double));

@@ -732,12 +732,43 @@ hipError_t launch_forces(sph_ctx *c, sph_particles *s, const sph_nlist *nl, doub
     return hipGetLastError();
 }
 
+// minimum over slices of the dt partials, one per block (min is exact, so
+// the two stages give the value of one)
+#define SPH_DT_SLICES 256
+__global__ __launch_bounds__(SPH_BLOCK) void k_min_slices(const double *__restrict__ part, int64_t nb,
+                                                          double *__restrict__ out)
+{
+    const int64_t per = (nb + SPH_DT_SLICES - 1) / SPH_DT_SLICES;
+    const int64_t lo = blockIdx.x * per, hi = min(nb, lo + per);
+    __shared__ double sh[SPH_BLOCK];
+    double v = INFINITY;
+    for (int64_t k = lo + threadIdx.x; k < hi; k += SPH_BLOCK) v = fmin(v, part[k]);
+    sh[threadIdx.x] = v;
+    __syncthreads();
+    for (int s = SPH_BLOCK / 2; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) sh[threadIdx.x] = fmin(sh[threadIdx.x], sh[threadIdx.x + s]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[blockIdx.x] = sh[0];
+}
+
 hipError_t launch_dt_min(sph_ctx *c, int64_t n, double *d_dt)
 {
     (void)n;
-    if (d_dt)
+    if (!d_dt) return hipSuccess;
+    const int64_t nb = c->dt_parts;
+    if (nb > 4 * SPH_DT_SLICES) {
+        // the slice minima go behind the partials (the area holds n_max / 32
+        // partials, at least 16384, and at most n_max / 64 are written)
+        double *slices = c->w.red_part + nb;
+        hipLaunchKernelGGL(k_min_slices, dim3(SPH_DT_SLICES), dim3(SPH_BLOCK), 0, c->stream,
+                           c->w.red_part, nb, slices);
+        hipLaunchKernelGGL(k_min_final, dim3(1), dim3(SPH_BLOCK), 0, c->stream, slices,
+                           (int64_t)SPH_DT_SLICES, d_dt);
+    } else {
         hipLaunchKernelGGL(k_min_final, dim3(1), dim3(SPH_BLOCK), 0, c->stream, c->w.red_part,
-                           c->dt_parts, d_dt);
+                           nb, d_dt);
+    }
     return hipGetLastError();
 }
 

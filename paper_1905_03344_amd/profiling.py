@@ -150,6 +150,25 @@ def dispatches(a):
     name starts with one of the prefixes, from a rocprofv3 kernel trace (the
     timed steps of a run, after its t = 0 evaluation and warmup steps)."""
     rows = _rows(a.trace)
+    if a.anchor:
+        # per step: the dispatches between consecutive starts of the anchor
+        # kernel (the first kernel of a step), over the last `last` starts
+        anc = sorted(int(r["Start_Timestamp"]) for r in rows
+                     if r["Kernel_Name"].startswith(a.anchor))[-a.last:]
+        nstep = len(anc) - 1
+        lo, hi = anc[0], anc[-1]
+        inside = [r for r in rows if lo <= int(r["Start_Timestamp"]) < hi]
+        print("| kernel | dispatches per step | us per step (%d steps) |" % nstep)
+        print("|---|---|---|")
+        for pre in a.kernel:
+            ds = [r for r in inside if r["Kernel_Name"].startswith(pre)]
+            if not ds:
+                continue
+            us = sum((int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3 for r in ds)
+            print(f"| `{pre}` | {len(ds) / nstep:g} | {us / nstep:.1f} |")
+        tot = sum((int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3 for r in inside)
+        print(f"| all kernels | {len(inside) / nstep:g} | {tot / nstep:.1f} |")
+        return
     print("| kernel | dispatches | avg us (last %d) |" % a.last)
     print("|---|---|---|")
     for pre in a.kernel:
@@ -189,6 +208,9 @@ def main(argv=None):
     d.add_argument("--trace", required=True)
     d.add_argument("--kernel", nargs="+", required=True)
     d.add_argument("--last", type=int, default=3)
+    d.add_argument("--anchor", default=None,
+                   help="first kernel of a step: report per-step sums between its last "
+                        "`--last` starts")
     c = sub.add_parser("counters")
     c.add_argument("--csv", nargs="+", required=True)
     for k in ("kernel", "source", "workload", "out"):
