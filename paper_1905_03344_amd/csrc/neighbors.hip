@@ -461,6 +461,12 @@ __device__ __forceinline__ double tile_r2(const WaveLds &L, int t, double xi, do
 #ifndef SPH_TRY_SHELL_D
 #define SPH_TRY_SHELL_D 0.0
 #endif
+// shell of round 0 under the worklist strategy (0: none).  Recording one
+// costs round 0 more than the worklist round saves: 64M patch 165.5 ms per
+// step without, 173.8 with |r - 2h| < 2h/48, 175.5 with 2h/96
+#ifndef SPH_WL_SHELL_D
+#define SPH_WL_SHELL_D 0.0
+#endif
 // A shell member is one 8-byte entry: its index and its r^2 rounded to FP32
 // (one store per member).  Counts from the shell stay exact: the FP32 value
 // decides a comparison with a threshold T when it lies outside a relative
@@ -1292,7 +1298,7 @@ __attribute__((amdgpu_waves_per_eu(SPH_ROUND_WAVES, SPH_ROUND_WAVES))) void k_hs
     // converge (SPH_BIG_N).
     const bool try_walk = FIRST && A.h_try != nullptr;
     const double sd = try_walk ? SPH_TRY_SHELL_D
-                               : ((FIRST && !A.first_shell) ? 0.0 : SPH_SHELL_D);
+                               : ((FIRST && !A.first_shell) ? SPH_WL_SHELL_D : SPH_SHELL_D);
     const double ta = sd > 0.0 ? 2.0 * hc * (1.0 - 1.0 / sd) : 2.0 * hc;
     const double tb = sd > 0.0 ? 2.0 * hc * (1.0 + 1.0 / sd) : 2.0 * hc;
     const double tt = 2.0 * hc;
