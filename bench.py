@@ -192,7 +192,7 @@ def run_form(args, config, form, ic, precision_mixed, learned_weights=None, defe
     from paper_1905_03344_amd.state import Simulation
 
     learned = learned_weights is not None
-    sim = Simulation(ic, search_div=args.search_div,
+    sim = Simulation(ic, search_div=args.search_div, max_level=args.max_level,
                      precision=ffi.SPH_MIXED if precision_mixed else ffi.SPH_FP64,
                      h_mode=ffi.SPH_H_LEARNED if learned else ffi.SPH_H_PLAIN,
                      extra_per_particle=extra_slots, walk_prefilter=args.prefilter,
@@ -262,7 +262,8 @@ def train_learned(args, config, ic_train, defer, extra_slots):
     from paper_1905_03344_amd import learned as L
     from paper_1905_03344_amd.state import Simulation
 
-    tr = Simulation(ic_train, search_div=args.search_div, precision=ffi.SPH_MIXED,
+    tr = Simulation(ic_train, search_div=args.search_div, max_level=args.max_level,
+                    precision=ffi.SPH_MIXED,
                     extra_per_particle=extra_slots, walk_prefilter=args.prefilter,
                     kernel=args.kernel_id, integrator=args.integrator_id, grad_h=args.grad_h,
                     gradients=args.gradients_id, walk_defer_group=defer,
@@ -486,6 +487,8 @@ def main():
                     help="headline: plain FP64 and mixed + learned h on the same input")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--search-div", type=int, default=2)
+    ap.add_argument("--max-level", type=int, default=None,
+                    help="finest cell level of the search table (default: from n and h)")
     ap.add_argument("--integrator", default="kdk", choices=["kdk", "ab2"],
                     help="kick-drift-kick, or its positions with Adams-Bashforth energy")
     ap.add_argument("--gradients", default="kernel", choices=["kernel", "iad"],

@@ -464,6 +464,16 @@ __device__ __forceinline__ double tile_r2(const WaveLds &L, int t, double xi, do
 // shell of round 0 under the worklist strategy (0: none).  Recording one
 // costs round 0 more than the worklist round saves: 64M patch 165.5 ms per
 // step without, 173.8 with |r - 2h| < 2h/48, 175.5 with 2h/96
+// widest union box, in cells per dimension, at the level a walk uses: a box
+// of span <= S cells touches at most S + 2 cells, and up to 13 cells lie in
+// at most 4 aligned blocks of 4 (64 blocks, one sorted batch).  On the 64M
+// patch a 64-member union spans more than 12 cells of the next finer level
+// (0.78 spacings), so S = 12 with level-9 cells and a search divisor of 3 or
+// 4 left the level, the candidates (~1,540 per particle) and the walk time
+// as they were, while the larger cell table cost 2.5 ms per step.
+#ifndef SPH_SPAN_CELLS
+#define SPH_SPAN_CELLS 11.0
+#endif
 #ifndef SPH_WL_SHELL_D
 #define SPH_WL_SHELL_D 0.0
 #endif
@@ -560,7 +570,8 @@ __device__ void walk_group(WaveLds &L, uint64_t members, int tm, int64_t i, doub
         bool ok = true;
         for (int d = 0; d < 3; ++d) {
             double cw = ldexp(S.L[d], -l);
-            if (S.L[d] > 0.0 && (cw * S.div < Rmax + S.margin || cw * 11.0 < span)) ok = false;
+            if (S.L[d] > 0.0 && (cw * S.div < Rmax + S.margin || cw * SPH_SPAN_CELLS < span))
+                ok = false;
         }
         if (ok) break;
         --l;
