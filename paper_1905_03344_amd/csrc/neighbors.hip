@@ -141,8 +141,9 @@ __device__ __forceinline__ int count_fill(const Search &S, const double *__restr
 // particle, full counts until the iteration ends.
 // With h_try (learned mode) round 0 counts at h_try[i], without a shell,
 // and accepts it when in the band.  A miss starts the plain iteration from
-// h[i] in the tail, whose first count of such a particle is the plain
-// solve's round-0 count (with the shell and the iteration on it); a miss
+// h[i] in the worklist round (the tail when misses are few), whose first
+// count of such a particle is the plain solve's round-0 count (with the
+// shell and the iteration on it); a miss
 // whose try equals h[i] exactly goes on with the plain iteration at once.
 // Every count is exact, so a miss follows the plain solve's path and ends
 // on its h; cells are walked in Morton order, so gather sets do not depend
@@ -479,6 +480,18 @@ __device__ __forceinline__ double tile_r2(const WaveLds &L, int t, double xi, do
 // as they were, while the larger cell table cost 2.5 ms per step.
 #ifndef SPH_SPAN_CELLS
 #define SPH_SPAN_CELLS 11.0
+#endif
+// Learned mode gives its misses (restarted from h_prev) a wave-cooperative
+// worklist round whatever n, unless they are few: fewer than
+// SPH_LEARNED_ROUND_MIN and under a tenth of the particles, when the
+// per-particle tail serves them better (scattered misses make large union
+// boxes).  Measured, ms per step (mixed + learned): 1M patch (55% misses)
+// 8.64 with the tail alone, 3.93 with the round; 8k patch 3.31 -> 1.55;
+// 1M clumpy mixture (0.6%) 4.73 with the tail, 5.63 with the round.
+// Deferring small groups of a worklist round to the tail (as round 0 does)
+// made the plain 64M step slower (163.7 -> 170.7 ms) and is not done.
+#ifndef SPH_LEARNED_ROUND_MIN
+#define SPH_LEARNED_ROUND_MIN 65536
 #endif
 #ifndef SPH_WL_SHELL_D
 #define SPH_WL_SHELL_D 0.0
@@ -1287,6 +1300,8 @@ __attribute__((amdgpu_waves_per_eu(SPH_ROUND_WAVES, SPH_ROUND_WAVES))) void k_hs
     const int64_t grp = blk * WAVES_PER_BLOCK + w;
     const int64_t slot = grp * 64 + lane;
     const int64_t total = wl ? *wcount : n;
+    // few learned misses: all of them to the tail
+    if (wl && A.h_try && total < SPH_LEARNED_ROUND_MIN && total * 10 < n) return;
     const bool listed = slot < total;
     const int64_t i = listed ? (wl ? (int64_t)wl[slot] : slot) : 0;
     // each particle takes at most A.rounds + 1 full walks in these
@@ -1310,7 +1325,8 @@ __attribute__((amdgpu_waves_per_eu(SPH_ROUND_WAVES, SPH_ROUND_WAVES))) void k_hs
     int64_t tested = 0, counts = 0, acc = 0, fallback = 0, nonconv = 0, overflow = 0;
     // The learned try, accepted almost always, is counted without a shell
     // (SPH_TRY_SHELL_D): a miss restarts the plain iteration from h_prev,
-    // with its shell, in the worklist round (large runs) or the tail.  Plain
+    // with its shell, in the worklist round (or, when misses are few, the
+    // tail: SPH_LEARNED_ROUND_MIN).  Plain
     // counts of small runs record the shell, on which most misses of h_prev
     // converge (SPH_BIG_N).
     const bool try_walk = FIRST && A.h_try != nullptr;
@@ -1557,7 +1573,7 @@ hipError_t launch_hsolve(sph_ctx *c, sph_particles *s, sph_nlist *nl, const doub
     const bool worklist = p.walk_strategy == SPH_WALK_WORKLIST ||
                           (p.walk_strategy == SPH_WALK_AUTO && n >= SPH_BIG_N);
     A.first_shell = worklist ? 0 : 1;
-    A.rounds = worklist ? 1 : 0;
+    A.rounds = (worklist || h_try) ? 1 : 0;
     A.target = p.n_target;
     A.tol = p.n_tol;
     A.maxit = p.h_max_iter;
