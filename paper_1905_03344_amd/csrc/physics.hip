@@ -482,7 +482,9 @@ __device__ __forceinline__ NbrF load_nbr(int j, const Pk64 &P, const double *__r
     const double2 a = P.xy[j], zh = P.zh[j], v = P.vxy[j], vm = P.vzm[j], rp = P.rp[j];
     b.x = a.x; b.y = a.y; b.z = zh.x; b.h = zh.y;
     b.vx = v.x; b.vy = v.y; b.vz = vm.x; b.m = vm.y;
-    b.rho = rp.x; b.p = rp.y; b.c = c[j];
+    // the plain form's sound speed follows from the record (ideal gas:
+    // c^2 = gamma P / rho = gamma (P / rho^2) rho), one gather fewer per pair
+    b.rho = rp.x; b.p = rp.y; b.c = GR == SPH_GR_AVG ? 0.0 : c[j];
     b.xw = GR == SPH_GR_GVE ? Xw[j] : 0.0;
     if (GR == SPH_GR_IAD) {
         const double2 p0 = I.a[j], p1 = I.b[j], p2 = I.c[j];
@@ -504,7 +506,7 @@ __device__ __forceinline__ void force_pair(const NbrF &b, double xi, double yi, 
                                            double inv_hi, double rhoi, double ci, double pi_term,
                                            const double *cmi, double ri, const Geo &g,
                                            double knorm, double alpha, double beta, double eta2,
-                                           ForceAcc &A)
+                                           double gamma, ForceAcc &A)
 {
     double dx = mimg<PM, 0>(xi, b.x, g);
     double dy = mimg<PM, 1>(yi, b.y, g);
@@ -555,7 +557,12 @@ __device__ __forceinline__ void force_pair(const NbrF &b, double xi, double yi, 
     double Pi = 0.0;
     if (w < 0.0) {
         double hb = 0.5 * (hi + hj);
-        double cb = 0.5 * (ci + b.c);
+        double cj = b.c;
+        if (GR == SPH_GR_AVG) {
+            const double c2 = gamma * b.p * rhoj;
+            cj = c2 > 0.0 ? c2 * rsqrt_nr(c2) : 0.0;
+        }
+        double cb = 0.5 * (ci + cj);
         double rb = 0.5 * (rhoi + rhoj);
         const double den = r2 + eta2 * hb * hb;
         const double rq = rcp_nr(den * rb);
@@ -598,7 +605,8 @@ __global__ __launch_bounds__(SPH_BLOCK) SPH_PAIR_WAVES_F void k_forces(
     int64_t n, Pk64 P, IadC I, const double *__restrict__ Xw, const double *__restrict__ c,
     const int32_t *__restrict__ nc, const int32_t *__restrict__ idx, int K,
     const int32_t *__restrict__ ecnt, const int32_t *__restrict__ eidx, int slots, Geo g,
-    double knorm, double alpha, double beta, double eta2, double cfl, double *__restrict__ ax,
+    double knorm, double alpha, double beta, double eta2, double gamma, double cfl,
+    double *__restrict__ ax,
     double *__restrict__ ay, double *__restrict__ az, double *__restrict__ du,
     double *__restrict__ dt_part)
 {
@@ -619,7 +627,7 @@ __global__ __launch_bounds__(SPH_BLOCK) SPH_PAIR_WAVES_F void k_forces(
             const double vxi = me.vx, vyi = me.vy, vzi = me.vz;
             hi = me.h;
             const double inv_hi = 1.0 / hi, rhoi = me.rho;
-            ci = me.c;
+            ci = c[i];
             const double pi_term = me.p;
             const double ri = GR == SPH_GR_GVE ? me.xw / me.m : 0.0;
             const int cnt = min(nc[i], K);
@@ -644,7 +652,8 @@ __global__ __launch_bounds__(SPH_BLOCK) SPH_PAIR_WAVES_F void k_forces(
                 for (int q = 0; q < SPH_FBATCH; ++q) {
                     if (k0 + q * SPH_GROUP >= tot) break;
                     force_pair<PM, KER, GR>(nb[q], xi, yi, zi, vxi, vyi, vzi, hi, inv_hi, rhoi, ci,
-                                            pi_term, me.cm, ri, g, knorm, alpha, beta, eta2, A);
+                                            pi_term, me.cm, ri, g, knorm, alpha, beta, eta2,
+                                            gamma, A);
                 }
             }
         }
@@ -701,7 +710,8 @@ hipError_t launch_forces(sph_ctx *c, sph_particles *s, const sph_nlist *nl, doub
     dim3((unsigned)nb), dim3(SPH_BLOCK), 0, c->stream, n, ctx_pk64(c), I, c->w.gve_x, s->c,      \
         s->nc[cur],                                                                             \
         nl->idx, p.list_stride, nl->ecnt, nl->eidx, p.extra_slots, g, c->knorm, p.av_alpha,     \
-        p.av_beta, p.av_eta2, p.cfl, s->ax[cur], s->ay[cur], s->az[cur], s->du[cur], part
+        p.av_beta, p.av_eta2, p.gamma, p.cfl, s->ax[cur], s->ay[cur], s->az[cur], s->du[cur],   \
+        part
     if (p.extra_slots > SPH_ELDS) {
         hipError_t e = launch_sort_extra(c, nl, n);
         if (e != hipSuccess) return e;
