@@ -252,51 +252,93 @@ __global__ __launch_bounds__(SPH_BLOCK) void k_sort_hist(const uint32_t *__restr
     }
 }
 
+// Stable scatter of one tile: the tile's keys are ranked in index order
+// (16 rounds of 256, equal digits of a wave ranked by ballots) into LDS,
+// grouped by digit, then written out in that order, so that the keys of one
+// digit leave the tile as one contiguous run instead of one store each.
 __global__ __launch_bounds__(SPH_BLOCK) void k_sort_scatter(
     const uint32_t *__restrict__ key_in, const int32_t *__restrict__ val_in, int64_t n, int shift,
     int64_t nb, const uint32_t *__restrict__ offs, uint32_t *__restrict__ key_out,
     int32_t *__restrict__ val_out)
 {
-    __shared__ uint32_t base[256];
+    __shared__ uint32_t lkey[SPH_SORT_TILE];
+    __shared__ int32_t lval[SPH_SORT_TILE];
+    __shared__ uint32_t lstart[256];   // first slot of each digit in the tile
+    __shared__ uint32_t run[256];      // next slot of each digit
     __shared__ uint32_t wcount[SPH_BLOCK / 64][256];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    for (int d = threadIdx.x; d < 256; d += SPH_BLOCK) base[d] = offs[(int64_t)d * nb + blockIdx.x];
+    const int64_t tile = blockIdx.x * (int64_t)SPH_SORT_TILE;
+    const int tn = (int)min((int64_t)SPH_SORT_TILE, n - tile);   // keys in this tile
+    // the tile's digit counts, then their exclusive prefix
+    for (int d = threadIdx.x; d < 256; d += SPH_BLOCK) run[d] = 0;
+    __syncthreads();
+    for (int r = 0; r < SPH_SORT_ITEMS; ++r) {
+        const int k = r * SPH_BLOCK + threadIdx.x;
+        if (k < tn) atomicAdd(&run[(key_in[tile + k] >> shift) & 255u], 1u);
+    }
+    __syncthreads();
+    if (threadIdx.x < 64) {
+        // 256 counts, 4 per lane, exclusive scan across the wave
+        uint32_t c[4], t = 0;
+        for (int v = 0; v < 4; ++v) {
+            c[v] = run[4 * threadIdx.x + v];
+            t += c[v];
+        }
+        uint32_t incl = t;
+        for (int o = 1; o < 64; o <<= 1) {
+            const uint32_t y = (uint32_t)__shfl_up((int)incl, o, 64);
+            if ((int)threadIdx.x >= o) incl += y;
+        }
+        uint32_t e = incl - t;
+        for (int v = 0; v < 4; ++v) {
+            lstart[4 * threadIdx.x + v] = e;
+            run[4 * threadIdx.x + v] = e;
+            e += c[v];
+        }
+    }
     const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-    int64_t tile = blockIdx.x * (int64_t)SPH_SORT_TILE;
     for (int r = 0; r < SPH_SORT_ITEMS; ++r) {
         for (int k = threadIdx.x; k < 256 * (SPH_BLOCK / 64); k += SPH_BLOCK)
             (&wcount[0][0])[k] = 0;
         __syncthreads();
-        int64_t i = tile + r * SPH_BLOCK + threadIdx.x;
-        bool valid = i < n;
-        uint32_t k_ = valid ? key_in[i] : 0u;
-        int32_t v_ = valid ? val_in[i] : 0;
-        uint32_t d = (k_ >> shift) & 255u;
+        const int k = r * SPH_BLOCK + threadIdx.x;
+        const bool valid = k < tn;
+        const uint32_t k_ = valid ? key_in[tile + k] : 0u;
+        const int32_t v_ = valid ? val_in[tile + k] : 0;
+        const uint32_t d = (k_ >> shift) & 255u;
         uint64_t same = __ballot(valid);
         for (int b = 0; b < 8; ++b) {
-            uint64_t bal = __ballot((d >> b) & 1u);
+            const uint64_t bal = __ballot((d >> b) & 1u);
             same &= ((d >> b) & 1u) ? bal : ~bal;
         }
-        uint32_t rank = (uint32_t)__popcll(same & lt);
+        const uint32_t rank = (uint32_t)__popcll(same & lt);
         if (valid && rank == 0) wcount[wv][d] = (uint32_t)__popcll(same);
         __syncthreads();
-        // per digit: prefix over waves, then advance the digit base
+        // per digit: prefix over the waves, then advance the digit's slot
         for (int dd = threadIdx.x; dd < 256; dd += SPH_BLOCK) {
-            uint32_t run = base[dd];
-            for (int k = 0; k < SPH_BLOCK / 64; ++k) {
-                uint32_t t = wcount[k][dd];
-                wcount[k][dd] = run;
-                run += t;
+            uint32_t at = run[dd];
+            for (int w = 0; w < SPH_BLOCK / 64; ++w) {
+                const uint32_t t = wcount[w][dd];
+                wcount[w][dd] = at;
+                at += t;
             }
-            base[dd] = run;
+            run[dd] = at;
         }
         __syncthreads();
         if (valid) {
-            uint32_t pos = wcount[wv][d] + rank;
-            key_out[pos] = k_;
-            val_out[pos] = v_;
+            const uint32_t pos = wcount[wv][d] + rank;
+            lkey[pos] = k_;
+            lval[pos] = v_;
         }
-        __syncthreads();
+    }
+    __syncthreads();
+    // out in slot order: slot s of digit d goes to offs[d] + (s - lstart[d])
+    for (int s = threadIdx.x; s < tn; s += SPH_BLOCK) {
+        const uint32_t k_ = lkey[s];
+        const uint32_t d = (k_ >> shift) & 255u;
+        const uint32_t pos = offs[(int64_t)d * nb + blockIdx.x] + ((uint32_t)s - lstart[d]);
+        key_out[pos] = k_;
+        val_out[pos] = lval[s];
     }
 }
 
