@@ -330,8 +330,9 @@ __global__ __launch_bounds__(SPH_BLOCK) void k_sort_scatter(
             lkey[pos] = k_;
             lval[pos] = v_;
         }
+        // every wave has read this round's wcount before the next clears it
+        __syncthreads();
     }
-    __syncthreads();
     // out in slot order: slot s of digit d goes to offs[d] + (s - lstart[d])
     for (int s = threadIdx.x; s < tn; s += SPH_BLOCK) {
         const uint32_t k_ = lkey[s];

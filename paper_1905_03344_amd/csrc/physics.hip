@@ -23,8 +23,11 @@
 #ifndef SPH_GROUP
 #define SPH_GROUP 8
 #endif
+// pairs per lane per batch of the density pass: 3 keeps it at 113 VGPRs (4
+// waves/SIMD; 4 pairs take 131, 3 waves): 64M density 37.7 -> 36.0 ms, 8M
+// 4.97 -> 4.72 (2 pairs: 37.3 ms at 5 waves)
 #ifndef SPH_BATCH
-#define SPH_BATCH 4
+#define SPH_BATCH 3
 #endif
 #ifndef SPH_FBATCH
 #define SPH_FBATCH 2

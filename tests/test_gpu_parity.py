@@ -603,6 +603,27 @@ def test_tiny_inputs():
     sim0.sync()
 
 
+def test_sort_of_scattered_keys_repeated():
+    """The radix sort on a million keys in generator order (every digit pass
+    moves nearly every key across its tile), on fresh states three times:
+    the permutation equals the oracle's stable sort each time.  The scatter
+    ranks a tile's keys into LDS round by round; a missing barrier between
+    its rounds once let a wave clear the round counts another wave still read,
+    which showed as an unsorted key at 8M particles."""
+    ic = inputs.clumpy(seed=inputs.CONFIG_SEEDS[4])
+    lo, hi = O.bbox(ic.x, ic.y, ic.z, ic.periodic, ic.box_lo, ic.box_hi)
+    key = O.cell_keys(ic.x, ic.y, ic.z, lo, hi)
+    perm = O.sort_perm(key)
+    assert np.mean(perm != np.arange(ic.n)) > 0.99
+    for rep in range(3):
+        print(f"sort of scattered keys, repeat {rep}", flush=True)
+        sim = _sim(ic)
+        sim.build_cells()
+        sim.sync()
+        np.testing.assert_array_equal(sim.numpy("perm"), perm)
+        np.testing.assert_array_equal(sim.numpy("key"), key[perm])
+
+
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
 @pytest.mark.parametrize("variant", ["grad_h", "iad"])
 def test_tiny_inputs_variants(variant, precision):
