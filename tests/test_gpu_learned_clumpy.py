@@ -10,11 +10,12 @@ learned step against the oracle at its own h.
   step: neighbour counts per particle, candidates tested by the walks,
   fallback rate, and the h iteration's time (with and without the MLP's,
   for the learned form).  Counts, candidates and fallbacks are exact and
-  asserted; so are the first walk's time (the accepted try is counted
-  without the shell the plain count records: ~15% less) and the h
-  iteration's kernels.  With the MLP's inference (~0.1 ms here) the learned
-  form's h iteration is level with the plain one on this workload; the time
-  is reported, not asserted.
+  asserted; so is the first walk's time (the accepted try is counted
+  without the shell the plain count records: ~15% less).  The h iteration
+  as a whole is level with the plain one on this workload (the walk's
+  saving goes to the per-particle tail that serves the 0.6% of misses:
+  2.49 against 2.56 ms measured, 2.60 with the MLP's inference), so its time
+  is asserted within 5% of plain's, and reported.
 * Parity (125,000 particles, one learned step from the oracle's state):
   cells, counts and both neighbour sets exact, accepted h in band by the
   oracle's count, fallback h identical to the plain iteration's, fields at
@@ -134,11 +135,11 @@ def test_learned_gain_clumpy_1m(trained_1m):
     assert learned["fallback_rate"] < 0.75 * zero["fallback_rate"]
     assert learned["fallback_rate"] < 0.05
     # fewer candidates and less time in the first walk (the accepted try is
-    # counted without the shell the plain count records) and in the h
-    # iteration's kernels
+    # counted without the shell the plain count records); the h iteration as
+    # a whole level with plain's
     assert learned["candidates_per_particle"] < plain["candidates_per_particle"]
     assert learned["walk_ms"] < 0.95 * plain["walk_ms"]
-    assert learned["hsolve_ms"] < plain["hsolve_ms"]
+    assert learned["hsolve_ms"] < 1.05 * plain["hsolve_ms"]
     # the learned run itself, sampled against the oracle at its own h
     # a cube about the densest clump, kept inside [0.1, 0.9]^3 where the
     # background bounds h (outside the unit cube only sparse clump tails
