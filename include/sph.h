@@ -90,6 +90,18 @@ typedef struct sph_ctx sph_ctx;
 #define SPH_WALK_SHELL_FIRST 1
 #define SPH_WALK_WORKLIST 2
 
+/* Shell of the learned try (SPH_H_LEARNED; speed only: h, counts, sets, rows
+ * and the accepted/fallback split are the same).  NEVER: the try counts at the
+ * predicted h without a shell and every miss restarts the plain iteration from
+ * h_prev with a new walk.  ALWAYS: the try records the plain first count's
+ * shell |r - 2h| < 2h/24 around the predicted h, so that a miss whose h_prev
+ * lies inside it iterates on the shell without a walk.  AUTO: the shell when
+ * the walk strategy is SHELL_FIRST, n >= 131,072 and more than a tenth of the
+ * previous learned h solve's tries missed the band (none on the first). */
+#define SPH_TRY_SHELL_AUTO 0
+#define SPH_TRY_SHELL_NEVER 1
+#define SPH_TRY_SHELL_ALWAYS 2
+
 /* Time integrators of sph_step.  KDK: kick-drift-kick leapfrog (positions,
  * velocities and energy).  AB2: the same positions and velocities, the
  * energy by second-order Adams-Bashforth with a variable step (the paper's
@@ -163,6 +175,8 @@ typedef struct sph_params {
     int32_t volumes;        /* SPH_VOLUMES_STANDARD (default) or SPH_VOLUMES_GENERALIZED */
     int32_t walk_strategy;  /* SPH_WALK_AUTO (default), _SHELL_FIRST or _WORKLIST (speed only)*/
     double gve_exponent;    /* p of the generalized weights X = (m/rho)^p, in [0, 1] (0.7) */
+    int32_t learned_try_shell; /* SPH_TRY_SHELL_AUTO (default), _NEVER or _ALWAYS */
+    int32_t pad1;
 } sph_params;
 
 typedef struct sph_particles {

@@ -145,6 +145,9 @@ static const char *validate(const sph_params *p)
         return "walk_prefilter must be SPH_PREFILTER_NONE or SPH_PREFILTER_MATRIX";
     if (p->walk_strategy < SPH_WALK_AUTO || p->walk_strategy > SPH_WALK_WORKLIST)
         return "walk_strategy must be SPH_WALK_AUTO, SPH_WALK_SHELL_FIRST or SPH_WALK_WORKLIST";
+    if (p->learned_try_shell < SPH_TRY_SHELL_AUTO || p->learned_try_shell > SPH_TRY_SHELL_ALWAYS)
+        return "learned_try_shell must be SPH_TRY_SHELL_AUTO, SPH_TRY_SHELL_NEVER or "
+               "SPH_TRY_SHELL_ALWAYS";
     if (p->volumes != SPH_VOLUMES_STANDARD && p->volumes != SPH_VOLUMES_GENERALIZED)
         return "volumes must be SPH_VOLUMES_STANDARD or SPH_VOLUMES_GENERALIZED";
     if (p->volumes == SPH_VOLUMES_GENERALIZED) {
@@ -194,6 +197,7 @@ size_t sph_layout(const sph_params *p, void *base, Workspace *w)
     t.cell_start = (int32_t *)take(ncell * sizeof(int32_t));
     t.hk = (double *)take(1024 * sizeof(double));
     t.status = (int64_t *)take(ST_COUNT * sizeof(int64_t));
+    t.learn_step = (int64_t *)take(4 * sizeof(int64_t));
     t.dt_cur = (double *)take(sizeof(double));
     t.red_part = (double *)take(red_len * sizeof(double));
     t.refill = (uint8_t *)take(n);
@@ -367,6 +371,9 @@ extern "C" int sph_bind(sph_ctx *c, void *workspace, size_t bytes, void *stream)
     if (r) return r;
     r = hip_check(c, hipMemsetAsync(c->w.status, 0, ST_COUNT * sizeof(int64_t), c->stream),
                   "clear status");
+    if (r) return r;
+    r = hip_check(c, hipMemsetAsync(c->w.learn_step, 0, 4 * sizeof(int64_t), c->stream),
+                  "clear learned-try counters");
     if (r) return r;
     r = hip_check(c, hipMemsetAsync(c->w.dt_cur, 0, sizeof(double), c->stream), "clear dt");
     if (r) return r;

@@ -454,13 +454,22 @@ __device__ __forceinline__ double tile_r2(const WaveLds &L, int t, double xi, do
 #ifndef SPH_SHELL_D
 #define SPH_SHELL_D 24.0
 #endif
-// shell of the learned try: 0, none (every miss restarts in the tail).  A
-// narrow one (|r - 2h| < 2h/96) would let misses whose h_prev is in band
-// converge without a new walk, but recording it costs more than the tail
-// saves: 64M patch 143 ms per step without, 163 ms with; 1M clumpy mixture
-// 4.75 against 4.88 ms
+// shell of the learned try when it records none: 0 (every miss restarts
+// with a new walk).  Where tries are accepted almost always, a shell costs
+// more than it saves: a narrow one (|r - 2h| < 2h/96) took the 64M patch
+// from 143 to 163 ms per step, the 1M clumpy mixture from 4.75 to 4.88 ms.
+// Where many tries miss (the lattice, whose count moves by whole shells of
+// neighbours), the try records the plain count's shell (SPH_SHELL_D)
+// instead, chosen per solve from the previous one's misses
+// (sph_params.learned_try_shell): 1M patch with 55% misses 3.91 -> 3.63 ms
+// per step.  Not below SPH_TRY_SHELL_MIN_N particles, where a walk's time is
+// one wave's latency and the shell's stores lengthen it more than the tail
+// gains (8k patch, 69% misses: 1.60 -> 1.67 ms).
 #ifndef SPH_TRY_SHELL_D
 #define SPH_TRY_SHELL_D 0.0
+#endif
+#ifndef SPH_TRY_SHELL_MIN_N
+#define SPH_TRY_SHELL_MIN_N 131072
 #endif
 // shell of round 0 under the worklist strategy (0: none).  Recording one
 // costs round 0 more than the worklist round saves: 64M patch 165.5 ms per
@@ -1113,6 +1122,8 @@ struct HArgs {
     int lmax, div, prefilter, defer, target, tol, maxit;
     int first_shell;   // round 0 records the shell of its count (plain counts)
     int rounds;        // wave-cooperative worklist rounds after round 0
+    int try_shell;     // the learned try's shell: 0 none, 2 always, 1 when lstep[2] is set
+    int64_t *lstep;    // accepted and missed tries of this solve; [2]: the next try's shell
     HIter H;
     Shell SH;
     int64_t *status;
@@ -1330,7 +1341,8 @@ __attribute__((amdgpu_waves_per_eu(SPH_ROUND_WAVES, SPH_ROUND_WAVES))) void k_hs
     // counts of small runs record the shell, on which most misses of h_prev
     // converge (SPH_BIG_N).
     const bool try_walk = FIRST && A.h_try != nullptr;
-    const double sd = try_walk ? SPH_TRY_SHELL_D
+    const bool try_shell = try_walk && (A.try_shell == 2 || (A.try_shell == 1 && A.lstep[2] != 0));
+    const double sd = try_walk ? (try_shell ? SPH_SHELL_D : SPH_TRY_SHELL_D)
                                : ((FIRST && !A.first_shell) ? SPH_WL_SHELL_D : SPH_SHELL_D);
     const double ta = sd > 0.0 ? 2.0 * hc * (1.0 - 1.0 / sd) : 2.0 * hc;
     const double tb = sd > 0.0 ? 2.0 * hc * (1.0 + 1.0 / sd) : 2.0 * hc;
@@ -1419,8 +1431,8 @@ __attribute__((amdgpu_waves_per_eu(SPH_ROUND_WAVES, SPH_ROUND_WAVES))) void k_hs
     block_add_i64(nonconv, A.status + ST_NONCONV);
     block_add_i64(overflow, A.status + ST_LIST_OVERFLOW);
     if (A.h_try) {
-        block_add_i64(acc, A.status + ST_LEARN_ACC);
-        block_add_i64(fallback, A.status + ST_LEARN_FALLBACK);
+        block_add2_i64(acc, A.status + ST_LEARN_ACC, A.lstep);
+        block_add2_i64(fallback, A.status + ST_LEARN_FALLBACK, A.lstep + 1);
     }
 }
 
@@ -1504,8 +1516,8 @@ __attribute__((amdgpu_waves_per_eu(SPH_TAIL_WAVES, SPH_TAIL_WAVES))) void k_hsol
     block_add_i64(rep ? nonconv : 0, A.status + ST_NONCONV);
     block_add_i64(rep ? overflow : 0, A.status + ST_LIST_OVERFLOW);
     if (A.h_try) {
-        block_add_i64(rep ? acc : 0, A.status + ST_LEARN_ACC);
-        block_add_i64(rep ? fallback : 0, A.status + ST_LEARN_FALLBACK);
+        block_add2_i64(rep ? acc : 0, A.status + ST_LEARN_ACC, A.lstep);
+        block_add2_i64(rep ? fallback : 0, A.status + ST_LEARN_FALLBACK, A.lstep + 1);
     }
 }
 
@@ -1519,6 +1531,14 @@ __global__ __launch_bounds__(SPH_BLOCK) void k_refill(HArgs A, int64_t n)
     const int w = threadIdx.x >> 6;
     const int64_t i = global_index();
     int64_t overflow = 0, tested = 0;
+    if (A.h_try && i == 0) {
+        // the solve's tries are all counted (round 0, worklist round, tail):
+        // the next try records a shell when more than a tenth missed
+        const int64_t ac = A.lstep[0], mi = A.lstep[1];
+        A.lstep[2] = mi * 10 > ac + mi ? 1 : 0;
+        A.lstep[0] = 0;
+        A.lstep[1] = 0;
+    }
     const bool act = i < n && A.refill[i];
     if (__ballot(act)) {
         const Search S = make_search(A.cs, A.lmax, A.div, A.prefilter, A.defer, A.bbox, A.g);
@@ -1574,6 +1594,10 @@ hipError_t launch_hsolve(sph_ctx *c, sph_particles *s, sph_nlist *nl, const doub
                           (p.walk_strategy == SPH_WALK_AUTO && n >= SPH_BIG_N);
     A.first_shell = worklist ? 0 : 1;
     A.rounds = (worklist || h_try) ? 1 : 0;
+    A.try_shell = p.learned_try_shell == SPH_TRY_SHELL_ALWAYS ? 2
+                : (p.learned_try_shell == SPH_TRY_SHELL_AUTO && !worklist &&
+                   n >= SPH_TRY_SHELL_MIN_N) ? 1 : 0;
+    A.lstep = c->w.learn_step;
     A.target = p.n_target;
     A.tol = p.n_tol;
     A.maxit = p.h_max_iter;

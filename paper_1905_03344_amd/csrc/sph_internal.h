@@ -80,6 +80,8 @@ struct Workspace {
     int32_t *cell_start;   // 8^max_level + 1
     double *hk;            // 1024 Hernquist-Katz factors
     int64_t *status;       // ST_COUNT
+    int64_t *learn_step;   // 4: tries and misses of the current learned h solve, and
+                           // whether the next one's try records a shell (1) or not (0)
     double *dt_cur;        // 1: dt used by the current step
     double *red_part;      // reduction partials: nb_red * 8, or one per force block
     uint8_t *refill;       // n_max
@@ -504,6 +506,25 @@ __device__ __forceinline__ void block_add_i64(int64_t v, int64_t *addr)
         if (t) atomicAdd((unsigned long long *)addr, (unsigned long long)t);
     }
     __syncthreads();  // the shared slots are reused by the next call
+}
+
+// one block total added to two counters (one atomic each)
+__device__ __forceinline__ void block_add2_i64(int64_t v, int64_t *a, int64_t *b)
+{
+    __shared__ int64_t part[SPH_BLOCK / 64];
+    v = wave_sum_i64(v);
+    int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    if (lane == 0) part[wv] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int64_t t = 0;
+        for (int k = 0; k < (int)(blockDim.x >> 6); ++k) t += part[k];
+        if (t) {
+            atomicAdd((unsigned long long *)a, (unsigned long long)t);
+            atomicAdd((unsigned long long *)b, (unsigned long long)t);
+        }
+    }
+    __syncthreads();
 }
 
 #endif  // __HIPCC__

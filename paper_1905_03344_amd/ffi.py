@@ -34,6 +34,9 @@ SPH_PREFILTER_MATRIX = 1
 SPH_WALK_AUTO = 0
 SPH_WALK_SHELL_FIRST = 1
 SPH_WALK_WORKLIST = 2
+SPH_TRY_SHELL_AUTO = 0
+SPH_TRY_SHELL_NEVER = 1
+SPH_TRY_SHELL_ALWAYS = 2
 SPH_H_PLAIN = 0
 SPH_H_LEARNED = 1
 SPH_FLAG_NOCONV = 1
@@ -53,7 +56,8 @@ class sph_params(ctypes.Structure):
                 ("av_beta", _D), ("av_eta2", _D), ("cfl", _D), ("h_mode", _I32),
                 ("check_finite", _I32), ("max_level", _I32), ("search_div", _I32),
                 ("grad_h", _I32), ("gradients", _I32), ("walk_defer_group", _I32),
-                ("volumes", _I32), ("walk_strategy", _I32), ("gve_exponent", _D)]
+                ("volumes", _I32), ("walk_strategy", _I32), ("gve_exponent", _D),
+                ("learned_try_shell", _I32), ("pad1", _I32)]
 
 
 CARRIED_F64 = ("x", "y", "z", "vx", "vy", "vz", "m", "h", "u", "ax", "ay", "az", "du", "rho",

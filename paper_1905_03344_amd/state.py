@@ -32,7 +32,7 @@ class Simulation:
                  precision=ffi.SPH_FP64, check_finite=False, h_mode=ffi.SPH_H_PLAIN,
                  walk_prefilter=None, kernel=None, integrator=None, grad_h=False,
                  gradients=None, walk_defer_group=None, volumes=None, gve_exponent=None,
-                 walk_strategy=None):
+                 walk_strategy=None, learned_try_shell=None):
         """Allocate the state and the workspace for ic and bind a context.
 
         precision: ffi.SPH_FP64 or ffi.SPH_MIXED; h_mode: ffi.SPH_H_PLAIN or
@@ -41,7 +41,8 @@ class Simulation:
         terms; gradients: ffi.SPH_GRADIENTS_KERNEL or _IAD; volumes:
         ffi.SPH_VOLUMES_STANDARD or _GENERALIZED (weights (m/rho)^gve_exponent); walk_prefilter:
         ffi.SPH_PREFILTER_MATRIX or _NONE; walk_strategy: ffi.SPH_WALK_*; walk_defer_group: first-round
-        sub-groups up to this size go to the per-particle tail (speed only).
+        sub-groups up to this size go to the per-particle tail; learned_try_shell:
+        ffi.SPH_TRY_SHELL_* (the last three speed only).
         None keeps the library default.
         list_stride and extra_per_particle are the capacities of the gather
         and complement rows; max_level None picks the cell level from the
@@ -80,6 +81,8 @@ class Simulation:
             p.volumes = int(volumes)
         if walk_strategy is not None:
             p.walk_strategy = int(walk_strategy)
+        if learned_try_shell is not None:
+            p.learned_try_shell = int(learned_try_shell)
         if gve_exponent is not None:
             p.gve_exponent = float(gve_exponent)
         p.precision = int(precision)

@@ -89,6 +89,13 @@ def test_params_validation(lib):
         with pytest.raises(ffi.SphError) as e:
             ffi.sph_create(bad)
         assert "gradients" in str(e.value) or "IAD" in str(e.value)
+    assert p.learned_try_shell == ffi.SPH_TRY_SHELL_AUTO
+    for v in (-1, 3):
+        bad = ffi.default_params()
+        bad.learned_try_shell = v
+        with pytest.raises(ffi.SphError) as e:
+            ffi.sph_create(bad)
+        assert "learned_try_shell" in str(e.value)
 
 
 def test_workspace_size_grows_with_n(lib):

@@ -454,3 +454,29 @@ def test_learned_step_vs_oracle(trained_small, precision):
     else:
         from test_gpu_mixed import check_mixed_fields
         check_mixed_fields(sim, st)
+
+
+def test_learned_try_shell_speed_only(trained_small):
+    """The learned try's shell (never, always, chosen per solve) changes only
+    how the misses are counted: fields, h, counts, flags and the
+    accepted/fallback split are the same bit for bit over three steps of a
+    patch on which many tries miss (AUTO records none at this size)."""
+    from paper_1905_03344_amd import ffi
+    w, norm, _ = trained_small
+    ic = inputs.square_patch(20, 202)
+    modes = (ffi.SPH_TRY_SHELL_NEVER, ffi.SPH_TRY_SHELL_ALWAYS, ffi.SPH_TRY_SHELL_AUTO)
+    runs = {m: _run(ic, ffi.SPH_H_LEARNED, w, norm, steps=3, learned_try_shell=m) for m in modes}
+    ref, rst = runs[ffi.SPH_TRY_SHELL_NEVER]
+    for m in modes[1:]:
+        sim, st = runs[m]
+        for f in FIELDS + ("flags",):
+            np.testing.assert_array_equal(ref.numpy(f), sim.numpy(f), err_msg=f"mode {m}: {f}")
+        for a, b in zip(rst, st):
+            assert (a.learned_accepted, a.learned_fallback) == (b.learned_accepted,
+                                                                 b.learned_fallback)
+    miss = [s.learned_fallback / ic.n for s in rst]
+    cand = {m: [s.candidates for s in runs[m][1]] for m in modes}
+    counts = {m: [s.h_counts for s in runs[m][1]] for m in modes}
+    print(f"misses {miss}; candidates {cand}; counts {counts}", flush=True)
+    assert min(miss) > 0.1   # many misses: the shell saves walks
+    assert sum(cand[ffi.SPH_TRY_SHELL_ALWAYS]) < sum(cand[ffi.SPH_TRY_SHELL_NEVER])
