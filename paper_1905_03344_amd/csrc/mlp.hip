@@ -19,6 +19,8 @@
 
 typedef short s4_t __attribute__((ext_vector_type(4)));
 typedef float f4_t __attribute__((ext_vector_type(4)));
+typedef float f2_t __attribute__((ext_vector_type(2)));
+typedef __bf16 b2_t __attribute__((ext_vector_type(2)));
 
 #define MLP_WAVES_PER_BLOCK (SPH_BLOCK / 64)
 
@@ -54,6 +56,16 @@ __device__ __forceinline__ uint16_t bf16_bits_d(double v)
     return (uint16_t)(__float_as_uint(f) >> 16);
 }
 __device__ __forceinline__ float bf16_val(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
+// four FP32 values rounded to bfloat16 (nearest, ties even) as an MFMA operand:
+// gfx950 converts two per instruction (v_cvt_pk_bf16_f32), the same rounding
+// as bf16_bits_f for finite values
+__device__ __forceinline__ s4_t bf16x4(float a, float b, float c, float d)
+{
+    const b2_t lo = __builtin_convertvector((f2_t){a, b}, b2_t);
+    const b2_t hi = __builtin_convertvector((f2_t){c, d}, b2_t);
+    const uint2 u = make_uint2(__builtin_bit_cast(uint32_t, lo), __builtin_bit_cast(uint32_t, hi));
+    return __builtin_bit_cast(s4_t, u);
+}
 
 struct MlpDev {
     const float *master;        // 4673 FP32 parameters
@@ -122,20 +134,14 @@ __device__ __forceinline__ float mlp_tile_forward(const MlpRegs &R, s4_t x, floa
     for (int t = 0; t < 4; ++t) {
         f4_t d = {0.f, 0.f, 0.f, 0.f};
         d = mfma(R.w1[t], x, d);
-        for (int v = 0; v < 4; ++v) {
-            float a = tanh_f(d[v] + R.b1[t][v]);
-            a1[t][v] = a;
-            h1[t][v] = (short)bf16_bits_f(a);
-        }
+        for (int v = 0; v < 4; ++v) a1[t][v] = tanh_f(d[v] + R.b1[t][v]);
+        h1[t] = bf16x4(a1[t][0], a1[t][1], a1[t][2], a1[t][3]);
     }
     for (int mt = 0; mt < 4; ++mt) {
         f4_t d = {0.f, 0.f, 0.f, 0.f};
         for (int kt = 0; kt < 4; ++kt) d = mfma(R.w2[mt][kt], h1[kt], d);
-        for (int v = 0; v < 4; ++v) {
-            float a = tanh_f(d[v] + R.b2[mt][v]);
-            a2[mt][v] = a;
-            h2[mt][v] = (short)bf16_bits_f(a);
-        }
+        for (int v = 0; v < 4; ++v) a2[mt][v] = tanh_f(d[v] + R.b2[mt][v]);
+        h2[mt] = bf16x4(a2[mt][0], a2[mt][1], a2[mt][2], a2[mt][3]);
     }
     f4_t d = {0.f, 0.f, 0.f, 0.f};
     for (int kt = 0; kt < 4; ++kt) d = mfma(R.w3[kt], h2[kt], d);
