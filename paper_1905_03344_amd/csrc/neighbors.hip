@@ -844,15 +844,28 @@ __device__ void walk_group(WaveLds &L, uint64_t members, int tm, int64_t i, doub
                             nsh = -1;
                         }
                     }
-                    // the row's members in candidate order, skipping self
-                    while (hin) {
-                        int t = __ffsll((unsigned long long)hin) - 1;
+                    // the row's members in candidate order, skipping self;
+                    // each hit's index is read from LDS one hit ahead, so
+                    // that the read is in flight while the previous hit is
+                    // stored
+                    if (hin) {
+                        int32_t *wq = wp + N;            // next entry of the row
+                        int32_t *const wend = wp + K;    // (counted on past it)
+                        int jj = L.c[__ffsll((unsigned long long)hin) - 1].j;
                         hin &= hin - 1;
-                        int jj = L.c[t].j;
-                        if (jj != (int)i) {
-                            if (N < K) wp[N] = jj;
-                            ++N;
+                        for (;;) {
+                            // (past the last hit: a read of slot 63, unused)
+                            const bool more = hin != 0;
+                            const int jn = L.c[(__ffsll((unsigned long long)hin) - 1) & 63].j;
+                            hin &= hin - 1;
+                            if (jj != (int)i) {
+                                if (wq < wend) *wq = jj;
+                                ++wq;
+                            }
+                            if (!more) break;
+                            jj = jn;
                         }
+                        N = (int)(wq - wp);
                     }
                 }
                 wave_lds_sync();
