@@ -78,6 +78,16 @@ __device__ __forceinline__ NeuF mgroup_neu(NeuF a)
 
 __device__ __forceinline__ uint32_t cell_of(float4 a) { return __float_as_uint(a.w); }
 
+// 1/sqrt(r^2) of a pair (r^2 > 0) by the hardware instruction (about 1 ulp),
+// without the denormal rescaling of the library's rsqrtf: a nonzero FP32 r^2
+// of split coordinates is at least (2^-24 w)^2 for the key-cell width w, a
+// normal number for any box wider than about 2e-9 length units; below that
+// the clamp keeps the result finite
+__device__ __forceinline__ float rsq_pair(float r2)
+{
+    return __builtin_amdgcn_rsqf(fmaxf(r2, 1.17549435e-38f));
+}
+
 // offset x_j - x_i in dimension D from split coordinates (wrap on the
 // integer cell difference in periodic dimensions)
 template <int PM, int D>
@@ -286,7 +296,7 @@ __global__ __launch_bounds__(SPH_BLOCK) SPH_PAIR_WAVES_D void k_density_mixed(
                         }
                         if (outside) extra_append(j, (int)i, ecnt, eidx, slots, appended, dropped);
                     }
-                    const float rinv = r2 > 0.0f ? rsqrtf(r2) : 0.0f;
+                    const float rinv = r2 > 0.0f ? rsq_pair(r2) : 0.0f;
                     const float r = r2 * rinv;
                     const float mj = bj.w;
                     const float wk = kern_w_f<KER>(r, inv_h, knorm);
@@ -392,8 +402,10 @@ __device__ __forceinline__ void force_pair_f(const QuadF &ri, float inv_hi, uint
     float dy = split_diff<PM, 1>(gi, gj, ri.a.y, rj.a.y, G);
     float dz = split_diff<PM, 2>(gi, gj, ri.a.z, rj.a.z, G);
     float r2 = dx * dx + dy * dy + dz * dz;
-    if (!(r2 > 0.0f)) return;
-    float inv_r = rsqrtf(r2);
+    // a pair at r = 0 adds zero to every sum (1/r taken as 0 zeroes the
+    // kernel gradients, the offset zeroes the IAD ones); no early exit, so
+    // that the compiler issues all of a batch's gathers before its arithmetic
+    float inv_r = r2 > 0.0f ? rsq_pair(r2) : 0.0f;
     float r = r2 * inv_r;
     float xij = -dx, yij = -dy, zij = -dz;
     float vxij = ri.b.x - rj.b.x, vyij = ri.b.y - rj.b.y, vzij = ri.b.z - rj.b.z;

@@ -515,8 +515,10 @@ __device__ __forceinline__ void force_pair(const NbrF &b, double xi, double yi, 
     double dy = mimg<PM, 1>(yi, b.y, g);
     double dz = mimg<PM, 2>(zi, b.z, g);
     double r2 = dx * dx + dy * dy + dz * dz;
-    if (!(r2 > 0.0)) return;
-    const double inv_r = rsqrt_nr(r2);
+    // a pair at r = 0 adds zero to every sum (1/r taken as 0 zeroes the
+    // kernel gradients, the offset zeroes the IAD ones); no early exit, so
+    // that the compiler issues all of a batch's gathers before its arithmetic
+    const double inv_r = r2 > 0.0 ? rsqrt_nr(r2) : 0.0;
     const double r = r2 * inv_r;
     double hj = b.h;
     double xij = -dx, yij = -dy, zij = -dz;
