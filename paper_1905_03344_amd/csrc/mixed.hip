@@ -257,12 +257,14 @@ __global__ __launch_bounds__(SPH_BLOCK) SPH_PAIR_WAVES_D void k_density_mixed(
                 }
                 float4 ab[SPH_MBATCH], bb[SPH_MBATCH];
                 float hb[SPH_MBATCH], xb[SPH_MBATCH];
+                int ek[SPH_MBATCH];   // complement slot taken for pair q (-1: none)
 #pragma unroll
                 for (int q = 0; q < SPH_MBATCH; ++q) {
                     ab[q] = Q.A[jb[q]];
                     bb[q] = Q.B[jb[q]];
                     if (EXTRA) hb[q] = Q.C[jb[q]].x;
                     xb[q] = GV ? Q.D[jb[q]].x : 0.0f;
+                    ek[q] = -1;
                 }
 #pragma unroll
                 for (int q = 0; q < SPH_MBATCH; ++q) {
@@ -294,7 +296,7 @@ __global__ __launch_bounds__(SPH_BLOCK) SPH_PAIR_WAVES_D void k_density_mixed(
                             double twoh = 2.0 * h[j];
                             outside = !(e2 < twoh * twoh);
                         }
-                        if (outside) extra_append(j, (int)i, ecnt, eidx, slots, appended, dropped);
+                        if (outside) ek[q] = extra_take(j, ecnt);
                     }
                     const float rinv = r2 > 0.0f ? rsq_pair(r2) : 0.0f;
                     const float r = r2 * rinv;
@@ -311,6 +313,11 @@ __global__ __launch_bounds__(SPH_BLOCK) SPH_PAIR_WAVES_D void k_density_mixed(
                     } else if (GH) {
                         neu_add(t, mj * 3.0f * wk);
                     }
+                }
+                if (EXTRA) {
+#pragma unroll
+                    for (int q = 0; q < SPH_MBATCH; ++q)
+                        if (ek[q] >= 0) extra_put(jb[q], ek[q], (int)i, eidx, slots, appended, dropped);
                 }
             }
         }

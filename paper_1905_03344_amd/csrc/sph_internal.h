@@ -313,6 +313,21 @@ __device__ __forceinline__ void extra_append(int j, int i, int32_t *__restrict__
     ++appended;
 }
 
+// The same append in two parts for a batch of pairs: the slot is taken by an
+// atomic (extra_take) and the entry stored (extra_put) after the batch's
+// arithmetic, so that the atomic's round trip overlaps it
+__device__ __forceinline__ int extra_take(int j, int32_t *__restrict__ ecnt)
+{
+    return atomicAdd(&ecnt[j], 1);
+}
+__device__ __forceinline__ void extra_put(int j, int k, int i, int32_t *__restrict__ eidx,
+                                          int slots, int64_t &appended, int64_t &dropped)
+{
+    if (k < slots) eidx[(int64_t)j * slots + k] = i;
+    else if (k == slots) ++dropped;
+    ++appended;
+}
+
 // r^2 = (dx*dx + dy*dy) + dz*dz, each operation rounded on its own
 __device__ __forceinline__ double exact_r2(double dx, double dy, double dz)
 {
