@@ -122,6 +122,7 @@ __global__ __launch_bounds__(SPH_BLOCK) SPH_PAIR_WAVES_D void k_density(
                 }
                 double xb[SPH_BATCH], yb[SPH_BATCH], zb[SPH_BATCH], hb[SPH_BATCH], mb[SPH_BATCH];
                 double ub[SPH_BATCH], vb[SPH_BATCH], wb[SPH_BATCH], qb[SPH_BATCH];
+                int ek[SPH_BATCH];   // complement slot taken for pair q (-1: none)
 #pragma unroll
                 for (int q = 0; q < SPH_BATCH; ++q) {
                     const int j = jb[q];
@@ -129,6 +130,7 @@ __global__ __launch_bounds__(SPH_BLOCK) SPH_PAIR_WAVES_D void k_density(
                     xb[q] = a.x; yb[q] = a.y; zb[q] = b.x; hb[q] = b.y;
                     ub[q] = cv.x; vb[q] = cv.y; wb[q] = d.x; mb[q] = d.y;
                     qb[q] = GV ? X[j] : 0.0;
+                    ek[q] = -1;
                 }
 #pragma unroll
                 for (int q = 0; q < SPH_BATCH; ++q) {
@@ -141,8 +143,7 @@ __global__ __launch_bounds__(SPH_BLOCK) SPH_PAIR_WAVES_D void k_density(
                     if (EXTRA) {
 #pragma clang fp contract(off)
                         double twoh = 2.0 * hb[q];
-                        if (!(r2 < twoh * twoh))
-                            extra_append(j, (int)i, ecnt, eidx, slots, appended, dropped);
+                        if (!(r2 < twoh * twoh)) ek[q] = extra_take(j, ecnt);
                     }
                     const double rinv = r2 > 0.0 ? rsqrt_nr(r2) : 0.0;
                     double rr = r2 * rinv;
@@ -158,6 +159,11 @@ __global__ __launch_bounds__(SPH_BLOCK) SPH_PAIR_WAVES_D void k_density(
                     } else if (GH) {
                         t += mj * 3.0 * wk;
                     }
+                }
+                if (EXTRA) {
+#pragma unroll
+                    for (int q = 0; q < SPH_BATCH; ++q)
+                        if (ek[q] >= 0) extra_put(jb[q], ek[q], (int)i, eidx, slots, appended, dropped);
                 }
             }
         }
