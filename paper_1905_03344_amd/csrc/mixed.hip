@@ -1,6 +1,6 @@
 // Mixed-precision form of the density and force kernels: pair arithmetic in
-// FP32 on cell-relative split coordinates, compensated FP32 sums (Kahan along
-// a lane's pairs, Neumaier across a particle's lanes), results stored in FP64.  Neighbour sets, counts and h come from the exact
+// FP32 on cell-relative split coordinates, Neumaier-compensated FP32 sums,
+// results stored in FP64.  Neighbour sets, counts and h come from the exact
 // FP64 search; the one-sided complement test keeps its exact answer through
 // an FP32 prefilter with an FP64 test for the ambiguous band.
 #include "sph_internal.h"
@@ -66,18 +66,6 @@ __device__ __forceinline__ void neu_add(NeuF &a, float v)
     a.s = t;
 }
 __device__ __forceinline__ double neu_val(const NeuF &a) { return (double)a.s + (double)a.c; }
-// Kahan (1965) compensated summation for the pair loops, the same pair
-// (value s + c): the part of each addition that FP32 drops is carried into
-// the next one; four operations where Neumaier's branch-free form takes
-// eight, the same first-order error bound (2u times the sum of |terms|)
-__device__ __forceinline__ void kah_add(NeuF &a, float v)
-{
-#pragma clang fp contract(off)
-    const float y = v + a.c;
-    const float t = a.s + y;
-    a.c = y - (t - a.s);
-    a.s = t;
-}
 __device__ __forceinline__ NeuF mgroup_neu(NeuF a)
 {
     for (int o = SPH_MGROUP / 2; o > 0; o >>= 1) {
@@ -314,16 +302,16 @@ __global__ __launch_bounds__(SPH_BLOCK) SPH_PAIR_WAVES_D void k_density_mixed(
                     const float r = r2 * rinv;
                     const float mj = bj.w;
                     const float wk = kern_w_f<KER>(r, inv_h, knorm);
-                    kah_add(s, (GV ? xb[q] : mj) * wk);
+                    neu_add(s, (GV ? xb[q] : mj) * wk);
                     if (r > 0.0f) {
                         const float dw = kern_dwdr_f<KER>(r, inv_h, knorm);
                         float gw = dw * rinv;
                         float vdot = (bj.x - bi.x) * (-dx) + (bj.y - bi.y) * (-dy) +
                                      (bj.z - bi.z) * (-dz);
-                        kah_add(dv, mj * vdot * gw);
-                        if (GH) kah_add(t, mj * (3.0f * wk + r * dw));
+                        neu_add(dv, mj * vdot * gw);
+                        if (GH) neu_add(t, mj * (3.0f * wk + r * dw));
                     } else if (GH) {
-                        kah_add(t, mj * 3.0f * wk);
+                        neu_add(t, mj * 3.0f * wk);
                     }
                 }
                 if (EXTRA) {
@@ -452,10 +440,10 @@ __device__ __forceinline__ void force_pair_f(const QuadF &ri, float inv_hi, uint
         const float ajz = (rj.d.z * dx + rj.e.x * dy + rj.e.y * dz) * wj;
         const float abx = 0.5f * (aix + ajx), aby = 0.5f * (aiy + ajy), abz = 0.5f * (aiz + ajz);
         const float mj = rj.b.w, pi_t = ri.c.w, pj_t = rj.c.w;
-        kah_add(A.ax, -mj * ((pi_t * aix + pj_t * ajx) + Pi * abx));
-        kah_add(A.ay, -mj * ((pi_t * aiy + pj_t * ajy) + Pi * aby));
-        kah_add(A.az, -mj * ((pi_t * aiz + pj_t * ajz) + Pi * abz));
-        kah_add(A.du, mj * (pi_t * (vxij * aix + vyij * aiy + vzij * aiz) +
+        neu_add(A.ax, -mj * ((pi_t * aix + pj_t * ajx) + Pi * abx));
+        neu_add(A.ay, -mj * ((pi_t * aiy + pj_t * ajy) + Pi * aby));
+        neu_add(A.az, -mj * ((pi_t * aiz + pj_t * ajz) + Pi * abz));
+        neu_add(A.du, mj * (pi_t * (vxij * aix + vyij * aiy + vzij * aiz) +
                             0.5f * Pi * (vxij * abx + vyij * aby + vzij * abz)));
         return;
     }
@@ -479,26 +467,26 @@ __device__ __forceinline__ void force_pair_f(const QuadF &ri, float inv_hi, uint
         // m_j r_i r_j g_i = X_j q_i and m_j r_i r_j g_j = r_i m_j q_j
         const float ti = rj.d.x * ri.c.w * gwi;
         float f = (ti + ri.d.y * mj * rj.c.w * gwj) + mj * Pi * gbar;
-        kah_add(A.ax, -f * xij);
-        kah_add(A.ay, -f * yij);
-        kah_add(A.az, -f * zij);
-        kah_add(A.du, (ti + 0.5f * mj * Pi * gbar) * w);
+        neu_add(A.ax, -f * xij);
+        neu_add(A.ay, -f * yij);
+        neu_add(A.az, -f * zij);
+        neu_add(A.du, (ti + 0.5f * mj * Pi * gbar) * w);
         return;
     }
     if (GR == 1) {
         float f = mj * ((ri.c.w * gwi + rj.c.w * gwj) + Pi * gbar);
-        kah_add(A.ax, -f * xij);
-        kah_add(A.ay, -f * yij);
-        kah_add(A.az, -f * zij);
-        kah_add(A.du, mj * (ri.c.w * gwi + 0.5f * Pi * gbar) * w);
+        neu_add(A.ax, -f * xij);
+        neu_add(A.ay, -f * yij);
+        neu_add(A.az, -f * zij);
+        neu_add(A.du, mj * (ri.c.w * gwi + 0.5f * Pi * gbar) * w);
         return;
     }
     float sfac = (ri.c.w + rj.c.w) + Pi;
     float f = mj * sfac * gbar;
-    kah_add(A.ax, -f * xij);
-    kah_add(A.ay, -f * yij);
-    kah_add(A.az, -f * zij);
-    kah_add(A.du, mj * (ri.c.w + 0.5f * Pi) * gbar * w);
+    neu_add(A.ax, -f * xij);
+    neu_add(A.ay, -f * yij);
+    neu_add(A.az, -f * zij);
+    neu_add(A.du, mj * (ri.c.w + 0.5f * Pi) * gbar * w);
 }
 
 // S_i = L_i (row order) then E_i (ascending), SPH_MGROUP lanes per particle;
@@ -725,9 +713,9 @@ __global__ __launch_bounds__(SPH_BLOCK) SPH_PAIR_WAVES_D void k_iad_mixed(
                     const float dz = split_diff<PM, 2>(gi, gj, ai.z, ab[q].z, G);
                     const float r = sqrtf(dx * dx + dy * dy + dz * dz);
                     const float vw = mb[q] / rb[q] * kern_w_f<KER>(r, inv_h, knorm);
-                    kah_add(t[0], vw * dx * dx); kah_add(t[1], vw * dx * dy);
-                    kah_add(t[2], vw * dx * dz); kah_add(t[3], vw * dy * dy);
-                    kah_add(t[4], vw * dy * dz); kah_add(t[5], vw * dz * dz);
+                    neu_add(t[0], vw * dx * dx); neu_add(t[1], vw * dx * dy);
+                    neu_add(t[2], vw * dx * dz); neu_add(t[3], vw * dy * dy);
+                    neu_add(t[4], vw * dy * dz); neu_add(t[5], vw * dz * dz);
                 }
             }
         }
