@@ -603,6 +603,34 @@ def test_tiny_inputs():
     sim0.sync()
 
 
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_coincident_particles(precision):
+    """Particles at exactly the same position (with different velocities):
+    each counts the other as a neighbour, the pair adds W(0) to the density
+    and nothing to the gradient sums (the oracle skips r = 0 in the pair
+    force; the kernels take 1/r as 0 there)."""
+    from paper_1905_03344_amd import ffi
+    from test_gpu_mixed import check_mixed_fields
+    ic = inputs.square_patch(16, 9)
+    rng = np.random.default_rng(4)
+    src = rng.choice(ic.n, size=6, replace=False)
+    for a, b in zip(src[:3], src[3:]):
+        ic.x[b], ic.y[b], ic.z[b] = ic.x[a], ic.y[a], ic.z[a]
+    st = O.State(ic.copy())
+    st.keep_gather = True
+    st.evaluate(method=1)
+    prec = ffi.SPH_FP64 if precision == "fp64" else ffi.SPH_MIXED
+    sim = _sim(ic, extra_per_particle=96, precision=prec)
+    sim.evaluate()
+    sim.sync()
+    compare_cells(sim, st)
+    compare_neighbors(sim, st)
+    if precision == "fp64":
+        compare_fields(sim, st)
+    else:
+        check_mixed_fields(sim, st)
+
+
 def test_sort_of_scattered_keys_repeated():
     """The radix sort on a million keys in generator order (every digit pass
     moves nearly every key across its tile), on fresh states three times:
