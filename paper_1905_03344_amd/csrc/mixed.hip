@@ -54,15 +54,20 @@ struct MixGeo {
     int per[3];
 };
 
-// Neumaier (1974) compensated summation in FP32
+// Neumaier (1974) compensated summation in FP32: the rounding error of each
+// addition s + v is accumulated in c.  The error is formed by Knuth's
+// branch-free TwoSum, exact whichever operand is larger (the same value as
+// Neumaier's choice between (s - t) + v and (v - t) + s, in six operations
+// instead of seven with the comparison and select)
 struct NeuF {
     float s, c;
 };
 __device__ __forceinline__ void neu_add(NeuF &a, float v)
 {
 #pragma clang fp contract(off)
-    float t = a.s + v;
-    a.c += (fabsf(a.s) >= fabsf(v)) ? ((a.s - t) + v) : ((v - t) + a.s);
+    const float t = a.s + v;
+    const float vv = t - a.s;
+    a.c += (a.s - (t - vv)) + (v - vv);
     a.s = t;
 }
 __device__ __forceinline__ double neu_val(const NeuF &a) { return (double)a.s + (double)a.c; }
