@@ -37,8 +37,11 @@ __host__ __device__ static inline MixQ mix_quads(void *base, int64_t n_max)
 #define SPH_MROUNDS_F 8
 #endif
 #define SPH_MPTILE_F (SPH_MROUNDS_F * (SPH_BLOCK / SPH_MGROUP))
+// pairs per lane per batch of the mixed density pass (64M patch, density
+// stage: 3 pairs 30.3 ms, 4 pairs 29.1, 5 pairs 27.7 at 124 VGPRs; a lane
+// takes the same pairs in the same order whatever the batch)
 #ifndef SPH_MBATCH
-#define SPH_MBATCH 4
+#define SPH_MBATCH 5
 #endif
 #ifndef SPH_MFBATCH
 #define SPH_MFBATCH 4
