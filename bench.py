@@ -513,7 +513,7 @@ def main():
         copy_calibration()
         return
     if args.gpus != 1:
-        print(f"bench.py measures one GPU only (got --gpus {args.gpus}): this build runs the "
+        print(f"bench.py measures one GPU only (got --gpus {args.gpus}): the library runs the "
               "hot path on a single GPU; the sharded multi-GPU path is a design, not code",
               file=sys.stderr)
         sys.exit(2)

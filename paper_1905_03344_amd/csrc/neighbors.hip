@@ -139,12 +139,12 @@ __device__ __forceinline__ int count_fill(const Search &S, const double *__restr
 // runs: with the shell there), and what remains, with the particles of small
 // (scattered) groups that round 0 leaves alone, to the tail: one wave per
 // particle, full counts until the iteration ends.
-// With h_try (learned mode) round 0 counts at h_try[i], without a shell,
-// and accepts it when in the band.  A miss starts the plain iteration from
-// h[i] in the worklist round (the tail when misses are few), whose first
-// count of such a particle is the plain solve's round-0 count (with the
-// shell and the iteration on it); a miss
-// whose try equals h[i] exactly goes on with the plain iteration at once.
+// With h_try (learned mode) round 0 counts at h_try[i] (with the plain
+// count's shell only where many tries miss, SPH_TRY_SHELL_MIN_N) and accepts
+// it when in the band.  A miss starts the plain iteration from h[i]: on the
+// try's shell when h[i] lies inside it, else in the worklist round (the tail
+// when misses are few), whose first count of such a particle is the plain
+// solve's round-0 count (with the shell and the iteration on it).
 // Every count is exact, so a miss follows the plain solve's path and ends
 // on its h; cells are walked in Morton order, so gather sets do not depend
 // on which wave counts them.
