@@ -198,7 +198,7 @@ def run_form(args, config, form, ic, precision_mixed, learned_weights=None, defe
                      extra_per_particle=extra_slots, walk_prefilter=args.prefilter,
                      kernel=args.kernel_id, integrator=args.integrator_id, grad_h=args.grad_h,
                      gradients=args.gradients_id, walk_defer_group=defer,
-                     walk_strategy=args.strategy_id)
+                     walk_strategy=args.strategy_id, learned_try_shell=args.try_shell_id)
     if learned:
         sim.set_mlp(*learned_weights)
     n = sim.n
@@ -506,6 +506,9 @@ def main():
     ap.add_argument("--walk-strategy", default="auto", choices=["auto", "shell", "worklist"],
                     help="after the first count: the shell of that count (small runs) or a "
                          "worklist round (large runs); auto picks by size")
+    ap.add_argument("--learned-try-shell", default="auto", choices=["auto", "never", "always"],
+                    help="shell of the learned form's try (speed only): auto records the plain "
+                         "count's shell where many tries miss in runs under 4M particles")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a 1 GiB device copy (PMC byte-counter calibration)")
     args = ap.parse_args()
@@ -533,6 +536,8 @@ def main():
                          else ffi.SPH_GRADIENTS_KERNEL)
     args.strategy_id = {"auto": ffi.SPH_WALK_AUTO, "shell": ffi.SPH_WALK_SHELL_FIRST,
                         "worklist": ffi.SPH_WALK_WORKLIST}[args.walk_strategy]
+    args.try_shell_id = {"auto": ffi.SPH_TRY_SHELL_AUTO, "never": ffi.SPH_TRY_SHELL_NEVER,
+                         "always": ffi.SPH_TRY_SHELL_ALWAYS}[args.learned_try_shell]
     config = args.config
     # complement rows: the clumpy mixture's density contrast needs more slots
     extra_slots = 96 if config == 4 else 48
@@ -597,6 +602,7 @@ def main():
                    "form": main_form, "dt": "courant cfl 0.3",
                    "walk_prefilter": args.walk_prefilter, "walk_defer_group": defer or 4,
                    "walk_strategy": args.walk_strategy,
+                   "learned_try_shell": args.learned_try_shell,
                    "kernel": args.kernel, "integrator": args.integrator,
                    "grad_h": bool(args.grad_h), "gradients": args.gradients},
         "roofline": _roofline(kernels, workload) if main_form == "plain" else None,
